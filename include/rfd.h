@@ -1,0 +1,263 @@
+/*
+ * rfd.h - C ABI of the ratio-filter dechirping library for AMD MI355X (gfx950).
+ *
+ * Method: A. H. Nitz, K. Kacanja, K. Soni, "Beyond FINDCHIRP: Breaking the
+ * memory wall and optimal FFTs for gravitational-wave matched-filter searches
+ * with Ratio-Filter Dechirping", arXiv:2601.18835.
+ *
+ * Two-step matched filtering (Sec. III, Fig. 2):
+ *   1. rfd_dechirp: one matched filter (Eq. 1) per *reference* template gives
+ *      the reference SNR series z_ref(t);
+ *   2. rfd_filter_bank: every target template of the reference's sub-bank is
+ *      a short complex FIR applied to z_ref (Eq. 3), with taps from the
+ *      weighted ridge least-squares fit of Sec. V.A (rfd_make_taps), and a
+ *      fused |z|^2 / threshold / per-window-peak epilogue (Table II's peak
+ *      find and trigger accumulation) so no per-template series is stored.
+ *   findchirp_filter is the standard FFT-per-template matched filter (Eq. 1
+ *   evaluated per template, Sec. III), the baseline the paper compares with.
+ *
+ * Conventions shared by every entry point
+ *   - Segment: N = seg_len samples at rate fs (dt = 1/fs, df = fs/N); the
+ *     transform convention is s(f_i) = dt * sum_m s[m] exp(-2 pi i i m/N),
+ *     bins i = 0..N/2 ("rfft grid").  The analysis band is
+ *     i_low = ceil(f_low/df) <= i <= N/2 - 1 (DC and Nyquist excluded).
+ *   - Frequency-domain waveforms are complex128, interleaved (re, im), one
+ *     row of N/2+1 bins per waveform, row-major, in DEVICE memory.
+ *   - Every "dev" pointer is device memory owned by the caller (e.g. a torch
+ *     tensor); the library never frees it and keeps no reference to it after
+ *     the call returns.  Pointers marked "host" are host memory.
+ *   - Device memory the library needs for itself (tables, the reference
+ *     series store, taps, epilogue slots) is allocated by rfd_plan_create /
+ *     rfd_taps_create and on the first use of a larger epilogue, and freed by
+ *     the matching destroy call.  Calls made with sizes already seen allocate
+ *     nothing.
+ *   - All work is enqueued on the plan's HIP stream.  Calls return once the
+ *     work is enqueued, except where an output is a host pointer (then the
+ *     call synchronises the stream before returning).
+ *   - Return value: RFD_OK (0) or a negative rfd_status.  No exception or
+ *     abort crosses the ABI.  rfd_last_error() gives a thread-local message
+ *     for the last failing call on the calling thread.
+ *   - A plan is not thread-safe; use one plan per host thread / stream.
+ */
+#ifndef RFD_H
+#define RFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rfd_status {
+  RFD_OK = 0,
+  RFD_E_INVALID = -1,     /* an argument is out of range or inconsistent */
+  RFD_E_NOMEM = -2,       /* device allocation failed */
+  RFD_E_DEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+  RFD_E_OVERFLOW = -4,    /* more triggers than `capacity`; *n_out = needed count */
+  RFD_E_STATE = -5,       /* call order violated (e.g. filtering before dechirp) */
+  RFD_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} rfd_status;
+
+/* FIR arithmetic (rfd_filter_bank). */
+typedef enum rfd_precision {
+  RFD_FP32 = 0,    /* FP32 operands, FP32 MFMA accumulation */
+  RFD_BF16X3 = 1,  /* x = hi + lo in bfloat16; hi*hi + hi*lo + lo*hi, FP32 accumulation */
+  RFD_FP16X3 = 2   /* the same split in IEEE half precision */
+} rfd_precision;
+
+/* Tap construction route (rfd_make_taps). */
+typedef enum rfd_taps_method {
+  RFD_TAPS_LS = 0,     /* weighted ridge least squares, Sec. V.A */
+  RFD_TAPS_WINDOW = 1  /* truncated inverse transform of the ratio, Tukey(0.25) taper */
+} rfd_taps_method;
+
+#define RFD_MAX_TAPS 2048
+
+/* One trigger: the peak of one template in one cluster window (32 bytes). */
+typedef struct rfd_trigger {
+  int64_t sample;   /* output sample n of the peak, 0 <= n < N */
+  int32_t tmpl;     /* template index (global over all sub-banks) */
+  int32_t subbank;  /* sub-bank index (0 for findchirp_filter) */
+  float rho;        /* normalised SNR |z| at the peak, as thresholded */
+  float z_re;       /* complex normalised SNR at the peak (FP32 re-evaluation) */
+  float z_im;
+  uint32_t flags;   /* 0; 1 when z_re/z_im were not evaluated (FINDCHIRP beyond 4096 triggers) */
+} rfd_trigger;
+
+typedef struct rfd_plan_info {
+  int64_t n;          /* N */
+  int64_t n_bins;     /* N/2 + 1 */
+  int64_t i_low;      /* first in-band bin */
+  int64_t i_high;     /* last in-band bin (N/2 - 1) */
+  int64_t n_band;     /* i_high - i_low + 1 */
+  double fs, f_low, df;
+  double data_scale;  /* FP64 factor applied to the data before its transform */
+  int32_t max_refs;   /* reference-series slots */
+  int32_t fft_n1, fft_n2;  /* two-pass FFT factorisation N = n1 * n2 */
+} rfd_plan_info;
+
+typedef struct rfd_plan rfd_plan;
+typedef struct rfd_taps rfd_taps;
+
+/*
+ * rfd_plan_create - analysis plan for one PSD and segment length (FP64 host
+ * planning: PSD weights w_i = 4 df / S_n(f_i) of Eq. 1, FP64-accurate
+ * twiddle tables rounded once to FP32, data scale).
+ *   psd      host float64 [n_psd], one-sided PSD on the rfft grid; must be
+ *            finite and > 0 on every in-band bin (other bins are ignored).
+ *   n_psd    must equal seg_len/2 + 1.
+ *   f_low    low-frequency cutoff, 0 < f_low < fs/2.
+ *   fs       sample rate (Hz), > 0.
+ *   seg_len  N, a power of two in [2^10, 2^22].
+ *   max_refs number of reference-series slots (1..4096); each holds the
+ *            normalised series in FP32 and the hi/lo 16-bit planes (24 N bytes).
+ *   stream   hipStream_t (NULL: the null stream).
+ *   out      receives the plan.
+ * Errors: RFD_E_INVALID for any violated range above, RFD_E_NOMEM,
+ * RFD_E_DEVICE.
+ */
+int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, int64_t seg_len,
+                    int32_t max_refs, void* stream, rfd_plan** out);
+int rfd_plan_info_get(const rfd_plan* plan, rfd_plan_info* out);
+int rfd_plan_set_stream(rfd_plan* plan, void* stream);
+int rfd_plan_destroy(rfd_plan* plan);
+
+/*
+ * rfd_dechirp - reference matched filter (Eq. 1 with h = h_ref; the
+ * dechirped series of Eq. 3 and Fig. 2).
+ *   data     dev float64 [N]: the segment's time series.  When non-NULL its
+ *            transform is computed first (once per segment) and every
+ *            reference series of the previous segment becomes stale.  NULL
+ *            reuses the current segment's transform (RFD_E_STATE if none).
+ *   h_ref    dev complex128 [N/2+1]: the reference template.
+ *   ref_id   slot 0 <= ref_id < max_refs that receives
+ *            z_ref[n]/sigma_ref, n = 0..N-1, where
+ *            z_ref[n] = sum_i w_i s_i conj(h_ref,i) exp(+2 pi i i n / N) and
+ *            sigma_ref^2 = sum_i w_i |h_ref,i|^2 (FP64 on the device).
+ *   sigma_ref_out  host double or NULL: receives sigma_ref (synchronises).
+ * Errors: RFD_E_INVALID (NULL h_ref, ref_id out of range, sigma_ref = 0),
+ * RFD_E_STATE (data NULL with no segment), RFD_E_DEVICE.
+ */
+int rfd_dechirp(rfd_plan* plan, const double* data, const double* h_ref, int32_t ref_id,
+                double* sigma_ref_out);
+
+/* Copy slot ref_id's normalised series z_ref/sigma_ref (dev complex64 [N]). */
+int rfd_get_zref(const rfd_plan* plan, int32_t ref_id, float* out);
+
+/*
+ * rfd_taps_create - storage for the ratio taps of a bank of sub-banks
+ * (Sec. IV: each target template belongs to one reference's sub-bank).
+ *   n_subbanks  >= 1.
+ *   offsets     host int64 [n_subbanks+1]: templates of sub-bank b are the
+ *               global indices offsets[b] .. offsets[b+1]-1; offsets[0] = 0,
+ *               non-decreasing.
+ *   ref_id      host int32 [n_subbanks]: reference slot filtered by sub-bank b.
+ *   taps        host int32 [n_subbanks]: tap count T_b, 1..RFD_MAX_TAPS.
+ *   k0          host int32 [n_subbanks]: lag of tap 0 (tap k sits at lag
+ *               k0 + k samples), |k0| < N/2.
+ * Errors: RFD_E_INVALID, RFD_E_NOMEM.
+ */
+int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, const int32_t* ref_id,
+                    const int32_t* taps, const int32_t* k0, rfd_taps** out);
+
+/*
+ * rfd_make_taps - FP64 ratio taps for `count` templates of one sub-bank
+ * (Sec. V.A), their fitted-template norms (Sec. VI.B) and the FIR operands.
+ *   subbank    sub-bank index.
+ *   h_ref      dev complex128 [N/2+1]: the sub-bank's reference template.
+ *   h_tmpl     dev complex128 [count][N/2+1]: templates first..first+count-1
+ *              of the sub-bank (indices relative to the sub-bank).
+ *   method     RFD_TAPS_LS: minimise sum_i u_i |R_i - A_i|^2 + lam |a|^2 with
+ *              R = h/h_ref, u_i = w_i |h_ref,i|^2, A_i = sum_k a_k
+ *              exp(-2 pi i i (k0+k)/N), lam = ridge_eps * sum_i u_i, solved
+ *              through the Hermitian Toeplitz normal equations by Cholesky.
+ *              RFD_TAPS_WINDOW: a_k = tukey_k (1/N) sum_i R_i exp(+2 pi i i
+ *              (k0+k)/N) (ridge_eps ignored).
+ *   ridge_eps  >= 0 (LS); 1e-4 is the documented default (it bounds the
+ *              normalised tap gain ||c||_2, which multiplies rounding noise).
+ * The FIR applies c_k = conj(a_k) sigma_ref / sigma_fit to z_ref/sigma_ref,
+ * sigma_fit^2 = a^H M a, M[l,k] = sum_i u_i exp(2 pi i i (l-k)/N).
+ * Errors: RFD_E_INVALID (ranges, NULL pointers, first+count beyond the
+ * sub-bank), RFD_E_DEVICE.
+ */
+int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double* h_ref,
+                  const double* h_tmpl, int64_t first, int64_t count, int32_t method, double ridge_eps);
+
+/* Read back one template's FP64 taps a (host complex128 [T]), sigma_fit,
+ * T and k0 (synchronises).  Any output pointer may be NULL. */
+int rfd_taps_get(const rfd_taps* taps, int64_t tmpl, double* a_out, double* sigma_fit_out,
+                 int32_t* taps_out, int32_t* k0_out);
+int rfd_taps_destroy(rfd_taps* taps);
+
+/*
+ * rfd_filter_bank - the ratio FIR of Eq. 3 for every template of every
+ * sub-bank, on the current segment's reference series, with the fused
+ * epilogue.  For template j of sub-bank b:
+ *     z_j[n] = sum_k c_j[k] zhat_ref[(n + k0_b + k) mod N],  rho = |z_j|,
+ * computed as a complex GEMM on MFMA; in each window [qW, (q+1)W) the sample
+ * of largest rho^2 (lowest n on ties) is a trigger when rho > threshold.
+ *   precision       rfd_precision.
+ *   threshold       >= 0, on rho (compared as rho^2 > threshold^2).
+ *   cluster_window  W, 1 <= W <= N.
+ *   out             dev rfd_trigger [capacity], sorted by (tmpl, sample).
+ *   capacity        >= 0.
+ *   n_out           host int64: number of triggers (synchronises).  On
+ *                   RFD_E_OVERFLOW it is the required count and the first
+ *                   `capacity` triggers are valid.
+ * Errors: RFD_E_INVALID, RFD_E_STATE (a sub-bank's reference slot was not
+ * dechirped on the current segment, or taps not made), RFD_E_OVERFLOW,
+ * RFD_E_NOMEM, RFD_E_DEVICE.
+ */
+int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                    int64_t cluster_window, rfd_trigger* out, int64_t capacity, int64_t* n_out);
+
+/*
+ * rfd_findchirp_prepare - FINDCHIRP filters F_j = w_i conj(h_j,i) / sigma_j
+ * (times the plan's data-scale compensation), FP64 on the device, stored in
+ * complex64 over the band bins.
+ *   h_tmpl     dev complex128 [count][N/2+1].
+ *   filt_out   dev complex64 [count][n_band] (n_band from rfd_plan_info).
+ *   sigma_out  dev float64 [count] or NULL: sigma_j.
+ */
+int rfd_findchirp_prepare(rfd_plan* plan, const double* h_tmpl, int64_t count, float* filt_out,
+                          double* sigma_out);
+
+/*
+ * findchirp_filter - the standard matched filter per template (Eq. 1: one
+ * pointwise product and one inverse FFT of length N per template) with the
+ * same fused epilogue as rfd_filter_bank.
+ *   data      dev float64 [N] or NULL (reuse the current segment transform).
+ *   filt      dev complex64 [n_templates][n_band] from rfd_findchirp_prepare.
+ *   Remaining arguments as rfd_filter_bank; triggers carry subbank = 0.
+ */
+int findchirp_filter(rfd_plan* plan, const double* data, const float* filt, int64_t n_templates,
+                     float threshold, int64_t cluster_window, rfd_trigger* out, int64_t capacity,
+                     int64_t* n_out);
+
+/*
+ * Stage timing with HIP events on the plan's stream (for profiling; the
+ * paper's Table II reports the same stages on a CPU).  While enabled, every
+ * entry point records an event pair around each of its stages; get returns
+ * the summed milliseconds and the number of recorded intervals since the
+ * previous get (synchronising on the recorded events), then resets them.
+ */
+typedef struct rfd_timing {
+  double data_fft_ms;   /* segment transform */
+  double dechirp_ms;    /* reference filters + reference-series transforms */
+  double fir_ms;        /* ratio-FIR GEMM kernels with the fused epilogue */
+  double compact_ms;    /* slot clearing, trigger compaction, z re-evaluation */
+  double findchirp_ms;  /* FINDCHIRP transforms with the fused epilogue */
+  double taps_ms;       /* tap construction */
+  int64_t n_data_fft, n_dechirp, n_fir, n_compact, n_findchirp, n_taps;
+} rfd_timing;
+int rfd_plan_set_timing(rfd_plan* plan, int32_t enable);
+int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* rfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFD_H */

@@ -1,0 +1,616 @@
+// C ABI of librfd: argument checking, FP64 host planning, device memory,
+// and the order of kernel launches for each entry point (include/rfd.h).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rfd_internal.h"
+
+namespace rfd {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+
+template <typename T>
+static int dalloc(T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(RFD_E_NOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  return RFD_OK;
+}
+template <typename T>
+static void dfree(T*& ptr) {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+}
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static int upload_table(Plan& p, int64_t len, int64_t step, int64_t den, float2** t32, double2** t64) {
+  std::vector<float2> h32(len);
+  std::vector<double2> h64(len);
+  for (int64_t k = 0; k < len; ++k) {
+    long double two_pi = 6.283185307179586476925286766559005768L;
+    long double a = two_pi * (long double)(k * step) / (long double)den;
+    long double cl = cosl(a), sl = sinl(a);
+    h64[k] = make_double2((double)cl, (double)sl);
+    h32[k] = make_float2((float)cl, (float)sl);
+  }
+  int rc = dalloc(t32, len);
+  if (rc) return rc;
+  rc = dalloc(t64, len);
+  if (rc) return rc;
+  RFD_HIP(hipMemcpy(*t32, h32.data(), len * sizeof(float2), hipMemcpyHostToDevice));
+  RFD_HIP(hipMemcpy(*t64, h64.data(), len * sizeof(double2), hipMemcpyHostToDevice));
+  return RFD_OK;
+}
+
+int stage_begin(Plan& p, int stage) {
+  if (!p.timing) return RFD_OK;
+  Plan::Mark m{stage, nullptr, nullptr};
+  RFD_HIP(hipEventCreate(&m.a));
+  RFD_HIP(hipEventCreate(&m.b));
+  RFD_HIP(hipEventRecord(m.a, p.stream));
+  p.marks.push_back(m);
+  return RFD_OK;
+}
+
+int stage_end(Plan& p) {
+  if (!p.timing || p.marks.empty()) return RFD_OK;
+  RFD_HIP(hipEventRecord(p.marks.back().b, p.stream));
+  return RFD_OK;
+}
+
+static void drop_marks(Plan& p) {
+  for (auto& m : p.marks) {
+    if (m.a) (void)hipEventDestroy(m.a);
+    if (m.b) (void)hipEventDestroy(m.b);
+  }
+  p.marks.clear();
+}
+
+static void plan_free(Plan& p) {
+  drop_marks(p);
+  dfree(p.w);
+  dfree(p.tw32c); dfree(p.tw32f); dfree(p.tw64c); dfree(p.tw64f);
+  dfree(p.tw32_n1); dfree(p.tw32_n2); dfree(p.tw64_n1); dfree(p.tw64_n2);
+  dfree(p.stilde64); dfree(p.stilde); dfree(p.work64); dfree(p.fref64); dfree(p.dscratch);
+  dfree(p.zref); dfree(p.zbf_hi); dfree(p.zbf_lo); dfree(p.zh_hi); dfree(p.zh_lo);
+  dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work);
+}
+
+static int ensure_slots(Plan& p, int64_t n_slots) {
+  if ((size_t)n_slots > p.slots_cap) {
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    dfree(p.slots);
+    p.slots_cap = 0;
+    int rc = dalloc(&p.slots, (size_t)n_slots);
+    if (rc) return rc;
+    p.slots_cap = (size_t)n_slots;
+  }
+  size_t nblk = (size_t)compaction_blocks(n_slots) + 1;
+  if (nblk > p.counts_cap) {
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    dfree(p.counts);
+    p.counts_cap = 0;
+    int rc = dalloc(&p.counts, nblk);
+    if (rc) return rc;
+    p.counts_cap = nblk;
+  }
+  return RFD_OK;
+}
+
+static int check_filter_args(const Plan& p, float threshold, int64_t W, const rfd_trigger* out, int64_t capacity,
+                             int64_t* n_out) {
+  if (!(threshold >= 0.f) || !isfinite(threshold)) return fail(RFD_E_INVALID, "threshold must be finite and >= 0");
+  if (W < 1 || W > p.n) return fail(RFD_E_INVALID, "cluster_window must satisfy 1 <= W <= N");
+  if (capacity < 0) return fail(RFD_E_INVALID, "capacity must be >= 0");
+  if (capacity > 0 && !out) return fail(RFD_E_INVALID, "out is NULL with capacity > 0");
+  if (!n_out) return fail(RFD_E_INVALID, "n_out is NULL");
+  return RFD_OK;
+}
+
+static int finish_triggers(Plan& p, int64_t capacity, int64_t* n_out) {
+  long long tot = 0;
+  RFD_HIP(hipMemcpyAsync(&tot, p.total, sizeof(long long), hipMemcpyDeviceToHost, p.stream));
+  RFD_HIP(hipStreamSynchronize(p.stream));
+  *n_out = tot;
+  if (tot > capacity)
+    return fail(RFD_E_OVERFLOW, "trigger capacity " + std::to_string(capacity) + " < " + std::to_string(tot));
+  return RFD_OK;
+}
+
+}  // namespace rfd
+
+using namespace rfd;
+
+extern "C" {
+
+const char* rfd_last_error(void) { return rfd::g_err.c_str(); }
+
+int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, int64_t seg_len, int32_t max_refs,
+                    void* stream, rfd_plan** out) {
+  if (!out) return fail(RFD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!psd) return fail(RFD_E_INVALID, "psd is NULL");
+  if (!is_pow2(seg_len) || seg_len < (1 << 10) || seg_len > (1 << 22))
+    return fail(RFD_E_INVALID, "seg_len must be a power of two in [2^10, 2^22]");
+  if (n_psd != seg_len / 2 + 1) return fail(RFD_E_INVALID, "n_psd must equal seg_len/2 + 1");
+  if (!(fs > 0.0) || !isfinite(fs)) return fail(RFD_E_INVALID, "fs must be finite and > 0");
+  if (!(f_low > 0.0) || !(f_low < fs / 2.0)) return fail(RFD_E_INVALID, "f_low must satisfy 0 < f_low < fs/2");
+  if (max_refs < 1 || max_refs > 4096) return fail(RFD_E_INVALID, "max_refs must be in [1, 4096]");
+  const int64_t n = seg_len, nb = n / 2 + 1;
+  const double df = fs / (double)n;
+  const int64_t i_low = (int64_t)ceil(f_low / df), i_high = n / 2 - 1;
+  if (i_low > i_high) return fail(RFD_E_INVALID, "empty analysis band");
+  double smin = INFINITY;
+  for (int64_t i = i_low; i <= i_high; ++i) {
+    if (!isfinite(psd[i]) || !(psd[i] > 0.0))
+      return fail(RFD_E_INVALID, "psd must be finite and > 0 on every in-band bin (bin " + std::to_string(i) + ")");
+    smin = std::min(smin, psd[i]);
+  }
+  rfd_plan* h = new (std::nothrow) rfd_plan();
+  if (!h) return fail(RFD_E_NOMEM, "host allocation failed");
+  Plan& p = h->p;
+  p.n = n;
+  p.nb = nb;
+  p.i_low = i_low;
+  p.i_high = i_high;
+  p.n_band = i_high - i_low + 1;
+  p.log2n = __builtin_ctzll((unsigned long long)n);
+  p.n1 = 1 << ((p.log2n + 1) / 2);
+  p.n2 = (int)(n / p.n1);
+  p.fs = fs;
+  p.f_low = f_low;
+  p.df = df;
+  // data scale: makes the in-band transform O(1) at the most sensitive bin
+  p.data_scale = sqrt(2.0 * df / smin);
+  p.max_refs = max_refs;
+  p.stream = (hipStream_t)stream;
+  p.ref_gen.assign(max_refs, 0);
+  int rc = RFD_OK;
+  std::vector<double> w(nb, 0.0);
+  for (int64_t i = i_low; i <= i_high; ++i) w[i] = 4.0 * df / psd[i];
+#define TRY(x) do { rc = (x); if (rc) { plan_free(p); delete h; return rc; } } while (0)
+  TRY(dalloc(&p.w, nb));
+  if (hipMemcpy(p.w, w.data(), nb * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    plan_free(p);
+    delete h;
+    return fail(RFD_E_DEVICE, "upload of PSD weights failed");
+  }
+  TRY(upload_table(p, n / kFine, kFine, n, &p.tw32c, &p.tw64c));
+  TRY(upload_table(p, kFine, 1, n, &p.tw32f, &p.tw64f));
+  TRY(upload_table(p, p.n1, 1, p.n1, &p.tw32_n1, &p.tw64_n1));
+  TRY(upload_table(p, p.n2, 1, p.n2, &p.tw32_n2, &p.tw64_n2));
+  TRY(dalloc(&p.stilde64, nb));
+  TRY(dalloc(&p.stilde, nb));
+  TRY(dalloc(&p.work64, n));
+  TRY(dalloc(&p.fref64, nb));
+  TRY(dalloc(&p.dscratch, 64));
+  TRY(dalloc(&p.total, 1));
+  TRY(dalloc(&p.zref, (size_t)max_refs * n));
+  TRY(dalloc(&p.zbf_hi, (size_t)max_refs * n));
+  TRY(dalloc(&p.zbf_lo, (size_t)max_refs * n));
+  TRY(dalloc(&p.zh_hi, (size_t)max_refs * n));
+  TRY(dalloc(&p.zh_lo, (size_t)max_refs * n));
+#undef TRY
+  *out = h;
+  return RFD_OK;
+}
+
+int rfd_plan_info_get(const rfd_plan* plan, rfd_plan_info* out) {
+  if (!plan || !out) return fail(RFD_E_INVALID, "NULL argument");
+  const Plan& p = plan->p;
+  out->n = p.n;
+  out->n_bins = p.nb;
+  out->i_low = p.i_low;
+  out->i_high = p.i_high;
+  out->n_band = p.n_band;
+  out->fs = p.fs;
+  out->f_low = p.f_low;
+  out->df = p.df;
+  out->data_scale = p.data_scale;
+  out->max_refs = p.max_refs;
+  out->fft_n1 = p.n1;
+  out->fft_n2 = p.n2;
+  return RFD_OK;
+}
+
+int rfd_plan_set_stream(rfd_plan* plan, void* stream) {
+  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
+  plan->p.stream = (hipStream_t)stream;
+  return RFD_OK;
+}
+
+int rfd_plan_set_timing(rfd_plan* plan, int32_t enable) {
+  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
+  plan->p.timing = enable != 0;
+  if (!plan->p.timing) {
+    (void)hipStreamSynchronize(plan->p.stream);
+    drop_marks(plan->p);
+  }
+  return RFD_OK;
+}
+
+int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out) {
+  if (!plan || !out) return fail(RFD_E_INVALID, "NULL argument");
+  Plan& p = plan->p;
+  memset(out, 0, sizeof(*out));
+  double* ms[kNumStages] = {&out->data_fft_ms, &out->dechirp_ms, &out->fir_ms, &out->compact_ms,
+                            &out->findchirp_ms, &out->taps_ms};
+  int64_t* cnt[kNumStages] = {&out->n_data_fft, &out->n_dechirp, &out->n_fir, &out->n_compact,
+                              &out->n_findchirp, &out->n_taps};
+  for (auto& m : p.marks) {
+    RFD_HIP(hipEventSynchronize(m.b));
+    float t = 0.f;
+    RFD_HIP(hipEventElapsedTime(&t, m.a, m.b));
+    *ms[m.stage] += t;
+    *cnt[m.stage] += 1;
+  }
+  drop_marks(p);
+  return RFD_OK;
+}
+
+int rfd_plan_destroy(rfd_plan* plan) {
+  if (!plan) return RFD_OK;
+  (void)hipStreamSynchronize(plan->p.stream);
+  plan_free(plan->p);
+  delete plan;
+  return RFD_OK;
+}
+
+int rfd_dechirp(rfd_plan* plan, const double* data, const double* h_ref, int32_t ref_id, double* sigma_ref_out) {
+  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
+  Plan& p = plan->p;
+  if (!h_ref) return fail(RFD_E_INVALID, "h_ref is NULL");
+  if (ref_id < 0 || ref_id >= p.max_refs) return fail(RFD_E_INVALID, "ref_id out of range");
+  if (data) {
+    int rc = stage_begin(p, kStDataFft);
+    if (!rc) rc = launch_data_fft(p, data);
+    if (!rc) rc = stage_end(p);
+    if (rc) return rc;
+    ++p.seg_gen;
+  } else if (p.seg_gen == 0) {
+    return fail(RFD_E_STATE, "no segment: pass data on the first dechirp");
+  }
+  double* s2 = p.dscratch;
+  int rc = stage_begin(p, kStDechirp);
+  if (!rc) rc = launch_dechirp(p, h_ref, ref_id, s2);
+  if (!rc) rc = stage_end(p);
+  if (rc) return rc;
+  p.ref_gen[ref_id] = p.seg_gen;
+  if (sigma_ref_out) {
+    double v = 0;
+    RFD_HIP(hipMemcpyAsync(&v, s2, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    if (!(v > 0.0)) return fail(RFD_E_INVALID, "reference template has zero norm in band");
+    *sigma_ref_out = sqrt(v);
+  }
+  return RFD_OK;
+}
+
+int rfd_get_zref(const rfd_plan* plan, int32_t ref_id, float* out) {
+  if (!plan || !out) return fail(RFD_E_INVALID, "NULL argument");
+  const Plan& p = plan->p;
+  if (ref_id < 0 || ref_id >= p.max_refs) return fail(RFD_E_INVALID, "ref_id out of range");
+  RFD_HIP(hipMemcpyAsync(out, p.zref + (int64_t)ref_id * p.n, p.n * sizeof(float2), hipMemcpyDeviceToDevice,
+                         p.stream));
+  return RFD_OK;
+}
+
+static void taps_free(Taps& t) {
+  for (auto& s : t.sb) {
+    dfree(s.L);
+    dfree(s.U);
+    dfree(s.g);
+  }
+  dfree(t.a64); dfree(t.sigma_fit); dfree(t.c32); dfree(t.pbf); dfree(t.pfh); dfree(t.p32);
+  dfree(t.d_first); dfree(t.d_meta); dfree(t.d_abase); dfree(t.work64); dfree(t.bvec);
+}
+
+int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, const int32_t* ref_id,
+                    const int32_t* taps, const int32_t* k0, rfd_taps** out) {
+  if (!out) return fail(RFD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!plan || !offsets || !ref_id || !taps || !k0) return fail(RFD_E_INVALID, "NULL argument");
+  Plan& p = plan->p;
+  if (n_subbanks < 1) return fail(RFD_E_INVALID, "n_subbanks must be >= 1");
+  if (offsets[0] != 0) return fail(RFD_E_INVALID, "offsets[0] must be 0");
+  for (int b = 0; b < n_subbanks; ++b) {
+    if (offsets[b + 1] < offsets[b]) return fail(RFD_E_INVALID, "offsets must be non-decreasing");
+    if (ref_id[b] < 0 || ref_id[b] >= p.max_refs) return fail(RFD_E_INVALID, "ref_id out of range");
+    if (taps[b] < 1 || taps[b] > RFD_MAX_TAPS) return fail(RFD_E_INVALID, "taps must be in [1, 2048]");
+    if (!(k0[b] > -p.n / 2 && k0[b] < p.n / 2)) return fail(RFD_E_INVALID, "|k0| must be < N/2");
+  }
+  if (offsets[n_subbanks] > ((int64_t)1 << 31) - 1) return fail(RFD_E_INVALID, "too many templates");
+  rfd_taps* h = new (std::nothrow) rfd_taps();
+  if (!h) return fail(RFD_E_NOMEM, "host allocation failed");
+  Taps& t = h->t;
+  t.plan = &p;
+  t.sb.resize(n_subbanks);
+  int64_t abase = 0, p16 = 0, p32 = 0;
+  std::vector<int64_t> firsts(n_subbanks);
+  std::vector<int32_t> meta(4 * n_subbanks);
+  std::vector<int64_t> abases(n_subbanks);
+  int rc = RFD_OK;
+  for (int b = 0; b < n_subbanks; ++b) {
+    SubBankTaps& s = t.sb[b];
+    s.first = offsets[b];
+    s.count = offsets[b + 1] - offsets[b];
+    s.ref_id = ref_id[b];
+    s.T = taps[b];
+    s.Tp = (int)round_up(s.T, 16);
+    s.k0 = k0[b];
+    s.npad = round_up(std::max<int64_t>(s.count, 1), kTmplTile);
+    s.a_base = abase;
+    s.p16_base = p16;
+    s.p32_base = p32;
+    s.made_mask.assign((size_t)s.count, 0);
+    abase += s.count * s.Tp;
+    p16 += (s.npad / 8) * (s.Tp / 16) * 128;
+    p32 += (s.npad / 8) * (s.Tp / 8) * 64;
+    firsts[b] = s.first;
+    abases[b] = s.a_base;
+    meta[4 * b + 0] = s.ref_id;
+    meta[4 * b + 1] = s.T;
+    meta[4 * b + 2] = s.Tp;
+    meta[4 * b + 3] = s.k0;
+  }
+  t.n_templates = offsets[n_subbanks];
+#define TRY(x) do { rc = (x); if (rc) { taps_free(t); delete h; return rc; } } while (0)
+  TRY(dalloc(&t.a64, (size_t)abase));
+  TRY(dalloc(&t.c32, (size_t)abase));
+  TRY(dalloc(&t.sigma_fit, (size_t)std::max<int64_t>(t.n_templates, 1)));
+  TRY(dalloc(&t.pbf, (size_t)p16));
+  TRY(dalloc(&t.pfh, (size_t)p16));
+  TRY(dalloc(&t.p32, (size_t)p32));
+  TRY(dalloc(&t.d_first, (size_t)n_subbanks));
+  TRY(dalloc(&t.d_meta, (size_t)4 * n_subbanks));
+  TRY(dalloc(&t.d_abase, (size_t)n_subbanks));
+  for (auto& s : t.sb) TRY(dalloc(&s.g, (size_t)s.T));
+#undef TRY
+  if (hipMemsetAsync(t.pbf, 0, p16 * sizeof(uint4), p.stream) != hipSuccess ||
+      hipMemsetAsync(t.pfh, 0, p16 * sizeof(uint4), p.stream) != hipSuccess ||
+      hipMemsetAsync(t.p32, 0, p32 * sizeof(float4), p.stream) != hipSuccess ||
+      hipMemcpy(t.d_first, firsts.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.d_meta, meta.data(), 4 * n_subbanks * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.d_abase, abases.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipStreamSynchronize(p.stream) != hipSuccess) {
+    taps_free(t);
+    delete h;
+    return fail(RFD_E_DEVICE, "taps initialisation failed");
+  }
+  *out = h;
+  return RFD_OK;
+}
+
+int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double* h_ref, const double* h_tmpl,
+                  int64_t first, int64_t count, int32_t method, double ridge_eps) {
+  if (!plan || !taps) return fail(RFD_E_INVALID, "NULL plan or taps");
+  Plan& p = plan->p;
+  Taps& t = taps->t;
+  if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
+  if (subbank < 0 || subbank >= (int)t.sb.size()) return fail(RFD_E_INVALID, "subbank out of range");
+  SubBankTaps& s = t.sb[subbank];
+  if (!h_ref) return fail(RFD_E_INVALID, "h_ref is NULL");
+  if (count < 0 || first < 0 || first + count > s.count) return fail(RFD_E_INVALID, "template range outside the sub-bank");
+  if (count > 0 && !h_tmpl) return fail(RFD_E_INVALID, "h_tmpl is NULL");
+  if (method != RFD_TAPS_LS && method != RFD_TAPS_WINDOW) return fail(RFD_E_INVALID, "unknown taps method");
+  if (method == RFD_TAPS_LS && (!(ridge_eps >= 0.0) || !isfinite(ridge_eps)))
+    return fail(RFD_E_INVALID, "ridge_eps must be finite and >= 0");
+  if (count == 0) return RFD_OK;
+  const int T = s.T;
+  // FFT scratch for a chunk of templates (<= 256 MiB)
+  int64_t chunk = std::max<int64_t>(1, ((int64_t)256 << 20) / (p.n * (int64_t)sizeof(double2)));
+  chunk = std::min<int64_t>(chunk, 64);
+  chunk = std::min<int64_t>(chunk, count);
+  size_t need_w = (size_t)std::max<int64_t>(chunk, 1) * p.n;
+  if (t.work64_cap < need_w) {
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    dfree(t.work64);
+    t.work64_cap = 0;
+    int rc = dalloc(&t.work64, need_w);
+    if (rc) return rc;
+    t.work64_cap = need_w;
+  }
+  size_t need_b = (size_t)chunk * T;
+  if (t.bvec_cap < need_b) {
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    dfree(t.bvec);
+    t.bvec_cap = 0;
+    int rc = dalloc(&t.bvec, need_b);
+    if (rc) return rc;
+    t.bvec_cap = need_b;
+  }
+  // reference autocorrelation g (always) and the Cholesky factor (LS)
+  const double eps = method == RFD_TAPS_LS ? ridge_eps : -1.0;
+  if (method == RFD_TAPS_LS && (!s.L || s.eps != ridge_eps)) {
+    if (!s.L) {
+      int rc = dalloc(&s.L, (size_t)T * T);
+      if (rc) return rc;
+      rc = dalloc(&s.U, (size_t)T * T);
+      if (rc) return rc;
+    }
+    int rc = taps_prepare_subbank(p, t, subbank, h_ref, eps);
+    if (rc) return rc;
+  } else {
+    // g is cheap; refresh it so sigma_fit always uses this reference
+    int rc = launch_corr64(p, t, 1, h_ref, nullptr, 1, T, 0, s.g, T);
+    if (rc) return rc;
+  }
+  {
+    int rc = stage_begin(p, kStTaps);
+    if (rc) return rc;
+  }
+  for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+    int64_t cn = std::min(chunk, count - c0);
+    int rc = launch_corr64(p, t, method == RFD_TAPS_LS ? 0 : 2, h_ref, h_tmpl + 2 * c0 * p.nb, cn, T, s.k0, t.bvec,
+                           T);
+    if (rc) return rc;
+    rc = taps_solve_and_pack(p, t, subbank, first + c0, cn, method);
+    if (rc) return rc;
+  }
+  {
+    int rc = stage_end(p);
+    if (rc) return rc;
+  }
+  for (int64_t i = first; i < first + count; ++i) {
+    if (!s.made_mask[i]) {
+      s.made_mask[i] = 1;
+      ++s.made;
+    }
+  }
+  return RFD_OK;
+}
+
+int rfd_taps_get(const rfd_taps* taps, int64_t tmpl, double* a_out, double* sigma_fit_out, int32_t* taps_out,
+                 int32_t* k0_out) {
+  if (!taps) return fail(RFD_E_INVALID, "taps is NULL");
+  const Taps& t = taps->t;
+  if (tmpl < 0 || tmpl >= t.n_templates) return fail(RFD_E_INVALID, "template index out of range");
+  int b = 0;
+  while (b + 1 < (int)t.sb.size() && t.sb[b + 1].first <= tmpl) ++b;
+  const SubBankTaps& s = t.sb[b];
+  hipStream_t st = t.plan->stream;
+  if (a_out)
+    RFD_HIP(hipMemcpyAsync(a_out, t.a64 + s.a_base + (tmpl - s.first) * s.Tp, s.T * sizeof(double2),
+                           hipMemcpyDeviceToHost, st));
+  if (sigma_fit_out)
+    RFD_HIP(hipMemcpyAsync(sigma_fit_out, t.sigma_fit + tmpl, sizeof(double), hipMemcpyDeviceToHost, st));
+  RFD_HIP(hipStreamSynchronize(st));
+  if (taps_out) *taps_out = s.T;
+  if (k0_out) *k0_out = s.k0;
+  return RFD_OK;
+}
+
+int rfd_taps_destroy(rfd_taps* taps) {
+  if (!taps) return RFD_OK;
+  (void)hipStreamSynchronize(taps->t.plan->stream);
+  taps_free(taps->t);
+  delete taps;
+  return RFD_OK;
+}
+
+int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold, int64_t cluster_window,
+                    rfd_trigger* out, int64_t capacity, int64_t* n_out) {
+  if (!plan || !taps) return fail(RFD_E_INVALID, "NULL plan or taps");
+  Plan& p = plan->p;
+  const Taps& t = taps->t;
+  if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
+  if (precision != RFD_FP32 && precision != RFD_BF16X3 && precision != RFD_FP16X3)
+    return fail(RFD_E_INVALID, "unknown precision");
+  int rc = check_filter_args(p, threshold, cluster_window, out, capacity, n_out);
+  if (rc) return rc;
+  for (size_t b = 0; b < t.sb.size(); ++b) {
+    const SubBankTaps& s = t.sb[b];
+    if (s.count == 0) continue;
+    if (p.seg_gen == 0 || p.ref_gen[s.ref_id] != p.seg_gen)
+      return fail(RFD_E_STATE, "sub-bank " + std::to_string(b) + ": reference slot not dechirped on this segment");
+    if (s.made != s.count) return fail(RFD_E_STATE, "sub-bank " + std::to_string(b) + ": taps not made");
+  }
+  const int64_t nwin = (p.n + cluster_window - 1) / cluster_window;
+  const int64_t n_slots = t.n_templates * nwin;
+  rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
+  if (rc) return rc;
+  rc = launch_slots_clear(p, n_slots);
+  if (rc) return rc;
+  rc = stage_begin(p, kStFir);
+  if (rc) return rc;
+  for (size_t b = 0; b < t.sb.size(); ++b) {
+    rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin);
+    if (rc) return rc;
+  }
+  rc = stage_end(p);
+  if (!rc) rc = stage_begin(p, kStCompact);
+  if (rc) return rc;
+  rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);
+  if (rc) return rc;
+  rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
+  if (!rc) rc = stage_end(p);
+  if (rc) return rc;
+  return finish_triggers(p, capacity, n_out);
+}
+
+int rfd_findchirp_prepare(rfd_plan* plan, const double* h_tmpl, int64_t count, float* filt_out, double* sigma_out) {
+  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
+  Plan& p = plan->p;
+  if (count < 0) return fail(RFD_E_INVALID, "count must be >= 0");
+  if (count == 0) return RFD_OK;
+  if (!h_tmpl || !filt_out) return fail(RFD_E_INVALID, "NULL argument");
+  double* sig = sigma_out;
+  double* tmp = nullptr;
+  if (!sig) {
+    int rc = dalloc(&tmp, (size_t)count);
+    if (rc) return rc;
+    sig = tmp;
+  }
+  int rc = launch_findchirp_prepare(p, h_tmpl, count, reinterpret_cast<float2*>(filt_out), sig);
+  if (tmp) {
+    (void)hipStreamSynchronize(p.stream);
+    dfree(tmp);
+  }
+  return rc;
+}
+
+int findchirp_filter(rfd_plan* plan, const double* data, const float* filt, int64_t n_templates, float threshold,
+                     int64_t cluster_window, rfd_trigger* out, int64_t capacity, int64_t* n_out) {
+  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
+  Plan& p = plan->p;
+  int rc = check_filter_args(p, threshold, cluster_window, out, capacity, n_out);
+  if (rc) return rc;
+  if (n_templates < 0 || n_templates > ((int64_t)1 << 31) - 1) return fail(RFD_E_INVALID, "n_templates out of range");
+  if (n_templates > 0 && !filt) return fail(RFD_E_INVALID, "filt is NULL");
+  if (data) {
+    rc = stage_begin(p, kStDataFft);
+    if (!rc) rc = launch_data_fft(p, data);
+    if (!rc) rc = stage_end(p);
+    if (rc) return rc;
+    ++p.seg_gen;
+  } else if (p.seg_gen == 0) {
+    return fail(RFD_E_STATE, "no segment: pass data");
+  }
+  const int64_t nwin = (p.n + cluster_window - 1) / cluster_window;
+  const int64_t n_slots = n_templates * nwin;
+  rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
+  if (rc) return rc;
+  size_t need = (size_t)findchirp_batch_size(p) * p.n;
+  if (p.fc_work_cap < need) {
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    dfree(p.fc_work);
+    p.fc_work_cap = 0;
+    rc = dalloc(&p.fc_work, need);
+    if (rc) return rc;
+    p.fc_work_cap = need;
+  }
+  rc = launch_slots_clear(p, n_slots);
+  if (rc) return rc;
+  if (n_templates > 0) {
+    rc = stage_begin(p, kStFindchirp);
+    if (!rc) rc = launch_findchirp(p, reinterpret_cast<const float2*>(filt), n_templates, cluster_window, nwin);
+    if (!rc) rc = stage_end(p);
+    if (rc) return rc;
+  }
+  rc = stage_begin(p, kStCompact);
+  if (rc) return rc;
+  rc = launch_compact(p, n_slots, nwin, cluster_window, threshold, out, capacity);
+  if (rc) return rc;
+  rc = launch_findchirp_z(p, reinterpret_cast<const float2*>(filt), out, std::min<int64_t>(capacity, 4096));
+  if (!rc) rc = stage_end(p);
+  if (rc) return rc;
+  return finish_triggers(p, capacity, n_out);
+}
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// Two-pass Stockham FFTs with fused loads and stores.
+//
+// N = N1 * N2.  For z[n] = sum_i Q[i] exp(s 2 pi i i n / N) with
+// i = i1 + N1 i2 and n = n2 + N2 n1:
+//   pass A (per column i1): X[i1][n2] = sum_i2 Q[i1 + N1 i2] exp(s 2 pi i i2 n2 / N2),
+//           times exp(s 2 pi i i1 n2 / N), stored at Y[n2 N1 + i1];
+//   pass B (per row n2):    z[n2 + N2 n1] = sum_i1 Y[n2 N1 + i1] exp(s 2 pi i i1 n1 / N1).
+// Each workgroup transforms C adjacent columns (pass A) or rows (pass B) in
+// LDS, so every global access is a run of C contiguous elements.  The first
+// pass fuses the pointwise product of Eq. 1 (data x conj(template) x weight);
+// the second fuses the consumer: spectrum store, reference-series store with
+// its 16-bit hi/lo planes, FINDCHIRP's |z|^2 / window-peak epilogue, or the
+// selection of the T correlation lags used by tap construction.
+#include "dev_common.h"
+#include "rfd_internal.h"
+
+namespace rfd {
+
+constexpr int kNT = 256;
+
+template <typename V> struct Cols;
+template <> struct Cols<float2> { static constexpr int value(int L) { return 8; } };
+template <> struct Cols<double2> { static constexpr int value(int L) { return L >= 2048 ? 2 : 4; } };
+
+template <typename V, int L, int C>
+constexpr size_t lds_bytes() { return (size_t)C * (L + 1) * sizeof(V) + (size_t)L * sizeof(V); }
+
+// ---------------------------------------------------------------- loaders
+struct LoadData64 {        // real FP64 series, scaled, FP64 complex
+  const double* x; double scale;
+  __device__ double2 operator()(int, int64_t i) const { return make_double2(x[i] * scale, 0.0); }
+};
+struct LoadDechirp64 {     // s_i * F_ref,i over the band, FP64 (Eq. 1 integrand)
+  const double2* s; const double2* f; int64_t i_low, i_high;
+  __device__ double2 operator()(int, int64_t i) const {
+    if (i < i_low || i > i_high) return make_double2(0.0, 0.0);
+    return cmul(s[i], f[i]);
+  }
+};
+struct LoadFindchirp {     // s_i * F_j,i with F_j stored over band bins
+  const float2* s; const float2* f; int64_t i_low, i_high, n_band;
+  __device__ float2 operator()(int b, int64_t i) const {
+    if (i < i_low || i > i_high) return make_float2(0.f, 0.f);
+    return cmul(s[i], f[(int64_t)b * n_band + (i - i_low)]);
+  }
+};
+struct LoadCorr64 {        // FP64 correlation integrands for tap construction
+  const double* w; const double2* hr; const double2* ht; int64_t nb, i_low, i_high; int mode;
+  __device__ double2 operator()(int b, int64_t i) const {
+    if (i < i_low || i > i_high) return make_double2(0.0, 0.0);
+    double2 r = hr[i];
+    double wi = w[i];
+    if (mode == 1) return make_double2(wi * (r.x * r.x + r.y * r.y), 0.0);
+    double2 t = ht[(int64_t)b * nb + i];
+    if (mode == 0) return make_double2(wi * (t.x * r.x + t.y * r.y), wi * (t.y * r.x - t.x * r.y));
+    // mode 2: ratio R = t / r where the chi^2 weight w |r|^2 is non-zero
+    double rr = r.x * r.x + r.y * r.y;
+    if (!(wi * rr > 0.0)) return make_double2(0.0, 0.0);
+    return make_double2((t.x * r.x + t.y * r.y) / rr, (t.y * r.x - t.x * r.y) / rr);
+  }
+};
+
+// ---------------------------------------------------------------- storers
+struct StoreSpectrum64 {   // FP64 spectrum and its FP32 copy (FINDCHIRP operand)
+  double2* s64; float2* s32; int64_t half;
+  __device__ void operator()(int, int64_t n, double2 v) const {
+    if (n <= half) {
+      s64[n] = v;
+      s32[n] = make_float2((float)v.x, (float)v.y);
+    }
+  }
+};
+struct StoreRef64 {        // FP64 series -> FP32 series + 16-bit hi/lo planes of it
+  float2* z; uint32_t* bh; uint32_t* bl; uint32_t* hh; uint32_t* hl;
+  __device__ void operator()(int, int64_t n, double2 v) const {
+    z[n] = make_float2((float)v.x, (float)v.y);
+    uint32_t rh, rl, ih, il;
+    split_bf16(v.x, rh, rl);
+    split_bf16(v.y, ih, il);
+    bh[n] = rh | (ih << 16);
+    bl[n] = rl | (il << 16);
+    split_f16(v.x, rh, rl);
+    split_f16(v.y, ih, il);
+    hh[n] = rh | (ih << 16);
+    hl[n] = rl | (il << 16);
+  }
+};
+struct StoreLags {         // keep lags k0 .. k0+T-1 (mod N), scaled
+  double2* out; int64_t stride, n; int k0, T; double scale;
+  __device__ void operator()(int b, int64_t m, double2 v) const {
+    int64_t l = (m - (int64_t)k0) & (n - 1);
+    if (l < T) out[(int64_t)b * stride + l] = make_double2(v.x * scale, v.y * scale);
+  }
+};
+
+// ------------------------------------------------------------------ passes
+template <typename V, int L>
+__device__ void load_twl(V* twl, const V* __restrict__ tab) {
+  for (int k = threadIdx.x; k < L; k += kNT) twl[k] = tab[k];
+}
+
+// pass A: L = N2-point transforms of C columns; writes Y with the inter-pass twiddle
+template <typename V, int L, class LD>
+__global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const V* __restrict__ coarse,
+                                              const V* __restrict__ fine, const V* __restrict__ tabL,
+                                              int n1, int sign) {
+  constexpr int C = Cols<V>::value(L);
+  constexpr int LP = L + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* buf = reinterpret_cast<V*>(smem);
+  V* twl = buf + C * LP;
+  const int b = blockIdx.y;
+  const int c0 = blockIdx.x * C;
+  const int64_t n = (int64_t)n1 * L;
+  load_twl<V, L>(twl, tabL);
+  for (int e = threadIdx.x; e < C * L; e += kNT) {
+    int c = e % C, i2 = e / C;
+    buf[c * LP + i2] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
+  }
+  __syncthreads();
+  lds_fft<V, L, C, kNT>(buf, twl, sign);
+  V* Yb = Y + (int64_t)b * n;
+  for (int e = threadIdx.x; e < C * L; e += kNT) {
+    int c = e % C, n2 = e / C;
+    int i1 = c0 + c;
+    V v = buf[c * LP + n2];
+    uint32_t p = (uint32_t)i1 * (uint32_t)n2;   // < N
+    if (p) v = cmul(v, twiddle_n(coarse, fine, p, sign));
+    Yb[(int64_t)n2 * n1 + i1] = v;
+  }
+}
+
+template <typename V, int L>
+__device__ void pass_b_load(const V* __restrict__ Yb, V* buf, V* twl, const V* __restrict__ tabL, int r0) {
+  constexpr int C = Cols<V>::value(L);
+  constexpr int LP = L + 1;
+  load_twl<V, L>(twl, tabL);
+  for (int e = threadIdx.x; e < C * L; e += kNT) {
+    int c = e / L, i1 = e % L;
+    buf[c * LP + i1] = Yb[(int64_t)(r0 + c) * L + i1];
+  }
+  __syncthreads();
+}
+
+// pass B: L = N1-point transforms of C rows, generic storer
+template <typename V, int L, class ST>
+__global__ __launch_bounds__(kNT) void k_pass_b(const V* __restrict__ Y, ST st, const V* __restrict__ tabL,
+                                              int n2, int sign) {
+  constexpr int C = Cols<V>::value(L);
+  constexpr int LP = L + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* buf = reinterpret_cast<V*>(smem);
+  V* twl = buf + C * LP;
+  const int b = blockIdx.y;
+  const int r0 = blockIdx.x * C;
+  const V* Yb = Y + (int64_t)b * L * n2;
+  pass_b_load<V, L>(Yb, buf, twl, tabL, r0);
+  lds_fft<V, L, C, kNT>(buf, twl, sign);
+  for (int e = threadIdx.x; e < C * L; e += kNT) {
+    int c = e % C, n1 = e / C;
+    st(b, (int64_t)(r0 + c) + (int64_t)n2 * n1, buf[c * LP + n1]);
+  }
+}
+
+// pass B of FINDCHIRP: rho^2 of the normalised series, per-window peak keys.
+// Key = (bits(rho^2) << 32) | (0xFFFFFFFF - (n - qW)): the largest rho^2
+// wins, and on equal rho^2 the lowest sample.  Thread layout: column
+// c = tid % C, a run of L/32 consecutive n1 per thread, so each thread keeps a
+// running maximum and flushes it when the window changes.
+template <int L>
+__global__ __launch_bounds__(kNT) void k_fc_pass_b(const float2* __restrict__ Y, unsigned long long* __restrict__ slots,
+                                                 const float2* __restrict__ tabL, int n2, int64_t tmpl0,
+                                                 int64_t nwin, int64_t W, int aligned) {
+  constexpr int C = Cols<float2>::value(L);
+  constexpr int LP = L + 1;
+  constexpr int RUNS = kNT / C;
+  constexpr int RUN = (L + RUNS - 1) / RUNS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float2* buf = reinterpret_cast<float2*>(smem);
+  float2* twl = buf + C * LP;
+  const int b = blockIdx.y;
+  const int r0 = blockIdx.x * C;
+  pass_b_load<float2, L>(Y + (int64_t)b * L * n2, buf, twl, tabL, r0);
+  lds_fft<float2, L, C, kNT>(buf, twl, +1);
+  const int c = threadIdx.x % C, run = threadIdx.x / C;
+  const int64_t col = r0 + c;
+  unsigned long long* srow = slots + (tmpl0 + b) * nwin;
+  int64_t qcur = -1;
+  unsigned long long kmax = 0;
+  for (int t = 0; t < RUN; ++t) {
+    int n1 = run * RUN + t;
+    if (n1 >= L) break;
+    int64_t n = col + (int64_t)n2 * n1;
+    float2 v = buf[c * LP + n1];
+    float r2 = v.x * v.x + v.y * v.y;
+    int64_t q = n / W;
+    unsigned long long key = ((unsigned long long)__float_as_uint(r2) << 32) |
+                             (unsigned long long)(0xFFFFFFFFu - (uint32_t)(n - q * W));
+    if (q != qcur) {
+      if (qcur >= 0) {
+        if (aligned) {
+#pragma unroll
+          for (int o = 1; o < C; o <<= 1) {
+            unsigned long long other = __shfl_xor(kmax, o);
+            kmax = other > kmax ? other : kmax;
+          }
+          if (c == 0) atomicMax(srow + qcur, kmax);
+        } else {
+          atomicMax(srow + qcur, kmax);
+        }
+      }
+      qcur = q;
+      kmax = key;
+    } else if (key > kmax) {
+      kmax = key;
+    }
+  }
+  if (qcur >= 0) {
+    if (aligned) {
+#pragma unroll
+      for (int o = 1; o < C; o <<= 1) {
+        unsigned long long other = __shfl_xor(kmax, o);
+        kmax = other > kmax ? other : kmax;
+      }
+      if (c == 0) atomicMax(srow + qcur, kmax);
+    } else {
+      atomicMax(srow + qcur, kmax);
+    }
+  }
+}
+
+// -------------------------------------------------------------- dispatch
+template <typename V, class LD>
+static int run_pass_a(Plan& p, LD ld, V* Y, const V* coarse, const V* fine, const V* tab2, int batch, int sign) {
+  dim3 blk(kNT);
+  switch (p.n2) {
+#define CASE_A(LL)                                                                         \
+  case LL: {                                                                               \
+    constexpr int C = Cols<V>::value(LL);                                                  \
+    size_t sh = lds_bytes<V, LL, C>();                                                     \
+    hipLaunchKernelGGL((k_pass_a<V, LL, LD>), dim3(p.n1 / C, batch), blk, sh, p.stream, ld, Y, coarse, \
+                       fine, tab2, p.n1, sign);                                            \
+    break;                                                                                 \
+  }
+    CASE_A(32) CASE_A(64) CASE_A(128) CASE_A(256) CASE_A(512) CASE_A(1024) CASE_A(2048)
+#undef CASE_A
+    default: return fail(RFD_E_UNSUPPORTED, "fft: unsupported N2");
+  }
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+template <typename V, class ST>
+static int run_pass_b(Plan& p, const V* Y, ST st, const V* tab1, int batch, int sign) {
+  dim3 blk(kNT);
+  switch (p.n1) {
+#define CASE_B(LL)                                                                          \
+  case LL: {                                                                                \
+    constexpr int C = Cols<V>::value(LL);                                                   \
+    size_t sh = lds_bytes<V, LL, C>();                                                      \
+    hipLaunchKernelGGL((k_pass_b<V, LL, ST>), dim3(p.n2 / C, batch), blk, sh, p.stream, Y, st, tab1, \
+                       p.n2, sign);                                                         \
+    break;                                                                                  \
+  }
+    CASE_B(32) CASE_B(64) CASE_B(128) CASE_B(256) CASE_B(512) CASE_B(1024) CASE_B(2048)
+#undef CASE_B
+    default: return fail(RFD_E_UNSUPPORTED, "fft: unsupported N1");
+  }
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+static int run_fc_pass_b(Plan& p, const float2* Y, int batch, int64_t tmpl0, int64_t nwin, int64_t W) {
+  int aligned = (W >= p.n2 && W % p.n2 == 0) ? 1 : 0;
+  dim3 blk(kNT);
+  switch (p.n1) {
+#define CASE_F(LL)                                                                          \
+  case LL: {                                                                                \
+    constexpr int C = Cols<float2>::value(LL);                                              \
+    size_t sh = lds_bytes<float2, LL, C>();                                                 \
+    hipLaunchKernelGGL((k_fc_pass_b<LL>), dim3(p.n2 / C, batch), blk, sh, p.stream, Y, p.slots, p.tw32_n1, \
+                       p.n2, tmpl0, nwin, W, aligned);                                      \
+    break;                                                                                  \
+  }
+    CASE_F(32) CASE_F(64) CASE_F(128) CASE_F(256) CASE_F(512) CASE_F(1024) CASE_F(2048)
+#undef CASE_F
+    default: return fail(RFD_E_UNSUPPORTED, "fft: unsupported N1");
+  }
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+// ------------------------------------------------------- small kernels
+// sigma^2 = sum_i w_i |h_i|^2 in FP64 by one workgroup (fixed order).
+__global__ __launch_bounds__(1024) void k_sigma_sq(const double* __restrict__ w, const double2* __restrict__ h,
+                                                  int64_t nb, int64_t stride, double* __restrict__ out) {
+  __shared__ double red[1024];
+  const double2* hb = h + (int64_t)blockIdx.x * stride;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < nb; i += 1024) {
+    double2 v = hb[i];
+    acc += w[i] * (v.x * v.x + v.y * v.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// F[i] = w_i conj(h_i) / (sigma * alpha), FP64 then rounded to FP32.
+__global__ void k_build_filter(const double* __restrict__ w, const double2* __restrict__ h, int64_t nb,
+                               int64_t hstride, const double* __restrict__ sigma_sq, double inv_alpha,
+                               int64_t i_low, int64_t n_band, float2* __restrict__ out, int64_t ostride,
+                               int band_only) {
+  const int b = blockIdx.y;
+  const double s = inv_alpha / sqrt(sigma_sq[b]);
+  int64_t cnt = band_only ? n_band : nb;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = band_only ? k + i_low : k;
+    double2 v = h[(int64_t)b * hstride + i];
+    double f = w[i] * s;
+    out[(int64_t)b * ostride + k] = make_float2((float)(f * v.x), (float)(-f * v.y));
+  }
+}
+
+// F[i] = w_i conj(h_i) / (sigma * alpha) kept in FP64 (reference filter).
+__global__ void k_build_filter64(const double* __restrict__ w, const double2* __restrict__ h, int64_t nb,
+                                 const double* __restrict__ sigma_sq, double inv_alpha, double2* __restrict__ out) {
+  const double s = inv_alpha / sqrt(sigma_sq[0]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 v = h[i];
+    double f = w[i] * s;
+    out[i] = make_double2(f * v.x, -f * v.y);
+  }
+}
+
+__global__ void k_sqrt_to(const double* __restrict__ in, double* __restrict__ out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sqrt(in[i]);
+}
+
+// ------------------------------------------------------------ launchers
+// The segment transform and the reference filters run in FP64: they are
+// cheap (once per segment / per reference) and the ratio FIR amplifies any
+// white rounding noise in the reference series by its out-of-band gain.
+int launch_data_fft(Plan& p, const double* data) {
+  LoadData64 ld{data, p.data_scale / p.fs};
+  int rc = run_pass_a<double2>(p, ld, p.work64, p.tw64c, p.tw64f, p.tw64_n2, 1, -1);
+  if (rc) return rc;
+  StoreSpectrum64 st{p.stilde64, p.stilde, p.n / 2};
+  return run_pass_b<double2>(p, p.work64, st, p.tw64_n1, 1, -1);
+}
+
+int launch_dechirp(Plan& p, const double* h_ref, int ref_id, double* sigma_dev) {
+  hipLaunchKernelGGL(k_sigma_sq, dim3(1), dim3(1024), 0, p.stream, p.w, (const double2*)h_ref, p.nb, p.nb,
+                     sigma_dev);
+  RFD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_build_filter64, dim3(256), dim3(256), 0, p.stream, p.w, (const double2*)h_ref, p.nb,
+                     (const double*)sigma_dev, 1.0 / p.data_scale, p.fref64);
+  RFD_CHECK_LAUNCH();
+  LoadDechirp64 ld{p.stilde64, p.fref64, p.i_low, p.i_high};
+  int rc = run_pass_a<double2>(p, ld, p.work64, p.tw64c, p.tw64f, p.tw64_n2, 1, +1);
+  if (rc) return rc;
+  int64_t o = (int64_t)ref_id * p.n;
+  StoreRef64 st{p.zref + o, p.zbf_hi + o, p.zbf_lo + o, p.zh_hi + o, p.zh_lo + o};
+  return run_pass_b<double2>(p, p.work64, st, p.tw64_n1, 1, +1);
+}
+
+int launch_findchirp_prepare(Plan& p, const double* h, int64_t count, float2* filt, double* sigma) {
+  // sigma^2 into the output buffer (or scratch), then the filters
+  double* s2 = sigma;
+  for (int64_t b0 = 0; b0 < count; b0 += 65535) {
+    int64_t nbat = count - b0 < 65535 ? count - b0 : 65535;
+    hipLaunchKernelGGL(k_sigma_sq, dim3((unsigned)nbat), dim3(1024), 0, p.stream, p.w,
+                       (const double2*)h + b0 * p.nb, p.nb, p.nb, s2 + b0);
+    RFD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_build_filter, dim3(64, (unsigned)nbat), dim3(256), 0, p.stream, p.w,
+                       (const double2*)h + b0 * p.nb, p.nb, p.nb, (const double*)(s2 + b0), 1.0 / p.data_scale,
+                       p.i_low, p.n_band, filt + b0 * p.n_band, p.n_band, 1);
+    RFD_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_sqrt_to, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, p.stream, s2, s2, count);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+int findchirp_batch_size(const Plan& p) {
+  // intermediates of up to ~128 MiB stay resident in the 256 MB MALL
+  int64_t b = ((int64_t)128 << 20) / (p.n * (int64_t)sizeof(float2));
+  if (b < 1) b = 1;
+  if (b > 64) b = 64;
+  return (int)b;
+}
+
+int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin) {
+  int bs = findchirp_batch_size(p);
+  for (int64_t t0 = 0; t0 < n_templates; t0 += bs) {
+    int nb = (int)((n_templates - t0) < bs ? (n_templates - t0) : bs);
+    LoadFindchirp ld{p.stilde, filt + t0 * p.n_band, p.i_low, p.i_high, p.n_band};
+    int rc = run_pass_a<float2>(p, ld, p.fc_work, p.tw32c, p.tw32f, p.tw32_n2, nb, +1);
+    if (rc) return rc;
+    rc = run_fc_pass_b(p, p.fc_work, nb, t0, nwin, W);
+    if (rc) return rc;
+  }
+  return RFD_OK;
+}
+
+int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch, int T,
+                  int k0, double2* out, int64_t out_stride) {
+  size_t need = (size_t)batch * p.n;
+  if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
+  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, p.i_low, p.i_high, mode};
+  int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1);
+  if (rc) return rc;
+  StoreLags st{out, out_stride, p.n, k0, T, mode == 2 ? 1.0 / (double)p.n : 1.0};
+  return run_pass_b<double2>(p, tp.work64, st, p.tw64_n1, (int)batch, +1);
+}
+
+}  // namespace rfd

@@ -1,0 +1,151 @@
+// Internal declarations shared by the HIP translation units of librfd.
+// Method: ratio-filter dechirping, arXiv:2601.18835 (see include/rfd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "rfd.h"
+
+namespace rfd {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+#define RFD_HIP(call)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return ::rfd::fail(RFD_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define RFD_CHECK_LAUNCH() RFD_HIP(hipGetLastError())
+
+constexpr int kFineBits = 10;                 // twiddle factorisation p = (c << 10) | f
+constexpr int kFine = 1 << kFineBits;
+
+// ------------------------------------------------------------- plan state
+struct Plan {
+  int64_t n = 0, nb = 0, i_low = 0, i_high = 0, n_band = 0;
+  int log2n = 0, n1 = 0, n2 = 0;
+  double fs = 0, f_low = 0, df = 0, data_scale = 0;
+  int max_refs = 0;
+  hipStream_t stream = nullptr;
+
+  // FP64 PSD weights w_i = 4 df / S_n(f_i) in band, 0 elsewhere  [nb]
+  double* w = nullptr;
+  // twiddles exp(+2 pi i p / N) = coarse[p >> 10] * fine[p & 1023]
+  float2* tw32c = nullptr;  float2* tw32f = nullptr;
+  double2* tw64c = nullptr; double2* tw64f = nullptr;
+  // exp(+2 pi i k / L) for the two sub-transform lengths
+  float2* tw32_n1 = nullptr; float2* tw32_n2 = nullptr;
+  double2* tw64_n1 = nullptr; double2* tw64_n2 = nullptr;
+
+  double2* stilde64 = nullptr; // current segment transform (scaled, FP64), [nb]
+  float2* stilde = nullptr;   // its FP32 copy (FINDCHIRP operand), [nb]
+  double2* work64 = nullptr;  // one N-point FP64 intermediate
+  double2* fref64 = nullptr;  // reference filter scratch [nb]
+  double* dscratch = nullptr; // small FP64 scratch (sigma etc.)  [64]
+  // reference series store, slot-major [max_refs][n]
+  float2* zref = nullptr;
+  uint32_t* zbf_hi = nullptr; uint32_t* zbf_lo = nullptr;
+  uint32_t* zh_hi = nullptr;  uint32_t* zh_lo = nullptr;
+  int64_t seg_gen = 0;
+  std::vector<int64_t> ref_gen;   // generation each slot was dechirped at (0: never)
+
+  // epilogue and compaction scratch (grown on demand)
+  unsigned long long* slots = nullptr; size_t slots_cap = 0;
+  long long* counts = nullptr; size_t counts_cap = 0;
+  long long* total = nullptr;
+
+  // FINDCHIRP batch intermediates (grown on demand)
+  float2* fc_work = nullptr; size_t fc_work_cap = 0;
+
+  // optional stage timing (hipEvent pairs on `stream`)
+  bool timing = false;
+  struct Mark { int stage; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+};
+
+enum Stage { kStDataFft = 0, kStDechirp, kStFir, kStCompact, kStFindchirp, kStTaps, kNumStages };
+// Record the start / stop of a stage when timing is enabled.
+int stage_begin(Plan& p, int stage);
+int stage_end(Plan& p);
+
+struct SubBankTaps {
+  int64_t first = 0, count = 0;     // global template range
+  int32_t ref_id = 0, T = 0, Tp = 0, k0 = 0;
+  int64_t npad = 0;                 // count rounded up to the FIR template tile
+  int64_t a_base = 0;               // offset (elements) into a64 / c32
+  int64_t p16_base = 0;             // offset (uint4) into packed 16-bit arrays
+  int64_t p32_base = 0;             // offset (float4) into packed fp32 array
+  double2* L = nullptr;             // Cholesky factor, column-major T x T
+  double2* U = nullptr;             // L^H, column-major
+  double2* g = nullptr;             // autocorrelation g[0..T-1]
+  double eps = -1.0;                // ridge of the cached factor
+  int64_t made = 0;                 // templates whose taps exist
+  std::vector<uint8_t> made_mask;
+};
+
+struct Taps {
+  Plan* plan = nullptr;
+  std::vector<SubBankTaps> sb;
+  int64_t n_templates = 0;
+  double2* a64 = nullptr;           // FP64 taps a (Sec. V.A), [sum count*Tp]
+  double* sigma_fit = nullptr;      // [n_templates]
+  float2* c32 = nullptr;            // normalised FIR taps c = conj(a) sigma_ref/sigma_fit
+  uint4* pbf = nullptr;             // packed bf16 hi/lo MFMA A operands
+  uint4* pfh = nullptr;             // packed fp16 hi/lo MFMA A operands
+  float4* p32 = nullptr;            // packed fp32 MFMA A operands
+  // device copy of per-sub-bank metadata for trigger kernels
+  int64_t* d_first = nullptr; int32_t* d_meta = nullptr;  // meta: ref_id, T, Tp, k0 per sub-bank
+  int64_t* d_abase = nullptr;
+  // scratch for tap construction
+  double2* work64 = nullptr; size_t work64_cap = 0;
+  double2* bvec = nullptr; size_t bvec_cap = 0;
+};
+
+// FIR tiling shared by packing and kernels
+constexpr int kTmplPerWave = 8;                 // 16 real MFMA rows
+constexpr int kWavesPerBlock = 4;
+constexpr int kTmplTile = kTmplPerWave * kWavesPerBlock;   // 32 templates per workgroup
+constexpr int kColBlocks = 16;                  // 16-column MFMA blocks per wave
+constexpr int kColsPerTile = 16 * kColBlocks;   // 256 output samples per workgroup
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ----------------------------------------------------- launchers (fft.hip)
+int launch_data_fft(Plan& p, const double* data);
+int launch_dechirp(Plan& p, const double* h_ref, int ref_id, double* sigma_dev);
+int launch_findchirp_prepare(Plan& p, const double* h, int64_t count, float2* filt, double* sigma);
+int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin);
+// FP64 correlation: out[t][l] = sum_i P_t[i] exp(+2 pi i i (k0+l)/N), l < T
+// mode 0: P = w h_t conj(h_r); mode 1: P = w |h_r|^2 (batch 1); mode 2: P = h_t/h_r
+// where w |h_r|^2 > 0, scaled by 1/N.
+int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch,
+                  int T, int k0, double2* out, int64_t out_stride);
+
+// ---------------------------------------------------- launchers (taps.hip)
+int taps_prepare_subbank(Plan& p, Taps& tp, int b, const double* h_ref, double eps);
+int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, int method);
+
+// ----------------------------------------------------- launchers (fir.hip)
+int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin);
+
+// ------------------------------------------------ launchers (triggers.hip)
+int launch_slots_clear(Plan& p, int64_t n_slots);
+int launch_compact(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
+                   rfd_trigger* out, int64_t capacity);
+int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
+                        rfd_trigger* out, int64_t capacity);
+int compaction_blocks(int64_t n_slots);
+int findchirp_batch_size(const Plan& p);
+int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity);
+int launch_findchirp_z(Plan& p, const float2* filt, rfd_trigger* out, int64_t capacity);
+
+}  // namespace rfd
+
+struct rfd_plan { rfd::Plan p; };
+struct rfd_taps { rfd::Taps t; };

@@ -1,0 +1,262 @@
+// FP64 ratio-tap construction on the device (Sec. V.A) and the fitted
+// template norms (Sec. VI.B).
+//
+// Weighted ridge least squares: minimise sum_i u_i |R_i - A_i|^2 + lam |a|^2
+// with u_i = w_i |h_ref,i|^2, R = h/h_ref, A_i = sum_k a_k exp(-2 pi i i
+// (k0+k)/N).  Setting the gradient to zero gives the normal equations
+//     (M + lam I) a = b,  M[l,k] = g[l-k],  g[m] = sum_i u_i exp(+2 pi i i m/N),
+//     b[l] = sum_i w_i h_i conj(h_ref,i) exp(+2 pi i i (k0+l)/N),
+// a Hermitian Toeplitz system shared by the whole sub-bank: g and every b
+// come from FP64 FFTs (fft.hip), M + lam I is factored once per sub-bank by
+// Cholesky, and each template costs two triangular solves.
+// Norm of the fitted template h_fit = h_ref A (Parseval form of Sec. VI.B):
+//     sigma_fit^2 = sum_i w_i |h_ref A|^2 = a^H M a.
+// The FIR applies c = conj(a) sigma_ref / sigma_fit to zhat = z_ref/sigma_ref,
+// so its output is directly the normalised SNR of h_fit.
+#include "dev_common.h"
+#include "rfd_internal.h"
+
+namespace rfd {
+
+__device__ __forceinline__ double2 gval(const double2* g, int m) {
+  return m >= 0 ? g[m] : cconj(g[-m]);
+}
+
+// lower triangle (column-major) of M + lam I, lam = eps * g[0]
+__global__ void k_toeplitz(const double2* __restrict__ g, int T, double eps, double2* __restrict__ A) {
+  const double lam = eps * g[0].x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)T * T;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int col = (int)(e / T), row = (int)(e % T);
+    double2 v = row >= col ? g[row - col] : make_double2(0.0, 0.0);
+    if (row == col) v = make_double2(v.x + lam, 0.0);
+    A[e] = v;
+  }
+}
+
+// In-place right-looking Cholesky of the lower triangle, one workgroup.
+__global__ __launch_bounds__(1024) void k_cholesky(double2* __restrict__ A, int T, int* __restrict__ info) {
+  __shared__ double dsh;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int j = 0; j < T; ++j) {
+    if (threadIdx.x == 0) {
+      double d = A[(int64_t)j * T + j].x;
+      if (!(d > 0.0)) {
+        *info = j + 1;
+        d = 1.0;
+      }
+      d = sqrt(d);
+      A[(int64_t)j * T + j] = make_double2(d, 0.0);
+      dsh = d;
+    }
+    __syncthreads();
+    const double inv = 1.0 / dsh;
+    double2* colj = A + (int64_t)j * T;
+    for (int i = j + 1 + threadIdx.x; i < T; i += 1024) colj[i] = make_double2(colj[i].x * inv, colj[i].y * inv);
+    __syncthreads();
+    for (int k = j + 1 + ty; k < T; k += 16) {
+      const double2 lk = cconj(colj[k]);
+      double2* colk = A + (int64_t)k * T;
+      for (int i = k + tx; i < T; i += 64) colk[i] = csub(colk[i], cmul(colj[i], lk));
+    }
+    __syncthreads();
+  }
+}
+
+// U = L^H (column-major upper triangle)
+__global__ void k_upper(const double2* __restrict__ L, int T, double2* __restrict__ U) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)T * T;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int col = (int)(e / T), row = (int)(e % T);
+    U[e] = row <= col ? cconj(L[(int64_t)row * T + col]) : make_double2(0.0, 0.0);
+  }
+}
+
+// (L L^H) a = b for one template per workgroup (column-oriented sweeps in LDS).
+__global__ __launch_bounds__(256) void k_trsv(const double2* __restrict__ L, const double2* __restrict__ U, int T,
+                                            const double2* __restrict__ b, int64_t bstride,
+                                            double2* __restrict__ a, int64_t astride) {
+  extern __shared__ double2 sh[];
+  double2* x = sh;
+  double2* y = sh + T;
+  const double2* bb = b + (int64_t)blockIdx.x * bstride;
+  for (int i = threadIdx.x; i < T; i += 256) x[i] = bb[i];
+  __syncthreads();
+  for (int j = 0; j < T; ++j) {
+    const double2* col = L + (int64_t)j * T;
+    const double inv = 1.0 / col[j].x;
+    const double2 yj = make_double2(x[j].x * inv, x[j].y * inv);
+    if (threadIdx.x == 0) y[j] = yj;
+    for (int i = j + 1 + threadIdx.x; i < T; i += 256) x[i] = csub(x[i], cmul(col[i], yj));
+    __syncthreads();
+  }
+  for (int j = T - 1; j >= 0; --j) {
+    const double2* col = U + (int64_t)j * T;
+    const double inv = 1.0 / col[j].x;
+    const double2 aj = make_double2(y[j].x * inv, y[j].y * inv);
+    if (threadIdx.x == 0) x[j] = aj;
+    for (int i = threadIdx.x; i < j; i += 256) y[i] = csub(y[i], cmul(col[i], aj));
+    __syncthreads();
+  }
+  double2* ao = a + (int64_t)blockIdx.x * astride;
+  for (int i = threadIdx.x; i < T; i += 256) ao[i] = x[i];
+}
+
+// Windowed variant: a = tukey(0.25) * (truncated inverse transform of R).
+__device__ double tukey(int l, int T) {
+  const double alpha = 0.25;
+  if (T == 1) return 1.0;
+  const double x = (double)l / (double)(T - 1);
+  const double pi = 3.141592653589793238462643;
+  if (x < alpha / 2) return 0.5 * (1.0 + cos(pi * (2.0 * x / alpha - 1.0)));
+  if (x > 1.0 - alpha / 2) return 0.5 * (1.0 + cos(pi * (2.0 * x / alpha - 2.0 / alpha + 1.0)));
+  return 1.0;
+}
+
+__global__ void k_window(const double2* __restrict__ b, int64_t bstride, int T, int64_t count,
+                         double2* __restrict__ a, int64_t astride) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count * T;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t t = e / T;
+    int l = (int)(e % T);
+    double2 v = b[t * bstride + l];
+    double wv = tukey(l, T);
+    a[t * astride + l] = make_double2(v.x * wv, v.y * wv);
+  }
+}
+
+// sigma_fit^2 = a^H M a with M[l,k] = g[l-k]; one workgroup per template.
+__global__ __launch_bounds__(256) void k_sigma_fit(const double2* __restrict__ a, int64_t astride, int T,
+                                                 const double2* __restrict__ g, double* __restrict__ sigma) {
+  extern __shared__ double2 sh[];
+  double2* av = sh;
+  double2* gv = sh + T;
+  __shared__ double red[256];
+  const double2* ab = a + (int64_t)blockIdx.x * astride;
+  for (int i = threadIdx.x; i < T; i += 256) {
+    av[i] = ab[i];
+    gv[i] = g[i];
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int l = threadIdx.x; l < T; l += 256) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int k = 0; k < T; ++k) s = cadd(s, cmul(gval(gv, l - k), av[k]));
+    acc += av[l].x * s.x + av[l].y * s.y;   // Re(conj(a_l) s)
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[blockIdx.x] = sqrt(red[0]);
+}
+
+// Normalised taps c = conj(a) sigma_ref / sigma_fit, and their MFMA A-operand
+// packings.  Row 2t holds (Re c, -Im c) per tap, row 2t+1 holds (Im c, Re c).
+//  16-bit: element e = 2 (k%4) + comp of lane (row + 16 ((k%16)/4)) in K block k/16,
+//          uint4 index ((tb*KB + kb)*2 + plane)*64 + lane.
+//  FP32:   K step kb2 = k/2, lane row + 16 (2 (k%2) + comp), float4 (tb*(Tp/8) + kb2/4)*64 + lane,
+//          component kb2 % 4.
+__global__ void k_pack(const double2* __restrict__ a, int64_t astride, const double* __restrict__ sigma_fit,
+                       const double2* __restrict__ g, int T, int Tp, int64_t t_first, int64_t count,
+                       float2* __restrict__ c32, uint16_t* __restrict__ pbf, uint16_t* __restrict__ pfh,
+                       float* __restrict__ p32) {
+  const double sig_ref = sqrt(g[0].x);
+  const int KB = Tp / 16;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count * Tp;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t tl = e / Tp;            // within this batch
+    int k = (int)(e % Tp);
+    int64_t t = t_first + tl;       // within the sub-bank
+    double2 c = make_double2(0.0, 0.0);
+    if (k < T) {
+      double2 av = a[tl * astride + k];
+      double s = sig_ref / sigma_fit[tl];
+      c = make_double2(av.x * s, -av.y * s);
+    }
+    c32[t * Tp + k] = make_float2((float)c.x, (float)c.y);
+    const int64_t tb = t / 8;
+    const int trow = (int)(t % 8);
+    const double vals[2][2] = {{c.x, -c.y}, {c.y, c.x}};
+    const int kb = k / 16, kk = k % 16, gq = kk / 4, jj = kk % 4;
+    const int kb2 = k / 2, kq = kb2 / 4, sub = kb2 % 4;
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      const int row = 2 * trow + o;
+#pragma unroll
+      for (int comp = 0; comp < 2; ++comp) {
+        const double v = vals[o][comp];
+        const int lane16 = row + 16 * gq;
+        const int64_t u4 = ((tb * KB + kb) * 2) * 64 + lane16;   // plane 0 (hi)
+        const int el = 2 * jj + comp;
+        uint32_t hi, lo;
+        split_bf16(v, hi, lo);
+        pbf[u4 * 8 + el] = (uint16_t)hi;
+        pbf[(u4 + 64) * 8 + el] = (uint16_t)lo;
+        split_f16(v, hi, lo);
+        pfh[u4 * 8 + el] = (uint16_t)hi;
+        pfh[(u4 + 64) * 8 + el] = (uint16_t)lo;
+        const int lane32 = row + 16 * (2 * (k % 2) + comp);
+        p32[((tb * (Tp / 8) + kq) * 64 + lane32) * 4 + sub] = (float)v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+int taps_prepare_subbank(Plan& p, Taps& tp, int b, const double* h_ref, double eps) {
+  SubBankTaps& s = tp.sb[b];
+  const int T = s.T;
+  int rc = launch_corr64(p, tp, 1, h_ref, nullptr, 1, T, 0, s.g, T);
+  if (rc) return rc;
+  if (eps >= 0.0) {
+    int64_t el = (int64_t)T * T;
+    int blocks = (int)((el + 255) / 256 < 4096 ? (el + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_toeplitz, dim3(blocks), dim3(256), 0, p.stream, s.g, T, eps, s.L);
+    RFD_CHECK_LAUNCH();
+    int* info = reinterpret_cast<int*>(p.dscratch + 8);
+    RFD_HIP(hipMemsetAsync(info, 0, sizeof(int), p.stream));
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, p.stream, s.L, T, info);
+    RFD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_upper, dim3(blocks), dim3(256), 0, p.stream, s.L, T, s.U);
+    RFD_CHECK_LAUNCH();
+    int hinfo = 0;
+    RFD_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, p.stream));
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    if (hinfo != 0) return fail(RFD_E_INVALID, "ridge-regularised Gram matrix is not positive definite");
+    s.eps = eps;
+  }
+  return RFD_OK;
+}
+
+int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, int method) {
+  SubBankTaps& s = tp.sb[b];
+  const int T = s.T;
+  double2* abase = tp.a64 + s.a_base + first * s.Tp;
+  if (method == RFD_TAPS_LS) {
+    size_t sh = (size_t)2 * T * sizeof(double2);
+    hipLaunchKernelGGL(k_trsv, dim3((unsigned)count), dim3(256), sh, p.stream, s.L, s.U, T, tp.bvec, (int64_t)T,
+                       abase, (int64_t)s.Tp);
+  } else {
+    int64_t el = count * T;
+    int blocks = (int)((el + 255) / 256 < 4096 ? (el + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_window, dim3(blocks), dim3(256), 0, p.stream, tp.bvec, (int64_t)T, T, count, abase,
+                       (int64_t)s.Tp);
+  }
+  RFD_CHECK_LAUNCH();
+  double* sig = tp.sigma_fit + s.first + first;
+  hipLaunchKernelGGL(k_sigma_fit, dim3((unsigned)count), dim3(256), (size_t)2 * T * sizeof(double2), p.stream,
+                     abase, (int64_t)s.Tp, T, s.g, sig);
+  RFD_CHECK_LAUNCH();
+  int64_t el = count * s.Tp;
+  int blocks = (int)((el + 255) / 256 < 8192 ? (el + 255) / 256 : 8192);
+  hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, p.stream, abase, (int64_t)s.Tp, sig, s.g, T, s.Tp, first,
+                     count, tp.c32 + s.a_base, reinterpret_cast<uint16_t*>(tp.pbf + s.p16_base),
+                     reinterpret_cast<uint16_t*>(tp.pfh + s.p16_base), reinterpret_cast<float*>(tp.p32 + s.p32_base));
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+}  // namespace rfd

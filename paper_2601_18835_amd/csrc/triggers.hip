@@ -1,0 +1,244 @@
+// Trigger accumulation (Table II's last stage): slot clearing, deterministic
+// compaction of the per-(template, window) peak keys by prefix sum, and the
+// FP32 re-evaluation of the complex SNR at each trigger.
+#include "dev_common.h"
+#include "rfd_internal.h"
+
+namespace rfd {
+
+constexpr int kSegThreads = 256;
+constexpr int kSegPer = 16;
+constexpr int kSeg = kSegThreads * kSegPer;   // slots per compaction block
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+__device__ __forceinline__ bool slot_fires(unsigned long long k, float thr2) {
+  return k != 0ull && __uint_as_float((uint32_t)(k >> 32)) > thr2;
+}
+
+__device__ int block_exclusive_scan(int v, int* sh, int& total) {
+  // sh: 256 ints
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kSegThreads; o <<= 1) {
+    int x = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  total = sh[kSegThreads - 1];
+  int r = sh[t] - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_count(const unsigned long long* __restrict__ slots, int64_t n,
+                                                     float thr2, long long* __restrict__ counts) {
+  __shared__ int sh[kSegThreads];
+  int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)threadIdx.x * kSegPer;
+  int c = 0;
+  for (int i = 0; i < kSegPer; ++i)
+    if (base + i < n && slot_fires(slots[base + i], thr2)) ++c;
+  int total;
+  block_exclusive_scan(c, sh, total);
+  if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// single-workgroup exclusive scan of the block counts; total at counts[nblk]
+__global__ __launch_bounds__(1024) void k_scan(long long* __restrict__ counts, int64_t nblk,
+                                             long long* __restrict__ total) {
+  __shared__ long long sh[1024];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nblk; b0 += 1024) {
+    int64_t i = b0 + threadIdx.x;
+    long long v = i < nblk ? counts[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      long long x = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (i < nblk) counts[i] = carry + sh[threadIdx.x] - v;
+    long long add = sh[1023];
+    __syncthreads();
+    if (threadIdx.x == 0) carry += add;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__device__ __forceinline__ int find_subbank(const int64_t* first, int nsb, int64_t t) {
+  int lo = 0, hi = nsb - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_write(const unsigned long long* __restrict__ slots, int64_t n,
+                                                     float thr2, const long long* __restrict__ offs, int64_t nwin,
+                                                     int64_t W, rfd_trigger* __restrict__ out, int64_t capacity,
+                                                     const int64_t* __restrict__ sb_first, int nsb) {
+  __shared__ int sh[kSegThreads];
+  int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)threadIdx.x * kSegPer;
+  int c = 0;
+  for (int i = 0; i < kSegPer; ++i)
+    if (base + i < n && slot_fires(slots[base + i], thr2)) ++c;
+  int total;
+  int pre = block_exclusive_scan(c, sh, total);
+  int64_t pos = offs[blockIdx.x] + pre;
+  for (int i = 0; i < kSegPer; ++i) {
+    int64_t si = base + i;
+    if (si >= n) break;
+    unsigned long long k = slots[si];
+    if (!slot_fires(k, thr2)) continue;
+    if (pos < capacity) {
+      int64_t tmpl = si / nwin, q = si - tmpl * nwin;
+      rfd_trigger t;
+      t.sample = q * W + (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
+      t.tmpl = (int32_t)tmpl;
+      t.subbank = sb_first ? find_subbank(sb_first, nsb, tmpl) : 0;
+      t.rho = sqrtf(__uint_as_float((uint32_t)(k >> 32)));
+      t.z_re = 0.f;
+      t.z_im = 0.f;
+      t.flags = 1u;       // complex SNR not yet evaluated
+      out[pos] = t;
+    }
+    ++pos;
+  }
+}
+
+// z_j[n] = sum_k c_j[k] zhat[(n + k0 + k) mod N]: one wave per trigger.
+__global__ __launch_bounds__(256) void k_fir_z(rfd_trigger* __restrict__ out, const long long* __restrict__ total,
+                                             int64_t capacity, const float2* __restrict__ c32,
+                                             const float2* __restrict__ zref, int64_t n,
+                                             const int64_t* __restrict__ sb_first, const int32_t* __restrict__ meta,
+                                             const int64_t* __restrict__ abase) {
+  int64_t lim = *total < capacity ? *total : capacity;
+  int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= lim) return;
+  const int lane = threadIdx.x & 63;
+  rfd_trigger t = out[i];
+  int b = t.subbank;
+  int ref = meta[4 * b + 0], T = meta[4 * b + 1], Tp = meta[4 * b + 2], k0 = meta[4 * b + 3];
+  const float2* c = c32 + abase[b] + (int64_t)(t.tmpl - sb_first[b]) * Tp;
+  const float2* z = zref + (int64_t)ref * n;
+  float re = 0.f, im = 0.f;
+  for (int k = lane; k < T; k += 64) {
+    float2 v = cmul(c[k], z[(t.sample + k0 + k) & (n - 1)]);
+    re += v.x;
+    im += v.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o);
+    im += __shfl_xor(im, o);
+  }
+  if (lane == 0) {
+    out[i].z_re = re;
+    out[i].z_im = im;
+    out[i].flags = 0u;
+  }
+}
+
+// FINDCHIRP: z_j[n] = sum_band s_i F_j,i exp(+2 pi i i n / N): one block per trigger.
+__global__ __launch_bounds__(256) void k_fc_z(rfd_trigger* __restrict__ out, const long long* __restrict__ total,
+                                            int64_t capacity, const float2* __restrict__ s,
+                                            const float2* __restrict__ filt, int64_t i_low, int64_t n_band,
+                                            int64_t n, const float2* __restrict__ coarse,
+                                            const float2* __restrict__ fine) {
+  __shared__ float red[2][256];
+  int64_t lim = *total < capacity ? *total : capacity;
+  int64_t i = blockIdx.x;
+  if (i >= lim) return;
+  rfd_trigger t = out[i];
+  const float2* f = filt + (int64_t)t.tmpl * n_band;
+  float re = 0.f, im = 0.f;
+  for (int64_t k = threadIdx.x; k < n_band; k += 256) {
+    int64_t bin = k + i_low;
+    uint32_t p = (uint32_t)((bin * t.sample) & (n - 1));
+    float2 v = cmul(cmul(s[bin], f[k]), twiddle_n(coarse, fine, p, +1));
+    re += v.x;
+    im += v.y;
+  }
+  red[0][threadIdx.x] = re;
+  red[1][threadIdx.x] = im;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[i].z_re = red[0][0];
+    out[i].z_im = red[1][0];
+    out[i].flags = 0u;
+  }
+}
+
+// ------------------------------------------------------------ launchers
+int launch_slots_clear(Plan& p, int64_t n_slots) {
+  int64_t blocks = (n_slots + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, p.stream, p.slots, n_slots);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+int launch_compact_impl(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float threshold, rfd_trigger* out,
+                        int64_t capacity, const int64_t* sb_first, int nsb) {
+  int64_t nblk = (n_slots + kSeg - 1) / kSeg;
+  if ((size_t)nblk > p.counts_cap) return fail(RFD_E_INVALID, "compaction scratch too small");
+  float thr2 = threshold * threshold;
+  hipLaunchKernelGGL(k_count, dim3((unsigned)nblk), dim3(kSegThreads), 0, p.stream, p.slots, n_slots, thr2,
+                     p.counts);
+  RFD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p.stream, p.counts, nblk, p.total);
+  RFD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_write, dim3((unsigned)nblk), dim3(kSegThreads), 0, p.stream, p.slots, n_slots, thr2,
+                     p.counts, nwin, W, out, capacity, sb_first, nsb);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+int launch_compact(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float threshold, rfd_trigger* out,
+                   int64_t capacity) {
+  return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, nullptr, 1);
+}
+
+int compaction_blocks(int64_t n_slots) { return (int)((n_slots + kSeg - 1) / kSeg); }
+
+int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
+                        rfd_trigger* out, int64_t capacity) {
+  return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, tp.d_first, (int)tp.sb.size());
+}
+
+int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity) {
+  if (capacity <= 0) return RFD_OK;
+  int64_t blocks = (capacity + 3) / 4;
+  hipLaunchKernelGGL(k_fir_z, dim3((unsigned)blocks), dim3(256), 0, p.stream, out, (const long long*)p.total,
+                     capacity, tp.c32, p.zref, p.n, tp.d_first, tp.d_meta, tp.d_abase);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+int launch_findchirp_z(Plan& p, const float2* filt, rfd_trigger* out, int64_t capacity) {
+  if (capacity <= 0) return RFD_OK;
+  hipLaunchKernelGGL(k_fc_z, dim3((unsigned)capacity), dim3(256), 0, p.stream, out, (const long long*)p.total,
+                     capacity, p.stilde, filt, p.i_low, p.n_band, p.n, p.tw32c, p.tw32f);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+}  // namespace rfd

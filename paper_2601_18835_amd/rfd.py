@@ -1,0 +1,269 @@
+"""Thin ctypes binding of librfd (include/rfd.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; torch supplies device memory
+and the stream.  Functions keep the C names.  Importing this module loads
+librfd.so and raises if it is missing: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+# torch first: it loads its bundled HIP runtime (soname libamdhip64.so.7), and
+# librfd then binds to that same runtime instead of loading a second copy.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_18835_amd.build` "
+                      "(or __graft_entry__.build()); there is no non-HIP fallback")
+_lib = C.CDLL(LIB_PATH)
+
+RFD_OK, RFD_E_INVALID, RFD_E_NOMEM, RFD_E_DEVICE, RFD_E_OVERFLOW, RFD_E_STATE, RFD_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+RFD_FP32, RFD_BF16X3, RFD_FP16X3 = 0, 1, 2
+RFD_TAPS_LS, RFD_TAPS_WINDOW = 0, 1
+RFD_MAX_TAPS = 2048
+PRECISIONS = {"fp32": RFD_FP32, "bf16x3": RFD_BF16X3, "fp16x3": RFD_FP16X3}
+
+TRIGGER_DTYPE = np.dtype([("sample", "<i8"), ("tmpl", "<i4"), ("subbank", "<i4"), ("rho", "<f4"),
+                          ("z_re", "<f4"), ("z_im", "<f4"), ("flags", "<u4")])
+assert TRIGGER_DTYPE.itemsize == 32
+
+
+class rfd_plan_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_bins", C.c_int64), ("i_low", C.c_int64), ("i_high", C.c_int64),
+                ("n_band", C.c_int64), ("fs", C.c_double), ("f_low", C.c_double), ("df", C.c_double),
+                ("data_scale", C.c_double), ("max_refs", C.c_int32), ("fft_n1", C.c_int32), ("fft_n2", C.c_int32)]
+
+
+class rfd_timing(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms", "findchirp_ms",
+                                          "taps_ms")] + \
+               [(k, C.c_int64) for k in ("n_data_fft", "n_dechirp", "n_fir", "n_compact", "n_findchirp", "n_taps")]
+
+
+_P = C.c_void_p
+_i64, _i32, _d, _f = C.c_int64, C.c_int32, C.c_double, C.c_float
+_SIGS = {
+    "rfd_plan_create": [_P, _i64, _d, _d, _i64, _i32, _P, C.POINTER(_P)],
+    "rfd_plan_info_get": [_P, C.POINTER(rfd_plan_info)],
+    "rfd_plan_set_stream": [_P, _P],
+    "rfd_plan_destroy": [_P],
+    "rfd_plan_set_timing": [_P, _i32],
+    "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
+    "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
+    "rfd_get_zref": [_P, _i32, _P],
+    "rfd_taps_create": [_P, _i32, _P, _P, _P, _P, C.POINTER(_P)],
+    "rfd_make_taps": [_P, _P, _i32, _P, _P, _i64, _i64, _i32, _d],
+    "rfd_taps_get": [_P, _i64, _P, C.POINTER(_d), C.POINTER(_i32), C.POINTER(_i32)],
+    "rfd_taps_destroy": [_P],
+    "rfd_filter_bank": [_P, _P, _i32, _f, _i64, _P, _i64, C.POINTER(_i64)],
+    "rfd_findchirp_prepare": [_P, _P, _i64, _P, _P],
+    "findchirp_filter": [_P, _P, _P, _i64, _f, _i64, _P, _i64, C.POINTER(_i64)],
+}
+for _name, _args in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = C.c_int
+_lib.rfd_last_error.argtypes = []
+_lib.rfd_last_error.restype = C.c_char_p
+
+EXPORTED = sorted(list(_SIGS) + ["rfd_last_error"])
+
+
+class RfdError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__(f"{fn} -> {code}: {msg}")
+        self.code = code
+
+
+def rfd_last_error():
+    return _lib.rfd_last_error().decode()
+
+
+def _check(rc, fn):
+    if rc != RFD_OK:
+        raise RfdError(rc, fn, rfd_last_error())
+
+
+def _ptr(t):
+    """Device (or host numpy) pointer of a buffer, or None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream
+
+
+def _dev_check(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+# ------------------------------------------------------------------ plan
+def rfd_plan_create(psd, f_low, fs, seg_len, max_refs=1, stream=None):
+    psd = np.ascontiguousarray(psd, dtype=np.float64)
+    h = _P()
+    _check(_lib.rfd_plan_create(psd.ctypes.data, psd.size, f_low, fs, seg_len, max_refs, _stream(stream),
+                                C.byref(h)), "rfd_plan_create")
+    return h
+
+
+def rfd_plan_info_get(plan):
+    info = rfd_plan_info()
+    _check(_lib.rfd_plan_info_get(plan, C.byref(info)), "rfd_plan_info_get")
+    return {k: getattr(info, k) for k, _ in rfd_plan_info._fields_}
+
+
+def rfd_plan_set_stream(plan, stream=None):
+    _check(_lib.rfd_plan_set_stream(plan, _stream(stream)), "rfd_plan_set_stream")
+
+
+def rfd_plan_set_timing(plan, enable=True):
+    _check(_lib.rfd_plan_set_timing(plan, 1 if enable else 0), "rfd_plan_set_timing")
+
+
+def rfd_plan_get_timing(plan):
+    t = rfd_timing()
+    _check(_lib.rfd_plan_get_timing(plan, C.byref(t)), "rfd_plan_get_timing")
+    return {k: getattr(t, k) for k, _ in rfd_timing._fields_}
+
+
+def rfd_plan_destroy(plan):
+    _check(_lib.rfd_plan_destroy(plan), "rfd_plan_destroy")
+
+
+# --------------------------------------------------------------- dechirp
+def rfd_dechirp(plan, data, h_ref, ref_id=0, want_sigma=True):
+    """data: float64 [N] tensor or None; h_ref: complex128 [N/2+1] tensor."""
+    import torch
+    info = rfd_plan_info_get(plan)
+    if data is not None:
+        _dev_check(data, torch.float64, info["n"], "data")
+    _dev_check(h_ref, torch.complex128, info["n_bins"], "h_ref")
+    sig = C.c_double(0.0)
+    _check(_lib.rfd_dechirp(plan, _ptr(data), _ptr(h_ref), ref_id, C.byref(sig) if want_sigma else None),
+           "rfd_dechirp")
+    return sig.value if want_sigma else None
+
+
+def rfd_get_zref(plan, ref_id, out=None):
+    import torch
+    info = rfd_plan_info_get(plan)
+    if out is None:
+        out = torch.empty(info["n"], dtype=torch.complex64, device="cuda")
+    _dev_check(out, torch.complex64, info["n"], "out")
+    _check(_lib.rfd_get_zref(plan, ref_id, _ptr(out)), "rfd_get_zref")
+    return out
+
+
+# ------------------------------------------------------------------ taps
+def rfd_taps_create(plan, offsets, ref_id, taps, k0):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    nsb = offsets.size - 1
+    ref_id = np.ascontiguousarray(ref_id, dtype=np.int32)
+    taps = np.ascontiguousarray(taps, dtype=np.int32)
+    k0 = np.ascontiguousarray(k0, dtype=np.int32)
+    if not (ref_id.size == taps.size == k0.size == nsb):
+        raise ValueError("offsets must have n_subbanks+1 entries and the others n_subbanks")
+    h = _P()
+    _check(_lib.rfd_taps_create(plan, nsb, offsets.ctypes.data, ref_id.ctypes.data, taps.ctypes.data,
+                                k0.ctypes.data, C.byref(h)), "rfd_taps_create")
+    return h
+
+
+def rfd_make_taps(plan, taps, subbank, h_ref, h_tmpl, first=0, method=RFD_TAPS_LS, ridge_eps=1e-4):
+    """h_ref: complex128 [N/2+1]; h_tmpl: complex128 [count, N/2+1] (templates first.. of the sub-bank)."""
+    import torch
+    info = rfd_plan_info_get(plan)
+    _dev_check(h_ref, torch.complex128, info["n_bins"], "h_ref")
+    if h_tmpl.dim() != 2 or h_tmpl.shape[1] != info["n_bins"]:
+        raise ValueError("h_tmpl must be [count, N/2+1]")
+    _dev_check(h_tmpl, torch.complex128, None, "h_tmpl")
+    _check(_lib.rfd_make_taps(plan, taps, subbank, _ptr(h_ref), _ptr(h_tmpl), first, h_tmpl.shape[0], method,
+                              ridge_eps), "rfd_make_taps")
+
+
+def rfd_taps_get(taps, tmpl, max_taps=RFD_MAX_TAPS):
+    a = np.zeros(max_taps, dtype=np.complex128)
+    sig = C.c_double(0)
+    T = C.c_int32(0)
+    k0 = C.c_int32(0)
+    _check(_lib.rfd_taps_get(taps, tmpl, a.ctypes.data, C.byref(sig), C.byref(T), C.byref(k0)), "rfd_taps_get")
+    return a[:T.value].copy(), sig.value, T.value, k0.value
+
+
+def rfd_taps_destroy(taps):
+    _check(_lib.rfd_taps_destroy(taps), "rfd_taps_destroy")
+
+
+# ---------------------------------------------------------------- filter
+def _trigger_buffer(capacity):
+    import torch
+    return torch.empty(max(capacity, 1) * 32, dtype=torch.uint8, device="cuda")
+
+
+def triggers_to_numpy(buf, n):
+    if n <= 0:
+        return np.zeros(0, dtype=TRIGGER_DTYPE)
+    return buf[: n * 32].cpu().numpy().view(TRIGGER_DTYPE).copy()
+
+
+def rfd_filter_bank(plan, taps, precision, threshold, cluster_window, capacity, out=None, raise_overflow=True):
+    """Returns (trigger buffer, n).  precision: name or rfd_precision value."""
+    prec = PRECISIONS.get(precision, precision)
+    if out is None:
+        out = _trigger_buffer(capacity)
+    n = C.c_int64(0)
+    rc = _lib.rfd_filter_bank(plan, taps, prec, threshold, cluster_window, _ptr(out), capacity, C.byref(n))
+    if rc == RFD_E_OVERFLOW and not raise_overflow:
+        return out, n.value
+    _check(rc, "rfd_filter_bank")
+    return out, n.value
+
+
+def rfd_findchirp_prepare(plan, h_tmpl, filt=None, sigma=None):
+    """FINDCHIRP filters of h_tmpl [count, N/2+1] into filt [count, n_band] (complex64)."""
+    import torch
+    info = rfd_plan_info_get(plan)
+    _dev_check(h_tmpl, torch.complex128, None, "h_tmpl")
+    count = h_tmpl.shape[0]
+    if filt is None:
+        filt = torch.empty((count, info["n_band"]), dtype=torch.complex64, device="cuda")
+    _dev_check(filt, torch.complex64, count * info["n_band"], "filt")
+    if sigma is None:
+        sigma = torch.empty(count, dtype=torch.float64, device="cuda")
+    _dev_check(sigma, torch.float64, count, "sigma")
+    _check(_lib.rfd_findchirp_prepare(plan, _ptr(h_tmpl), count, _ptr(filt), _ptr(sigma)), "rfd_findchirp_prepare")
+    return filt, sigma
+
+
+def findchirp_filter(plan, data, filt, threshold, cluster_window, capacity, out=None, raise_overflow=True):
+    import torch
+    if data is not None:
+        _dev_check(data, torch.float64, None, "data")
+    _dev_check(filt, torch.complex64, None, "filt")
+    if out is None:
+        out = _trigger_buffer(capacity)
+    n = C.c_int64(0)
+    rc = _lib.findchirp_filter(plan, _ptr(data), _ptr(filt), filt.shape[0], threshold, cluster_window, _ptr(out),
+                               capacity, C.byref(n))
+    if rc == RFD_E_OVERFLOW and not raise_overflow:
+        return out, n.value
+    _check(rc, "findchirp_filter")
+    return out, n.value

@@ -1,0 +1,149 @@
+"""Shared case construction for the GPU parity tests.
+
+Inputs come from `synth` only; expected values from `oracle` only.  The GPU
+side is driven through the C ABI (paper_2601_18835_amd.driver / rfd).
+"""
+from dataclasses import dataclass, field
+from typing import Dict, List
+
+import numpy as np
+
+import synth
+from oracle import cluster as ocl
+from oracle import pipeline as orc
+
+
+@dataclass
+class SB:
+    ref: int
+    T: int
+    k0: int
+    H: np.ndarray          # complex128 [count, N/2+1]
+    method: str = "ls"     # "ls" | "window"
+
+
+@dataclass
+class Case:
+    name: str
+    n: int
+    fs: float
+    f_low: float
+    psd: np.ndarray
+    data: np.ndarray
+    refs: Dict[int, np.ndarray]
+    subbanks: List[SB]
+    oracle: dict = field(default_factory=dict)
+
+    @property
+    def n_templates(self):
+        return sum(sb.H.shape[0] for sb in self.subbanks)
+
+    def first(self, b):
+        return sum(sb.H.shape[0] for sb in self.subbanks[:b])
+
+
+def workload_case(name, max_templates=None, subbank_limit=None):
+    w = synth.get_workload(name)
+    bank = synth.make_bank(w, max_templates=max_templates)
+    sbs = bank.subbanks[:subbank_limit] if subbank_limit else bank.subbanks
+    seg = synth.make_segment(w, bank)
+    refs = {}
+    out = []
+    for b, sb in enumerate(sbs):
+        refs[b] = synth.reference_waveform(w, sb)
+        out.append(SB(b, sb.taps, sb.k0, synth.template_batch(w, sb.params)))
+    return Case(name, w.n, w.fs, w.f_low, synth.psd_array(w.n, w.fs), seg.data, refs, out)
+
+
+def ragged_case():
+    """Small segment with three uneven sub-banks: tap counts off the 16-tap
+    K block, template counts off the 8/32-template tiles, positive and
+    negative lag offsets, two references."""
+    n, fs, f_low = 1 << 13, 2048.0, 30.0
+    w = synth.Workload("ragged", 9, n, fs, f_low, 0, 2, 0, "fp32", "nonspin")
+    rng = np.random.default_rng(7)
+    psd = synth.psd_array(n, fs)
+    s = synth.make_noise_spectrum(w, rng)
+    refs = {0: synth.taylorf2(synth.WaveformParams(6.0, 5.0), n, fs, f_low),
+            1: synth.taylorf2(synth.WaveformParams(9.0, 7.5), n, fs, f_low)}
+    specs = [(0, 37, -18, 5, "ls"), (1, 16, 5, 33, "ls"), (0, 100, -60, 1, "ls"), (1, 250, -3, 9, "window"),
+             (0, 2048, -1024, 3, "window")]
+    subbanks = []
+    for ref, T, k0, count, method in specs:
+        params = [synth.WaveformParams(*m) for m in rng.uniform(4.5, 10.0, size=(count, 2))]
+        subbanks.append(SB(ref, T, k0, synth.template_batch(w, params), method))
+    # an injection of the first template of sub-bank 1 at SNR 15
+    h = subbanks[1].H[0]
+    amp = synth.workloads.optimal_snr_amplitude(h, w, 15.0)
+    k = np.arange(n // 2 + 1)
+    n0 = 3001
+    s = s + amp * h * np.exp(-2j * np.pi * ((k * n0) % n) / n)
+    return Case("ragged", n, fs, f_low, psd, synth.spectrum_to_time(s, n, fs), refs, subbanks)
+
+
+def oracle_case(case: Case, with_findchirp=False):
+    """FP64 oracle: reference series, taps, normalised ratio-filter series."""
+    p = orc.prepare(case.psd, case.data, case.fs, case.f_low)
+    refs = {r: orc.dechirp(p, h) for r, h in case.refs.items()}
+    taps, z = [], []
+    fc = []
+    for sb in case.subbanks:
+        from oracle import taps as otaps
+        M = otaps.gram(case.refs[sb.ref], p.w, sb.T)
+        for j in range(sb.H.shape[0]):
+            tt = orc.make_taps(p, sb.H[j], case.refs[sb.ref], sb.T, sb.k0, method=sb.method, M=M)
+            taps.append(tt)
+            z.append(orc.ratio_snr(refs[sb.ref], tt))
+            if with_findchirp:
+                fc.append(orc.findchirp_snr(p, sb.H[j]))
+    case.oracle = dict(p=p, refs=refs, taps=taps, z=np.array(z), fc=np.array(fc) if fc else None)
+    return case.oracle
+
+
+def gpu_search(case: Case):
+    from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec
+    specs = [SubBankSpec(sb.ref, sb.T, sb.k0, sb.H.shape[0]) for sb in case.subbanks]
+    s = RatioFilterSearch(case.psd, case.f_low, case.fs, case.n, specs, max_refs=max(case.refs) + 1)
+    for r, h in case.refs.items():
+        s.set_reference(r, h)
+    from paper_2601_18835_amd import rfd
+    for b, sb in enumerate(case.subbanks):
+        s.make_taps(b, sb.H, method=rfd.RFD_TAPS_LS if sb.method == "ls" else rfd.RFD_TAPS_WINDOW)
+    s.set_segment(case.data)
+    s.dechirp_all()
+    return s
+
+
+def rho_matrix(trig, n_templates, n):
+    rho = np.full((n_templates, n), np.nan)
+    rho[trig["tmpl"], trig["sample"]] = trig["rho"]
+    return rho
+
+
+def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None):
+    """Trigger identity on every unambiguous (template, window).
+
+    Returns (n_compared_windows, n_ambiguous, max |drho| at matched triggers).
+    Raises AssertionError on a mismatch.
+    """
+    templates = range(rho_oracle.shape[0]) if templates is None else templates
+    n_cmp = n_amb = 0
+    dmax = 0.0
+    by_t = {}
+    for t in trig:
+        by_t.setdefault(int(t["tmpl"]), []).append((int(t["sample"]), float(t["rho"])))
+    for j in templates:
+        rho = rho_oracle[j]
+        want = {s // window: (s, r) for s, r in ocl.cluster(rho, threshold, window)}
+        got = {s // window: (s, r) for s, r in by_t.get(j, [])}
+        amb = ocl.window_ambiguity(rho, threshold, window, tau)
+        for q in range(len(amb)):
+            if amb[q]:
+                n_amb += 1
+                continue
+            n_cmp += 1
+            assert (q in want) == (q in got), f"template {j} window {q}: oracle {want.get(q)} gpu {got.get(q)}"
+            if q in want:
+                assert want[q][0] == got[q][0], f"template {j} window {q}: sample {want[q][0]} vs {got[q][0]}"
+                dmax = max(dmax, abs(want[q][1] - got[q][1]))
+    return n_cmp, n_amb, dmax

@@ -1,0 +1,207 @@
+"""GPU parity against the FP64 oracle, through the C ABI.
+
+Tolerances on the normalised SNR rho: 1e-5 for the FP32 FIR (the stated
+single-precision target), 1e-3 for the hi/lo split 16-bit forms (the stated
+mixed-precision target).  Trigger indices must be identical on every
+unambiguous (template, window); ambiguous windows (a tie or the threshold
+within the tolerance) are counted and printed.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import (compare_triggers, gpu_search, oracle_case, ragged_case, rho_matrix, workload_case)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3}
+# unit roundoff of each form's operands: FP32; hi+lo with 8+8 (bf16) or 11+11
+# (fp16) significand bits, the dropped lo*lo term included
+UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22}
+
+
+@pytest.fixture(scope="module")
+def small(rfd):
+    case = workload_case("bns64s")
+    oracle_case(case, with_findchirp=True)
+    s = gpu_search(case)
+    yield case, s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def ragged(rfd):
+    case = ragged_case()
+    oracle_case(case)
+    s = gpu_search(case)
+    yield case, s
+    s.close()
+
+
+def _validation_rho(rfd, s, case, precision):
+    cap = case.n_templates * case.n
+    buf, n = s.filter(precision, 0.0, 1, cap)
+    trig = rfd.triggers_to_numpy(buf, n)
+    return trig, rho_matrix(trig, case.n_templates, case.n)
+
+
+def test_reference_series_matches_oracle(rfd, small):
+    case, s = small
+    o = case.oracle
+    ref = o["refs"][0]
+    z = s.zref(0).cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(z - ref.z / ref.sigma))
+    print(f"\n[bns64s] dechirp: max |dz_ref| = {err:.3e} (normalised units)")
+    assert err <= 1e-5
+    sig = s.dechirp_all(want_sigma=True)[0]
+    assert abs(sig - ref.sigma) <= 1e-12 * ref.sigma
+
+
+def test_fp64_taps_match_oracle(rfd, small):
+    case, s = small
+    worst_a = worst_s = 0.0
+    for j, tt in enumerate(case.oracle["taps"]):
+        a, sig, T, k0 = s.tap(j)
+        assert T == case.subbanks[0].T and k0 == case.subbanks[0].k0
+        worst_a = max(worst_a, np.max(np.abs(a - tt.a)) / np.max(np.abs(tt.a)))
+        worst_s = max(worst_s, abs(sig - tt.sigma_fit) / tt.sigma_fit)
+    print(f"\n[bns64s] taps: max rel |da| = {worst_a:.3e}, max rel dsigma_fit = {worst_s:.3e}")
+    assert worst_a <= 1e-8 and worst_s <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_fir_full_series_parity(rfd, small, precision):
+    case, s = small
+    trig, rho = _validation_rho(rfd, s, case, precision)
+    want = np.abs(case.oracle["z"])
+    assert not np.isnan(rho).any(), "validation mode must report every sample"
+    err = np.max(np.abs(rho - want))
+    print(f"\n[bns64s] FIR {precision}: {case.n_templates}x{case.n} samples, max |drho| = {err:.3e}")
+    assert err <= TOL[precision]
+    # complex SNR at the triggers (FP32 re-evaluation)
+    z = trig["z_re"] + 1j * trig["z_im"]
+    zerr = np.max(np.abs(z - case.oracle["z"][trig["tmpl"], trig["sample"]]))
+    assert zerr <= 1e-5 and (trig["flags"] == 0).all()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_fir_triggers_identical(rfd, small, precision):
+    case, s = small
+    rho_o = np.abs(case.oracle["z"])
+    for threshold, window in [(4.0, 2048), (3.5, 300), (5.0, 131072)]:
+        buf, n = s.filter(precision, threshold, window, 1 << 16)
+        trig = rfd.triggers_to_numpy(buf, n)
+        assert (np.diff(trig["tmpl"].astype(np.int64) * case.n + trig["sample"]) > 0).all(), "sorted by (tmpl, sample)"
+        ncmp, namb, dmax = compare_triggers(trig, rho_o, threshold, window, TOL[precision])
+        print(f"\n[bns64s] {precision} theta={threshold} W={window}: {n} triggers, {ncmp} windows identical, "
+              f"{namb} ambiguous, max |drho| {dmax:.2e}")
+
+
+def test_findchirp_parity(rfd, small):
+    import torch
+    case, s = small
+    from paper_2601_18835_amd import rfd as R
+    H = torch.from_numpy(case.subbanks[0].H).to("cuda")
+    filt, sigma = R.rfd_findchirp_prepare(s.plan, H)
+    data = torch.from_numpy(case.data).to("cuda")
+    cap = case.n_templates * case.n
+    buf, n = R.findchirp_filter(s.plan, data, filt, 0.0, 1, cap)
+    trig = R.triggers_to_numpy(buf, n)
+    rho = rho_matrix(trig, case.n_templates, case.n)
+    want = np.abs(case.oracle["fc"])
+    err = np.max(np.abs(rho - want))
+    print(f"\n[bns64s] FINDCHIRP: max |drho| = {err:.3e}")
+    assert err <= 1e-5
+    buf, n = R.findchirp_filter(s.plan, None, filt, 6.0, 2048, 4096)
+    trig = R.triggers_to_numpy(buf, n)
+    ncmp, namb, dmax = compare_triggers(trig, want, 6.0, 2048, 1e-5)
+    z = trig["z_re"] + 1j * trig["z_im"]
+    assert np.max(np.abs(z - case.oracle["fc"][trig["tmpl"], trig["sample"]]), initial=0) <= 1e-5
+    print(f"[bns64s] FINDCHIRP theta=6: {n} triggers, {ncmp} windows identical, {namb} ambiguous")
+    # the injected template is found at the injected sample (noise moves the peak by at most a few samples)
+    assert n >= 1
+
+
+def tap_gain(case):
+    """||c_j||_1 of the normalised FIR taps c = conj(a) sigma_ref / sigma_fit.
+
+    To first order, operand rounding reaches the output bounded by
+    u * ||c||_1 * max|zhat| per rounded operand (u the unit roundoff of the
+    form), and the FP32 accumulation of 2T real products adds a random walk
+    of about sqrt(2T) u max|z|.  Edge-case taps (very short, very long or
+    windowed, so without the ridge's bound on the gain) get the tolerance
+    max(TOL, 3 u max|zhat| (||c||_1 + sqrt(2T))); the workload tests keep
+    the fixed TOL."""
+    out = []
+    for sb in case.subbanks:
+        sig_r = case.oracle["refs"][sb.ref].sigma
+        for j in range(sb.H.shape[0]):
+            tt = case.oracle["taps"][len(out)]
+            out.append(np.sum(np.abs(tt.a)) * sig_r / tt.sigma_fit)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_ragged_subbanks_parity(rfd, ragged, precision):
+    case, s = ragged
+    trig, rho = _validation_rho(rfd, s, case, precision)
+    want = np.abs(case.oracle["z"])
+    gain = tap_gain(case)
+    zmax = max(np.max(np.abs(r.z)) / r.sigma for r in case.oracle["refs"].values())
+    taps = np.concatenate([[sb.T] * sb.H.shape[0] for sb in case.subbanks])
+    tol = np.maximum(TOL[precision], 3.0 * zmax * (UNIT[precision] * gain + 2.0 ** -24 * np.sqrt(2.0 * taps)))
+    err_t = np.max(np.abs(rho - want), axis=1)
+    print(f"\n[ragged] FIR {precision}: {case.n_templates} templates in {len(case.subbanks)} sub-banks, "
+          f"max |drho| = {err_t.max():.3e}; ||c||_1 {gain.min():.1f}..{gain.max():.1f}; "
+          f"worst err/tol = {np.max(err_t / tol):.2f}")
+    assert (err_t <= tol).all()
+    # sub-bank index of each trigger
+    first = np.cumsum([0] + [sb.H.shape[0] for sb in case.subbanks])
+    assert (trig["subbank"] == np.searchsorted(first, trig["tmpl"], side="right") - 1).all()
+    for threshold, window in [(3.0, 300), (2.5, 8192), (3.0, 17)]:
+        buf, n = s.filter(precision, threshold, window, 1 << 16)
+        t2 = rfd.triggers_to_numpy(buf, n)
+        compare_triggers(t2, want, threshold, window, float(tol.max()))
+
+
+def test_ragged_taps_parity(rfd, ragged):
+    case, s = ragged
+    worst = 0.0
+    for j, tt in enumerate(case.oracle["taps"]):
+        a, sig, T, k0 = s.tap(j)
+        worst = max(worst, np.max(np.abs(a - tt.a)) / np.max(np.abs(tt.a)))
+        assert abs(sig - tt.sigma_fit) <= 1e-9 * tt.sigma_fit
+    print(f"\n[ragged] taps (LS and windowed, T up to 2048): max rel |da| = {worst:.3e}")
+    assert worst <= 1e-8
+
+
+def test_overflow_and_state_errors(rfd, ragged):
+    case, s = ragged
+    buf, n = s.filter("fp32", 0.0, 1, 0, raise_overflow=False)
+    assert n == case.n_templates * case.n
+    with pytest.raises(rfd.RfdError) as e:
+        s.filter("fp32", 0.0, 1, 10)
+    assert e.value.code == rfd.RFD_E_OVERFLOW
+    # first `capacity` triggers are still written and sorted
+    buf, n = s.filter("fp32", 0.0, 1, 100, raise_overflow=False)
+    t = rfd.triggers_to_numpy(buf, 100)
+    assert (t["tmpl"] == 0).all() and (t["sample"] == np.arange(100)).all()
+    for bad in [dict(threshold=-1.0), dict(window=0), dict(window=case.n + 1)]:
+        with pytest.raises(rfd.RfdError) as e:
+            s.filter("fp32", bad.get("threshold", 1.0), bad.get("window", 8), 16)
+        assert e.value.code == rfd.RFD_E_INVALID
+
+
+def test_filter_before_dechirp_is_a_state_error(rfd):
+    case = ragged_case()
+    from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec
+    sb = case.subbanks[0]
+    s = RatioFilterSearch(case.psd, case.f_low, case.fs, case.n, [SubBankSpec(0, sb.T, sb.k0, sb.H.shape[0])])
+    s.set_reference(0, case.refs[0])
+    with pytest.raises(rfd.RfdError) as e:
+        s.filter("fp32", 6.0, 2048, 16)
+    assert e.value.code == rfd.RFD_E_STATE          # taps not made
+    s.make_taps(0, sb.H)
+    with pytest.raises(rfd.RfdError) as e:
+        s.filter("fp32", 6.0, 2048, 16)
+    assert e.value.code == rfd.RFD_E_STATE          # no segment dechirped
+    s.close()

@@ -254,6 +254,13 @@ typedef struct rfd_timing {
 int rfd_plan_set_timing(rfd_plan* plan, int32_t enable);
 int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
 
+/*
+ * FIR tile configuration of the 16-bit forms: MFMA 16-column blocks swept by
+ * each wave (8 or 16; default 8).  Output is identical for every setting;
+ * only speed differs.  RFD_E_INVALID for other values.
+ */
+int rfd_plan_set_fir_tiles(rfd_plan* plan, int32_t col_blocks);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* rfd_last_error(void);
 

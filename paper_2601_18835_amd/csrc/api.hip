@@ -264,6 +264,13 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out) {
   return RFD_OK;
 }
 
+int rfd_plan_set_fir_tiles(rfd_plan* plan, int32_t col_blocks) {
+  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
+  if (col_blocks != 8 && col_blocks != 16) return fail(RFD_E_INVALID, "col_blocks must be 8 or 16");
+  plan->p.fir_nb16 = col_blocks;
+  return RFD_OK;
+}
+
 int rfd_plan_destroy(rfd_plan* plan) {
   if (!plan) return RFD_OK;
   (void)hipStreamSynchronize(plan->p.stream);

@@ -23,6 +23,8 @@
 #include "dev_common.h"
 #include "rfd_internal.h"
 
+#include <algorithm>
+
 namespace rfd {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -41,6 +43,7 @@ struct FirArgs {
   int64_t tmpl0;            // global index of its first template
   int64_t nwin, W;
   int k0, Tp, KB;           // Tp = taps padded to 16, KB = Tp / 16
+  int S;                    // 256-sample tiles swept by one workgroup
 };
 
 __device__ __forceinline__ unsigned long long peak_key(float r2, int64_t n, int64_t W, int64_t& q) {
@@ -60,37 +63,41 @@ __device__ __forceinline__ unsigned long long reduce16(unsigned long long k) {
   return k;
 }
 
-// Epilogue over NB 16x16 accumulator blocks of one wave.
-// acc[nb][i]: rows 4*(lane>>4)+i, column lane&15 of block nb.
+// Window-peak bookkeeping of one wave over the tiles of its workgroup.
+// acc[nb][i]: rows 4*(lane>>4)+i, column lane&15 of 16x16 block nb, i.e.
+// templates 2g (rows 0,1 = Re, Im) and 2g+1 (rows 2,3), g = lane>>4.
+struct PeakState {
+  unsigned long long ka, kb;   // running keys when the whole range is one window
+  bool one_window;
+  int64_t q;                   // that window (uniform)
+  int64_t qW;                  // its first sample
+};
+
+__device__ __forceinline__ unsigned long long offset_key(float r2, uint32_t off) {
+  return ((unsigned long long)__float_as_uint(r2) << 32) | (unsigned long long)(0xFFFFFFFFu - off);
+}
+
 template <int NB>
-__device__ __forceinline__ void fir_epilogue(const f32x4 (&acc)[NB], const FirArgs& a, int64_t m0, int64_t tb) {
+__device__ __forceinline__ void fir_tile_epilogue(const f32x4 (&acc)[NB], const FirArgs& a, int64_t m0, int64_t tb,
+                                                  PeakState& ps) {
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const int64_t ta = tb * 8 + 2 * g;          // templates ta, ta+1 (within the sub-bank)
-  const bool va = ta < a.count, vb = ta + 1 < a.count;
-  unsigned long long* sa = a.slots + (a.tmpl0 + ta) * a.nwin;
-  unsigned long long* sb = sa + a.nwin;
   const int64_t W = a.W;
-  if (m0 / W == (m0 + 16 * NB - 1) / W) {
-    // whole tile inside one window
-    unsigned long long ka = 0, kb = 0;
-    int64_t q = 0;
+  if (ps.one_window) {
+    const uint32_t base = (uint32_t)(m0 - ps.qW) + (uint32_t)n;   // offset within the window
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int64_t s = m0 + 16 * nb + n;
       float r2a = acc[nb][0] * acc[nb][0] + acc[nb][1] * acc[nb][1];
       float r2b = acc[nb][2] * acc[nb][2] + acc[nb][3] * acc[nb][3];
-      ka = umax64(ka, peak_key(r2a, s, W, q));
-      kb = umax64(kb, peak_key(r2b, s, W, q));
-    }
-    ka = reduce16(ka);
-    kb = reduce16(kb);
-    if (n == 0) {
-      if (va) atomicMax(sa + q, ka);
-      if (vb) atomicMax(sb + q, kb);
+      ps.ka = umax64(ps.ka, offset_key(r2a, base + 16u * nb));
+      ps.kb = umax64(ps.kb, offset_key(r2b, base + 16u * nb));
     }
     return;
   }
+  const bool va = ta < a.count, vb = ta + 1 < a.count;
+  unsigned long long* sa = a.slots + (a.tmpl0 + ta) * a.nwin;
+  unsigned long long* sb = sa + a.nwin;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int64_t c0 = m0 + 16 * nb;
@@ -114,6 +121,18 @@ __device__ __forceinline__ void fir_epilogue(const f32x4 (&acc)[NB], const FirAr
   }
 }
 
+__device__ __forceinline__ void fir_final_epilogue(const FirArgs& a, int64_t tb, PeakState& ps) {
+  if (!ps.one_window) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t ta = tb * 8 + 2 * (lane >> 4);
+  unsigned long long ka = reduce16(ps.ka), kb = reduce16(ps.kb);
+  if ((lane & 15) == 0) {
+    unsigned long long* sa = a.slots + (a.tmpl0 + ta) * a.nwin + ps.q;
+    if (ta < a.count) atomicMax(sa, ka);
+    if (ta + 1 < a.count) atomicMax(sa + a.nwin, kb);
+  }
+}
+
 __device__ __forceinline__ uint4 lds4(const uint32_t* p) {
   uint4 v;
   v.x = p[0];
@@ -134,91 +153,135 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
   }
 }
 
-template <bool BF16>
+// Stage the workgroup's window zhat[m_start + k0 + p], p < S*256 + Tp, in LDS.
+template <typename V>
+__device__ __forceinline__ void load_window(V* dst, const V* __restrict__ src, int64_t start, int len, int64_t nm) {
+  for (int p = threadIdx.x; p < len; p += 256) dst[p] = src[(start + p) & nm];
+}
+
+template <bool BF16, int NB>
 __global__ __launch_bounds__(256) void k_fir16(FirArgs a) {
-  constexpr int NB = kColBlocks;
+  constexpr int kColsPerTile = 16 * NB;
   extern __shared__ __align__(16) uint32_t win[];
-  const int Lw = kColsPerTile + a.Tp;
+  const int Lw = a.S * kColsPerTile + a.Tp;
   uint32_t* whi = win;
   uint32_t* wlo = win + Lw;
-  const int64_t m0 = (int64_t)blockIdx.x * kColsPerTile;
+  const int64_t mbase = (int64_t)blockIdx.x * a.S * kColsPerTile;
   const int64_t nm = a.n - 1;
-  for (int p = threadIdx.x; p < Lw; p += 256) {
-    int64_t s = (m0 + a.k0 + p) & nm;
-    whi[p] = a.zhi[s];
-    wlo[p] = a.zlo[s];
-  }
+  load_window(whi, a.zhi, mbase + a.k0, Lw, nm);
+  load_window(wlo, a.zlo, mbase + a.k0, Lw, nm);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t tb = (int64_t)blockIdx.y * kWavesPerBlock + wave;
   if (tb * kTmplPerWave >= a.count) return;
   const int off = (lane & 15) + 4 * (lane >> 4);
-
-  f32x4 acc[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  uint4 rh[NB], rl[NB];
-#pragma unroll
-  for (int s = 0; s < NB - 1; ++s) {
-    rh[s] = lds4(whi + 16 * s + off);
-    rl[s] = lds4(wlo + 16 * s + off);
-  }
   const uint4* A = a.pa16 + tb * (int64_t)a.KB * 128 + lane;
-  for (int kb0 = 0; kb0 < a.KB; kb0 += NB) {
+  PeakState ps;
+  ps.ka = ps.kb = 0;
+  ps.q = mbase / a.W;
+  ps.qW = ps.q * a.W;
+  ps.one_window = ps.q == ((mbase + (int64_t)a.S * kColsPerTile - 1) / a.W);
+
+  const int F = a.KB / NB, R = a.KB % NB;
+  for (int t = 0; t < a.S; ++t) {
+    const uint32_t* th = whi + t * kColsPerTile + off;
+    const uint32_t* tl = wlo + t * kColsPerTile + off;
+    f32x4 acc[NB];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int kb = kb0 + u;
-      if (kb < a.KB) {
-        const int sn = kb + NB - 1;
-        rh[(u + NB - 1) % NB] = lds4(whi + 16 * sn + off);
-        rl[(u + NB - 1) % NB] = lds4(wlo + 16 * sn + off);
-        const uint4 ah = A[(int64_t)kb * 128];
-        const uint4 al = A[(int64_t)kb * 128 + 64];
+    for (int i = 0; i < NB; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint4 rh[NB], rl[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int sl = (u + nb) % NB;
-          acc[nb] = mfma16<BF16>(ah, rh[sl], acc[nb]);
-          acc[nb] = mfma16<BF16>(ah, rl[sl], acc[nb]);
-          acc[nb] = mfma16<BF16>(al, rh[sl], acc[nb]);
-        }
-      }
+    for (int s = 0; s < NB - 1; ++s) {
+      rh[s] = lds4(th + 16 * s);
+      rl[s] = lds4(tl + 16 * s);
     }
+    // tap operands of steps kb (a0) and kb+1 (a1); step kb prefetches kb+2
+    const int k1 = a.KB > 1 ? 1 : 0;
+    uint4 a0h = A[0], a0l = A[64], a1h = A[(int64_t)k1 * 128], a1l = A[(int64_t)k1 * 128 + 64];
+    auto step = [&](const int kb, const int u) __attribute__((always_inline)) {
+      const int sn = kb + NB - 1;
+      rh[(u + NB - 1) % NB] = lds4(th + 16 * sn);
+      rl[(u + NB - 1) % NB] = lds4(tl + 16 * sn);
+      const int kn = kb + 2 < a.KB ? kb + 2 : a.KB - 1;
+      const uint4 nh = A[(int64_t)kn * 128];
+      const uint4 nl = A[(int64_t)kn * 128 + 64];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16<BF16>(a0h, rh[(u + nb) % NB], acc[nb]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16<BF16>(a0h, rl[(u + nb) % NB], acc[nb]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16<BF16>(a0l, rh[(u + nb) % NB], acc[nb]);
+      a0h = a1h;
+      a0l = a1l;
+      a1h = nh;
+      a1l = nl;
+    };
+    // full chunks of NB steps: straight-line code, static ring slots
+    for (int f = 0; f < F; ++f) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) step(f * NB + u, u);
+    }
+    // remaining KB mod NB steps
+#pragma unroll
+    for (int u = 0; u < NB - 1; ++u)
+      if (u < R) step(F * NB + u, u);
+    fir_tile_epilogue<NB>(acc, a, mbase + (int64_t)t * kColsPerTile, tb, ps);
   }
-  fir_epilogue<NB>(acc, a, m0, tb);
+  fir_final_epilogue(a, tb, ps);
 }
 
 // FP32: v_mfma_f32_16x16x4f32, K step = 2 complex taps; B read from LDS.
+template <int NB>
 __global__ __launch_bounds__(256) void k_fir32(FirArgs a) {
-  constexpr int NB = kColBlocks;
+  constexpr int kColsPerTile = 16 * NB;
   extern __shared__ __align__(16) float2 wz[];
-  const int Lw = kColsPerTile + a.Tp;
-  const int64_t m0 = (int64_t)blockIdx.x * kColsPerTile;
-  const int64_t nm = a.n - 1;
-  for (int p = threadIdx.x; p < Lw; p += 256) wz[p] = a.z32[(m0 + a.k0 + p) & nm];
+  const int Lw = a.S * kColsPerTile + a.Tp;
+  const int64_t mbase = (int64_t)blockIdx.x * a.S * kColsPerTile;
+  load_window(wz, a.z32, mbase + a.k0, Lw, a.n - 1);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t tb = (int64_t)blockIdx.y * kWavesPerBlock + wave;
   if (tb * kTmplPerWave >= a.count) return;
-  const float* wf = reinterpret_cast<const float*>(wz) + 2 * (lane & 15) + (lane >> 4);
-  f32x4 acc[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   const float4* A = a.pa32 + tb * (int64_t)(a.Tp / 8) * 64 + lane;
   const int KQ = a.Tp / 8;
-  for (int kq = 0; kq < KQ; ++kq) {
-    const float4 av = A[(int64_t)kq * 64];
-    const float avs[4] = {av.x, av.y, av.z, av.w};
+  PeakState ps;
+  ps.ka = ps.kb = 0;
+  ps.q = mbase / a.W;
+  ps.qW = ps.q * a.W;
+  ps.one_window = ps.q == ((mbase + (int64_t)a.S * kColsPerTile - 1) / a.W);
+  for (int t = 0; t < a.S; ++t) {
+    const float* wf = reinterpret_cast<const float*>(wz + t * kColsPerTile) + 2 * (lane & 15) + (lane >> 4);
+    f32x4 acc[NB];
 #pragma unroll
-    for (int sub = 0; sub < 4; ++sub) {
-      const int kb2 = 4 * kq + sub;
+    for (int i = 0; i < NB; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float4 av = A[0];
+    for (int kq = 0; kq < KQ; ++kq) {
+      const float4 an = A[(int64_t)(kq + 1 < KQ ? kq + 1 : kq) * 64];
+      const float avs[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const float bv = wf[32 * nb + 4 * kb2];
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avs[sub], bv, acc[nb], 0, 0, 0);
+      for (int sub = 0; sub < 4; ++sub) {
+        const int kb2 = 4 * kq + sub;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float bv = wf[32 * nb + 4 * kb2];
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avs[sub], bv, acc[nb], 0, 0, 0);
+        }
       }
+      av = an;
     }
+    fir_tile_epilogue<NB>(acc, a, mbase + (int64_t)t * kColsPerTile, tb, ps);
   }
-  fir_epilogue<NB>(acc, a, m0, tb);
+  fir_final_epilogue(a, tb, ps);
+}
+
+// Tiles per workgroup: one workgroup covers a whole cluster window when W is
+// a multiple of 256 (so each (template, window) peak gets one update), capped
+// at 8 tiles; otherwise 4 tiles.
+static int tiles_per_block(int64_t n, int64_t W, int cols) {
+  const int smax = 2048 / cols;
+  int S = (W % cols == 0) ? (int)std::min<int64_t>(W / cols, smax) : std::max(1, smax / 2);
+  while (S > 1 && (n % ((int64_t)S * cols)) != 0) S >>= 1;
+  return S < 1 ? 1 : S;
 }
 
 int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin) {
@@ -240,16 +303,24 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
   a.k0 = s.k0;
   a.Tp = s.Tp;
   a.KB = s.Tp / 16;
-  dim3 grid((unsigned)(p.n / kColsPerTile), (unsigned)((s.count + kTmplTile - 1) / kTmplTile));
+  // column blocks per wave: FP32 16; 16-bit forms 8 (tile config knob)
+  const int nb = precision == RFD_FP32 ? 16 : p.fir_nb16;
+  const int cols = 16 * nb;
+  a.S = tiles_per_block(p.n, W, cols);
+  dim3 grid((unsigned)(p.n / ((int64_t)a.S * cols)), (unsigned)((s.count + kTmplTile - 1) / kTmplTile));
+  const int Lw = a.S * cols + s.Tp;
   if (precision == RFD_FP32) {
-    size_t sh = (size_t)(kColsPerTile + s.Tp) * sizeof(float2);
-    hipLaunchKernelGGL(k_fir32, grid, dim3(256), sh, p.stream, a);
+    hipLaunchKernelGGL(k_fir32<16>, grid, dim3(256), (size_t)Lw * sizeof(float2), p.stream, a);
   } else {
-    size_t sh = (size_t)2 * (kColsPerTile + s.Tp) * sizeof(uint32_t);
-    if (precision == RFD_BF16X3)
-      hipLaunchKernelGGL(k_fir16<true>, grid, dim3(256), sh, p.stream, a);
-    else
-      hipLaunchKernelGGL(k_fir16<false>, grid, dim3(256), sh, p.stream, a);
+    size_t sh = (size_t)2 * Lw * sizeof(uint32_t);
+    const bool bf = precision == RFD_BF16X3;
+    if (nb == 16) {
+      if (bf) hipLaunchKernelGGL((k_fir16<true, 16>), grid, dim3(256), sh, p.stream, a);
+      else hipLaunchKernelGGL((k_fir16<false, 16>), grid, dim3(256), sh, p.stream, a);
+    } else {
+      if (bf) hipLaunchKernelGGL((k_fir16<true, 8>), grid, dim3(256), sh, p.stream, a);
+      else hipLaunchKernelGGL((k_fir16<false, 8>), grid, dim3(256), sh, p.stream, a);
+    }
   }
   RFD_CHECK_LAUNCH();
   return RFD_OK;

@@ -63,6 +63,9 @@ struct Plan {
   // FINDCHIRP batch intermediates (grown on demand)
   float2* fc_work = nullptr; size_t fc_work_cap = 0;
 
+  // FIR tile configuration of the 16-bit forms: MFMA column blocks per wave (8 or 16)
+  int fir_nb16 = 8;
+
   // optional stage timing (hipEvent pairs on `stream`)
   bool timing = false;
   struct Mark { int stage; hipEvent_t a, b; };
@@ -111,8 +114,6 @@ struct Taps {
 constexpr int kTmplPerWave = 8;                 // 16 real MFMA rows
 constexpr int kWavesPerBlock = 4;
 constexpr int kTmplTile = kTmplPerWave * kWavesPerBlock;   // 32 templates per workgroup
-constexpr int kColBlocks = 16;                  // 16-column MFMA blocks per wave
-constexpr int kColsPerTile = 16 * kColBlocks;   // 256 output samples per workgroup
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

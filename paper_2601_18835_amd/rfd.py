@@ -51,6 +51,7 @@ _SIGS = {
     "rfd_plan_set_stream": [_P, _P],
     "rfd_plan_destroy": [_P],
     "rfd_plan_set_timing": [_P, _i32],
+    "rfd_plan_set_fir_tiles": [_P, _i32],
     "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
     "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
     "rfd_get_zref": [_P, _i32, _P],
@@ -142,6 +143,10 @@ def rfd_plan_get_timing(plan):
     t = rfd_timing()
     _check(_lib.rfd_plan_get_timing(plan, C.byref(t)), "rfd_plan_get_timing")
     return {k: getattr(t, k) for k, _ in rfd_timing._fields_}
+
+
+def rfd_plan_set_fir_tiles(plan, col_blocks):
+    _check(_lib.rfd_plan_set_fir_tiles(plan, col_blocks), "rfd_plan_set_fir_tiles")
 
 
 def rfd_plan_destroy(plan):

@@ -255,11 +255,67 @@ int rfd_plan_set_timing(rfd_plan* plan, int32_t enable);
 int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
 
 /*
- * FIR tile configuration of the 16-bit forms: MFMA 16-column blocks swept by
- * each wave (8 or 16; default 8).  Output is identical for every setting;
- * only speed differs.  RFD_E_INVALID for other values.
+ * FIR launch configuration.  Output is identical for every setting; only
+ * speed differs.  Fields:
+ *   col_blocks  MFMA 16-column blocks per wave for the 16-bit forms: 8 or 16
+ *               (the FP32 form always uses 16).
+ *   mode        0 auto (one persistent launch when there is more than one
+ *               sub-bank), 1 one launch per sub-bank, 2 always persistent:
+ *               a fixed grid pulls (sub-bank, 32-template tile, tile group)
+ *               work items from a counter, heaviest sub-banks first.
+ *   max_tiles   most tiles one workgroup sweeps from one LDS window: 1, 2,
+ *               4, 8 or 16 (fewer when the cluster window is shorter).
+ *   wg_per_cu   persistent grid size in workgroups per CU (0: all that fit).
+ * RFD_E_INVALID for values outside these sets.
  */
-int rfd_plan_set_fir_tiles(rfd_plan* plan, int32_t col_blocks);
+typedef struct rfd_fir_config {
+  int32_t col_blocks;
+  int32_t mode;
+  int32_t max_tiles;
+  int32_t wg_per_cu;
+} rfd_fir_config;
+int rfd_plan_set_fir_config(rfd_plan* plan, const rfd_fir_config* cfg);
+int rfd_plan_get_fir_config(const rfd_plan* plan, rfd_fir_config* cfg);
+
+/*
+ * rfd_autotune_fir - pick the FIR configuration by measurement on the
+ * current segment (the project's own autotuner).  Every candidate of
+ * {col_blocks 8, 16} x {max_tiles 4, 8, 16} x {per-sub-bank launches,
+ * persistent with all / one workgroup per CU} (FP32: col_blocks 16 only) is
+ * run `reps` times on `taps` with HIP events; the fastest becomes the plan's
+ * configuration.  Requires the same state as rfd_filter_bank (slots and
+ * triggers of the tuning runs are discarded).
+ *   out  host: best configuration, its FIR time (ms, minimum over reps), the
+ *        time of the configuration in force before the call, candidates run.
+ */
+typedef struct rfd_tune_result {
+  rfd_fir_config best;
+  double best_ms;
+  double before_ms;
+  int32_t n_candidates;
+} rfd_tune_result;
+int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, int64_t cluster_window, int32_t reps,
+                     rfd_tune_result* out);
+
+/*
+ * Segment graph: the whole per-segment pass (segment transform, the
+ * dechirp of every listed reference, slot clearing, FIR with epilogue,
+ * trigger compaction, complex-SNR re-evaluation) captured once into a HIP
+ * graph and replayed per segment.  The graph reads `data` (dev float64 [N])
+ * and the reference templates at the addresses given here: refill those
+ * buffers between replays.  Captured on a private stream; replayed on the
+ * plan's stream.  Arguments as rfd_dechirp / rfd_filter_bank; h_refs is a
+ * host array of n_refs device pointers (complex128 [N/2+1]) for the slots
+ * ref_ids.  Changing the plan's FIR configuration needs a new graph.
+ * rfd_segment_graph_launch replays it; with n_out non-NULL it synchronises
+ * and returns the trigger count (RFD_E_OVERFLOW as rfd_filter_bank).
+ */
+typedef struct rfd_graph rfd_graph;
+int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                             int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                             const double* const* h_refs, rfd_trigger* out, int64_t capacity, rfd_graph** graph);
+int rfd_segment_graph_launch(rfd_graph* graph, int64_t* n_out);
+int rfd_graph_destroy(rfd_graph* graph);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* rfd_last_error(void);

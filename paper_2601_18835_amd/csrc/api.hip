@@ -89,7 +89,7 @@ static void plan_free(Plan& p) {
   dfree(p.tw32_n1); dfree(p.tw32_n2); dfree(p.tw64_n1); dfree(p.tw64_n2);
   dfree(p.stilde64); dfree(p.stilde); dfree(p.work64); dfree(p.fref64); dfree(p.dscratch);
   dfree(p.zref); dfree(p.zbf_hi); dfree(p.zbf_lo); dfree(p.zh_hi); dfree(p.zh_lo);
-  dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work);
+  dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work); dfree(p.counter);
 }
 
 static int ensure_slots(Plan& p, int64_t n_slots) {
@@ -130,6 +130,31 @@ static int finish_triggers(Plan& p, int64_t capacity, int64_t* n_out) {
   *n_out = tot;
   if (tot > capacity)
     return fail(RFD_E_OVERFLOW, "trigger capacity " + std::to_string(capacity) + " < " + std::to_string(tot));
+  return RFD_OK;
+}
+
+static bool use_persistent(const Plan& p, const Taps& t) {
+  return p.fir_mode == 2 || (p.fir_mode == 0 && t.sb.size() > 1);
+}
+
+// FIR kernels of every sub-bank (one persistent launch or one per sub-bank).
+static int enqueue_fir(Plan& p, Taps& t, int precision, int64_t W, int64_t nwin) {
+  if (use_persistent(p, t)) return launch_fir_persistent(p, t, precision, W, nwin);
+  for (size_t b = 0; b < t.sb.size(); ++b) {
+    int rc = launch_fir(p, t, (int)b, precision, W, nwin);
+    if (rc) return rc;
+  }
+  return RFD_OK;
+}
+
+static int check_bank_state(const Plan& p, const Taps& t) {
+  for (size_t b = 0; b < t.sb.size(); ++b) {
+    const SubBankTaps& s = t.sb[b];
+    if (s.count == 0) continue;
+    if (p.seg_gen == 0 || p.ref_gen[s.ref_id] != p.seg_gen)
+      return fail(RFD_E_STATE, "sub-bank " + std::to_string(b) + ": reference slot not dechirped on this segment");
+    if (s.made != s.count) return fail(RFD_E_STATE, "sub-bank " + std::to_string(b) + ": taps not made");
+  }
   return RFD_OK;
 }
 
@@ -200,6 +225,14 @@ int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, i
   TRY(dalloc(&p.work64, n));
   TRY(dalloc(&p.fref64, nb));
   TRY(dalloc(&p.dscratch, 64));
+  TRY(dalloc(&p.counter, 1));
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      p.n_cu = ncu;
+    if (p.n_cu < 1) p.n_cu = 1;
+  }
   TRY(dalloc(&p.total, 1));
   TRY(dalloc(&p.zref, (size_t)max_refs * n));
   TRY(dalloc(&p.zbf_hi, (size_t)max_refs * n));
@@ -264,10 +297,102 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out) {
   return RFD_OK;
 }
 
-int rfd_plan_set_fir_tiles(rfd_plan* plan, int32_t col_blocks) {
-  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
-  if (col_blocks != 8 && col_blocks != 16) return fail(RFD_E_INVALID, "col_blocks must be 8 or 16");
-  plan->p.fir_nb16 = col_blocks;
+int rfd_plan_set_fir_config(rfd_plan* plan, const rfd_fir_config* cfg) {
+  if (!plan || !cfg) return fail(RFD_E_INVALID, "NULL argument");
+  if (cfg->col_blocks != 8 && cfg->col_blocks != 16) return fail(RFD_E_INVALID, "col_blocks must be 8 or 16");
+  if (cfg->mode < 0 || cfg->mode > 2) return fail(RFD_E_INVALID, "mode must be 0, 1 or 2");
+  const int mt = cfg->max_tiles;
+  if (!(mt == 1 || mt == 2 || mt == 4 || mt == 8 || mt == 16)) return fail(RFD_E_INVALID, "max_tiles must be 1..16, a power of two");
+  if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 32) return fail(RFD_E_INVALID, "wg_per_cu must be in [0, 32]");
+  Plan& p = plan->p;
+  p.fir_nb16 = cfg->col_blocks;
+  p.fir_mode = cfg->mode;
+  p.fir_smax = mt;
+  p.fir_wg_per_cu = cfg->wg_per_cu;
+  return RFD_OK;
+}
+
+int rfd_plan_get_fir_config(const rfd_plan* plan, rfd_fir_config* cfg) {
+  if (!plan || !cfg) return fail(RFD_E_INVALID, "NULL argument");
+  cfg->col_blocks = plan->p.fir_nb16;
+  cfg->mode = plan->p.fir_mode;
+  cfg->max_tiles = plan->p.fir_smax;
+  cfg->wg_per_cu = plan->p.fir_wg_per_cu;
+  return RFD_OK;
+}
+
+int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, int64_t cluster_window, int32_t reps,
+                     rfd_tune_result* out) {
+  if (!plan || !taps || !out) return fail(RFD_E_INVALID, "NULL argument");
+  Plan& p = plan->p;
+  Taps& t = const_cast<Taps&>(taps->t);
+  if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
+  if (precision != RFD_FP32 && precision != RFD_BF16X3 && precision != RFD_FP16X3)
+    return fail(RFD_E_INVALID, "unknown precision");
+  if (cluster_window < 1 || cluster_window > p.n) return fail(RFD_E_INVALID, "cluster_window must satisfy 1 <= W <= N");
+  if (reps < 1 || reps > 100) return fail(RFD_E_INVALID, "reps must be in [1, 100]");
+  int rc = check_bank_state(p, t);
+  if (rc) return rc;
+  const int64_t nwin = (p.n + cluster_window - 1) / cluster_window;
+  rc = ensure_slots(p, std::max<int64_t>(t.n_templates * nwin, 1));
+  if (rc) return rc;
+  const bool saved_timing = p.timing;
+  p.timing = false;
+  rfd_fir_config before;
+  rfd_plan_get_fir_config(plan, &before);
+  auto measure = [&](const rfd_fir_config& c, double& ms) -> int {
+    int r = rfd_plan_set_fir_config(plan, &c);
+    if (r) return r;
+    if (use_persistent(p, t)) {
+      r = prepare_fir_items(p, t, precision, cluster_window);
+      if (r) return r;
+    }
+    hipEvent_t a, b;
+    RFD_HIP(hipEventCreate(&a));
+    RFD_HIP(hipEventCreate(&b));
+    ms = 1e30;
+    for (int i = 0; i < reps + 1; ++i) {      // first run warms caches and code
+      RFD_HIP(hipEventRecord(a, p.stream));
+      r = enqueue_fir(p, t, precision, cluster_window, nwin);
+      if (r) break;
+      RFD_HIP(hipEventRecord(b, p.stream));
+      RFD_HIP(hipEventSynchronize(b));
+      float e = 0.f;
+      RFD_HIP(hipEventElapsedTime(&e, a, b));
+      if (i > 0) ms = std::min(ms, (double)e);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return r;
+  };
+  double before_ms = 0.0;
+  rc = measure(before, before_ms);
+  if (rc) { p.timing = saved_timing; return rc; }
+  rfd_fir_config best = before;
+  double best_ms = before_ms;
+  int n = 1;
+  const int nbs16[2] = {8, 16};
+  const int tiles[3] = {4, 8, 16};
+  for (int ib = 0; ib < 2; ++ib) {
+    if (precision == RFD_FP32 && ib > 0) break;
+    for (int it = 0; it < 3; ++it) {
+      const rfd_fir_config cands[3] = {{nbs16[ib], 1, tiles[it], 0}, {nbs16[ib], 2, tiles[it], 0},
+                                       {nbs16[ib], 2, tiles[it], 1}};
+      for (const auto& c : cands) {
+        double ms = 0.0;
+        rc = measure(c, ms);
+        if (rc) { rfd_plan_set_fir_config(plan, &before); p.timing = saved_timing; return rc; }
+        ++n;
+        if (ms < best_ms) { best_ms = ms; best = c; }
+      }
+    }
+  }
+  rfd_plan_set_fir_config(plan, &best);
+  p.timing = saved_timing;
+  out->best = best;
+  out->best_ms = best_ms;
+  out->before_ms = before_ms;
+  out->n_candidates = n;
   return RFD_OK;
 }
 
@@ -326,6 +451,8 @@ static void taps_free(Taps& t) {
   }
   dfree(t.a64); dfree(t.sigma_fit); dfree(t.c32); dfree(t.pbf); dfree(t.pfh); dfree(t.p32);
   dfree(t.d_first); dfree(t.d_meta); dfree(t.d_abase); dfree(t.work64); dfree(t.bvec);
+  dfree(t.d_p16); dfree(t.d_p32); dfree(t.d_count);
+  dfree(t.d_it_off); dfree(t.d_it_sb); dfree(t.d_it_S); dfree(t.d_it_nsg);
 }
 
 int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, const int32_t* ref_id,
@@ -351,7 +478,7 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
   int64_t abase = 0, p16 = 0, p32 = 0;
   std::vector<int64_t> firsts(n_subbanks);
   std::vector<int32_t> meta(4 * n_subbanks);
-  std::vector<int64_t> abases(n_subbanks);
+  std::vector<int64_t> abases(n_subbanks), p16s(n_subbanks), p32s(n_subbanks), counts(n_subbanks);
   int rc = RFD_OK;
   for (int b = 0; b < n_subbanks; ++b) {
     SubBankTaps& s = t.sb[b];
@@ -371,6 +498,9 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
     p32 += (s.npad / 8) * (s.Tp / 8) * 64;
     firsts[b] = s.first;
     abases[b] = s.a_base;
+    p16s[b] = s.p16_base;
+    p32s[b] = s.p32_base;
+    counts[b] = s.count;
     meta[4 * b + 0] = s.ref_id;
     meta[4 * b + 1] = s.T;
     meta[4 * b + 2] = s.Tp;
@@ -387,6 +517,9 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
   TRY(dalloc(&t.d_first, (size_t)n_subbanks));
   TRY(dalloc(&t.d_meta, (size_t)4 * n_subbanks));
   TRY(dalloc(&t.d_abase, (size_t)n_subbanks));
+  TRY(dalloc(&t.d_p16, (size_t)n_subbanks));
+  TRY(dalloc(&t.d_p32, (size_t)n_subbanks));
+  TRY(dalloc(&t.d_count, (size_t)n_subbanks));
   for (auto& s : t.sb) TRY(dalloc(&s.g, (size_t)s.T));
 #undef TRY
   if (hipMemsetAsync(t.pbf, 0, p16 * sizeof(uint4), p.stream) != hipSuccess ||
@@ -395,6 +528,9 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
       hipMemcpy(t.d_first, firsts.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t.d_meta, meta.data(), 4 * n_subbanks * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t.d_abase, abases.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.d_p16, p16s.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.d_p32, p32s.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.d_count, counts.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipStreamSynchronize(p.stream) != hipSuccess) {
     taps_free(t);
     delete h;
@@ -521,25 +657,23 @@ int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, flo
     return fail(RFD_E_INVALID, "unknown precision");
   int rc = check_filter_args(p, threshold, cluster_window, out, capacity, n_out);
   if (rc) return rc;
-  for (size_t b = 0; b < t.sb.size(); ++b) {
-    const SubBankTaps& s = t.sb[b];
-    if (s.count == 0) continue;
-    if (p.seg_gen == 0 || p.ref_gen[s.ref_id] != p.seg_gen)
-      return fail(RFD_E_STATE, "sub-bank " + std::to_string(b) + ": reference slot not dechirped on this segment");
-    if (s.made != s.count) return fail(RFD_E_STATE, "sub-bank " + std::to_string(b) + ": taps not made");
-  }
+  rc = check_bank_state(p, t);
+  if (rc) return rc;
+  Taps& tm = const_cast<Taps&>(t);   // the work-item tables are a cache
   const int64_t nwin = (p.n + cluster_window - 1) / cluster_window;
   const int64_t n_slots = t.n_templates * nwin;
   rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
   if (rc) return rc;
+  if (use_persistent(p, t)) {
+    rc = prepare_fir_items(p, tm, precision, cluster_window);
+    if (rc) return rc;
+  }
   rc = launch_slots_clear(p, n_slots);
   if (rc) return rc;
   rc = stage_begin(p, kStFir);
   if (rc) return rc;
-  for (size_t b = 0; b < t.sb.size(); ++b) {
-    rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin);
-    if (rc) return rc;
-  }
+  rc = enqueue_fir(p, tm, precision, cluster_window, nwin);
+  if (rc) return rc;
   rc = stage_end(p);
   if (!rc) rc = stage_begin(p, kStCompact);
   if (rc) return rc;
@@ -618,6 +752,112 @@ int findchirp_filter(rfd_plan* plan, const double* data, const float* filt, int6
   if (!rc) rc = stage_end(p);
   if (rc) return rc;
   return finish_triggers(p, capacity, n_out);
+}
+
+struct rfd_graph {
+  rfd_plan* plan = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int32_t> ref_ids;
+  int64_t capacity = 0;
+};
+
+int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                             int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                             const double* const* h_refs, rfd_trigger* out, int64_t capacity, rfd_graph** graph) {
+  if (!graph) return fail(RFD_E_INVALID, "graph is NULL");
+  *graph = nullptr;
+  if (!plan || !taps || !data || !ref_ids || !h_refs) return fail(RFD_E_INVALID, "NULL argument");
+  Plan& p = plan->p;
+  Taps& t = const_cast<Taps&>(taps->t);
+  if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
+  if (precision != RFD_FP32 && precision != RFD_BF16X3 && precision != RFD_FP16X3)
+    return fail(RFD_E_INVALID, "unknown precision");
+  int64_t dummy = 0;
+  int rc = check_filter_args(p, threshold, cluster_window, out, capacity, &dummy);
+  if (rc) return rc;
+  if (n_refs < 1 || n_refs > p.max_refs) return fail(RFD_E_INVALID, "n_refs out of range");
+  std::vector<int> seen(p.max_refs, 0);
+  for (int i = 0; i < n_refs; ++i) {
+    if (ref_ids[i] < 0 || ref_ids[i] >= p.max_refs || seen[ref_ids[i]]) return fail(RFD_E_INVALID, "bad ref_ids");
+    if (!h_refs[i]) return fail(RFD_E_INVALID, "NULL reference template");
+    seen[ref_ids[i]] = 1;
+  }
+  for (auto& s : t.sb)
+    if (s.count && !seen[s.ref_id]) return fail(RFD_E_INVALID, "a sub-bank's reference is not in ref_ids");
+  for (auto& s : t.sb)
+    if (s.made != s.count) return fail(RFD_E_STATE, "taps not made");
+  const int64_t nwin = (p.n + cluster_window - 1) / cluster_window;
+  const int64_t n_slots = t.n_templates * nwin;
+  rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
+  if (rc) return rc;
+  if (use_persistent(p, t)) {
+    rc = prepare_fir_items(p, t, precision, cluster_window);
+    if (rc) return rc;
+  }
+  RFD_HIP(hipStreamSynchronize(p.stream));
+  hipStream_t cap = nullptr;
+  RFD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipStream_t saved = p.stream;
+  const bool saved_timing = p.timing;
+  p.stream = cap;
+  p.timing = false;
+  hipGraph_t g = nullptr;
+  rc = RFD_OK;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = fail(RFD_E_DEVICE, "hipStreamBeginCapture failed");
+  } else {
+    rc = launch_data_fft(p, data);
+    for (int i = 0; !rc && i < n_refs; ++i) rc = launch_dechirp(p, h_refs[i], ref_ids[i], p.dscratch);
+    if (!rc) rc = launch_slots_clear(p, n_slots);
+    if (!rc) rc = enqueue_fir(p, t, precision, cluster_window, nwin);
+    if (!rc) rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);
+    if (!rc) rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
+    hipError_t e = hipStreamEndCapture(cap, &g);
+    if (!rc && e != hipSuccess) rc = fail(RFD_E_DEVICE, "hipStreamEndCapture failed");
+  }
+  p.stream = saved;
+  p.timing = saved_timing;
+  (void)hipStreamDestroy(cap);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  rfd_graph* h = new (std::nothrow) rfd_graph();
+  if (!h) {
+    (void)hipGraphDestroy(g);
+    return fail(RFD_E_NOMEM, "host allocation failed");
+  }
+  h->plan = plan;
+  h->graph = g;
+  h->ref_ids.assign(ref_ids, ref_ids + n_refs);
+  h->capacity = capacity;
+  if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete h;
+    return fail(RFD_E_DEVICE, "hipGraphInstantiate failed");
+  }
+  *graph = h;
+  return RFD_OK;
+}
+
+int rfd_segment_graph_launch(rfd_graph* graph, int64_t* n_out) {
+  if (!graph) return fail(RFD_E_INVALID, "graph is NULL");
+  Plan& p = graph->plan->p;
+  RFD_HIP(hipGraphLaunch(graph->exec, p.stream));
+  ++p.seg_gen;
+  for (int32_t r : graph->ref_ids) p.ref_gen[r] = p.seg_gen;
+  if (!n_out) return RFD_OK;
+  return finish_triggers(p, graph->capacity, n_out);
+}
+
+int rfd_graph_destroy(rfd_graph* graph) {
+  if (!graph) return RFD_OK;
+  (void)hipStreamSynchronize(graph->plan->p.stream);
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return RFD_OK;
 }
 
 }  // extern "C"

@@ -159,21 +159,21 @@ __device__ __forceinline__ void load_window(V* dst, const V* __restrict__ src, i
   for (int p = threadIdx.x; p < len; p += 256) dst[p] = src[(start + p) & nm];
 }
 
+// One workgroup's work: S tiles of 16*NB samples from mbase, for the 4 template
+// blocks tb0..tb0+3 (8 templates per wave).  All threads must call it.
 template <bool BF16, int NB>
-__global__ __launch_bounds__(256) void k_fir16(FirArgs a) {
+__device__ __forceinline__ void fir16_block(const FirArgs& a, int64_t mbase, int64_t tb0, uint32_t* win) {
   constexpr int kColsPerTile = 16 * NB;
-  extern __shared__ __align__(16) uint32_t win[];
   const int Lw = a.S * kColsPerTile + a.Tp;
   uint32_t* whi = win;
   uint32_t* wlo = win + Lw;
-  const int64_t mbase = (int64_t)blockIdx.x * a.S * kColsPerTile;
   const int64_t nm = a.n - 1;
   load_window(whi, a.zhi, mbase + a.k0, Lw, nm);
   load_window(wlo, a.zlo, mbase + a.k0, Lw, nm);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t tb = (int64_t)blockIdx.y * kWavesPerBlock + wave;
-  if (tb * kTmplPerWave >= a.count) return;
+  const int64_t tb = tb0 + wave;
+  if (tb * kTmplPerWave >= a.count) return;   // wave-uniform; no barrier follows
   const int off = (lane & 15) + 4 * (lane >> 4);
   const uint4* A = a.pa16 + tb * (int64_t)a.KB * 128 + lane;
   PeakState ps;
@@ -230,18 +230,22 @@ __global__ __launch_bounds__(256) void k_fir16(FirArgs a) {
   fir_final_epilogue(a, tb, ps);
 }
 
+template <bool BF16, int NB>
+__global__ __launch_bounds__(256) void k_fir16(FirArgs a) {
+  extern __shared__ __align__(16) uint32_t win[];
+  fir16_block<BF16, NB>(a, (int64_t)blockIdx.x * a.S * 16 * NB, (int64_t)blockIdx.y * kWavesPerBlock, win);
+}
+
 // FP32: v_mfma_f32_16x16x4f32, K step = 2 complex taps; B read from LDS.
 template <int NB>
-__global__ __launch_bounds__(256) void k_fir32(FirArgs a) {
+__device__ __forceinline__ void fir32_block(const FirArgs& a, int64_t mbase, int64_t tb0, float2* wz) {
   constexpr int kColsPerTile = 16 * NB;
-  extern __shared__ __align__(16) float2 wz[];
   const int Lw = a.S * kColsPerTile + a.Tp;
-  const int64_t mbase = (int64_t)blockIdx.x * a.S * kColsPerTile;
   load_window(wz, a.z32, mbase + a.k0, Lw, a.n - 1);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t tb = (int64_t)blockIdx.y * kWavesPerBlock + wave;
-  if (tb * kTmplPerWave >= a.count) return;
+  const int64_t tb = tb0 + wave;
+  if (tb * kTmplPerWave >= a.count) return;   // wave-uniform; no barrier follows
   const float4* A = a.pa32 + tb * (int64_t)(a.Tp / 8) * 64 + lane;
   const int KQ = a.Tp / 8;
   PeakState ps;
@@ -274,11 +278,97 @@ __global__ __launch_bounds__(256) void k_fir32(FirArgs a) {
   fir_final_epilogue(a, tb, ps);
 }
 
+template <int NB>
+__global__ __launch_bounds__(256) void k_fir32(FirArgs a) {
+  extern __shared__ __align__(16) float2 wz[];
+  fir32_block<NB>(a, (int64_t)blockIdx.x * a.S * 16 * NB, (int64_t)blockIdx.y * kWavesPerBlock, wz);
+}
+
+// ------------------------------------------------------------ persistent
+// One launch for every sub-bank: a fixed grid of workgroups pulls work items
+// (sub-bank, template tile of 32, group of S tiles) from a global counter.
+// Items are ordered heaviest sub-bank first (n_b * T_b), and within a
+// sub-bank sample groups fastest, so concurrent workgroups share the same
+// template tile's taps in L2 and the short items fill the tail.
+struct PersistArgs {
+  FirArgs base;                 // n, nwin, W, slots
+  const int64_t* it_off;        // [nsb+1] first item of each (sorted) sub-bank
+  const int32_t* it_sb;         // sorted position -> sub-bank
+  const int32_t* it_S;          // tiles per item
+  const int64_t* it_nsg;        // sample groups per template tile
+  const int64_t* sb_first;      // global index of the first template
+  const int32_t* sb_meta;       // ref_id, T, Tp, k0
+  const int64_t* sb_p16;        // packed 16-bit operand base (uint4)
+  const int64_t* sb_p32;        // packed FP32 operand base (float4)
+  const int64_t* sb_count;
+  const uint32_t* zhi_all;      // slot-major planes
+  const uint32_t* zlo_all;
+  const float2* z32_all;
+  const uint4* pa16_all;
+  const float4* pa32_all;
+  unsigned long long* counter;
+  int64_t total;
+  int nsb;
+  int cols;
+};
+
+__device__ __forceinline__ bool next_item(const PersistArgs& pa, FirArgs& a, int64_t& mbase, int64_t& tb0) {
+  __shared__ long long s_item;
+  __syncthreads();                                  // previous item's LDS reads are done
+  if (threadIdx.x == 0) s_item = (long long)atomicAdd(pa.counter, 1ull);
+  __syncthreads();
+  const int64_t w = s_item;
+  if (w >= pa.total) return false;
+  int lo = 0, hi = pa.nsb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pa.it_off[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  const int b = pa.it_sb[lo];
+  const int64_t rem = w - pa.it_off[lo];
+  const int64_t nsg = pa.it_nsg[lo];
+  const int64_t tt = rem / nsg, sg = rem - tt * nsg;
+  a = pa.base;
+  const int ref = pa.sb_meta[4 * b + 0];
+  a.Tp = pa.sb_meta[4 * b + 2];
+  a.k0 = pa.sb_meta[4 * b + 3];
+  a.KB = a.Tp / 16;
+  a.S = pa.it_S[lo];
+  a.count = pa.sb_count[b];
+  a.tmpl0 = pa.sb_first[b];
+  a.zhi = pa.zhi_all + (int64_t)ref * a.n;
+  a.zlo = pa.zlo_all + (int64_t)ref * a.n;
+  a.z32 = pa.z32_all + (int64_t)ref * a.n;
+  a.pa16 = pa.pa16_all + pa.sb_p16[b];
+  a.pa32 = pa.pa32_all + pa.sb_p32[b];
+  mbase = sg * a.S * pa.cols;
+  tb0 = tt * kWavesPerBlock;
+  return true;
+}
+
+template <bool BF16, int NB>
+__global__ __launch_bounds__(256) void k_fir16_persistent(PersistArgs pa) {
+  extern __shared__ __align__(16) uint32_t win[];
+  FirArgs a;
+  int64_t mbase, tb0;
+  while (next_item(pa, a, mbase, tb0)) fir16_block<BF16, NB>(a, mbase, tb0, win);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_fir32_persistent(PersistArgs pa) {
+  extern __shared__ __align__(16) float2 wz[];
+  FirArgs a;
+  int64_t mbase, tb0;
+  while (next_item(pa, a, mbase, tb0)) fir32_block<NB>(a, mbase, tb0, wz);
+}
+
+__global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
+
 // Tiles per workgroup: one workgroup covers a whole cluster window when W is
 // a multiple of 256 (so each (template, window) peak gets one update), capped
 // at 8 tiles; otherwise 4 tiles.
-static int tiles_per_block(int64_t n, int64_t W, int cols) {
-  const int smax = 2048 / cols;
+static int tiles_per_block(int64_t n, int64_t W, int cols, int smax_cfg) {
+  const int smax = std::max(1, std::min(2048 / cols, smax_cfg));
   int S = (W % cols == 0) ? (int)std::min<int64_t>(W / cols, smax) : std::max(1, smax / 2);
   while (S > 1 && (n % ((int64_t)S * cols)) != 0) S >>= 1;
   return S < 1 ? 1 : S;
@@ -306,7 +396,7 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
   // column blocks per wave: FP32 16; 16-bit forms 8 (tile config knob)
   const int nb = precision == RFD_FP32 ? 16 : p.fir_nb16;
   const int cols = 16 * nb;
-  a.S = tiles_per_block(p.n, W, cols);
+  a.S = tiles_per_block(p.n, W, cols, p.fir_smax);
   dim3 grid((unsigned)(p.n / ((int64_t)a.S * cols)), (unsigned)((s.count + kTmplTile - 1) / kTmplTile));
   const int Lw = a.S * cols + s.Tp;
   if (precision == RFD_FP32) {
@@ -321,6 +411,131 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
       if (bf) hipLaunchKernelGGL((k_fir16<true, 8>), grid, dim3(256), sh, p.stream, a);
       else hipLaunchKernelGGL((k_fir16<false, 8>), grid, dim3(256), sh, p.stream, a);
     }
+  }
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+}  // namespace rfd
+
+namespace rfd {
+
+static int fir_cols(const Plan& p, int precision) { return 16 * (precision == RFD_FP32 ? 16 : p.fir_nb16); }
+
+template <typename K>
+static int persistent_grid(Plan& p, K kernel, size_t lds, int64_t total) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (p.fir_wg_per_cu > 0) per_cu = std::min(per_cu, p.fir_wg_per_cu);
+  int64_t g = (int64_t)per_cu * std::max(p.n_cu, 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, total));
+}
+
+int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W) {
+  const int cols = fir_cols(p, precision);
+  if (tp.it_key_W == W && tp.it_key_cols == cols && tp.it_key_smax == p.fir_smax && tp.it_key_prec == precision &&
+      tp.it_key_wg == p.fir_wg_per_cu)
+    return RFD_OK;
+  const int nsb = (int)tp.sb.size();
+  std::vector<int> order;
+  for (int b = 0; b < nsb; ++b)
+    if (tp.sb[b].count > 0) order.push_back(b);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return tp.sb[x].count * tp.sb[x].Tp > tp.sb[y].count * tp.sb[y].Tp;
+  });
+  const int m = (int)order.size();
+  std::vector<int64_t> off(m + 1, 0), nsg(std::max(m, 1), 0);
+  std::vector<int32_t> S(std::max(m, 1), 1), sbv(std::max(m, 1), 0);
+  size_t lds = 0;
+  for (int j = 0; j < m; ++j) {
+    const SubBankTaps& s = tp.sb[order[j]];
+    S[j] = tiles_per_block(p.n, W, cols, p.fir_smax);
+    nsg[j] = p.n / ((int64_t)S[j] * cols);
+    sbv[j] = order[j];
+    off[j + 1] = off[j] + nsg[j] * ((s.count + kTmplTile - 1) / kTmplTile);
+    const size_t win = (size_t)(S[j] * cols + s.Tp) * (precision == RFD_FP32 ? sizeof(float2) : 2 * sizeof(uint32_t));
+    lds = std::max(lds, win);
+  }
+  auto up = [&](auto*& dst, const auto& src, size_t n) -> int {
+    if (dst) { (void)hipFree(dst); dst = nullptr; }
+    if (hipMalloc((void**)&dst, std::max<size_t>(n, 1) * sizeof(src[0])) != hipSuccess)
+      return fail(RFD_E_NOMEM, "work-item table allocation failed");
+    if (n && hipMemcpy(dst, src.data(), n * sizeof(src[0]), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RFD_E_DEVICE, "work-item table upload failed");
+    return RFD_OK;
+  };
+  int rc;
+  if ((rc = up(tp.d_it_off, off, m + 1))) return rc;
+  if ((rc = up(tp.d_it_sb, sbv, m))) return rc;
+  if ((rc = up(tp.d_it_S, S, m))) return rc;
+  if ((rc = up(tp.d_it_nsg, nsg, m))) return rc;
+  tp.it_total = off[m];
+  tp.it_nsb = m;
+  tp.it_lds = lds;
+  const bool f16 = precision == RFD_FP16X3;
+  if (precision == RFD_FP32)
+    tp.it_grid = persistent_grid(p, k_fir32_persistent<16>, lds, tp.it_total);
+  else if (p.fir_nb16 == 16)
+    tp.it_grid = persistent_grid(p, f16 ? k_fir16_persistent<false, 16> : k_fir16_persistent<true, 16>, lds, tp.it_total);
+  else
+    tp.it_grid = persistent_grid(p, f16 ? k_fir16_persistent<false, 8> : k_fir16_persistent<true, 8>, lds, tp.it_total);
+  tp.it_key_W = W;
+  tp.it_key_cols = cols;
+  tp.it_key_smax = p.fir_smax;
+  tp.it_key_prec = precision;
+  tp.it_key_wg = p.fir_wg_per_cu;
+  return RFD_OK;
+}
+
+int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin) {
+  if (tp.it_total == 0) return RFD_OK;
+  PersistArgs pa;
+  FirArgs& a = pa.base;
+  a.zhi = a.zlo = nullptr;
+  a.z32 = nullptr;
+  a.pa16 = nullptr;
+  a.pa32 = nullptr;
+  a.slots = p.slots;
+  a.n = p.n;
+  a.count = 0;
+  a.tmpl0 = 0;
+  a.nwin = nwin;
+  a.W = W;
+  a.k0 = a.Tp = a.KB = 0;
+  a.S = 1;
+  pa.it_off = tp.d_it_off;
+  pa.it_sb = tp.d_it_sb;
+  pa.it_S = tp.d_it_S;
+  pa.it_nsg = tp.d_it_nsg;
+  pa.sb_first = tp.d_first;
+  pa.sb_meta = tp.d_meta;
+  pa.sb_p16 = tp.d_p16;
+  pa.sb_p32 = tp.d_p32;
+  pa.sb_count = tp.d_count;
+  const bool f16 = precision == RFD_FP16X3;
+  pa.zhi_all = f16 ? p.zh_hi : p.zbf_hi;
+  pa.zlo_all = f16 ? p.zh_lo : p.zbf_lo;
+  pa.z32_all = p.zref;
+  pa.pa16_all = f16 ? tp.pfh : tp.pbf;
+  pa.pa32_all = tp.p32;
+  pa.counter = p.counter;
+  pa.total = tp.it_total;
+  pa.nsb = tp.it_nsb;
+  pa.cols = fir_cols(p, precision);
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, p.stream, p.counter);
+  RFD_CHECK_LAUNCH();
+  if (tp.it_key_prec != precision || tp.it_key_W != W || tp.it_key_cols != pa.cols)
+    return fail(RFD_E_STATE, "persistent FIR work items were prepared for another configuration");
+  const size_t lds = tp.it_lds;
+  const dim3 grid(tp.it_grid);
+  if (precision == RFD_FP32) {
+    hipLaunchKernelGGL(k_fir32_persistent<16>, grid, dim3(256), lds, p.stream, pa);
+  } else if (p.fir_nb16 == 16) {
+    if (f16) hipLaunchKernelGGL((k_fir16_persistent<false, 16>), grid, dim3(256), lds, p.stream, pa);
+    else hipLaunchKernelGGL((k_fir16_persistent<true, 16>), grid, dim3(256), lds, p.stream, pa);
+  } else {
+    if (f16) hipLaunchKernelGGL((k_fir16_persistent<false, 8>), grid, dim3(256), lds, p.stream, pa);
+    else hipLaunchKernelGGL((k_fir16_persistent<true, 8>), grid, dim3(256), lds, p.stream, pa);
   }
   RFD_CHECK_LAUNCH();
   return RFD_OK;

@@ -65,6 +65,15 @@ struct Plan {
 
   // FIR tile configuration of the 16-bit forms: MFMA column blocks per wave (8 or 16)
   int fir_nb16 = 8;
+  // FIR launch mode: 0 auto (persistent when more than one sub-bank), 1 one launch
+  // per sub-bank, 2 persistent work queue always
+  int fir_mode = 0;
+  // largest number of tiles one work item sweeps (1, 2, 4, ..., 16)
+  int fir_smax = 16;
+  // persistent grid: workgroups per CU (0: as many as fit)
+  int fir_wg_per_cu = 0;
+  int n_cu = 0;
+  unsigned long long* counter = nullptr;   // persistent work-queue counter
 
   // optional stage timing (hipEvent pairs on `stream`)
   bool timing = false;
@@ -105,6 +114,12 @@ struct Taps {
   // device copy of per-sub-bank metadata for trigger kernels
   int64_t* d_first = nullptr; int32_t* d_meta = nullptr;  // meta: ref_id, T, Tp, k0 per sub-bank
   int64_t* d_abase = nullptr;
+  // static per-sub-bank tables for the persistent FIR
+  int64_t* d_p16 = nullptr; int64_t* d_p32 = nullptr; int64_t* d_count = nullptr;
+  // work-item tables for the persistent FIR (rebuilt when the key changes)
+  int64_t* d_it_off = nullptr; int32_t* d_it_sb = nullptr; int32_t* d_it_S = nullptr; int64_t* d_it_nsg = nullptr;
+  int64_t it_key_W = -1; int it_key_cols = -1; int it_key_smax = -1; int it_key_prec = -1; int it_key_wg = -1;
+  int64_t it_total = 0; int it_nsb = 0; size_t it_lds = 0; int it_grid = 1;
   // scratch for tap construction
   double2* work64 = nullptr; size_t work64_cap = 0;
   double2* bvec = nullptr; size_t bvec_cap = 0;
@@ -134,6 +149,10 @@ int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, 
 
 // ----------------------------------------------------- launchers (fir.hip)
 int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin);
+// all sub-banks in one persistent launch (builds the work-item tables if needed;
+// must not be called for the first time with a given key inside graph capture)
+int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W);
+int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin);
 
 // ------------------------------------------------ launchers (triggers.hip)
 int launch_slots_clear(Plan& p, int64_t n_slots);

@@ -43,6 +43,15 @@ class rfd_timing(C.Structure):
                [(k, C.c_int64) for k in ("n_data_fft", "n_dechirp", "n_fir", "n_compact", "n_findchirp", "n_taps")]
 
 
+class rfd_fir_config(C.Structure):
+    _fields_ = [("col_blocks", C.c_int32), ("mode", C.c_int32), ("max_tiles", C.c_int32), ("wg_per_cu", C.c_int32)]
+
+
+class rfd_tune_result(C.Structure):
+    _fields_ = [("best", rfd_fir_config), ("best_ms", C.c_double), ("before_ms", C.c_double),
+                ("n_candidates", C.c_int32)]
+
+
 _P = C.c_void_p
 _i64, _i32, _d, _f = C.c_int64, C.c_int32, C.c_double, C.c_float
 _SIGS = {
@@ -51,7 +60,12 @@ _SIGS = {
     "rfd_plan_set_stream": [_P, _P],
     "rfd_plan_destroy": [_P],
     "rfd_plan_set_timing": [_P, _i32],
-    "rfd_plan_set_fir_tiles": [_P, _i32],
+    "rfd_plan_set_fir_config": [_P, C.POINTER(rfd_fir_config)],
+    "rfd_plan_get_fir_config": [_P, C.POINTER(rfd_fir_config)],
+    "rfd_autotune_fir": [_P, _P, _i32, _i64, _i32, C.POINTER(rfd_tune_result)],
+    "rfd_segment_graph_create": [_P, _P, _i32, _f, _i64, _P, _i32, _P, _P, _P, _i64, C.POINTER(_P)],
+    "rfd_segment_graph_launch": [_P, C.POINTER(_i64)],
+    "rfd_graph_destroy": [_P],
     "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
     "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
     "rfd_get_zref": [_P, _i32, _P],
@@ -145,8 +159,51 @@ def rfd_plan_get_timing(plan):
     return {k: getattr(t, k) for k, _ in rfd_timing._fields_}
 
 
-def rfd_plan_set_fir_tiles(plan, col_blocks):
-    _check(_lib.rfd_plan_set_fir_tiles(plan, col_blocks), "rfd_plan_set_fir_tiles")
+def _cfg_dict(c):
+    return {k: getattr(c, k) for k, _ in rfd_fir_config._fields_}
+
+
+def rfd_plan_set_fir_config(plan, col_blocks=8, mode=0, max_tiles=16, wg_per_cu=0):
+    c = rfd_fir_config(col_blocks, mode, max_tiles, wg_per_cu)
+    _check(_lib.rfd_plan_set_fir_config(plan, C.byref(c)), "rfd_plan_set_fir_config")
+
+
+def rfd_plan_get_fir_config(plan):
+    c = rfd_fir_config()
+    _check(_lib.rfd_plan_get_fir_config(plan, C.byref(c)), "rfd_plan_get_fir_config")
+    return _cfg_dict(c)
+
+
+def rfd_autotune_fir(plan, taps, precision, cluster_window, reps=3):
+    r = rfd_tune_result()
+    _check(_lib.rfd_autotune_fir(plan, taps, PRECISIONS.get(precision, precision), cluster_window, reps, C.byref(r)),
+           "rfd_autotune_fir")
+    return {"best": _cfg_dict(r.best), "best_ms": r.best_ms, "before_ms": r.before_ms,
+            "n_candidates": r.n_candidates}
+
+
+def rfd_segment_graph_create(plan, taps, precision, threshold, cluster_window, data, refs, out, capacity):
+    """refs: {ref_id: complex128 device tensor}.  data: float64 device tensor [N] (read at replay)."""
+    ids = np.array(sorted(refs), dtype=np.int32)
+    ptrs = (C.c_void_p * len(ids))(*[refs[int(i)].data_ptr() for i in ids])
+    g = _P()
+    _check(_lib.rfd_segment_graph_create(plan, taps, PRECISIONS.get(precision, precision), threshold, cluster_window,
+                                         _ptr(data), len(ids), ids.ctypes.data, ptrs, _ptr(out), capacity,
+                                         C.byref(g)), "rfd_segment_graph_create")
+    return g
+
+
+def rfd_segment_graph_launch(graph, want_count=True, raise_overflow=True):
+    n = C.c_int64(0)
+    rc = _lib.rfd_segment_graph_launch(graph, C.byref(n) if want_count else None)
+    if rc == RFD_E_OVERFLOW and not raise_overflow:
+        return n.value
+    _check(rc, "rfd_segment_graph_launch")
+    return n.value if want_count else None
+
+
+def rfd_graph_destroy(graph):
+    _check(_lib.rfd_graph_destroy(graph), "rfd_graph_destroy")
 
 
 def rfd_plan_destroy(plan):

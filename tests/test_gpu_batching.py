@@ -1,0 +1,132 @@
+"""Batching: persistent multi-sub-bank launch, segment graph, autotuner, and
+parity of the uneven-sub-bank and eccentric workloads on seeded subsets."""
+import numpy as np
+import pytest
+
+from gpu_cases import gpu_search, oracle_case, ragged_case, rho_matrix, workload_case, compare_triggers
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def ragged(rfd):
+    case = ragged_case()
+    s = gpu_search(case)
+    yield case, s
+    s.close()
+
+
+def _trig(rfd, s, precision, threshold, window, cap):
+    buf, n = s.filter(precision, threshold, window, cap)
+    return rfd.triggers_to_numpy(buf, n)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_persistent_launch_is_bit_identical(rfd, ragged, precision):
+    case, s = ragged
+    cap = case.n_templates * case.n
+    out = {}
+    for mode in (1, 2):
+        rfd.rfd_plan_set_fir_config(s.plan, 8, mode, 16, 0)
+        out[mode] = _trig(rfd, s, precision, 0.0, 1, cap)
+    rfd.rfd_plan_set_fir_config(s.plan, 8, 0, 16, 0)
+    a, b = out[1], out[2]
+    assert len(a) == len(b) == cap
+    assert np.array_equal(a, b), "persistent and per-sub-bank launches must agree bit for bit"
+    for mode, nb, mt, wg in [(2, 16, 4, 1), (2, 8, 2, 0), (1, 16, 1, 0)]:
+        rfd.rfd_plan_set_fir_config(s.plan, nb, mode, mt, wg)
+        c = _trig(rfd, s, precision, 0.0, 1, cap)
+        rfd.rfd_plan_set_fir_config(s.plan, 8, 0, 16, 0)
+        np.testing.assert_allclose(c["rho"], a["rho"], rtol=0, atol=1e-6 if precision == "fp32" else 1e-5)
+        assert np.array_equal(c["sample"], a["sample"]) and np.array_equal(c["tmpl"], a["tmpl"])
+
+
+def test_segment_graph_replays_match_eager(rfd, ragged):
+    import torch
+    case, s = ragged
+    th, W, cap = 2.5, 300, 1 << 16
+    s.dechirp_all()
+    eager = _trig(rfd, s, "bf16x3", th, W, cap)
+    out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    g = rfd.rfd_segment_graph_create(s.plan, s.taps, "bf16x3", th, W, s.data, s.h_ref, out, cap)
+    try:
+        for rep in range(4):
+            n = rfd.rfd_segment_graph_launch(g)
+            got = rfd.triggers_to_numpy(out, n)
+            assert np.array_equal(got, eager), f"replay {rep} differs from the eager result"
+            # the program's own eager work between replays
+            s.dechirp_all()
+            again = _trig(rfd, s, "bf16x3", th, W, cap)
+            assert np.array_equal(again, eager)
+            torch.cuda.synchronize()
+        # refill the captured input buffer in place with another segment
+        other = torch.roll(s.data, shifts=777)
+        s.data.copy_(other)
+        n = rfd.rfd_segment_graph_launch(g)
+        got = rfd.triggers_to_numpy(out, n)
+        s.dechirp_all()
+        eager2 = _trig(rfd, s, "bf16x3", th, W, cap)
+        assert np.array_equal(got, eager2)
+        assert not np.array_equal(eager2, eager)
+        s.data.copy_(torch.roll(other, shifts=-777))
+    finally:
+        rfd.rfd_graph_destroy(g)
+        s.dechirp_all()
+
+
+def test_autotuner_picks_a_measured_configuration(rfd, ragged):
+    case, s = ragged
+    before = _trig(rfd, s, "fp16x3", 0.0, 1, case.n_templates * case.n)
+    res = rfd.rfd_autotune_fir(s.plan, s.taps, "fp16x3", 1, reps=2)
+    print(f"\n[ragged] autotune fp16x3: {res}")
+    assert res["n_candidates"] == 19
+    assert res["best_ms"] <= res["before_ms"] + 1e-9
+    assert rfd.rfd_plan_get_fir_config(s.plan) == res["best"]
+    after = _trig(rfd, s, "fp16x3", 0.0, 1, case.n_templates * case.n)
+    assert np.array_equal(before["sample"], after["sample"])
+    np.testing.assert_allclose(after["rho"], before["rho"], rtol=0, atol=1e-5)
+    rfd.rfd_plan_set_fir_config(s.plan, 8, 0, 16, 0)
+
+
+def _subset_parity(rfd, case, forms, tol_fp32):
+    oracle_case(case)
+    s = gpu_search(case)
+    try:
+        want = np.abs(case.oracle["z"])
+        res = {}
+        for form in forms:
+            buf, n = s.filter(form, 0.0, 1, case.n_templates * case.n)
+            rho = rho_matrix(rfd.triggers_to_numpy(buf, n), case.n_templates, case.n)
+            res[form] = float(np.max(np.abs(rho - want)))
+        for form in forms:
+            buf, n = s.filter(form, 6.0, 2048, 1 << 16)
+            tr = rfd.triggers_to_numpy(buf, n)
+            compare_triggers(tr, want, 6.0, 2048, TOL[form] if form != "fp32" else tol_fp32)
+            buf, n = s.filter(form, 4.0, 2048, 1 << 18)
+            tr = rfd.triggers_to_numpy(buf, n)
+            compare_triggers(tr, want, 4.0, 2048, TOL[form] if form != "fp32" else tol_fp32)
+        return res
+    finally:
+        s.close()
+
+
+def test_tidal_uneven_subbanks_parity(rfd):
+    """tidal256s: the first 8 of 64 sub-banks (uneven T from the seeded draw), 2 templates each."""
+    case = workload_case("tidal256s", max_templates=128, subbank_limit=8)
+    case.subbanks = [type(sb)(sb.ref, sb.T, sb.k0, sb.H[:2]) for sb in case.subbanks]
+    res = _subset_parity(rfd, case, ["fp16x3", "bf16x3", "fp32"], 3e-5)
+    print(f"\n[tidal256s] 8 sub-banks, T = {[sb.T for sb in case.subbanks]}: max |drho| {res}")
+    assert res["fp16x3"] <= TOL["fp16x3"] and res["bf16x3"] <= TOL["bf16x3"]
+    assert res["fp32"] <= 3e-5
+
+
+def test_eccentric_subsolar_parity(rfd):
+    """ecc512s: 4 of 32 sub-banks, 2 templates each, N = 2^20, T = 1024."""
+    case = workload_case("ecc512s", max_templates=64, subbank_limit=4)
+    case.subbanks = [type(sb)(sb.ref, sb.T, sb.k0, sb.H[:2]) for sb in case.subbanks]
+    res = _subset_parity(rfd, case, ["bf16x3", "fp32"], 3e-5)
+    print(f"\n[ecc512s] 4 sub-banks x 2 templates, N = 2^20, T = 1024: max |drho| {res}")
+    assert res["bf16x3"] <= TOL["bf16x3"]
+    assert res["fp32"] <= 3e-5

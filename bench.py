@@ -1,20 +1,26 @@
 #!/usr/bin/env python
 """Throughput of the ratio-filter dechirping hot path on one MI355X.
 
-Workload spin256s: one 256 s segment (N = 2^19 samples at 2048 Hz, f_low =
-20 Hz) of coloured Gaussian noise with one SNR-12 injection; one reference
-at (2, 2) Msun; 4096 aligned-spin TaylorF2 templates (m1, m2 in [1, 3] Msun,
-|chi| <= 0.05); 256 complex taps per template; BF16 hi/lo split MFMA FIR with
-FP32 accumulation; threshold rho > 6; 1 s (2048-sample) cluster windows.
+Default workload spin256s: one 256 s segment (N = 2^19 samples at 2048 Hz,
+f_low = 20 Hz) of coloured Gaussian noise with one SNR-12 injection; one
+reference at (2, 2) Msun; 4096 aligned-spin TaylorF2 templates (m1, m2 in
+[1, 3] Msun, |chi| <= 0.05); 256 complex taps per template; BF16 hi/lo split
+MFMA FIR with FP32 accumulation; threshold rho > 6; 1 s cluster windows.
 
 One step = one pass of the per-segment hot path with all inputs resident in
-HBM: segment transform, dechirp (reference matched filter), ratio-FIR GEMM
-with the fused |z|^2 / threshold / window-peak epilogue for every template,
-trigger compaction.  The taps are built once before timing (the paper
-precomputes them with the bank); their construction is timed separately.
+HBM: segment transform, dechirp of every reference, ratio-FIR GEMM with the
+fused |z|^2 / threshold / window-peak epilogue for every template, trigger
+compaction.  Taps are built once before timing (the paper precomputes them
+with the bank); their construction is timed separately.
 
-Prints one JSON line (metric template*samples/s).  `--gpus` above 1 exits:
-the build targets one GPU.
+Other workloads (--workload): tidal256s (64 uneven sub-banks, T 32..1024,
+FP16 hi/lo; the step is one replay of the captured segment graph with the
+persistent FIR in the configuration the autotuner picked) and ecc512s
+(N = 2^20, 16384 eccentric templates under 32 references, T = 1024, BF16
+hi/lo, FINDCHIRP on the same GPU).  They generate 73k / 16k waveforms on the
+host first (a minute or two).
+
+Prints one JSON line.  `--gpus` above 1 exits: the build targets one GPU.
 """
 import argparse
 import json
@@ -25,8 +31,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X
-HBM_PEAK_GBS = 8000.0
+PEAK = {"bf16x3": 2500.0, "fp16x3": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X datasheet
+COUNTERS = {"spin256s": "fir_bf16x3_spin256s_counters.txt"}
 
 
 def log(msg):
@@ -35,6 +41,8 @@ def log(msg):
 
 def read_traffic(name):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if present."""
+    if not name:
+        return None
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -52,9 +60,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="spin256s", choices=["spin256s", "tidal256s", "ecc512s"])
     ap.add_argument("--cpu-sample", type=int, default=6, help="templates in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip FP32 / FP16 / FINDCHIRP comparison legs")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32 / FP16 / FINDCHIRP comparison legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -70,34 +79,48 @@ def main():
     from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = synth.get_workload("spin256s")
+    w = synth.get_workload(args.workload)
     bank = synth.make_bank(w)
-    sb = bank.subbanks[0]
     psd = synth.psd_array(w.n, w.fs)
     seg = synth.make_segment(w, bank)
-    hr = synth.reference_waveform(w, sb)
     nt = bank.n_templates
-    T = sb.taps
-    log(f"workload {w.name}: N={w.n} templates={nt} taps={T} precision={w.precision}")
+    nsb = len(bank.subbanks)
+    prec = w.precision
+    multi = nsb > 1
+    with_fc = args.workload in ("spin256s", "ecc512s") and not args.no_compare
+    log(f"workload {w.name}: N={w.n} templates={nt} sub-banks={nsb} precision={prec}")
 
-    s = RatioFilterSearch(psd, w.f_low, w.fs, w.n, [SubBankSpec(0, T, sb.k0, nt)])
-    s.set_reference(0, hr)
+    specs = [SubBankSpec(b, sb.taps, sb.k0, sb.size) for b, sb in enumerate(bank.subbanks)]
+    s = RatioFilterSearch(psd, w.f_low, w.fs, w.n, specs, max_refs=nsb)
+    hrefs = [synth.reference_waveform(w, sb) for sb in bank.subbanks]
+    for b in range(nsb):
+        s.set_reference(b, hrefs[b])
     info = s.info
-    filt = torch.empty((nt, info["n_band"]), dtype=torch.complex64, device="cuda")
-    fsig = torch.empty(nt, dtype=torch.float64, device="cuda")
+    filt = fsig = None
+    if with_fc:
+        filt = torch.empty((nt, info["n_band"]), dtype=torch.complex64, device="cuda")
+        fsig = torch.empty(nt, dtype=torch.float64, device="cuda")
     rfd.rfd_plan_set_timing(s.plan, True)
     batch = 256
     t_gen = 0.0
-    for b0 in range(0, nt, batch):
-        tg = time.perf_counter()
-        H = synth.template_batch(w, sb.params[b0:b0 + batch])
-        t_gen += time.perf_counter() - tg
-        Hd = torch.from_numpy(H).to("cuda")
-        s.make_taps(0, Hd, first=b0)
-        rfd.rfd_findchirp_prepare(s.plan, Hd, filt[b0:b0 + len(H)], fsig[b0:b0 + len(H)])
-        del Hd, H
-        if b0 % 1024 == 0:
-            log(f"taps + FINDCHIRP filters: {b0 + batch}/{nt}")
+    done = 0
+    next_log = 0
+    for b, sb in enumerate(bank.subbanks):
+        g0 = int(bank.offsets[b])
+        for b0 in range(0, sb.size, batch):
+            tg = time.perf_counter()
+            H = synth.template_batch(w, sb.params[b0:b0 + batch])
+            t_gen += time.perf_counter() - tg
+            Hd = torch.from_numpy(H).to("cuda")
+            s.make_taps(b, Hd, first=b0)
+            if with_fc:
+                k = len(H)
+                rfd.rfd_findchirp_prepare(s.plan, Hd, filt[g0 + b0:g0 + b0 + k], fsig[g0 + b0:g0 + b0 + k])
+            done += len(H)
+            del Hd, H
+            if done >= next_log:
+                log(f"taps{' + FINDCHIRP filters' if with_fc else ''}: {done}/{nt}")
+                next_log += max(1024, nt // 8)
     torch.cuda.synchronize()
     tap_timing = rfd.rfd_plan_get_timing(s.plan)
     taps_per_s = nt / (tap_timing["taps_ms"] / 1e3)
@@ -105,131 +128,84 @@ def main():
         f"waveform generation (host) {t_gen:.1f} s")
 
     data = torch.from_numpy(seg.data).to("cuda")
-    cap = 1 << 20
+    s.set_segment(data)
+    cap = 1 << 21
     out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
-    prec = w.precision
+    ts = nt * w.n
+    flops_alg = 8.0 * w.n * sum(sb.size * sb.taps for sb in bank.subbanks)   # 8T flop per template*sample
 
-    def step(precision):
-        rfd.rfd_dechirp(s.plan, data, s.h_ref[0], 0, False)
+    def eager_step(precision):
+        for r in range(nsb):
+            rfd.rfd_dechirp(s.plan, data if r == 0 else None, s.h_ref[r], r, False)
         return rfd.rfd_filter_bank(s.plan, s.taps, precision, w.threshold, w.window, cap, out)[1]
 
-    def timed(precision, steps, warmup):
+    def timed(fn, steps, warmup):
         for _ in range(warmup):
-            step(precision)
+            fn()
         torch.cuda.synchronize()
         rfd.rfd_plan_get_timing(s.plan)          # discard warm-up marks
         t0 = time.perf_counter()
         for _ in range(steps):
-            ntrig = step(precision)
+            n = fn()
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return dt, ntrig, rfd.rfd_plan_get_timing(s.plan)
+        return time.perf_counter() - t0, n, rfd.rfd_plan_get_timing(s.plan)
 
-    log(f"timing {args.steps} steps ({args.warmup} warm-up), {prec}")
-    dt, ntrig, tim = timed(prec, args.steps, args.warmup)
+    tune = None
+    graph = None
+    if multi:
+        s.dechirp_all()
+        tune = rfd.rfd_autotune_fir(s.plan, s.taps, prec, w.window, reps=1)
+        log(f"autotuner: {tune}")
+        graph = rfd.rfd_segment_graph_create(s.plan, s.taps, prec, w.threshold, w.window, data, s.h_ref, out, cap)
+        step = lambda: rfd.rfd_segment_graph_launch(graph)   # noqa: E731
+        # FIR kernel time (eager, same configuration) for the roofline
+        _, _, tfir = timed(lambda: eager_step(prec), 2, 1)
+        fir_ms = tfir["fir_ms"] / max(1, tfir["n_fir"])
+    else:
+        step = lambda: eager_step(prec)   # noqa: E731
+
+    log(f"timing {args.steps} steps ({args.warmup} warm-up), {prec}{' (segment graph)' if multi else ''}")
+    dt, ntrig, tim = timed(step, args.steps, args.warmup)
     ms_step = dt / args.steps * 1e3
-    value = nt * w.n * args.steps / dt
-    fir_ms = tim["fir_ms"] / max(1, tim["n_fir"])
+    value = ts * args.steps / dt
+    if not multi:
+        fir_ms = tim["fir_ms"] / max(1, tim["n_fir"])
+        stages = {k: tim[k] / args.steps for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms")}
+    else:
+        stages = {"fir_ms": fir_ms}
     log(f"{prec}: {ms_step:.3f} ms/step, {value:.4g} t*s/s, FIR kernel {fir_ms:.3f} ms, {ntrig} triggers")
-    stages = {k: tim[k] / args.steps for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms")}
-
-    ts = nt * w.n
-    flops_alg = 8.0 * T * ts                      # 8T real flops per template*sample
     achieved = flops_alg / (fir_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["bf16"], 4),
-                "traffic": read_traffic("fir_bf16x3_spin256s_counters.txt"),
-                "kernel": "k_fir16<bf16>", "issued_frac": round(3 * achieved / PEAK["bf16"], 4),
+    peak = PEAK[prec]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": read_traffic(COUNTERS.get(w.name)),
+                "kernel": f"k_fir16<{prec[:4]}>" + ("_persistent" if multi else ""),
+                "issued_frac": round(3 * achieved / peak, 4) if prec != "fp32" else round(achieved / peak, 4),
                 "flops_per_launch": flops_alg, "avg_launch_ms": round(fir_ms, 4)}
 
     compare = {}
     if not args.no_compare:
         k2 = max(3, args.steps // 4)
-        for other in ("fp32", "fp16x3"):
-            d2, n2, t2 = timed(other, k2, 1)
-            compare[f"fir_{other}"] = {"value": nt * w.n * k2 / d2, "ms_per_step": d2 / k2 * 1e3,
+        others = [f for f in ("fp32", "bf16x3", "fp16x3") if f != prec]
+        for other in others:
+            d2, n2, t2 = timed(lambda: eager_step(other), k2, 1)
+            compare[f"fir_{other}"] = {"value": ts * k2 / d2, "ms_per_step": d2 / k2 * 1e3,
                                        "fir_kernel_ms": t2["fir_ms"] / max(1, t2["n_fir"]), "triggers": n2}
             log(f"{other}: {d2 / k2 * 1e3:.3f} ms/step")
-        for _ in range(1):
-            rfd.findchirp_filter(s.plan, data, filt, w.threshold, w.window, cap, out)
-        torch.cuda.synchronize()
-        rfd.rfd_plan_get_timing(s.plan)
-        t0 = time.perf_counter()
-        for _ in range(k2):
-            _, nfc = rfd.findchirp_filter(s.plan, data, filt, w.threshold, w.window, cap, out)
-        torch.cuda.synchronize()
-        d3 = time.perf_counter() - t0
-        t3 = rfd.rfd_plan_get_timing(s.plan)
-        fc_ms = t3["findchirp_ms"] / k2
-        # FINDCHIRP streams 8 B/bin of filter; algorithmic HBM bytes per template = 8 n_band
-        compare["findchirp_fp32"] = {"value": nt * w.n * k2 / d3, "ms_per_step": d3 / k2 * 1e3,
-                                     "fft_ms": fc_ms, "triggers": nfc,
-                                     "filter_stream_GBs": nt * info["n_band"] * 8 / (fc_ms * 1e-3) / 1e9}
-        log(f"findchirp: {d3 / k2 * 1e3:.3f} ms/step")
+        if with_fc:
+            d3, nfc, t3 = timed(lambda: rfd.findchirp_filter(s.plan, data, filt, w.threshold, w.window, cap, out)[1],
+                                k2, 1)
+            fc_ms = t3["findchirp_ms"] / k2
+            compare["findchirp_fp32"] = {"value": ts * k2 / d3, "ms_per_step": d3 / k2 * 1e3, "fft_ms": fc_ms,
+                                         "triggers": nfc,
+                                         "filter_stream_GBs": nt * info["n_band"] * 8 / (fc_ms * 1e-3) / 1e9}
+            log(f"findchirp: {d3 / k2 * 1e3:.3f} ms/step")
 
-    # parity on a seeded sample (oracle) + CPU baseline timing of the same oracle
-    parity = None
-    cpu = None
+    parity = cpu = None
     if not args.no_cpu_baseline:
-        from oracle import pipeline as orc
-        from oracle import taps as otaps
-        from oracle import cluster as ocl
-        rng = np.random.default_rng(2601)
-        sample = sorted(set([seg.inj_template] + list(rng.choice(nt, size=max(0, args.cpu_sample - 1),
-                                                                  replace=False))))
-        Hs = synth.template_batch(w, [sb.params[j] for j in sample])
-        p = orc.prepare(psd, seg.data, w.fs, w.f_low)
-        M = otaps.gram(hr, p.w, T)
-        tts = [orc.make_taps(p, Hs[i], hr, T, sb.k0, M=M) for i in range(len(sample))]
-        c0, w0 = time.process_time(), time.perf_counter()
-        ref = orc.dechirp(orc.prepare(psd, seg.data, w.fs, w.f_low), hr)
-        zs = [orc.ratio_snr(ref, tt) for tt in tts]
-        wall = time.perf_counter() - w0
-        cpu_t = time.process_time() - c0
-        cpu = {"value": len(sample) * w.n / wall, "unit": "template*samples/s",
-               "cores": max(1, int(round(cpu_t / wall))), "kind": "oracle",
-               "sample": f"{len(sample)} of {nt} templates (seeded, incl. the injected one), full {w.n}-sample "
-                         f"segment: FP64 dechirp + direct-sum FIR ({T} taps); taps built outside the timing",
-               "seconds": round(wall, 2)}
-        log(f"cpu oracle: {cpu['value']:.3g} t*s/s on {cpu['cores']} core(s), {wall:.1f} s")
-        # GPU triggers of the sampled templates vs the oracle (same step as timed)
-        ntr = step(prec)
-        trig = rfd.triggers_to_numpy(out, min(ntr, cap))
-        amb = mism = cmp = 0
-        dmax = 0.0
-        for i, j in enumerate(sample):
-            rho = np.abs(zs[i])
-            want = {q: v for q, v in ((sm // w.window, (sm, r)) for sm, r in ocl.cluster(rho, w.threshold, w.window))}
-            got = {int(t["sample"]) // w.window: (int(t["sample"]), float(t["rho"])) for t in trig[trig["tmpl"] == j]}
-            fl = ocl.window_ambiguity(rho, w.threshold, w.window, 1e-3)
-            for q in range(len(fl)):
-                if fl[q]:
-                    amb += 1
-                    continue
-                cmp += 1
-                if (q in want) != (q in got) or (q in want and want[q][0] != got[q][0]):
-                    mism += 1
-                elif q in want:
-                    dmax = max(dmax, abs(want[q][1] - got[q][1]))
-        # full-series check of the sampled templates in validation mode (a second, small taps object)
-        s2 = RatioFilterSearch(psd, w.f_low, w.fs, w.n, [SubBankSpec(0, T, sb.k0, len(sample))])
-        s2.set_reference(0, hr)
-        s2.make_taps(0, Hs)
-        s2.set_segment(seg.data)
-        s2.dechirp_all()
-        full = {}
-        for form in ("bf16x3", "fp32", "fp16x3"):
-            buf, n = s2.filter(form, 0.0, 1, len(sample) * w.n)
-            tv = rfd.triggers_to_numpy(buf, n)
-            r = np.zeros((len(sample), w.n))
-            r[tv["tmpl"], tv["sample"]] = tv["rho"]
-            full[form] = float(max(np.max(np.abs(r[i] - np.abs(zs[i]))) for i in range(len(sample))))
-        s2.close()
-        parity = {"templates": [int(j) for j in sample], "windows_compared": cmp, "ambiguous": amb,
-                  "mismatches": mism, "max_drho_at_triggers": dmax, "max_drho_full_series": full,
-                  "tolerance": {"bf16x3": 1e-3, "fp16x3": 1e-3, "fp32": 1e-5}}
-        log(f"parity: {parity}")
+        parity, cpu = oracle_sample(args, w, bank, psd, seg, hrefs, s, out, cap, eager_step, prec, np, synth)
 
+    if graph is not None:
+        rfd.rfd_graph_destroy(graph)
     s.close()
     if args.calibrate_copy:
         # plain streaming kernel of known traffic: reads 1 GiB, writes 1 GiB
@@ -244,16 +220,98 @@ def main():
         "metric": "template*samples/s at SNR err <=1e-3 vs FP32 ratio-FIR and FINDCHIRP, 1 GPU",
         "value": value, "unit": "template*samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16", "precision": "bf16 hi/lo split operands (3 MFMA terms), fp32 accumulation",
+        "dtype": "f16" if prec == "fp16x3" else ("bf16" if prec == "bf16x3" else "f32"),
+        "precision": {"bf16x3": "bf16 hi/lo split operands (3 MFMA terms), fp32 accumulation",
+                      "fp16x3": "fp16 hi/lo split operands (3 MFMA terms), fp32 accumulation",
+                      "fp32": "fp32 operands, fp32 accumulation"}[prec],
         "data": "synthetic",
-        "config": {"workload": "spin256s", "segment_samples": w.n, "fs": w.fs, "f_low": w.f_low,
-                   "templates": nt, "references": 1, "taps": T, "threshold": w.threshold,
-                   "cluster_window": w.window, "fir_form": prec},
+        "config": {"workload": w.name, "segment_samples": w.n, "fs": w.fs, "f_low": w.f_low, "templates": nt,
+                   "references": nsb, "taps": sorted(set(sb.taps for sb in bank.subbanks))
+                   if multi else bank.subbanks[0].taps, "threshold": w.threshold, "cluster_window": w.window,
+                   "fir_form": prec, "segment_graph": multi},
         "stages_ms": stages, "triggers": ntrig,
         "tap_construction": {"templates_per_s": taps_per_s, "gpu_ms": tap_timing["taps_ms"]},
-        "roofline": roofline, "compare": compare, "parity": parity, "cpu_baseline": cpu,
+        "autotune": tune, "roofline": roofline, "compare": compare, "parity": parity, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def oracle_sample(args, w, bank, psd, seg, hrefs, s, out, cap, eager_step, prec, np, synth):
+    """Parity of a seeded template sample against the FP64 oracle, and the
+    oracle's own rate on this host (the CPU baseline)."""
+    from oracle import cluster as ocl
+    from oracle import pipeline as orc
+    from oracle import taps as otaps
+    from paper_2601_18835_amd import rfd
+    from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec
+    nt = bank.n_templates
+    rng = np.random.default_rng(2601)
+    pick = [seg.inj_template] + list(rng.choice(nt, size=max(0, args.cpu_sample - 1), replace=False))
+    sample = sorted(set(int(j) for j in pick))
+    sbi = [bank.subbank_of(j) for j in sample]
+    Hs = synth.template_batch(w, [bank.params(j) for j in sample])
+    p = orc.prepare(psd, seg.data, w.fs, w.f_low)
+    tts = []
+    grams = {}
+    for i, j in enumerate(sample):
+        sb = bank.subbanks[sbi[i]]
+        if sbi[i] not in grams:
+            grams[sbi[i]] = otaps.gram(hrefs[sbi[i]], p.w, sb.taps)
+        tts.append(orc.make_taps(p, Hs[i], hrefs[sbi[i]], sb.taps, sb.k0, M=grams[sbi[i]]))
+    # timed oracle leg: dechirp of the references involved + direct-sum FIR of the sample
+    c0, w0 = time.process_time(), time.perf_counter()
+    p2 = orc.prepare(psd, seg.data, w.fs, w.f_low)
+    refs = {b: orc.dechirp(p2, hrefs[b]) for b in sorted(set(sbi))}
+    zs = [orc.ratio_snr(refs[sbi[i]], tts[i]) for i in range(len(sample))]
+    wall = time.perf_counter() - w0
+    cpu_t = time.process_time() - c0
+    taps_desc = sorted(set(bank.subbanks[b].taps for b in sbi))
+    cpu = {"value": len(sample) * w.n / wall, "unit": "template*samples/s",
+           "cores": max(1, int(round(cpu_t / wall))), "kind": "oracle",
+           "sample": f"{len(sample)} of {nt} templates (seeded, incl. the injected one) over the full {w.n}-sample "
+                     f"segment: FP64 dechirp of their {len(refs)} reference(s) + direct-sum FIR ({taps_desc} taps); "
+                     f"taps built outside the timing", "seconds": round(wall, 2)}
+    log(f"cpu oracle: {cpu['value']:.3g} t*s/s on {cpu['cores']} core(s), {wall:.1f} s")
+    ntr = eager_step(prec)
+    trig = rfd.triggers_to_numpy(out, min(ntr, cap))
+    amb = mism = cmp = 0
+    dmax = 0.0
+    for i, j in enumerate(sample):
+        rho = np.abs(zs[i])
+        want = {sm // w.window: (sm, r) for sm, r in ocl.cluster(rho, w.threshold, w.window)}
+        got = {int(t["sample"]) // w.window: (int(t["sample"]), float(t["rho"])) for t in trig[trig["tmpl"] == j]}
+        fl = ocl.window_ambiguity(rho, w.threshold, w.window, 1e-3)
+        for q in range(len(fl)):
+            if fl[q]:
+                amb += 1
+                continue
+            cmp += 1
+            if (q in want) != (q in got) or (q in want and want[q][0] != got[q][0]):
+                mism += 1
+            elif q in want:
+                dmax = max(dmax, abs(want[q][1] - got[q][1]))
+    # every sample of the sampled templates through the same kernels (validation mode), one
+    # sub-bank per sampled template on its own reference
+    specs = [SubBankSpec(i, bank.subbanks[sbi[i]].taps, bank.subbanks[sbi[i]].k0, 1) for i in range(len(sample))]
+    s2 = RatioFilterSearch(psd, w.f_low, w.fs, w.n, specs, max_refs=len(sample))
+    for i in range(len(sample)):
+        s2.set_reference(i, hrefs[sbi[i]])
+        s2.make_taps(i, Hs[i:i + 1])
+    s2.set_segment(seg.data)
+    s2.dechirp_all()
+    full = {}
+    for form in ("bf16x3", "fp32", "fp16x3"):
+        buf, n = s2.filter(form, 0.0, 1, len(sample) * w.n)
+        tv = rfd.triggers_to_numpy(buf, n)
+        r = np.zeros((len(sample), w.n))
+        r[tv["tmpl"], tv["sample"]] = tv["rho"]
+        full[form] = float(max(np.max(np.abs(r[i] - np.abs(zs[i]))) for i in range(len(sample))))
+    s2.close()
+    parity = {"templates": sample, "windows_compared": cmp, "ambiguous": amb, "mismatches": mism,
+              "max_drho_at_triggers": dmax, "max_drho_full_series": full,
+              "tolerance": {"bf16x3": 1e-3, "fp16x3": 1e-3, "fp32": 1e-5}}
+    log(f"parity: {parity}")
+    return parity, cpu
 
 
 if __name__ == "__main__":

@@ -569,7 +569,7 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
     if (rc) return rc;
     t.work64_cap = need_w;
   }
-  size_t need_b = (size_t)chunk * T;
+  size_t need_b = (size_t)count * T;          // right-hand sides of the whole call
   if (t.bvec_cap < need_b) {
     RFD_HIP(hipStreamSynchronize(p.stream));
     dfree(t.bvec);
@@ -598,12 +598,16 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
     int rc = stage_begin(p, kStTaps);
     if (rc) return rc;
   }
+  // correlation FFTs in chunks bounded by the FP64 scratch, then one solve
+  // launch over every template of the call
   for (int64_t c0 = 0; c0 < count; c0 += chunk) {
     int64_t cn = std::min(chunk, count - c0);
-    int rc = launch_corr64(p, t, method == RFD_TAPS_LS ? 0 : 2, h_ref, h_tmpl + 2 * c0 * p.nb, cn, T, s.k0, t.bvec,
-                           T);
+    int rc = launch_corr64(p, t, method == RFD_TAPS_LS ? 0 : 2, h_ref, h_tmpl + 2 * c0 * p.nb, cn, T, s.k0,
+                           t.bvec + c0 * T, T);
     if (rc) return rc;
-    rc = taps_solve_and_pack(p, t, subbank, first + c0, cn, method);
+  }
+  {
+    int rc = taps_solve_and_pack(p, t, subbank, first, count, method);
     if (rc) return rc;
   }
   {

@@ -1,0 +1,107 @@
+"""Pins for the FP64 surrogate oracle: gradients against central finite
+differences, Adam against a hand-computed first step, whitening round trip,
+the basis against the Eckart-Young optimum, the match bounds."""
+import numpy as np
+
+from oracle import surrogate as sg
+
+RNG = np.random.default_rng(99)
+
+
+def small_net():
+    params = sg.init_params([4, 7, 6, 5], RNG)
+    params = [(W, RNG.standard_normal(b.shape) * 0.1) for W, b in params]
+    x = RNG.uniform(-1, 1, size=(9, 4))
+    c = RNG.standard_normal((9, 5))
+    return params, x, c
+
+
+def test_gradients_match_central_finite_differences():
+    params, x, c = small_net()
+    loss, grads = sg.loss_and_grads(params, x, c)
+    h = 1e-6
+    for li in range(3):
+        for wi in range(2):
+            P = params[li][wi]
+            G = grads[li][wi]
+            it = np.nditer(P, flags=["multi_index"])
+            for _ in it:
+                idx = it.multi_index
+                old = P[idx]
+                P[idx] = old + h
+                lp, _ = sg.loss_and_grads(params, x, c)
+                P[idx] = old - h
+                lm, _ = sg.loss_and_grads(params, x, c)
+                P[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - G[idx]) <= 1e-7 * max(1.0, abs(fd)), (li, wi, idx, fd, G[idx])
+
+
+def test_silu_derivative():
+    z = np.linspace(-6, 6, 101)
+    h = 1e-6
+    assert np.allclose((sg.silu(z + h) - sg.silu(z - h)) / (2 * h), sg.silu_grad(z), atol=1e-9)
+    assert sg.silu(0.0) == 0.0 and abs(sg.silu(50.0) - 50.0) < 1e-12
+
+
+def test_adam_first_step_moves_each_weight_by_lr_times_sign():
+    params, x, c = small_net()
+    loss, grads = sg.loss_and_grads(params, x, c)
+    new, st = sg.adam_step(params, grads, sg.adam_init(params), lr=1e-3)
+    for (P, _), (Q, _), (G, _) in zip(params, new, grads):
+        # bias-corrected first step: m_hat = g, v_hat = g^2  ->  delta = -lr g / (|g| + eps)
+        want = -1e-3 * G / (np.abs(G) + 1e-8)
+        assert np.allclose(Q - P, want, atol=1e-15)
+    assert st[0] == 1
+
+
+def test_training_reduces_loss():
+    params = sg.init_params([4, 32, 32, 3], RNG)
+    x = RNG.uniform(-1, 1, size=(64, 4))
+    c = np.stack([np.sin(x[:, 0]) + x[:, 1], x[:, 2] * x[:, 3], np.cos(x.sum(1))], axis=1)
+    st = sg.adam_init(params)
+    l0, _ = sg.loss_and_grads(params, x, c)
+    for _ in range(300):
+        l, g = sg.loss_and_grads(params, x, c)
+        params, st = sg.adam_step(params, g, st, lr=3e-3)
+    assert l < 0.05 * l0
+
+
+def test_whitening_round_trip_and_norm():
+    T = 12
+    A = RNG.standard_normal((T, T)) + 1j * RNG.standard_normal((T, T))
+    M = A @ np.conj(A).T + T * np.eye(T)
+    L = np.linalg.cholesky(M)
+    a = RNG.standard_normal((5, T)) + 1j * RNG.standard_normal((5, T))
+    x = sg.whiten(a, L)
+    assert np.allclose(np.linalg.norm(x, axis=1), 1.0)
+    # ||L^H a||^2 = a^H M a
+    v = a @ np.conj(L)
+    assert np.allclose(np.sum(np.abs(v) ** 2, axis=1), np.real(np.einsum("ij,jk,ik->i", np.conj(a), M, a)))
+    back = sg.unwhiten(x, L)
+    ratio = back / a
+    assert np.allclose(ratio, ratio[:, :1])            # same taps up to one real positive scale per row
+    assert np.allclose(ratio.imag, 0, atol=1e-12) and (ratio.real > 0).all()
+
+
+def test_basis_is_the_best_rank_k_subspace():
+    X = RNG.standard_normal((200, 30)) @ RNG.standard_normal((30, 30))
+    B = sg.basis_svd(X, 8)
+    assert np.allclose(B.T @ B, np.eye(8), atol=1e-12)
+    err_opt = np.linalg.norm(X - X @ B @ B.T) ** 2
+    s = np.linalg.svd(X, compute_uv=False)
+    assert abs(err_opt - np.sum(s[8:] ** 2)) <= 1e-9 * np.sum(s ** 2)     # Eckart-Young
+    Q, _ = np.linalg.qr(RNG.standard_normal((30, 8)))
+    assert np.linalg.norm(X - X @ Q @ Q.T) ** 2 >= err_opt
+
+
+def test_match_bounds():
+    T = 10
+    A = RNG.standard_normal((T, T)) + 1j * RNG.standard_normal((T, T))
+    M = A @ np.conj(A).T
+    a = RNG.standard_normal((4, T)) + 1j * RNG.standard_normal((4, T))
+    assert np.allclose(sg.match(a, a, M), 1.0)
+    assert np.allclose(sg.match(3j * a, a, M), 1.0)           # phase and scale free
+    b = RNG.standard_normal((4, T)) + 1j * RNG.standard_normal((4, T))
+    m = sg.match(b, a, M)
+    assert (m <= 1.0 + 1e-12).all() and (m >= 0).all()

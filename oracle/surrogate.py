@@ -4,7 +4,13 @@ Test infrastructure only (see package header).
 
 The surrogate maps template parameters p (4 numbers, scaled to [-1, 1]) to
 coefficients on an orthonormal basis of whitened ratio taps:
-    x(a)   = [Re v; Im v] / ||v||,   v = L^H a,  M + lam I = L L^H
+    a'     = a exp(-i arg z),  z = ((M + lam I) a)[-k0]
+             (a global phase, so that the fitted template's zero-lag overlap
+             with the reference, the right-hand side b[-k0] of Sec. V.A's
+             normal equations, is real and positive; the ratio filter's |z|
+             and every match are unchanged by it, and it removes the fast
+             phase rotation of the taps across a sub-bank),
+    x(a')  = [Re v; Im v] / ||v||,   v = L^H a',  M + lam I = L L^H
              (whitening makes ||x_hat - x||^2 the fitted-template mismatch
              proxy of Sec. V.A's chi^2 metric),
     c      = B^T x                        (B: 2T x K, orthonormal columns),
@@ -88,6 +94,13 @@ def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 def adam_init(params):
     flat = [q for pair in params for q in pair]
     return (0, [np.zeros_like(q) for q in flat], [np.zeros_like(q) for q in flat])
+
+
+def phase_align(a, M, lam, k0):
+    """a exp(-i arg z) with z = ((M + lam I) a)[-k0] (a: [n, T] complex)."""
+    T = M.shape[0]
+    z = (a @ (M + lam * np.eye(T)).T)[:, -k0]
+    return a * np.exp(-1j * np.angle(z))[:, None]
 
 
 def whiten(a, L):

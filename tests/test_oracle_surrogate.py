@@ -105,3 +105,29 @@ def test_match_bounds():
     b = RNG.standard_normal((4, T)) + 1j * RNG.standard_normal((4, T))
     m = sg.match(b, a, M)
     assert (m <= 1.0 + 1e-12).all() and (m >= 0).all()
+
+
+def test_phase_align_is_the_zero_lag_overlap_phase():
+    """For least-squares taps (M + lam I) a = b, so z = b[-k0], the weighted
+    zero-lag inner product sum_i w_i h_j conj(h_ref) of Eq. 1's weights: the
+    rotation follows from the spectra alone."""
+    from oracle import spectral, taps as tp
+    from synth.waveforms import WaveformParams, taylorf2
+    from synth.psd import psd_array
+    n, fs, f_low, T = 8192, 2048.0, 20.0, 32
+    k0 = -(T // 2)
+    w = spectral.psd_weights(psd_array(n, fs), n, fs, f_low)
+    h_ref = taylorf2(WaveformParams(1.4, 1.4), n, fs, f_low)
+    M = tp.gram(h_ref, w, T)
+    lam = tp.DEFAULT_RIDGE_EPS * M[0, 0].real
+    hs = [taylorf2(WaveformParams(1.4 + 0.01 * k, 1.39, e0=0.02 * k), n, fs, f_low) for k in range(4)]
+    a = np.stack([tp.ls_taps_normal(h, h_ref, w, T, k0, M=M) for h in hs])
+    al = sg.phase_align(a, M, lam, k0)
+    zero_lag = np.array([np.sum(w * h * np.conj(h_ref)) for h in hs])
+    rot = al / a
+    assert np.allclose(np.abs(rot), 1.0, atol=1e-12)
+    assert np.allclose(rot, rot[:, :1], atol=1e-12)
+    assert np.allclose(rot[:, 0], np.exp(-1j * np.angle(zero_lag)), atol=1e-9)
+    z = (al @ (M + lam * np.eye(T)).T)[:, -k0]
+    assert np.allclose(z.imag, 0, atol=1e-9 * np.abs(z).max()) and (z.real > 0).all()
+    assert np.allclose(sg.match(al, a, M), 1.0, atol=1e-12)

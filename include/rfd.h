@@ -317,6 +317,91 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
 int rfd_segment_graph_launch(rfd_graph* graph, int64_t* n_out);
 int rfd_graph_destroy(rfd_graph* graph);
 
+/*
+ * Learned tap surrogate (an extension to the method; the paper does not
+ * define it).  A small MLP (4 -> hidden -> hidden -> n_basis, SiLU, BF16
+ * weights, FP32 accumulation) maps scaled template parameters to
+ * coefficients on an orthonormal basis of whitened ratio taps of ONE
+ * sub-bank.  Each exact tap set a (Sec. V.A) is first given one global
+ * phase so that z = ((M + lam I) a)[-k0] -- the normal equations'
+ * right-hand side at zero lag, the weighted zero-lag overlap of template and
+ * reference -- is real and positive (|z| of Eq. 3 and every match ignore a
+ * global tap phase), then whitened: x = [Re v; Im v]/||v||, v = L^H a, with
+ * L the sub-bank's Cholesky factor of M + lam I, so ||x_hat - x||^2 is a
+ * mismatch proxy of the fitted template.  The exact taps are the training
+ * data, the fallback and the judge of the SNR loss (rfd_taps_match).
+ *
+ * rfd_surrogate_create     whitens the exact taps of every template of
+ *                          `subbank` in `taps` (all made by the LS route;
+ *                          RFD_E_STATE otherwise).  The surrogate keeps
+ *                          pointers to plan and taps: both must outlive it.
+ *                          n_basis in [1, min(2T, 1024)], hidden in
+ *                          [1, 4096]; seed fixes initial weights, the basis
+ *                          start and the shuffles.
+ * rfd_surrogate_fit_basis  subspace iteration (iters in [1, 100]) for the
+ *                          basis; *captured_out (host, may be NULL) = mean
+ *                          ||B^T x||^2 over the training set (<= 1).
+ * rfd_surrogate_train      Adam (beta 0.9/0.999, eps 1e-8) on mean
+ *                          ||c_hat - c||^2 over whole batches of a seeded
+ *                          shuffle; params: dev float [count][4] (count =
+ *                          training templates, same order); batch in
+ *                          [1, 1024]; repeated calls continue the same
+ *                          optimiser state (a learning-rate schedule is a
+ *                          sequence of calls); loss_out: host float
+ *                          [epochs] (mean loss per epoch) or NULL.
+ * rfd_surrogate_loss_grad  loss and gradients (dev float [n_params], order
+ *                          W1, b1, W2, b2, W3, b3; W row-major [out][in])
+ *                          for the first n (<= 1024) rows of params;
+ *                          targets dev [n][n_basis] or NULL for the
+ *                          training targets.  The forward pass uses the
+ *                          BF16-rounded weights, as training does.
+ * rfd_surrogate_get_state  host copies of weights / basis [n_basis][2T] /
+ *                          targets [count][n_basis] (each may be NULL);
+ *                          sizes (host int64[6], may be NULL): n_params,
+ *                          basis, targets, 2T, n_basis, hidden.
+ * rfd_surrogate_set_state  replace weights and/or basis (host arrays, same
+ *                          layouts; either may be NULL, not both); new
+ *                          weights restart Adam (moments and step zeroed),
+ *                          a new basis recomputes the training targets.
+ * rfd_surrogate_make_taps  taps for templates first..first+count-1 of a
+ *                          sub-bank of `target` with the same reference, T
+ *                          and k0, from params dev float [count][4]:
+ *                          c_hat -> x_hat = B^T c_hat -> a = L^-H v, then
+ *                          sigma_fit and packing as rfd_make_taps.  Marks
+ *                          the templates made.
+ * rfd_taps_match           dev double [count]: |a^H M b| / sqrt(a^H M a
+ *                          b^H M b) between the FP64 taps of two objects of
+ *                          one plan (same sub-bank index, T and size); M
+ *                          from `a`'s sub-bank.
+ * rfd_taps_fallback        copies the exact taps of `exact` into `target`
+ *                          for every template of the range whose match
+ *                          (dev double [count], e.g. from rfd_taps_match)
+ *                          is below min_match or NaN, and re-normalises
+ *                          and packs them; *n_fallback_out (host, may be
+ *                          NULL) = templates replaced.  RFD_E_STATE if a
+ *                          replaced template has no exact taps.
+ * rfd_surrogate_destroy    frees the surrogate (NULL is a no-op).
+ * All calls enqueue on the plan's stream and return after it drained,
+ * except rfd_taps_match, which only enqueues.
+ */
+typedef struct rfd_surrogate rfd_surrogate;
+int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_t n_basis, int32_t hidden,
+                         uint64_t seed, rfd_surrogate** out);
+int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_out);
+int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs, int32_t batch, float lr,
+                        float* loss_out);
+int rfd_surrogate_loss_grad(rfd_surrogate* sur, const float* params, const float* targets, int32_t n, float* grads,
+                            double* loss_out);
+int rfd_surrogate_get_state(rfd_surrogate* sur, float* weights, float* basis, float* targets, int64_t* sizes);
+int rfd_surrogate_set_state(rfd_surrogate* sur, const float* weights, const float* basis);
+int rfd_surrogate_make_taps(rfd_surrogate* sur, const float* params, rfd_taps* target, int32_t subbank,
+                            int64_t first, int64_t count);
+int rfd_taps_match(const rfd_taps* a, const rfd_taps* b, int32_t subbank, int64_t first, int64_t count,
+                   double* match_out);
+int rfd_taps_fallback(rfd_taps* target, const rfd_taps* exact, int32_t subbank, int64_t first, int64_t count,
+                      const double* match, double min_match, int64_t* n_fallback_out);
+int rfd_surrogate_destroy(rfd_surrogate* sur);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* rfd_last_error(void);
 

@@ -1,0 +1,853 @@
+// Learned tap surrogate (an extension; the paper mentions ML only as a
+// downstream layer): a small MLP maps template parameters to coefficients on
+// an orthonormal basis of whitened ratio taps, so dense banks get taps
+// without waveforms.  Everything below runs on the device:
+//   alignment   a <- a e^{-i arg z}, z = ((M + lam I) a)[-k0]: the zero-lag
+//               overlap of fitted template and reference made real positive
+//               (|z| of the filter and every match ignore a global phase),
+//   whitening   x = [Re v; Im v]/||v||, v = L^H a  (M + lam I = L L^H, so
+//               ||x_hat - x||^2 is the fitted-template mismatch proxy),
+//   basis       subspace iteration Q <- orth(X^T X Q) with two-pass
+//               Gram-Schmidt, K orthonormal directions (B, stored K x D),
+//   targets     c = X B^T... (coefficients of each training tap set),
+//   MLP         4 -> H -> H -> K, SiLU; BF16 weights, FP32 accumulation,
+//               hand-written forward / backward / Adam kernels,
+//   inference   params -> c_hat -> x_hat = c_hat B -> a = L^-H v -> the
+//               usual sigma_fit normalisation and MFMA operand packing.
+// The exact taps (Sec. V.A) stay the training data, the fallback and the
+// judge: rfd_taps_match gives the fitted templates' normalised overlap.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "dev_common.h"
+#include "rfd_internal.h"
+
+namespace rfd {
+
+int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
+
+// ------------------------------------------------------------------ GEMM
+__device__ __forceinline__ float ld_op(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ld_op(const uint16_t* p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
+
+// C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation.
+// op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __restrict__ A, int lda, int ta,
+                                            const TB* __restrict__ B, int ldb, int tb, float* __restrict__ C,
+                                            int ldc, int accumulate) {
+  __shared__ float As[16][68];
+  __shared__ float Bs[16][68];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;                 // 1024 elements of each 16 x 64 tile
+      const int kk = e >> 6, mm = e & 63;
+      const int gm = m0 + mm, gk = k0 + kk;
+      float av = 0.f;
+      if (gm < M && gk < K) av = ta ? ld_op(A, (int64_t)gk * lda + gm) : ld_op(A, (int64_t)gm * lda + gk);
+      As[kk][mm] = av;
+      const int gn = n0 + mm;
+      float bv = 0.f;
+      if (gn < N && gk < K) bv = tb ? ld_op(B, (int64_t)gn * ldb + gk) : ld_op(B, (int64_t)gk * ldb + gn);
+      Bs[kk][mm] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + ty * 4 + i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tx * 4 + j;
+      if (gn >= N) continue;
+      float v = acc[i][j];
+      if (accumulate) v += C[(int64_t)gm * ldc + gn];
+      C[(int64_t)gm * ldc + gn] = v;
+    }
+  }
+}
+
+template <typename TA, typename TB>
+static int gemm(hipStream_t st, int M, int N, int K, const TA* A, int lda, int ta, const TB* B, int ldb, int tb,
+                float* C, int ldc, int accumulate = 0) {
+  if (M <= 0 || N <= 0) return RFD_OK;
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, accumulate);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+// ------------------------------------------------------- elementwise
+__device__ __forceinline__ float silu_f(float z) { return z / (1.f + __expf(-z)); }
+__device__ __forceinline__ float silu_g(float z) {
+  const float s = 1.f / (1.f + __expf(-z));
+  return s * (1.f + z * (1.f - s));
+}
+
+__global__ void k_bias_act(float* __restrict__ Z, float* __restrict__ Hout, const float* __restrict__ b, int64_t n,
+                           int H, int act) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * H; e += (int64_t)gridDim.x * blockDim.x) {
+    const float z = Z[e] + b[e % H];
+    Z[e] = z;
+    if (act) Hout[e] = silu_f(z);
+  }
+}
+
+__global__ void k_silu_bwd(float* __restrict__ dH, const float* __restrict__ Z, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dH[e] *= silu_g(Z[e]);
+}
+
+// dY = 2 (Y - C) / nb, and the per-block sums of squares (deterministic order)
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const float* __restrict__ Cb,
+                                            float* __restrict__ dY, int64_t n, float scale,
+                                            double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const float r = Y[e] - Cb[e];
+    dY[e] = 2.f * r * scale;
+    acc += (double)r * r;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partial, int n, double scale, double* __restrict__ out,
+                               int accumulate) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += partial[i];
+  s *= scale;
+  *out = accumulate ? *out + s : s;
+}
+
+__global__ void k_colsum(const float* __restrict__ X, int64_t n, int H, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= H) return;
+  float s = 0.f;
+  for (int64_t i = 0; i < n; ++i) s += X[i * H + j];
+  out[j] = s;
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (uint16_t)bf16_bits(w[i]);
+}
+
+__global__ void k_gather(const float* __restrict__ P, const float* __restrict__ C, const int32_t* __restrict__ idx,
+                         int nb, int K, float* __restrict__ Pb, float* __restrict__ Cb) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb * (4 + K); e += gridDim.x * blockDim.x) {
+    const int r = e / (4 + K), c = e % (4 + K);
+    const int64_t src = idx[r];
+    if (c < 4) Pb[r * 4 + c] = P[src * 4 + c];
+    else Cb[(int64_t)r * K + (c - 4)] = C[src * K + (c - 4)];
+  }
+}
+
+// splitmix64 (Steele, Lea, Flood 2014) of (seed, index) -> uniform in (-1, 1)
+__device__ __forceinline__ float hash_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (float)((double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+}
+
+__global__ void k_random(float* __restrict__ Q, int64_t n, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    Q[i] = hash_uniform(seed, (uint64_t)i);
+}
+
+// ------------------------------------------------------ whitening & basis
+// Phase alignment, then whitening, one workgroup per tap set:
+//   z   = ((M + lam I) a)[i0] = sum_k g[i0 - k] a_k + lam a_i0,  i0 = -k0
+//         (the zero-lag tap; clamped into [0, T) when the window misses lag
+//         0), lam = eps g[0]; g at negative lags is conj(g) at positive ones,
+//   v   = U a e^{-i arg z}, U = L^H (column-major upper),
+//   x   = [Re v; Im v] / ||v||.
+__global__ __launch_bounds__(256) void k_whiten(const double2* __restrict__ a, int Tp,
+                                              const double2* __restrict__ U, const double2* __restrict__ g,
+                                              double eps, int i0, int T, float* __restrict__ X) {
+  const double lam = eps * g[0].x;
+  extern __shared__ double2 sa[];
+  __shared__ double red[2][256];
+  const double2* aj = a + (int64_t)blockIdx.x * Tp;
+  for (int i = threadIdx.x; i < T; i += 256) sa[i] = aj[i];
+  __syncthreads();
+  double zr = 0.0, zi = 0.0;
+  for (int k = threadIdx.x; k < T; k += 256) {
+    const int d = i0 - k;
+    double2 gk = d >= 0 ? g[d] : cconj(g[-d]);
+    if (d == 0) gk.x += lam;
+    const double2 t = cmul(gk, sa[k]);
+    zr += t.x;
+    zi += t.y;
+  }
+  red[0][threadIdx.x] = zr;
+  red[1][threadIdx.x] = zi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double zabs = sqrt(red[0][0] * red[0][0] + red[1][0] * red[1][0]);
+  const double2 rot = zabs > 0.0 ? make_double2(red[0][0] / zabs, -red[1][0] / zabs) : make_double2(1.0, 0.0);
+  __syncthreads();
+  float* xj = X + (int64_t)blockIdx.x * 2 * T;
+  double nrm = 0.0;
+  for (int i = threadIdx.x; i < T; i += 256) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int k = i; k < T; ++k) s = cadd(s, cmul(U[(int64_t)k * T + i], sa[k]));
+    s = cmul(s, rot);
+    xj[i] = (float)s.x;
+    xj[T + i] = (float)s.y;
+    nrm += s.x * s.x + s.y * s.y;
+  }
+  red[0][threadIdx.x] = nrm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[0][threadIdx.x] += red[0][threadIdx.x + o];
+    __syncthreads();
+  }
+  const float inv = (float)(1.0 / sqrt(red[0][0]));
+  for (int i = threadIdx.x; i < 2 * T; i += 256) xj[i] *= inv;
+}
+
+// Orthonormalise the K rows of Q (K x D) by two passes of Gram-Schmidt, one workgroup.
+__global__ __launch_bounds__(1024) void k_orthonormalise(float* __restrict__ Q, int K, int D) {
+  __shared__ double red[1024];
+  for (int k = 0; k < K; ++k) {
+    float* qk = Q + (int64_t)k * D;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < k; ++j) {
+        const float* qj = Q + (int64_t)j * D;
+        double s = 0.0;
+        for (int i = threadIdx.x; i < D; i += 1024) s += (double)qj[i] * qk[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = 512; o > 0; o >>= 1) {
+          if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+          __syncthreads();
+        }
+        const double r = red[0];
+        __syncthreads();
+        for (int i = threadIdx.x; i < D; i += 1024) qk[i] = (float)(qk[i] - r * qj[i]);
+        __syncthreads();
+      }
+    }
+    double s = 0.0;
+    for (int i = threadIdx.x; i < D; i += 1024) s += (double)qk[i] * qk[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    const double inv = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < D; i += 1024) qk[i] = (float)(qk[i] * inv);
+    __syncthreads();
+  }
+}
+
+// a_j = U^-1 v_j (back substitution, U = L^H upper), v_j = x_j[:T] + i x_j[T:].
+__global__ __launch_bounds__(256) void k_unwhiten(const float* __restrict__ Xh, const double2* __restrict__ U, int T,
+                                                double2* __restrict__ a, int Tp) {
+  extern __shared__ double2 sh[];
+  double2* y = sh;
+  double2* x = sh + T;
+  const float* xj = Xh + (int64_t)blockIdx.x * 2 * T;
+  for (int i = threadIdx.x; i < T; i += 256) y[i] = make_double2((double)xj[i], (double)xj[T + i]);
+  __syncthreads();
+  for (int j = T - 1; j >= 0; --j) {
+    const double2* col = U + (int64_t)j * T;
+    const double inv = 1.0 / col[j].x;
+    const double2 aj = make_double2(y[j].x * inv, y[j].y * inv);
+    if (threadIdx.x == 0) x[j] = aj;
+    for (int i = threadIdx.x; i < j; i += 256) y[i] = csub(y[i], cmul(col[i], aj));
+    __syncthreads();
+  }
+  double2* ao = a + (int64_t)blockIdx.x * Tp;
+  for (int i = threadIdx.x; i < T; i += 256) ao[i] = x[i];
+}
+
+// |a^H M b| / sqrt(a^H M a b^H M b), M[l,k] = g[l-k]; one workgroup per template.
+__global__ __launch_bounds__(256) void k_match(const double2* __restrict__ A, const double2* __restrict__ Bt, int Tp,
+                                             int T, const double2* __restrict__ g, double* __restrict__ out) {
+  extern __shared__ double2 sh[];
+  double2* av = sh;
+  double2* bv = sh + T;
+  double2* gv = sh + 2 * T;
+  __shared__ double red[4][256];
+  const double2* aj = A + (int64_t)blockIdx.x * Tp;
+  const double2* bj = Bt + (int64_t)blockIdx.x * Tp;
+  for (int i = threadIdx.x; i < T; i += 256) {
+    av[i] = aj[i];
+    bv[i] = bj[i];
+    gv[i] = g[i];
+  }
+  __syncthreads();
+  double saa = 0.0, sbb = 0.0, sabr = 0.0, sabi = 0.0;
+  for (int l = threadIdx.x; l < T; l += 256) {
+    double2 ma = make_double2(0.0, 0.0), mb = make_double2(0.0, 0.0);
+    for (int k = 0; k < T; ++k) {
+      const int d = l - k;
+      const double2 gk = d >= 0 ? gv[d] : cconj(gv[-d]);
+      ma = cadd(ma, cmul(gk, av[k]));
+      mb = cadd(mb, cmul(gk, bv[k]));
+    }
+    saa += av[l].x * ma.x + av[l].y * ma.y;        // Re(conj(a_l) (M a)_l)
+    sbb += bv[l].x * mb.x + bv[l].y * mb.y;
+    sabr += av[l].x * mb.x + av[l].y * mb.y;       // conj(a_l) (M b)_l
+    sabi += av[l].x * mb.y - av[l].y * mb.x;
+  }
+  red[0][threadIdx.x] = saa;
+  red[1][threadIdx.x] = sbb;
+  red[2][threadIdx.x] = sabr;
+  red[3][threadIdx.x] = sabi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(red[2][0] * red[2][0] + red[3][0] * red[3][0]) / sqrt(red[0][0] * red[1][0]);
+}
+
+// ------------------------------------------------------------- state
+struct Surrogate {
+  Plan* plan = nullptr;
+  Taps* taps = nullptr;
+  int sb = 0, T = 0, Tp = 0, D = 0, K = 0, H = 0;
+  int64_t n = 0;                       // training tap sets
+  float* X = nullptr;                  // [n x D] whitened training taps
+  float* Bt = nullptr;                 // [K x D] orthonormal basis
+  float* C = nullptr;                  // [n x K] target coefficients
+  float* Q2 = nullptr;                 // [n x K] scratch (X B^T during iteration)
+  // parameters, flat: W1 [H x 4], b1 [H], W2 [H x H], b2 [H], W3 [K x H], b3 [K]
+  int64_t np = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t* wbf = nullptr;             // BF16 copy used by every GEMM
+  int64_t step = 0;
+  int nb = 0;                          // batch capacity
+  float *Pb = nullptr, *Cb = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr,
+        *dY = nullptr, *dA = nullptr, *dB = nullptr;
+  int32_t* idx = nullptr;
+  double* partial = nullptr;
+  double* loss = nullptr;
+  uint64_t seed = 0;
+};
+
+template <typename T>
+static int salloc(T** p, size_t n) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(RFD_E_NOMEM, "surrogate: hipMalloc failed");
+  }
+  return RFD_OK;
+}
+template <typename T>
+static void sfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+static void sur_free(Surrogate& s) {
+  sfree(s.X); sfree(s.Bt); sfree(s.C); sfree(s.Q2); sfree(s.w); sfree(s.g); sfree(s.m); sfree(s.v); sfree(s.wbf);
+  sfree(s.Pb); sfree(s.Cb); sfree(s.Z1); sfree(s.H1); sfree(s.Z2); sfree(s.H2); sfree(s.Y); sfree(s.dY);
+  sfree(s.dA); sfree(s.dB); sfree(s.idx); sfree(s.partial); sfree(s.loss);
+}
+
+// dynamic LDS a launch may request on the current device
+static int lds_fits(size_t bytes) {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 0;
+  return bytes <= (size_t)v;
+}
+
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+
+static int refresh_bf16(Surrogate& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(s.np)), dim3(256), 0, st, s.w, s.wbf, s.np);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+// forward pass for n rows (n <= nb) of parameters P -> Y (and the activations)
+static int forward(Surrogate& s, hipStream_t st, const float* P, int n) {
+  int rc;
+  const int H = s.H, K = s.K;
+  if ((rc = gemm<float, uint16_t>(st, n, H, 4, P, 4, 0, s.wbf + s.oW1, 4, 1, s.Z1, H))) return rc;
+  hipLaunchKernelGGL(k_bias_act, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.Z1, s.H1, s.w + s.ob1,
+                     (int64_t)n, H, 1);
+  RFD_CHECK_LAUNCH();
+  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.H1, H, 0, s.wbf + s.oW2, H, 1, s.Z2, H))) return rc;
+  hipLaunchKernelGGL(k_bias_act, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.Z2, s.H2, s.w + s.ob2,
+                     (int64_t)n, H, 1);
+  RFD_CHECK_LAUNCH();
+  if ((rc = gemm<float, uint16_t>(st, n, K, H, s.H2, H, 0, s.wbf + s.oW3, H, 1, s.Y, K))) return rc;
+  hipLaunchKernelGGL(k_bias_act, dim3(grid_for((int64_t)n * K)), dim3(256), 0, st, s.Y, (float*)nullptr, s.w + s.ob3,
+                     (int64_t)n, K, 0);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+// loss (added to *s.loss when accumulate) and gradients into s.g for n rows (Pb, Cb)
+static int backward(Surrogate& s, hipStream_t st, const float* P, const float* Cb, int n, int accumulate_loss,
+                    double loss_scale) {
+  int rc;
+  const int H = s.H, K = s.K;
+  const int64_t ny = (int64_t)n * K;
+  const int nblk = std::min<int>(grid_for(ny), 256);
+  hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, st, s.Y, Cb, s.dY, ny, 1.f / n, s.partial);
+  RFD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, loss_scale, s.loss, accumulate_loss);
+  RFD_CHECK_LAUNCH();
+  // layer 3
+  if ((rc = gemm<float, float>(st, K, H, n, s.dY, K, 1, s.H2, H, 0, s.g + s.oW3, H))) return rc;
+  hipLaunchKernelGGL(k_colsum, dim3((K + 255) / 256), dim3(256), 0, st, s.dY, (int64_t)n, K, s.g + s.ob3);
+  RFD_CHECK_LAUNCH();
+  if ((rc = gemm<float, uint16_t>(st, n, H, K, s.dY, K, 0, s.wbf + s.oW3, H, 0, s.dA, H))) return rc;
+  hipLaunchKernelGGL(k_silu_bwd, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.dA, s.Z2, (int64_t)n * H);
+  RFD_CHECK_LAUNCH();
+  // layer 2
+  if ((rc = gemm<float, float>(st, H, H, n, s.dA, H, 1, s.H1, H, 0, s.g + s.oW2, H))) return rc;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, s.dA, (int64_t)n, H, s.g + s.ob2);
+  RFD_CHECK_LAUNCH();
+  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.dA, H, 0, s.wbf + s.oW2, H, 0, s.dB, H))) return rc;
+  hipLaunchKernelGGL(k_silu_bwd, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.dB, s.Z1, (int64_t)n * H);
+  RFD_CHECK_LAUNCH();
+  // layer 1
+  if ((rc = gemm<float, float>(st, H, 4, n, s.dB, H, 1, P, 4, 0, s.g + s.oW1, 4))) return rc;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, s.dB, (int64_t)n, H, s.g + s.ob1);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+}  // namespace rfd
+
+using namespace rfd;
+
+struct rfd_surrogate { rfd::Surrogate s; };
+
+extern "C" {
+
+int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_t n_basis, int32_t hidden,
+                         uint64_t seed, rfd_surrogate** out) {
+  if (!out) return fail(RFD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!plan || !taps) return fail(RFD_E_INVALID, "NULL plan or taps");
+  Plan& p = plan->p;
+  Taps& t = taps->t;
+  if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
+  if (subbank < 0 || subbank >= (int)t.sb.size()) return fail(RFD_E_INVALID, "subbank out of range");
+  SubBankTaps& sb = t.sb[subbank];
+  if (sb.count < 2 || sb.made != sb.count) return fail(RFD_E_STATE, "training sub-bank needs >= 2 made tap sets");
+  if (!sb.U) return fail(RFD_E_STATE, "training taps must come from the least-squares route (Cholesky factor)");
+  if (n_basis < 1 || n_basis > 2 * sb.T || n_basis > 1024) return fail(RFD_E_INVALID, "n_basis out of range");
+  if (hidden < 1 || hidden > 4096) return fail(RFD_E_INVALID, "hidden out of range");
+  rfd_surrogate* h = new (std::nothrow) rfd_surrogate();
+  if (!h) return fail(RFD_E_NOMEM, "host allocation failed");
+  Surrogate& s = h->s;
+  s.plan = &p;
+  s.taps = &t;
+  s.sb = subbank;
+  s.T = sb.T;
+  s.Tp = sb.Tp;
+  s.D = 2 * sb.T;
+  s.K = n_basis;
+  s.H = hidden;
+  s.n = sb.count;
+  s.seed = seed;
+  s.nb = 1024;
+  const int H = s.H, K = s.K;
+  s.oW1 = 0;
+  s.ob1 = s.oW1 + (int64_t)H * 4;
+  s.oW2 = s.ob1 + H;
+  s.ob2 = s.oW2 + (int64_t)H * H;
+  s.oW3 = s.ob2 + H;
+  s.ob3 = s.oW3 + (int64_t)K * H;
+  s.np = s.ob3 + K;
+  int rc = RFD_OK;
+#define TRY(x) do { rc = (x); if (rc) { sur_free(s); delete h; return rc; } } while (0)
+  TRY(salloc(&s.X, (size_t)s.n * s.D));
+  TRY(salloc(&s.Bt, (size_t)K * s.D));
+  TRY(salloc(&s.C, (size_t)s.n * K));
+  TRY(salloc(&s.Q2, (size_t)s.n * K));
+  TRY(salloc(&s.w, (size_t)s.np));
+  TRY(salloc(&s.g, (size_t)s.np));
+  TRY(salloc(&s.m, (size_t)s.np));
+  TRY(salloc(&s.v, (size_t)s.np));
+  TRY(salloc(&s.wbf, (size_t)s.np));
+  TRY(salloc(&s.Pb, (size_t)s.nb * 4));
+  TRY(salloc(&s.Cb, (size_t)s.nb * K));
+  TRY(salloc(&s.Z1, (size_t)s.nb * H));
+  TRY(salloc(&s.H1, (size_t)s.nb * H));
+  TRY(salloc(&s.Z2, (size_t)s.nb * H));
+  TRY(salloc(&s.H2, (size_t)s.nb * H));
+  TRY(salloc(&s.Y, (size_t)s.nb * K));
+  TRY(salloc(&s.dY, (size_t)s.nb * K));
+  TRY(salloc(&s.dA, (size_t)s.nb * H));
+  TRY(salloc(&s.dB, (size_t)s.nb * H));
+  TRY(salloc(&s.idx, (size_t)s.nb));
+  TRY(salloc(&s.partial, 256));
+  TRY(salloc(&s.loss, 1));
+#undef TRY
+  // He-uniform initial weights, zero biases (host, seeded)
+  std::vector<float> w0(s.np, 0.f);
+  std::mt19937_64 gen(seed);
+  auto fill = [&](int64_t off, int64_t rows, int64_t cols) {
+    std::uniform_real_distribution<float> u(-std::sqrt(6.f / cols), std::sqrt(6.f / cols));
+    for (int64_t i = 0; i < rows * cols; ++i) w0[off + i] = u(gen);
+  };
+  fill(s.oW1, H, 4);
+  fill(s.oW2, H, H);
+  fill(s.oW3, K, H);
+  hipStream_t st = p.stream;
+  if (hipMemcpy(s.w, w0.data(), s.np * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemsetAsync(s.m, 0, s.np * sizeof(float), st) != hipSuccess ||
+      hipMemsetAsync(s.v, 0, s.np * sizeof(float), st) != hipSuccess) {
+    sur_free(s);
+    delete h;
+    return fail(RFD_E_DEVICE, "surrogate initialisation failed");
+  }
+  // whitened training taps
+  hipLaunchKernelGGL(k_whiten, dim3((unsigned)s.n), dim3(256), (size_t)s.T * sizeof(double2), st,
+                     t.a64 + sb.a_base, sb.Tp, (const double2*)sb.U, (const double2*)sb.g, sb.eps,
+                     std::min(std::max(-sb.k0, 0), s.T - 1), s.T, s.X);
+  if (hipGetLastError() != hipSuccess || refresh_bf16(s, st)) {
+    sur_free(s);
+    delete h;
+    return fail(RFD_E_DEVICE, "surrogate whitening failed");
+  }
+  *out = h;
+  return RFD_OK;
+}
+
+int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_out) {
+  if (!sur) return fail(RFD_E_INVALID, "NULL surrogate");
+  if (iters < 1 || iters > 100) return fail(RFD_E_INVALID, "iters must be in [1, 100]");
+  Surrogate& s = sur->s;
+  hipStream_t st = s.plan->stream;
+  const int D = s.D, K = s.K;
+  const int n = (int)s.n;
+  hipLaunchKernelGGL(k_random, dim3(grid_for((int64_t)K * D)), dim3(256), 0, st, s.Bt, (int64_t)K * D, s.seed ^ 0xB5ull);
+  RFD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_orthonormalise, dim3(1), dim3(1024), 0, st, s.Bt, K, D);
+  RFD_CHECK_LAUNCH();
+  int rc;
+  for (int it = 0; it < iters; ++it) {
+    // Q2 = X B^T  (n x K);  B = Q2^T X  (K x D);  orthonormalise
+    if ((rc = gemm<float, float>(st, n, K, D, s.X, D, 0, s.Bt, D, 1, s.Q2, K))) return rc;
+    if ((rc = gemm<float, float>(st, K, D, n, s.Q2, K, 1, s.X, D, 0, s.Bt, D))) return rc;
+    hipLaunchKernelGGL(k_orthonormalise, dim3(1), dim3(1024), 0, st, s.Bt, K, D);
+    RFD_CHECK_LAUNCH();
+  }
+  // target coefficients C = X B^T
+  if ((rc = gemm<float, float>(st, n, K, D, s.X, D, 0, s.Bt, D, 1, s.C, K))) return rc;
+  if (captured_out) {
+    // sum ||c_i||^2 / sum ||x_i||^2  (rows of X have unit norm)
+    const int64_t ny = (int64_t)n * K;
+    const int nblk = std::min<int>(grid_for(ny), 256);
+    float* zeros = s.Q2;   // loss kernel of C against zero: sum of squares
+    RFD_HIP(hipMemsetAsync(zeros, 0, ny * sizeof(float), st));
+    float* dummy = nullptr;
+    if ((rc = salloc(&dummy, (size_t)ny))) return rc;
+    hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, st, s.C, zeros, dummy, ny, 1.f, s.partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, 1.0 / n, s.loss, 0);
+    double v = 0;
+    RFD_HIP(hipMemcpyAsync(&v, s.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    RFD_HIP(hipStreamSynchronize(st));
+    sfree(dummy);
+    *captured_out = v;
+  }
+  return RFD_OK;
+}
+
+int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs, int32_t batch, float lr,
+                        float* loss_out) {
+  if (!sur || !params) return fail(RFD_E_INVALID, "NULL argument");
+  Surrogate& s = sur->s;
+  if (epochs < 1 || batch < 1 || batch > s.nb || !(lr > 0.f)) return fail(RFD_E_INVALID, "bad training arguments");
+  hipStream_t st = s.plan->stream;
+  std::mt19937_64 gen(s.seed + 7);
+  std::vector<int32_t> perm(s.n);
+  for (int64_t i = 0; i < s.n; ++i) perm[i] = (int32_t)i;
+  int32_t* dperm = nullptr;
+  int rc = salloc(&dperm, (size_t)s.n);
+  if (rc) return rc;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int e = 0; e < epochs && !rc; ++e) {
+    std::shuffle(perm.begin(), perm.end(), gen);
+    if (hipMemcpy(dperm, perm.data(), s.n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(RFD_E_DEVICE, "permutation upload failed");
+      break;
+    }
+    const int64_t nbatches = s.n / batch;            // whole batches only
+    for (int64_t bi = 0; bi < nbatches && !rc; ++bi) {
+      hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)batch * (4 + s.K))), dim3(256), 0, st, params, s.C,
+                         dperm + bi * batch, batch, s.K, s.Pb, s.Cb);
+      if (hipGetLastError() != hipSuccess) { rc = fail(RFD_E_DEVICE, "gather launch failed"); break; }
+      if ((rc = forward(s, st, s.Pb, batch))) break;
+      if ((rc = backward(s, st, s.Pb, s.Cb, batch, bi > 0, 1.0 / (double)(batch * nbatches)))) break;
+      ++s.step;
+      const float bc1 = 1.f - powf(b1, (float)s.step), bc2 = 1.f - powf(b2, (float)s.step);
+      hipLaunchKernelGGL(k_adam, dim3(grid_for(s.np)), dim3(256), 0, st, s.w, s.g, s.m, s.v, s.np, lr, b1, b2, eps,
+                         bc1, bc2);
+      if (hipGetLastError() != hipSuccess) { rc = fail(RFD_E_DEVICE, "adam launch failed"); break; }
+      if ((rc = refresh_bf16(s, st))) break;
+    }
+    if (!rc && loss_out) {
+      double v = 0;
+      if (hipMemcpyAsync(&v, s.loss, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        rc = fail(RFD_E_DEVICE, "loss readback failed");
+      loss_out[e] = (float)v;   // mean per-sample squared coefficient error over the epoch
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  sfree(dperm);
+  return rc;
+}
+
+int rfd_surrogate_loss_grad(rfd_surrogate* sur, const float* params, const float* targets, int32_t n, float* grads,
+                            double* loss_out) {
+  if (!sur || !params || !grads) return fail(RFD_E_INVALID, "NULL argument");
+  Surrogate& s = sur->s;
+  if (n < 1 || n > s.nb) return fail(RFD_E_INVALID, "n out of range");
+  hipStream_t st = s.plan->stream;
+  const float* Cb = targets ? targets : s.C;
+  int rc = forward(s, st, params, n);
+  if (!rc) rc = backward(s, st, params, Cb, n, 0, (double)1.0 / n);
+  if (rc) return rc;
+  RFD_HIP(hipMemcpyAsync(grads, s.g, s.np * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (loss_out) {
+    double v = 0;
+    RFD_HIP(hipMemcpyAsync(&v, s.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    RFD_HIP(hipStreamSynchronize(st));
+    *loss_out = v;         // mean over rows of ||y - c||^2
+  }
+  return RFD_OK;
+}
+
+int rfd_surrogate_get_state(rfd_surrogate* sur, float* weights, float* basis, float* targets, int64_t* sizes) {
+  if (!sur) return fail(RFD_E_INVALID, "NULL surrogate");
+  Surrogate& s = sur->s;
+  hipStream_t st = s.plan->stream;
+  if (sizes) {
+    sizes[0] = s.np;
+    sizes[1] = (int64_t)s.K * s.D;
+    sizes[2] = s.n * s.K;
+    sizes[3] = s.D;
+    sizes[4] = s.K;
+    sizes[5] = s.H;
+  }
+  if (weights) RFD_HIP(hipMemcpyAsync(weights, s.w, s.np * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (basis) RFD_HIP(hipMemcpyAsync(basis, s.Bt, (size_t)s.K * s.D * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (targets) RFD_HIP(hipMemcpyAsync(targets, s.C, (size_t)s.n * s.K * sizeof(float), hipMemcpyDeviceToHost, st));
+  RFD_HIP(hipStreamSynchronize(st));
+  return RFD_OK;
+}
+
+int rfd_surrogate_set_state(rfd_surrogate* sur, const float* weights, const float* basis) {
+  if (!sur || (!weights && !basis)) return fail(RFD_E_INVALID, "NULL argument");
+  Surrogate& s = sur->s;
+  hipStream_t st = s.plan->stream;
+  if (weights) {
+    // new weights restart the optimiser
+    RFD_HIP(hipMemcpyAsync(s.w, weights, s.np * sizeof(float), hipMemcpyHostToDevice, st));
+    RFD_HIP(hipMemsetAsync(s.m, 0, s.np * sizeof(float), st));
+    RFD_HIP(hipMemsetAsync(s.v, 0, s.np * sizeof(float), st));
+    s.step = 0;
+  }
+  if (basis) {
+    RFD_HIP(hipMemcpyAsync(s.Bt, basis, (size_t)s.K * s.D * sizeof(float), hipMemcpyHostToDevice, st));
+    // the training targets are the coefficients on the new basis
+    int rc = gemm<float, float>(st, (int)s.n, s.K, s.D, s.X, s.D, 0, s.Bt, s.D, 1, s.C, s.K);
+    if (rc) return rc;
+  }
+  int rc = refresh_bf16(s, st);
+  if (rc) return rc;
+  RFD_HIP(hipStreamSynchronize(st));
+  return RFD_OK;
+}
+
+int rfd_surrogate_make_taps(rfd_surrogate* sur, const float* params, rfd_taps* target, int32_t subbank, int64_t first,
+                            int64_t count) {
+  if (!sur || !params || !target) return fail(RFD_E_INVALID, "NULL argument");
+  Surrogate& s = sur->s;
+  Taps& t = target->t;
+  if (t.plan != s.plan) return fail(RFD_E_INVALID, "target taps belong to another plan");
+  if (subbank < 0 || subbank >= (int)t.sb.size()) return fail(RFD_E_INVALID, "subbank out of range");
+  SubBankTaps& sb = t.sb[subbank];
+  const SubBankTaps& src = s.taps->sb[s.sb];
+  if (sb.T != src.T || sb.k0 != src.k0 || sb.ref_id != src.ref_id)
+    return fail(RFD_E_INVALID, "target sub-bank must have the training sub-bank's reference, T and k0");
+  if (count < 0 || first < 0 || first + count > sb.count) return fail(RFD_E_INVALID, "template range outside the sub-bank");
+  if (count == 0) return RFD_OK;
+  Plan& p = *s.plan;
+  hipStream_t st = p.stream;
+  // the fitted-template norm of the target uses the reference autocorrelation of the training sub-bank
+  RFD_HIP(hipMemcpyAsync(sb.g, src.g, sb.T * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  if (!lds_fits((size_t)2 * s.T * sizeof(double2))) return fail(RFD_E_INVALID, "T too large for the device's LDS");
+  float* Xh = nullptr;
+  const int64_t chunk = s.nb;
+  int rc = salloc(&Xh, (size_t)chunk * s.D);
+  if (rc) return rc;
+  for (int64_t c0 = 0; c0 < count && !rc; c0 += chunk) {
+    const int cn = (int)std::min<int64_t>(chunk, count - c0);
+    rc = forward(s, st, params + 4 * c0, cn);
+    if (!rc) rc = gemm<float, float>(st, cn, s.D, s.K, s.Y, s.K, 0, s.Bt, s.D, 0, Xh, s.D);
+    if (!rc) {
+      hipLaunchKernelGGL(k_unwhiten, dim3((unsigned)cn), dim3(256), (size_t)2 * s.T * sizeof(double2), st, Xh,
+                         (const double2*)src.U, s.T, t.a64 + sb.a_base + (first + c0) * sb.Tp, sb.Tp);
+      if (hipGetLastError() != hipSuccess) rc = fail(RFD_E_DEVICE, "unwhiten launch failed");
+    }
+  }
+  if (!rc) rc = taps_norm_and_pack(p, t, subbank, first, count);
+  (void)hipStreamSynchronize(st);
+  sfree(Xh);
+  if (rc) return rc;
+  for (int64_t i = first; i < first + count; ++i) {
+    if (!sb.made_mask[i]) {
+      sb.made_mask[i] = 1;
+      ++sb.made;
+    }
+  }
+  return RFD_OK;
+}
+
+int rfd_taps_match(const rfd_taps* a, const rfd_taps* b, int32_t subbank, int64_t first, int64_t count,
+                   double* match_out) {
+  if (!a || !b || !match_out) return fail(RFD_E_INVALID, "NULL argument");
+  const Taps& ta = a->t;
+  const Taps& tb = b->t;
+  if (ta.plan != tb.plan) return fail(RFD_E_INVALID, "taps belong to different plans");
+  if (subbank < 0 || subbank >= (int)ta.sb.size() || subbank >= (int)tb.sb.size())
+    return fail(RFD_E_INVALID, "subbank out of range");
+  const SubBankTaps& sa = ta.sb[subbank];
+  const SubBankTaps& sbb = tb.sb[subbank];
+  if (sa.T != sbb.T || sa.count != sbb.count) return fail(RFD_E_INVALID, "sub-banks differ in T or size");
+  if (count < 0 || first < 0 || first + count > sa.count) return fail(RFD_E_INVALID, "template range outside the sub-bank");
+  if (count == 0) return RFD_OK;
+  hipStream_t st = ta.plan->stream;
+  if (!lds_fits((size_t)3 * sa.T * sizeof(double2) + 4 * 256 * sizeof(double)))
+    return fail(RFD_E_INVALID, "T too large for the device's LDS");
+  hipLaunchKernelGGL(k_match, dim3((unsigned)count), dim3(256), (size_t)3 * sa.T * sizeof(double2), st,
+                     ta.a64 + sa.a_base + first * sa.Tp, tb.a64 + sbb.a_base + first * sbb.Tp, sa.Tp, sa.T,
+                     (const double2*)sa.g, match_out);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+int rfd_taps_fallback(rfd_taps* target, const rfd_taps* exact, int32_t subbank, int64_t first, int64_t count,
+                      const double* match, double min_match, int64_t* n_fallback_out) {
+  if (n_fallback_out) *n_fallback_out = 0;
+  if (!target || !exact || (!match && count > 0)) return fail(RFD_E_INVALID, "NULL argument");
+  Taps& tt = target->t;
+  const Taps& te = exact->t;
+  if (tt.plan != te.plan) return fail(RFD_E_INVALID, "taps belong to different plans");
+  if (subbank < 0 || subbank >= (int)tt.sb.size() || subbank >= (int)te.sb.size())
+    return fail(RFD_E_INVALID, "subbank out of range");
+  SubBankTaps& st_ = tt.sb[subbank];
+  const SubBankTaps& se = te.sb[subbank];
+  if (st_.T != se.T || st_.k0 != se.k0 || st_.ref_id != se.ref_id || st_.count != se.count)
+    return fail(RFD_E_INVALID, "sub-banks differ in reference, T, k0 or size");
+  if (count < 0 || first < 0 || first + count > st_.count) return fail(RFD_E_INVALID, "template range outside the sub-bank");
+  if (count == 0) return RFD_OK;
+  Plan& p = *tt.plan;
+  hipStream_t st = p.stream;
+  std::vector<double> m(count);
+  RFD_HIP(hipMemcpyAsync(m.data(), match, count * sizeof(double), hipMemcpyDeviceToHost, st));
+  RFD_HIP(hipStreamSynchronize(st));
+  std::vector<uint8_t> fb(count, 0);
+  int64_t nfb = 0;
+  for (int64_t j = 0; j < count; ++j) {
+    fb[j] = !(m[j] >= min_match);           // NaN falls back too
+    if (fb[j]) {
+      if (!se.made_mask[first + j]) return fail(RFD_E_STATE, "exact taps missing for a template that falls back");
+      ++nfb;
+    }
+  }
+  if (nfb) {
+    RFD_HIP(hipMemcpyAsync(st_.g, se.g, st_.T * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    for (int64_t j = 0; j < count;) {
+      if (!fb[j]) { ++j; continue; }
+      int64_t e = j;
+      while (e < count && fb[e]) ++e;
+      RFD_HIP(hipMemcpyAsync(tt.a64 + st_.a_base + (first + j) * st_.Tp, te.a64 + se.a_base + (first + j) * se.Tp,
+                             (size_t)(e - j) * st_.Tp * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      int rc = taps_norm_and_pack(p, tt, subbank, first + j, e - j);
+      if (rc) return rc;
+      for (int64_t q = j; q < e; ++q) {
+        if (!st_.made_mask[first + q]) {
+          st_.made_mask[first + q] = 1;
+          ++st_.made;
+        }
+      }
+      j = e;
+    }
+    RFD_HIP(hipStreamSynchronize(st));
+  }
+  if (n_fallback_out) *n_fallback_out = nfb;
+  return RFD_OK;
+}
+
+int rfd_surrogate_destroy(rfd_surrogate* sur) {
+  if (!sur) return RFD_OK;
+  (void)hipStreamSynchronize(sur->s.plan->stream);
+  sur_free(sur->s);
+  delete sur;
+  return RFD_OK;
+}
+
+}  // extern "C"

@@ -231,6 +231,8 @@ int taps_prepare_subbank(Plan& p, Taps& tp, int b, const double* h_ref, double e
   return RFD_OK;
 }
 
+int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
+
 int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, int method) {
   SubBankTaps& s = tp.sb[b];
   const int T = s.T;
@@ -246,6 +248,14 @@ int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, 
                        (int64_t)s.Tp);
   }
   RFD_CHECK_LAUNCH();
+  return taps_norm_and_pack(p, tp, b, first, count);
+}
+
+// sigma_fit of taps already in a64, then the normalised taps and MFMA packings.
+int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count) {
+  SubBankTaps& s = tp.sb[b];
+  const int T = s.T;
+  double2* abase = tp.a64 + s.a_base + first * s.Tp;
   double* sig = tp.sigma_fit + s.first + first;
   hipLaunchKernelGGL(k_sigma_fit, dim3((unsigned)count), dim3(256), (size_t)2 * T * sizeof(double2), p.stream,
                      abase, (int64_t)s.Tp, T, s.g, sig);

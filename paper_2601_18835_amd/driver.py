@@ -91,3 +91,83 @@ class RatioFilterSearch:
             self.close()
         except Exception:
             pass
+
+
+def surrogate_features(params):
+    """(m1, m2, chi, e0) [n, 4] -> (chirp mass, symmetric mass ratio, chi, e0):
+    the same four degrees of freedom in the coordinates the phase depends on
+    most directly."""
+    p = np.asarray(params, dtype=np.float64).reshape(-1, 4)
+    m1, m2 = p[:, 0], p[:, 1]
+    mt = m1 + m2
+    eta = m1 * m2 / mt ** 2
+    return np.stack([mt * eta ** 0.6, eta, p[:, 2], p[:, 3]], axis=1)
+
+
+class TapSurrogate:
+    """A learned tap generator for one (reference, T, k0) of a plan.
+
+    Training taps are exact least-squares taps (Sec. V.A) made by librfd
+    from training waveforms; the network maps scaled features to the
+    coefficients of their phase-aligned, whitened form.  Inference fills a
+    sub-bank of a search's taps; validation against exact taps and the
+    per-template fallback use rfd_taps_match and rfd_taps_fallback.
+    """
+
+    def __init__(self, search, ref_id, T, k0, n_train, n_basis=64, hidden=256, seed=2601):
+        import torch
+        self.torch = torch
+        self.search = search
+        self.ref_id, self.T, self.k0 = ref_id, T, k0
+        self.n_train = n_train
+        self.n_basis, self.hidden, self.seed = n_basis, hidden, seed
+        self.train_taps = rfd.rfd_taps_create(search.plan, np.array([0, n_train], np.int64), [ref_id], [T], [k0])
+        self.sur = None
+        self.lo = self.hi = None
+        self.params_dev = None
+
+    def add_training_waveforms(self, h_tmpl, first, ridge_eps=1e-4):
+        ht = h_tmpl if isinstance(h_tmpl, self.torch.Tensor) else self.search.to_dev(
+            np.asarray(h_tmpl, np.complex128))
+        rfd.rfd_make_taps(self.search.plan, self.train_taps, 0, self.search.h_ref[self.ref_id], ht, first,
+                          rfd.RFD_TAPS_LS, ridge_eps)
+
+    def scale(self, params):
+        f = surrogate_features(params)
+        span = np.where(self.hi > self.lo, self.hi - self.lo, 1.0)
+        return (2.0 * (f - self.lo) / span - 1.0).astype(np.float32)
+
+    def fit(self, train_params, basis_iters=20):
+        """Whiten the training taps and fit the basis; returns the captured fraction."""
+        f = surrogate_features(train_params)
+        self.lo, self.hi = f.min(axis=0), f.max(axis=0)
+        self.params_dev = self.search.to_dev(self.scale(train_params))
+        self.sur = rfd.rfd_surrogate_create(self.search.plan, self.train_taps, 0, self.n_basis, self.hidden,
+                                            self.seed)
+        return rfd.rfd_surrogate_fit_basis(self.sur, basis_iters)
+
+    def train(self, epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10):
+        """Adam with a geometric learning-rate decay over `stages` calls."""
+        losses = []
+        per = max(1, epochs // stages)
+        done = 0
+        for s in range(stages):
+            e = per if s < stages - 1 else epochs - done
+            if e <= 0:
+                break
+            rate = lr * (lr_end / lr) ** (s / max(1, stages - 1))
+            losses.append(rfd.rfd_surrogate_train(self.sur, self.params_dev, e, batch, rate))
+            done += e
+        return np.concatenate(losses)
+
+    def make_taps(self, target_taps, subbank, params, first=0):
+        p = self.search.to_dev(self.scale(params))
+        rfd.rfd_surrogate_make_taps(self.sur, p, target_taps, subbank, first)
+
+    def close(self):
+        if self.sur is not None:
+            rfd.rfd_surrogate_destroy(self.sur)
+            self.sur = None
+        if self.train_taps is not None:
+            rfd.rfd_taps_destroy(self.train_taps)
+            self.train_taps = None

@@ -66,6 +66,16 @@ _SIGS = {
     "rfd_segment_graph_create": [_P, _P, _i32, _f, _i64, _P, _i32, _P, _P, _P, _i64, C.POINTER(_P)],
     "rfd_segment_graph_launch": [_P, C.POINTER(_i64)],
     "rfd_graph_destroy": [_P],
+    "rfd_surrogate_create": [_P, _P, _i32, _i32, _i32, C.c_uint64, C.POINTER(_P)],
+    "rfd_surrogate_fit_basis": [_P, _i32, C.POINTER(_d)],
+    "rfd_surrogate_train": [_P, _P, _i32, _i32, _f, _P],
+    "rfd_surrogate_loss_grad": [_P, _P, _P, _i32, _P, C.POINTER(_d)],
+    "rfd_surrogate_get_state": [_P, _P, _P, _P, _P],
+    "rfd_surrogate_set_state": [_P, _P, _P],
+    "rfd_surrogate_make_taps": [_P, _P, _P, _i32, _i64, _i64],
+    "rfd_taps_match": [_P, _P, _i32, _i64, _i64, _P],
+    "rfd_taps_fallback": [_P, _P, _i32, _i64, _i64, _P, _d, C.POINTER(_i64)],
+    "rfd_surrogate_destroy": [_P],
     "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
     "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
     "rfd_get_zref": [_P, _i32, _P],
@@ -329,3 +339,92 @@ def findchirp_filter(plan, data, filt, threshold, cluster_window, capacity, out=
         return out, n.value
     _check(rc, "findchirp_filter")
     return out, n.value
+
+
+# ------------------------------------------------------------- surrogate
+def rfd_surrogate_create(plan, taps, subbank, n_basis=64, hidden=256, seed=2601):
+    h = _P()
+    _check(_lib.rfd_surrogate_create(plan, taps, subbank, n_basis, hidden, seed, C.byref(h)), "rfd_surrogate_create")
+    return h
+
+
+def rfd_surrogate_fit_basis(sur, iters=20):
+    cap = C.c_double(0)
+    _check(_lib.rfd_surrogate_fit_basis(sur, iters, C.byref(cap)), "rfd_surrogate_fit_basis")
+    return cap.value
+
+
+def rfd_surrogate_train(sur, params, epochs, batch=256, lr=1e-3):
+    """params: float32 device tensor [n_train, 4] (training templates, same order)."""
+    import torch
+    sizes = np.zeros(6, dtype=np.int64)
+    _check(_lib.rfd_surrogate_get_state(sur, None, None, None, sizes.ctypes.data), "rfd_surrogate_get_state")
+    _dev_check(params, torch.float32, 4 * (int(sizes[2]) // int(sizes[4])), "params")
+    losses = np.zeros(epochs, dtype=np.float32)
+    _check(_lib.rfd_surrogate_train(sur, _ptr(params), epochs, batch, lr, losses.ctypes.data), "rfd_surrogate_train")
+    return losses
+
+
+def rfd_surrogate_state(sur):
+    sizes = np.zeros(6, dtype=np.int64)
+    _check(_lib.rfd_surrogate_get_state(sur, None, None, None, sizes.ctypes.data), "rfd_surrogate_get_state")
+    w = np.zeros(sizes[0], dtype=np.float32)
+    b = np.zeros(sizes[1], dtype=np.float32)
+    t = np.zeros(sizes[2], dtype=np.float32)
+    _check(_lib.rfd_surrogate_get_state(sur, w.ctypes.data, b.ctypes.data, t.ctypes.data, None),
+           "rfd_surrogate_get_state")
+    D, K, H = int(sizes[3]), int(sizes[4]), int(sizes[5])
+    return {"weights": w, "basis": b.reshape(K, D), "targets": t.reshape(-1, K), "D": D, "K": K, "H": H}
+
+
+def rfd_surrogate_set_state(sur, weights=None, basis=None):
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    b = None if basis is None else np.ascontiguousarray(basis, dtype=np.float32)
+    _check(_lib.rfd_surrogate_set_state(sur, None if w is None else w.ctypes.data,
+                                        None if b is None else b.ctypes.data), "rfd_surrogate_set_state")
+
+
+def rfd_surrogate_loss_grad(sur, params, targets=None):
+    import torch
+    sizes = np.zeros(6, dtype=np.int64)
+    _check(_lib.rfd_surrogate_get_state(sur, None, None, None, sizes.ctypes.data), "rfd_surrogate_get_state")
+    _dev_check(params, torch.float32, None, "params")
+    if params.dim() != 2 or params.shape[1] != 4:
+        raise ValueError("params must be [n, 4]")
+    if targets is not None:
+        _dev_check(targets, torch.float32, params.shape[0] * int(sizes[4]), "targets")
+    g = torch.empty(int(sizes[0]), dtype=torch.float32, device="cuda")
+    loss = C.c_double(0)
+    _check(_lib.rfd_surrogate_loss_grad(sur, _ptr(params), _ptr(targets), params.shape[0], _ptr(g), C.byref(loss)),
+           "rfd_surrogate_loss_grad")
+    return loss.value, g.cpu().numpy()
+
+
+def rfd_surrogate_make_taps(sur, params, target_taps, subbank, first=0):
+    import torch
+    _dev_check(params, torch.float32, None, "params")
+    if params.dim() != 2 or params.shape[1] != 4:
+        raise ValueError("params must be [count, 4]")
+    _check(_lib.rfd_surrogate_make_taps(sur, _ptr(params), target_taps, subbank, first, params.shape[0]),
+           "rfd_surrogate_make_taps")
+
+
+def rfd_taps_match(taps_a, taps_b, subbank, first, count):
+    import torch
+    out = torch.empty(max(count, 1), dtype=torch.float64, device="cuda")
+    _check(_lib.rfd_taps_match(taps_a, taps_b, subbank, first, count, _ptr(out)), "rfd_taps_match")
+    return out[:count].cpu().numpy()
+
+
+def rfd_taps_fallback(target, exact, subbank, first, match, min_match=0.99):
+    """match: float64 device tensor [count]; returns the number of templates replaced."""
+    import torch
+    _dev_check(match, torch.float64, None, "match")
+    n = C.c_int64(0)
+    _check(_lib.rfd_taps_fallback(target, exact, subbank, first, match.numel(), _ptr(match), min_match, C.byref(n)),
+           "rfd_taps_fallback")
+    return n.value
+
+
+def rfd_surrogate_destroy(sur):
+    _check(_lib.rfd_surrogate_destroy(sur), "rfd_surrogate_destroy")

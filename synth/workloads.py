@@ -180,6 +180,17 @@ def _draw_params(w: Workload, rng, count):
     return out
 
 
+def draw_in_chirp_mass_range(w: Workload, lo, hi, count, stream=5):
+    """`count` parameter draws of workload w's family whose chirp mass lies in
+    [lo, hi] (rejection from the family's distribution; a seeded stream of
+    its own, so the bank's draws are untouched)."""
+    rng = np.random.default_rng(np.random.SeedSequence(MASTER_SEED + w.index).spawn(stream + 1)[stream])
+    out = []
+    while len(out) < count:
+        out += [p for p in _draw_params(w, rng, 8192) if lo <= p.mchirp <= hi]
+    return out[:count]
+
+
 def _equal_mass_with_mchirp(mc):
     m = mc * 2.0 ** 0.2          # equal masses: Mc = m * 2^(-1/5)
     return WaveformParams(m, m)

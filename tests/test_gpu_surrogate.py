@@ -1,0 +1,314 @@
+"""Learned tap surrogate on the GPU against the FP64 oracle (oracle/surrogate.py):
+whitening targets and basis, gradients, two Adam steps, inference
+(params -> coefficients -> taps), the match kernel, the exact-tap fallback,
+and the gain over the two no-network tap generators (nearest training
+template, reference only).
+
+Case: one sub-bank of the (m1, m2, chi, e0) family (the chirp-mass slice and
+reference of the 17th of 32 sub-banks of the 65536-template bank), on a
+2^17-sample segment from 30 Hz with T = 128 taps; 1024 training templates
+drawn from the same slice, 256 held-out bank templates.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import spectral as osp
+from oracle import surrogate as osg
+from oracle import taps as otaps
+
+pytestmark = pytest.mark.gpu
+
+N, FS, F_LOW, T = 1 << 17, 2048.0, 30.0, 128
+K0 = -(T // 2)
+N_TRAIN, N_TEST = 1024, 256
+K, H = 64, 256
+U32 = 2.0 ** -24
+
+
+def bf16_round(x):
+    """Round float32 values to the nearest bfloat16 (ties to even), as float32."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def unpack(w):
+    """flat [W1 (H x 4), b1, W2 (H x H), b2, W3 (K x H), b3] -> oracle params (FP64)."""
+    w = np.asarray(w, dtype=np.float64)
+    o = 0
+    out = []
+    for fan_in, fan_out in [(4, H), (H, H), (H, K)]:
+        W = w[o:o + fan_in * fan_out].reshape(fan_out, fan_in)
+        o += fan_in * fan_out
+        b = w[o:o + fan_out]
+        o += fan_out
+        out.append((W, b))
+    assert o == w.size
+    return out
+
+
+def flat(params):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params])
+
+
+@dataclass
+class SurCase:
+    search: object
+    sur: object            # TapSurrogate
+    sur_taps: object       # rfd_taps receiving surrogate taps (same sub-bank layout)
+    p_train: np.ndarray    # physical (m1, m2, chi, e0)
+    p_test: np.ndarray
+    M: np.ndarray
+    lam: float
+    L: np.ndarray
+    A_train: np.ndarray    # oracle exact taps
+    A_test: np.ndarray
+    B: np.ndarray          # oracle basis, float32-rounded, [K, 2T]
+    exact_ms: float
+    w0: np.ndarray         # initial weights rounded to bf16
+
+
+def _phys(ps):
+    return np.array([[p.m1, p.m2, p.chi1, p.e0] for p in ps])
+
+
+@pytest.fixture(scope="module")
+def case(rfd):
+    import time
+    import torch
+    from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec, TapSurrogate
+    w = synth.get_workload("surr512s")
+    bank = synth.make_bank(w)
+    sb = bank.subbanks[16]
+    mc = [p.mchirp for p in sb.params]
+    train = synth.workloads.draw_in_chirp_mass_range(w, min(mc), max(mc), N_TRAIN)
+    test = sb.params[:N_TEST]
+    small = synth.Workload("surrogate-test", 5, N, FS, F_LOW, 0, 1, T, "bf16x3", "surrogate")
+    psd = synth.psd_array(N, FS)
+    h_ref = synth.taylorf2(sb.ref, N, FS, F_LOW)
+    Htr = synth.template_batch(small, train)
+    Hte = synth.template_batch(small, test)
+    print(f"\n[surrogate] case: N={N}, T={T}, ref {sb.ref}, chirp mass [{min(mc):.5f}, {max(mc):.5f}]", flush=True)
+
+    s = RatioFilterSearch(psd, F_LOW, FS, N, [SubBankSpec(0, T, K0, N_TEST)], max_refs=1)
+    s.set_reference(0, h_ref)
+    hte = s.to_dev(Hte)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.make_taps(0, hte)
+    torch.cuda.synchronize()
+    exact_ms = (time.perf_counter() - t0) * 1e3
+    sur = TapSurrogate(s, 0, T, K0, N_TRAIN, n_basis=K, hidden=H, seed=11)
+    sur.add_training_waveforms(Htr, 0)
+    del hte
+    sur_taps = rfd.rfd_taps_create(s.plan, np.array([0, N_TEST], np.int64), [0], [T], [K0])
+
+    # oracle: exact taps, whitening, basis (FP64, from the waveforms alone)
+    wts = osp.psd_weights(psd, N, FS, F_LOW)
+    M = otaps.gram(h_ref, wts, T)
+    lam = otaps.DEFAULT_RIDGE_EPS * float(M[0, 0].real)
+    L = np.linalg.cholesky(M + lam * np.eye(T))
+    A_train = np.stack([otaps.ls_taps_normal(h, h_ref, wts, T, K0, M=M) for h in Htr])
+    A_test = np.stack([otaps.ls_taps_normal(h, h_ref, wts, T, K0, M=M) for h in Hte])
+    X = osg.whiten(osg.phase_align(A_train, M, lam, K0), L)
+    B = osg.basis_svd(X, K).T.astype(np.float32)
+    sur.fit(_phys(train))
+    w0 = bf16_round(rfd.rfd_surrogate_state(sur.sur)["weights"])
+    c = SurCase(s, sur, sur_taps, _phys(train), _phys(test), M, lam, L, A_train, A_test, B, exact_ms, w0)
+    yield c
+    rfd.rfd_taps_destroy(sur_taps)
+    sur.close()
+    s.close()
+
+
+def _oracle_targets(c):
+    X = osg.whiten(osg.phase_align(c.A_train, c.M, c.lam, K0), c.L)
+    return X @ c.B.astype(np.float64).T
+
+
+def test_targets_and_basis_match_oracle(rfd, case):
+    c = case
+    sur = c.sur.sur
+    st = rfd.rfd_surrogate_state(sur)
+    Bg = st["basis"].astype(np.float64)
+    assert st["D"] == 2 * T and st["K"] == K and st["H"] == H
+    # the fitted basis is orthonormal and captures what the SVD optimum captures
+    np.testing.assert_allclose(Bg @ Bg.T, np.eye(K), atol=1e-5)
+    X = osg.whiten(osg.phase_align(c.A_train, c.M, c.lam, K0), c.L)
+    cap_opt = float(np.mean(np.sum((X @ c.B.astype(np.float64).T) ** 2, axis=1)))
+    cap_gpu = float(np.mean(np.sum((X @ Bg.T) ** 2, axis=1)))
+    print(f"\n[surrogate] captured fraction: GPU basis {cap_gpu:.9f}, SVD optimum {cap_opt:.9f}")
+    assert cap_gpu <= cap_opt + 1e-5 and cap_gpu >= cap_opt - 1e-3
+    # targets on the oracle's basis: c = B x, |x| = |b_k| = 1, FP32 products of 2T terms
+    rfd.rfd_surrogate_set_state(sur, basis=c.B)
+    got = rfd.rfd_surrogate_state(sur)["targets"].astype(np.float64)
+    want = _oracle_targets(c)
+    err = float(np.max(np.abs(got - want)))
+    print(f"[surrogate] targets: max |dc| = {err:.3e} (bound {2 * T * U32 * 4:.3e})")
+    assert err <= 2 * T * U32 * 4
+
+
+def test_gradients_match_oracle(rfd, case):
+    import torch
+    c = case
+    sur = c.sur.sur
+    rfd.rfd_surrogate_set_state(sur, weights=c.w0)
+    rng = np.random.default_rng(3)
+    n = 200
+    P = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    C = (0.3 * rng.standard_normal((n, K))).astype(np.float32)
+    loss, g = rfd.rfd_surrogate_loss_grad(sur, torch.from_numpy(P).cuda(), torch.from_numpy(C).cuda())
+    lo, go = osg.loss_and_grads(unpack(c.w0), P.astype(np.float64), C.astype(np.float64))
+    go = flat(go)
+    print(f"\n[surrogate] loss GPU {loss:.9f} oracle {lo:.9f}")
+    assert abs(loss - lo) <= 1e-5 * lo
+    # FP32 sums of at most max(n, H) products per element, through three layers
+    tol = 3 * max(n, H) * U32
+    o = 0
+    for name, size in [("W1", 4 * H), ("b1", H), ("W2", H * H), ("b2", H), ("W3", H * K), ("b3", K)]:
+        a, b = g[o:o + size].astype(np.float64), go[o:o + size]
+        o += size
+        rel = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        print(f"[surrogate] grad {name}: max |dg| / max |g| = {rel:.3e}")
+        assert rel <= tol, name
+
+
+def test_two_adam_steps_match_oracle(rfd, case):
+    """Full-batch steps (batch = training set), so the shuffle only reorders sums."""
+    c = case
+    sur = c.sur.sur
+    rfd.rfd_surrogate_set_state(sur, weights=c.w0, basis=c.B)
+    lr = 1e-3
+    P = c.sur.scale(c.p_train).astype(np.float64)
+    Ct = _oracle_targets(c)
+    params = unpack(c.w0)
+    state = osg.adam_init(params)
+    g_first = None
+    for step in range(2):
+        _, grads = osg.loss_and_grads(params, P, Ct)
+        params, state = osg.adam_step(params, grads, state, lr)
+        rfd.rfd_surrogate_train(sur, c.sur.params_dev, 1, N_TRAIN, lr)
+        got = rfd.rfd_surrogate_state(sur)["weights"].astype(np.float64)
+        want = flat(params)
+        g = np.abs(flat(grads))
+        if step == 0:
+            # update = lr * g / (|g| + eps): exact up to FP32 rounding of w
+            g_first = g
+            sure = g > 1e-3 * g.max()
+            tol = 1e-3 * lr
+        else:
+            # the GPU's forward pass now sees bf16-rounded weights (relative
+            # 2^-9), which moves g2 and so m2 / sqrt(v2) for small gradients;
+            # a wrong moment or bias-correction formula moves it by O(1)
+            sure = (g > 0.1 * g.max()) & (g_first > 0.1 * g_first.max())
+            tol = 5e-2 * lr
+        dev = np.abs(got - want)[sure]
+        print(f"\n[surrogate] Adam step {step + 1}: max |dw| = {dev.max():.3e} over {sure.mean():.1%} "
+              f"of the weights (tol {tol:.1e}); moved {np.abs(got - c.w0).max():.3e}")
+        assert dev.max() <= tol
+
+
+def test_inference_matches_oracle(rfd, case):
+    import torch
+    c = case
+    sur = c.sur.sur
+    rfd.rfd_surrogate_set_state(sur, weights=c.w0, basis=c.B)
+    c.sur.make_taps(c.sur_taps, 0, c.p_test)
+    torch.cuda.synchronize()
+    P = c.sur.scale(c.p_test).astype(np.float64)
+    y, _ = osg.forward(unpack(c.w0), P)
+    a_or = osg.unwhiten(y @ c.B.astype(np.float64), c.L)
+    a_gpu = np.stack([rfd.rfd_taps_get(c.sur_taps, j)[0] for j in range(N_TEST)])
+    sig_gpu = np.array([rfd.rfd_taps_get(c.sur_taps, j)[1] for j in range(N_TEST)])
+    # FP32 forward (bf16-exact weights) and basis expansion: rounding that
+    # grows like sqrt(terms) over the 2H + K products on the longest path;
+    # then an FP64 back substitution that amplifies relative error by at
+    # most cond(L^H)
+    ev = np.linalg.eigvalsh(c.M + c.lam * np.eye(T))
+    cond = float(np.sqrt(ev[-1] / ev[0]))
+    tol = cond * 4 * np.sqrt(2 * H + K) * U32
+    rel = np.linalg.norm(a_gpu - a_or, axis=1) / np.linalg.norm(a_or, axis=1)
+    print(f"\n[surrogate] inference: max relative tap error {rel.max():.3e} (cond(L) {cond:.1f}, tol {tol:.3e})")
+    assert rel.max() <= tol
+    sig_or = np.sqrt(np.real(np.einsum("ij,jk,ik->i", np.conj(a_or), c.M, a_or)))
+    np.testing.assert_allclose(sig_gpu, sig_or, rtol=2 * tol)
+
+
+def _gpu_match(rfd, c):
+    return rfd.rfd_taps_match(c.sur_taps, c.search.taps, 0, 0, N_TEST)
+
+
+def test_match_kernel_and_fallback(rfd, case):
+    import torch
+    c = case
+    sur = c.sur.sur
+    rfd.rfd_surrogate_set_state(sur, weights=c.w0, basis=c.B)
+    c.sur.make_taps(c.sur_taps, 0, c.p_test)
+    m_gpu = _gpu_match(rfd, c)
+    # oracle: its own surrogate taps (same weights and basis) against its own exact taps
+    P = c.sur.scale(c.p_test).astype(np.float64)
+    y, _ = osg.forward(unpack(c.w0), P)
+    a_or = osg.unwhiten(y @ c.B.astype(np.float64), c.L)
+    m_or = osg.match(a_or, c.A_test, c.M)
+    err = float(np.max(np.abs(m_gpu - m_or)))
+    print(f"\n[surrogate] match kernel vs oracle: max |dm| = {err:.3e}; untrained match mean {m_or.mean():.3f}")
+    assert err <= 1e-3
+    # exact taps against themselves
+    self_m = rfd.rfd_taps_match(c.search.taps, c.search.taps, 0, 0, N_TEST)
+    np.testing.assert_allclose(self_m, 1.0, atol=1e-12)
+    # fallback below the median match: exact taps replace exactly those templates
+    thr = float(np.median(m_gpu))
+    before = [rfd.rfd_taps_get(c.sur_taps, j) for j in range(N_TEST)]
+    n_fb = rfd.rfd_taps_fallback(c.sur_taps, c.search.taps, 0, 0, torch.from_numpy(m_gpu).cuda(), thr)
+    assert n_fb == int(np.sum(m_gpu < thr))
+    after = _gpu_match(rfd, c)
+    fb = m_gpu < thr
+    np.testing.assert_allclose(after[fb], 1.0, atol=1e-12)
+    assert np.array_equal(after[~fb], m_gpu[~fb])
+    for j in range(N_TEST):
+        a, sig, _, _ = rfd.rfd_taps_get(c.sur_taps, j)
+        if fb[j]:
+            ae, se, _, _ = rfd.rfd_taps_get(c.search.taps, j)
+            assert np.array_equal(a, ae) and sig == se
+        else:
+            assert np.array_equal(a, before[j][0]) and sig == before[j][1]
+
+
+def test_trained_surrogate_beats_no_network_taps(rfd, case):
+    """Gain test: after training, the surrogate's taps match the exact taps of
+    held-out templates better than the nearest training template's exact taps
+    (a table lookup) and than the reference alone (a single zero-lag tap)."""
+    import time
+    import torch
+    c = case
+    sur = c.sur.sur
+    rfd.rfd_surrogate_set_state(sur, weights=c.w0, basis=c.B)
+    t0 = time.perf_counter()
+    losses = c.sur.train(epochs=1500, batch=256, lr=2e-3, lr_end=2e-5, stages=10)
+    train_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.sur.make_taps(c.sur_taps, 0, c.p_test)
+    torch.cuda.synchronize()
+    infer_ms = (time.perf_counter() - t0) * 1e3
+    m = _gpu_match(rfd, c)
+    # no-network generators, judged by the oracle on its own exact taps
+    f = c.sur.scale(c.p_train).astype(np.float64)
+    ft = c.sur.scale(c.p_test).astype(np.float64)
+    nn = np.argmin(((ft[:, None, :] - f[None, :, :]) ** 2).sum(-1), axis=1)
+    m_nn = osg.match(c.A_train[nn], c.A_test, c.M)
+    a0 = np.zeros((N_TEST, T), complex)
+    a0[:, -K0] = 1.0
+    m_ref = osg.match(a0, c.A_test, c.M)
+    print(f"\n[surrogate] training: 1500 epochs in {train_s:.1f} s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    print(f"[surrogate] held-out match: surrogate mean {m.mean():.4f} min {m.min():.4f} "
+          f"(>= 0.99: {np.mean(m >= 0.99):.1%}); nearest template mean {m_nn.mean():.4f} min {m_nn.min():.4f}; "
+          f"reference only mean {m_ref.mean():.4f}")
+    print(f"[surrogate] tap generation for {N_TEST} templates: surrogate {infer_ms:.2f} ms, "
+          f"exact (device, waveforms resident) {c.exact_ms:.2f} ms")
+    assert losses[-1] < 0.5 * losses[0]
+    assert m.mean() > m_nn.mean() and m.mean() > m_ref.mean()
+    assert np.median(m) > np.median(m_nn)

@@ -97,9 +97,12 @@ def adam_init(params):
 
 
 def phase_align(a, M, lam, k0):
-    """a exp(-i arg z) with z = ((M + lam I) a)[-k0] (a: [n, T] complex)."""
+    """a exp(-i arg z) with z = ((M + lam I) a)[i0] (a: [n, T] complex);
+    i0 = -k0 is the zero-lag tap, clamped into [0, T) when the tap window
+    does not contain lag 0."""
     T = M.shape[0]
-    z = (a @ (M + lam * np.eye(T)).T)[:, -k0]
+    i0 = min(max(-k0, 0), T - 1)
+    z = (a @ (M + lam * np.eye(T)).T)[:, i0]
     return a * np.exp(-1j * np.angle(z))[:, None]
 
 

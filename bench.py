@@ -60,7 +60,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="spin256s", choices=["spin256s", "tidal256s", "ecc512s"])
+    ap.add_argument("--workload", default="spin256s", choices=["spin256s", "tidal256s", "ecc512s", "surr512s"])
+    ap.add_argument("--subbanks", default="4,12,20,28", help="surr512s: sub-banks given a surrogate")
+    ap.add_argument("--train", type=int, default=4096, help="surr512s: exact tap sets per surrogate")
+    ap.add_argument("--epochs", type=int, default=2000, help="surr512s: training epochs per surrogate")
     ap.add_argument("--cpu-sample", type=int, default=6, help="templates in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 / FP16 / FINDCHIRP comparison legs")
@@ -79,6 +82,8 @@ def main():
     from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "surr512s":
+        return surrogate_main(args)
     w = synth.get_workload(args.workload)
     bank = synth.make_bank(w)
     psd = synth.psd_array(w.n, w.fs)
@@ -234,6 +239,193 @@ def main():
         "autotune": tune, "roofline": roofline, "compare": compare, "parity": parity, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def surrogate_main(args):
+    """surr512s: learned tap generation for whole sub-banks of the 65536-template
+    (m1, m2, chi, e0) bank (N = 2^20, T = 1024).  Per selected sub-bank: exact
+    taps of its 2048 bank templates (the judge and the fallback), a surrogate
+    trained on `--train` exact tap sets drawn from the sub-bank's chirp-mass
+    slice, then timed inference (params resident in HBM -> packed taps) and
+    validation.  One step = surrogate taps for every template of the selected
+    sub-banks."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_18835_amd import rfd
+    from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec, TapSurrogate
+
+    w = synth.get_workload("surr512s")
+    bank = synth.make_bank(w)
+    sel = [int(x) for x in args.subbanks.split(",")]
+    sbs = [bank.subbanks[b] for b in sel]
+    psd = synth.psd_array(w.n, w.fs)
+    specs = [SubBankSpec(i, sb.taps, sb.k0, sb.size) for i, sb in enumerate(sbs)]
+    s = RatioFilterSearch(psd, w.f_low, w.fs, w.n, specs, max_refs=len(sel))
+    sur_taps = rfd.rfd_taps_create(s.plan, s.offsets, [sp.ref_id for sp in specs], [sp.taps for sp in specs],
+                                   [sp.k0 for sp in specs])
+    for i, sb in enumerate(sbs):
+        s.set_reference(i, synth.reference_waveform(w, sb))
+    phys = lambda ps: np.array([[p.m1, p.m2, p.chi1, p.e0] for p in ps])   # noqa: E731
+    rfd.rfd_plan_set_timing(s.plan, True)
+    nt = int(s.offsets[-1])
+    log(f"workload surr512s: N={w.n}, sub-banks {sel} of {len(bank.subbanks)}, {nt} bank templates, "
+        f"T={sbs[0].taps}, {args.train} training tap sets and {args.epochs} epochs per surrogate")
+    gen_s = exact_ms = train_s = 0.0
+    surs, pdev, per = [], [], []
+    batch = 256
+    for i, (b, sb) in enumerate(zip(sel, sbs)):
+        mc = [p.mchirp for p in sb.params]
+        train = synth.workloads.draw_in_chirp_mass_range(w, min(mc), max(mc), args.train, stream=5 + b)
+        rfd.rfd_plan_get_timing(s.plan)
+        for b0 in range(0, sb.size, batch):
+            tg = time.perf_counter()
+            H = synth.template_batch(w, sb.params[b0:b0 + batch])
+            gen_s += time.perf_counter() - tg
+            s.make_taps(i, torch.from_numpy(H).to("cuda"), first=b0)
+        torch.cuda.synchronize()
+        exact_ms += rfd.rfd_plan_get_timing(s.plan)["taps_ms"]
+        sur = TapSurrogate(s, i, sb.taps, sb.k0, len(train), n_basis=64, hidden=256, seed=2601 + b)
+        for b0 in range(0, len(train), batch):
+            tg = time.perf_counter()
+            H = synth.template_batch(w, train[b0:b0 + batch])
+            gen_s += time.perf_counter() - tg
+            sur.add_training_waveforms(torch.from_numpy(H).to("cuda"), b0)
+        torch.cuda.synchronize()
+        captured = sur.fit(phys(train))
+        t0 = time.perf_counter()
+        losses = sur.train(epochs=args.epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        train_s += dt
+        log(f"sub-bank {b}: basis captures {captured:.6f}; trained in {dt:.1f} s, loss {losses[0]:.4f} -> "
+            f"{losses[-1]:.4f}")
+        surs.append(sur)
+        pdev.append(s.to_dev(sur.scale(phys(sb.params))))
+        per.append({"subbank": b, "captured": captured, "loss_first": float(losses[0]),
+                    "loss_last": float(losses[-1]), "train_s": round(dt, 2)})
+        rfd.rfd_plan_get_timing(s.plan)
+
+    def step():
+        for i in range(len(sel)):
+            rfd.rfd_surrogate_make_taps(surs[i].sur, pdev[i], sur_taps, i, 0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rfd.rfd_plan_get_timing(s.plan)
+    log(f"timing {args.steps} steps ({args.warmup} warm-up): surrogate taps for {nt} templates per step")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = rfd.rfd_plan_get_timing(s.plan)
+    value = nt * args.steps / dt
+    ms_step = dt / args.steps * 1e3
+    # validation against the exact taps, then the fallback below 0.99
+    matches = []
+    for i, sb in enumerate(sbs):
+        matches.append(rfd.rfd_taps_match(sur_taps, s.taps, i, 0, sb.size))
+    torch.cuda.synchronize()
+    tv = rfd.rfd_plan_get_timing(s.plan)
+    m = np.concatenate(matches)
+    n_fb = 0
+    for i, sb in enumerate(sbs):
+        n_fb += rfd.rfd_taps_fallback(sur_taps, s.taps, i, 0, torch.from_numpy(matches[i]).cuda(), 0.99)
+        per[i].update({"match_mean": float(matches[i].mean()), "match_min": float(matches[i].min()),
+                       "pass_0.99": float(np.mean(matches[i] >= 0.99))})
+    after = np.concatenate([rfd.rfd_taps_match(sur_taps, s.taps, i, 0, sb.size) for i, sb in enumerate(sbs)])
+    T = sbs[0].taps
+    K, Hd = 64, 256
+    st = {k: tim[k] / args.steps for k in ("sur_net_ms", "sur_expand_ms", "sur_pack_ms")}
+    # algorithmic work per launch (one sub-bank of 2048 templates)
+    n1 = sbs[0].size
+    net_flop = 2.0 * n1 * (4 * Hd + Hd * Hd + Hd * K)
+    exp_flop = 8.0 * n1 * K * T
+    pack_bytes = n1 * T * (16 + 8 + 16 + 16 + 16)
+    per_launch = {k: st[k] / len(sel) for k in st}
+    cand = {"sur_net_ms": ("k_gemm (MLP forward)", "alu", net_flop / (per_launch["sur_net_ms"] * 1e-3) / 1e12,
+                           157.3, "TFLOP/s", net_flop),
+            "sur_expand_ms": ("k_expand", "alu", exp_flop / (per_launch["sur_expand_ms"] * 1e-3) / 1e12, 78.6,
+                              "TFLOP/s", exp_flop),
+            "sur_pack_ms": ("k_pack", "hbm", pack_bytes / (per_launch["sur_pack_ms"] * 1e-3) / 1e9, 8000.0,
+                            "GB/s", pack_bytes)}
+    dom = max(st, key=st.get)
+    name, bound, ach, peak, unit, work = cand[dom]
+    roofline = {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit, "frac": round(ach / peak, 5),
+                "traffic": None, "kernel": name, "stage": dom, "work_per_launch": work,
+                "avg_launch_ms": round(per_launch[dom], 4),
+                "others": {k: {"kernel": cand[k][0], "achieved": round(cand[k][2], 3), "unit": cand[k][4],
+                               "frac": round(cand[k][2] / cand[k][3], 5), "ms_per_launch": round(per_launch[k], 4)}
+                           for k in st if k != dom}}
+    exact_per_s = nt / (exact_ms * 1e-3)
+    gen_per_s = (nt + len(sel) * args.train) / gen_s
+    log(f"surrogate: {ms_step:.3f} ms/step, {value:.4g} tap sets/s; exact taps on the GPU {exact_per_s:.4g}/s, "
+        f"host waveforms {gen_per_s:.4g}/s")
+    log(f"match: mean {m.mean():.4f}, median {np.median(m):.4f}, min {m.min():.4f}, >= 0.99: {np.mean(m >= 0.99):.1%};"
+        f" fallback {n_fb} -> min after {after.min():.4f}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = surrogate_cpu_baseline(w, sbs[0], psd, np)
+    for sur in surs:
+        sur.close()
+    rfd.rfd_taps_destroy(sur_taps)
+    s.close()
+    line = {
+        "metric": "surrogate tap sets/s (params resident -> packed taps), 1 GPU",
+        "value": value, "unit": "tap sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "precision": "bf16 weights, fp32 accumulation; fp64 expansion and normalisation",
+        "data": "synthetic",
+        "config": {"workload": "surr512s", "segment_samples": w.n, "fs": w.fs, "f_low": w.f_low,
+                   "subbanks": sel, "templates": nt, "taps": T, "n_basis": K, "hidden": Hd,
+                   "train_sets_per_surrogate": args.train, "epochs": args.epochs},
+        "stages_ms": st, "match_ms": tv["match_ms"],
+        "validation": {"match_mean": float(m.mean()), "match_median": float(np.median(m)),
+                       "match_p01": float(np.quantile(m, 0.01)), "match_min": float(m.min()),
+                       "pass_0.99": float(np.mean(m >= 0.99)), "fallback": int(n_fb),
+                       "match_min_after_fallback": float(after.min()),
+                       "snr_loss_mean_after_fallback": float(1.0 - after.mean())},
+        "exact_taps": {"gpu_tap_sets_per_s": exact_per_s, "host_waveforms_per_s": gen_per_s,
+                       "note": "exact taps need a waveform per template (host here) plus the GPU FFT and solves"},
+        "training": {"seconds_total": round(train_s, 2), "per_subbank": per},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def surrogate_cpu_baseline(w, sb, psd, np):
+    """The oracle's surrogate inference (forward pass, basis expansion, FP64
+    unwhitening, fitted norm) on this host for 256 templates of one sub-bank,
+    with seeded random weights and basis of the same shapes."""
+    import synth
+    from oracle import spectral as osp
+    from oracle import surrogate as osg
+    from oracle import taps as otaps
+    T, K, Hd, n = sb.taps, 64, 256, 256
+    wts = osp.psd_weights(psd, w.n, w.fs, w.f_low)
+    h_ref = synth.reference_waveform(w, sb)
+    M = otaps.gram(h_ref, wts, T)
+    L = np.linalg.cholesky(M + otaps.DEFAULT_RIDGE_EPS * M[0, 0].real * np.eye(T))
+    rng = np.random.default_rng(5)
+    params = osg.init_params([4, Hd, Hd, K], rng)
+    B, _ = np.linalg.qr(rng.standard_normal((2 * T, K)))
+    P = rng.uniform(-1, 1, size=(n, 4))
+    c0, w0 = time.process_time(), time.perf_counter()
+    y, _ = osg.forward(params, P)
+    a = osg.unwhiten(y @ B.T, L)
+    sig = np.sqrt(np.real(np.einsum("ij,jk,ik->i", np.conj(a), M, a)))
+    wall = time.perf_counter() - w0
+    cpu_t = time.process_time() - c0
+    assert np.all(np.isfinite(sig))
+    out = {"value": n / wall, "unit": "tap sets/s", "cores": max(1, int(round(cpu_t / wall))), "kind": "oracle",
+           "sample": f"{n} templates of one sub-bank (T = {T}): FP64 forward pass, basis expansion, "
+                     f"unwhitening solve and fitted norm; seeded random weights and basis",
+           "seconds": round(wall, 2)}
+    log(f"cpu oracle (surrogate inference): {out['value']:.4g} tap sets/s on {out['cores']} core(s)")
+    return out
 
 
 def oracle_sample(args, w, bank, psd, seg, hrefs, s, out, cap, eager_step, prec, np, synth):

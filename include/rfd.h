@@ -249,7 +249,12 @@ typedef struct rfd_timing {
   double compact_ms;    /* slot clearing, trigger compaction, z re-evaluation */
   double findchirp_ms;  /* FINDCHIRP transforms with the fused epilogue */
   double taps_ms;       /* tap construction */
-  int64_t n_data_fft, n_dechirp, n_fir, n_compact, n_findchirp, n_taps;
+  double sur_net_ms;    /* surrogate network forward pass (inference) */
+  double sur_expand_ms; /* surrogate coefficients -> FP64 taps and sigma_fit */
+  double sur_pack_ms;   /* surrogate taps: normalisation and MFMA packing */
+  double match_ms;      /* fitted-template match of two tap sets */
+  int64_t n_data_fft, n_dechirp, n_fir, n_compact, n_findchirp, n_taps, n_sur_net, n_sur_expand, n_sur_pack,
+      n_match;
 } rfd_timing;
 int rfd_plan_set_timing(rfd_plan* plan, int32_t enable);
 int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
@@ -366,9 +371,12 @@ int rfd_graph_destroy(rfd_graph* graph);
  * rfd_surrogate_make_taps  taps for templates first..first+count-1 of a
  *                          sub-bank of `target` with the same reference, T
  *                          and k0, from params dev float [count][4]:
- *                          c_hat -> x_hat = B^T c_hat -> a = L^-H v, then
- *                          sigma_fit and packing as rfd_make_taps.  Marks
- *                          the templates made.
+ *                          c_hat, then a = L^-H (B^T c_hat) through the
+ *                          folded FP64 matrix L^-H B (made when the basis
+ *                          is fitted or set), then sigma_fit and packing as
+ *                          rfd_make_taps.  Marks the templates made.
+ *                          Training and inference before a basis exists
+ *                          give RFD_E_STATE.
  * rfd_taps_match           dev double [count]: |a^H M b| / sqrt(a^H M a
  *                          b^H M b) between the FP64 taps of two objects of
  *                          one plan (same sub-bank index, T and size); M

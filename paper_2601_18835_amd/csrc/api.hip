@@ -283,9 +283,11 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out) {
   Plan& p = plan->p;
   memset(out, 0, sizeof(*out));
   double* ms[kNumStages] = {&out->data_fft_ms, &out->dechirp_ms, &out->fir_ms, &out->compact_ms,
-                            &out->findchirp_ms, &out->taps_ms};
+                            &out->findchirp_ms, &out->taps_ms, &out->sur_net_ms, &out->sur_expand_ms,
+                            &out->sur_pack_ms, &out->match_ms};
   int64_t* cnt[kNumStages] = {&out->n_data_fft, &out->n_dechirp, &out->n_fir, &out->n_compact,
-                              &out->n_findchirp, &out->n_taps};
+                              &out->n_findchirp, &out->n_taps, &out->n_sur_net, &out->n_sur_expand,
+                              &out->n_sur_pack, &out->n_match};
   for (auto& m : p.marks) {
     RFD_HIP(hipEventSynchronize(m.b));
     float t = 0.f;

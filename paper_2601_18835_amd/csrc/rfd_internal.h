@@ -81,7 +81,11 @@ struct Plan {
   std::vector<Mark> marks;
 };
 
-enum Stage { kStDataFft = 0, kStDechirp, kStFir, kStCompact, kStFindchirp, kStTaps, kNumStages };
+enum Stage {
+  kStDataFft = 0, kStDechirp, kStFir, kStCompact, kStFindchirp, kStTaps, kStSurNet, kStSurExpand, kStSurPack,
+  kStMatch,
+  kNumStages
+};
 // Record the start / stop of a stage when timing is enabled.
 int stage_begin(Plan& p, int stage);
 int stage_end(Plan& p);

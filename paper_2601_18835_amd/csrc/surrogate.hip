@@ -30,6 +30,7 @@
 namespace rfd {
 
 int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
+int taps_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
 
 // ------------------------------------------------------------------ GEMM
 __device__ __forceinline__ float ld_op(const float* p, int64_t i) { return p[i]; }
@@ -316,6 +317,71 @@ __global__ __launch_bounds__(256) void k_unwhiten(const float* __restrict__ Xh, 
   for (int i = threadIdx.x; i < T; i += 256) ao[i] = x[i];
 }
 
+// Coefficients -> FP64 taps and their fitted norm, kExpandRows templates per
+// workgroup (the folded matrix is read once per group):
+//   a_j = sum_k y_jk W_k      (W = L^-H B: row k is the back-substituted
+//                              basis vector k),
+//   v_j = sum_k y_jk B_k      (= L^H a_j, B_k = b_k[:T] + i b_k[T:]),
+//   sigma_fit^2 = a^H M a = ||v||^2 - lam ||a||^2   (M + lam I = L L^H),
+// an O(K T) form of the Sec. VI.B norm for taps given in whitened form.
+constexpr int kExpandRows = 4;
+__global__ __launch_bounds__(256) void k_expand(const float* __restrict__ Y, int n, int K,
+                                              const double2* __restrict__ W, const float* __restrict__ Bt, int T,
+                                              double eps, const double2* __restrict__ g, double2* __restrict__ a,
+                                              int Tp, double* __restrict__ sigma) {
+  __shared__ double yk[kExpandRows][1024];
+  __shared__ double red[2 * kExpandRows][256];
+  const int j0 = blockIdx.x * kExpandRows;
+  const int rows = min(kExpandRows, n - j0);
+  for (int e = threadIdx.x; e < kExpandRows * K; e += 256) {
+    const int r = e / K, k = e % K;
+    yk[r][k] = r < rows ? (double)Y[(int64_t)(j0 + r) * K + k] : 0.0;
+  }
+  __syncthreads();
+  double aa[kExpandRows], vv[kExpandRows];
+#pragma unroll
+  for (int r = 0; r < kExpandRows; ++r) aa[r] = vv[r] = 0.0;
+  for (int t = threadIdx.x; t < T; t += 256) {
+    double ar[kExpandRows], ai[kExpandRows], vr[kExpandRows], vi[kExpandRows];
+#pragma unroll
+    for (int r = 0; r < kExpandRows; ++r) ar[r] = ai[r] = vr[r] = vi[r] = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double2 w = W[(int64_t)k * T + t];
+      const double br = (double)Bt[(int64_t)k * 2 * T + t], bi = (double)Bt[(int64_t)k * 2 * T + T + t];
+#pragma unroll
+      for (int r = 0; r < kExpandRows; ++r) {
+        const double y = yk[r][k];
+        ar[r] = fma(y, w.x, ar[r]);
+        ai[r] = fma(y, w.y, ai[r]);
+        vr[r] = fma(y, br, vr[r]);
+        vi[r] = fma(y, bi, vi[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kExpandRows; ++r) {
+      if (r < rows) a[(int64_t)(j0 + r) * Tp + t] = make_double2(ar[r], ai[r]);
+      aa[r] += ar[r] * ar[r] + ai[r] * ai[r];
+      vv[r] += vr[r] * vr[r] + vi[r] * vi[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kExpandRows; ++r) {
+    red[2 * r][threadIdx.x] = aa[r];
+    red[2 * r + 1][threadIdx.x] = vv[r];
+  }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int q = 0; q < 2 * kExpandRows; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < rows) {
+    const int r = threadIdx.x;
+    const double lam = eps * g[0].x;
+    sigma[j0 + r] = sqrt(fmax(red[2 * r + 1][0] - lam * red[2 * r][0], 0.0));
+  }
+}
+
 // |a^H M b| / sqrt(a^H M a b^H M b), M[l,k] = g[l-k]; one workgroup per template.
 __global__ __launch_bounds__(256) void k_match(const double2* __restrict__ A, const double2* __restrict__ Bt, int Tp,
                                              int T, const double2* __restrict__ g, double* __restrict__ out) {
@@ -366,6 +432,7 @@ struct Surrogate {
   int sb = 0, T = 0, Tp = 0, D = 0, K = 0, H = 0;
   int64_t n = 0;                       // training tap sets
   float* X = nullptr;                  // [n x D] whitened training taps
+  double2* Weff = nullptr;             // [K x T] L^-H applied to each basis vector
   float* Bt = nullptr;                 // [K x D] orthonormal basis
   float* C = nullptr;                  // [n x K] target coefficients
   float* Q2 = nullptr;                 // [n x K] scratch (X B^T during iteration)
@@ -381,6 +448,7 @@ struct Surrogate {
   double* partial = nullptr;
   double* loss = nullptr;
   uint64_t seed = 0;
+  bool basis_ready = false;            // basis, targets and Weff exist
 };
 
 template <typename T>
@@ -400,7 +468,7 @@ static void sfree(T*& p) {
 }
 
 static void sur_free(Surrogate& s) {
-  sfree(s.X); sfree(s.Bt); sfree(s.C); sfree(s.Q2); sfree(s.w); sfree(s.g); sfree(s.m); sfree(s.v); sfree(s.wbf);
+  sfree(s.X); sfree(s.Weff); sfree(s.Bt); sfree(s.C); sfree(s.Q2); sfree(s.w); sfree(s.g); sfree(s.m); sfree(s.v); sfree(s.wbf);
   sfree(s.Pb); sfree(s.Cb); sfree(s.Z1); sfree(s.H1); sfree(s.Z2); sfree(s.H2); sfree(s.Y); sfree(s.dY);
   sfree(s.dA); sfree(s.dB); sfree(s.idx); sfree(s.partial); sfree(s.loss);
 }
@@ -473,6 +541,17 @@ static int backward(Surrogate& s, hipStream_t st, const float* P, const float* C
   return RFD_OK;
 }
 
+// Fold the inverse whitening into the basis: row k of Weff = L^-H (b_k re + i b_k im),
+// so inference is a = sum_k c_k Weff_k (the map x -> a is linear).
+static int update_expansion(Surrogate& s, hipStream_t st) {
+  const SubBankTaps& src = s.taps->sb[s.sb];
+  if (!lds_fits((size_t)2 * s.T * sizeof(double2))) return fail(RFD_E_INVALID, "T too large for the device's LDS");
+  hipLaunchKernelGGL(k_unwhiten, dim3((unsigned)s.K), dim3(256), (size_t)2 * s.T * sizeof(double2), st, s.Bt,
+                     (const double2*)src.U, s.T, s.Weff, s.T);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
 }  // namespace rfd
 
 using namespace rfd;
@@ -521,6 +600,7 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
 #define TRY(x) do { rc = (x); if (rc) { sur_free(s); delete h; return rc; } } while (0)
   TRY(salloc(&s.X, (size_t)s.n * s.D));
   TRY(salloc(&s.Bt, (size_t)K * s.D));
+  TRY(salloc(&s.Weff, (size_t)K * s.T));
   TRY(salloc(&s.C, (size_t)s.n * K));
   TRY(salloc(&s.Q2, (size_t)s.n * K));
   TRY(salloc(&s.w, (size_t)s.np));
@@ -592,8 +672,10 @@ int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_
     hipLaunchKernelGGL(k_orthonormalise, dim3(1), dim3(1024), 0, st, s.Bt, K, D);
     RFD_CHECK_LAUNCH();
   }
-  // target coefficients C = X B^T
+  // target coefficients C = X B^T and the folded expansion matrix
   if ((rc = gemm<float, float>(st, n, K, D, s.X, D, 0, s.Bt, D, 1, s.C, K))) return rc;
+  if ((rc = update_expansion(s, st))) return rc;
+  s.basis_ready = true;
   if (captured_out) {
     // sum ||c_i||^2 / sum ||x_i||^2  (rows of X have unit norm)
     const int64_t ny = (int64_t)n * K;
@@ -618,6 +700,7 @@ int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs,
   if (!sur || !params) return fail(RFD_E_INVALID, "NULL argument");
   Surrogate& s = sur->s;
   if (epochs < 1 || batch < 1 || batch > s.nb || !(lr > 0.f)) return fail(RFD_E_INVALID, "bad training arguments");
+  if (!s.basis_ready) return fail(RFD_E_STATE, "fit or set the basis before training");
   hipStream_t st = s.plan->stream;
   std::mt19937_64 gen(s.seed + 7);
   std::vector<int32_t> perm(s.n);
@@ -713,7 +796,9 @@ int rfd_surrogate_set_state(rfd_surrogate* sur, const float* weights, const floa
     RFD_HIP(hipMemcpyAsync(s.Bt, basis, (size_t)s.K * s.D * sizeof(float), hipMemcpyHostToDevice, st));
     // the training targets are the coefficients on the new basis
     int rc = gemm<float, float>(st, (int)s.n, s.K, s.D, s.X, s.D, 0, s.Bt, s.D, 1, s.C, s.K);
+    if (!rc) rc = update_expansion(s, st);
     if (rc) return rc;
+    s.basis_ready = true;
   }
   int rc = refresh_bf16(s, st);
   if (rc) return rc;
@@ -734,28 +819,31 @@ int rfd_surrogate_make_taps(rfd_surrogate* sur, const float* params, rfd_taps* t
     return fail(RFD_E_INVALID, "target sub-bank must have the training sub-bank's reference, T and k0");
   if (count < 0 || first < 0 || first + count > sb.count) return fail(RFD_E_INVALID, "template range outside the sub-bank");
   if (count == 0) return RFD_OK;
+  if (!s.basis_ready) return fail(RFD_E_STATE, "fit or set the basis before inference");
   Plan& p = *s.plan;
   hipStream_t st = p.stream;
   // the fitted-template norm of the target uses the reference autocorrelation of the training sub-bank
   RFD_HIP(hipMemcpyAsync(sb.g, src.g, sb.T * sizeof(double2), hipMemcpyDeviceToDevice, st));
-  if (!lds_fits((size_t)2 * s.T * sizeof(double2))) return fail(RFD_E_INVALID, "T too large for the device's LDS");
-  float* Xh = nullptr;
   const int64_t chunk = s.nb;
-  int rc = salloc(&Xh, (size_t)chunk * s.D);
-  if (rc) return rc;
+  int rc = RFD_OK;
   for (int64_t c0 = 0; c0 < count && !rc; c0 += chunk) {
     const int cn = (int)std::min<int64_t>(chunk, count - c0);
-    rc = forward(s, st, params + 4 * c0, cn);
-    if (!rc) rc = gemm<float, float>(st, cn, s.D, s.K, s.Y, s.K, 0, s.Bt, s.D, 0, Xh, s.D);
+    rc = stage_begin(p, kStSurNet);
+    if (!rc) rc = forward(s, st, params + 4 * c0, cn);
+    if (!rc) rc = stage_end(p);
+    if (!rc) rc = stage_begin(p, kStSurExpand);
     if (!rc) {
-      hipLaunchKernelGGL(k_unwhiten, dim3((unsigned)cn), dim3(256), (size_t)2 * s.T * sizeof(double2), st, Xh,
-                         (const double2*)src.U, s.T, t.a64 + sb.a_base + (first + c0) * sb.Tp, sb.Tp);
-      if (hipGetLastError() != hipSuccess) rc = fail(RFD_E_DEVICE, "unwhiten launch failed");
+      hipLaunchKernelGGL(k_expand, dim3((unsigned)((cn + kExpandRows - 1) / kExpandRows)), dim3(256), 0, st, s.Y,
+                         cn, s.K, (const double2*)s.Weff, s.Bt, s.T, src.eps, (const double2*)src.g,
+                         t.a64 + sb.a_base + (first + c0) * sb.Tp, sb.Tp, t.sigma_fit + sb.first + first + c0);
+      if (hipGetLastError() != hipSuccess) rc = fail(RFD_E_DEVICE, "expansion launch failed");
     }
+    if (!rc) rc = stage_end(p);
   }
-  if (!rc) rc = taps_norm_and_pack(p, t, subbank, first, count);
+  if (!rc) rc = stage_begin(p, kStSurPack);
+  if (!rc) rc = taps_pack(p, t, subbank, first, count);
+  if (!rc) rc = stage_end(p);
   (void)hipStreamSynchronize(st);
-  sfree(Xh);
   if (rc) return rc;
   for (int64_t i = first; i < first + count; ++i) {
     if (!sb.made_mask[i]) {
@@ -782,11 +870,14 @@ int rfd_taps_match(const rfd_taps* a, const rfd_taps* b, int32_t subbank, int64_
   hipStream_t st = ta.plan->stream;
   if (!lds_fits((size_t)3 * sa.T * sizeof(double2) + 4 * 256 * sizeof(double)))
     return fail(RFD_E_INVALID, "T too large for the device's LDS");
+  Plan& p = *ta.plan;
+  int rc = stage_begin(p, kStMatch);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_match, dim3((unsigned)count), dim3(256), (size_t)3 * sa.T * sizeof(double2), st,
                      ta.a64 + sa.a_base + first * sa.Tp, tb.a64 + sbb.a_base + first * sbb.Tp, sa.Tp, sa.T,
                      (const double2*)sa.g, match_out);
   RFD_CHECK_LAUNCH();
-  return RFD_OK;
+  return stage_end(p);
 }
 
 int rfd_taps_fallback(rfd_taps* target, const rfd_taps* exact, int32_t subbank, int64_t first, int64_t count,

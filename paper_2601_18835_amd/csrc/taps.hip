@@ -232,6 +232,7 @@ int taps_prepare_subbank(Plan& p, Taps& tp, int b, const double* h_ref, double e
 }
 
 int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
+int taps_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
 
 int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, int method) {
   SubBankTaps& s = tp.sb[b];
@@ -260,6 +261,15 @@ int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count) {
   hipLaunchKernelGGL(k_sigma_fit, dim3((unsigned)count), dim3(256), (size_t)2 * T * sizeof(double2), p.stream,
                      abase, (int64_t)s.Tp, T, s.g, sig);
   RFD_CHECK_LAUNCH();
+  return taps_pack(p, tp, b, first, count);
+}
+
+// normalised taps and MFMA packings from a64 and sigma_fit already in place
+int taps_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count) {
+  SubBankTaps& s = tp.sb[b];
+  const int T = s.T;
+  double2* abase = tp.a64 + s.a_base + first * s.Tp;
+  double* sig = tp.sigma_fit + s.first + first;
   int64_t el = count * s.Tp;
   int blocks = (int)((el + 255) / 256 < 8192 ? (el + 255) / 256 : 8192);
   hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, p.stream, abase, (int64_t)s.Tp, sig, s.g, T, s.Tp, first,

@@ -39,8 +39,9 @@ class rfd_plan_info(C.Structure):
 
 class rfd_timing(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms", "findchirp_ms",
-                                          "taps_ms")] + \
-               [(k, C.c_int64) for k in ("n_data_fft", "n_dechirp", "n_fir", "n_compact", "n_findchirp", "n_taps")]
+                                          "taps_ms", "sur_net_ms", "sur_expand_ms", "sur_pack_ms", "match_ms")] + \
+               [(k, C.c_int64) for k in ("n_data_fft", "n_dechirp", "n_fir", "n_compact", "n_findchirp", "n_taps",
+                                         "n_sur_net", "n_sur_expand", "n_sur_pack", "n_match")]
 
 
 class rfd_fir_config(C.Structure):

@@ -223,10 +223,10 @@ def test_inference_matches_oracle(rfd, case):
     a_or = osg.unwhiten(y @ c.B.astype(np.float64), c.L)
     a_gpu = np.stack([rfd.rfd_taps_get(c.sur_taps, j)[0] for j in range(N_TEST)])
     sig_gpu = np.array([rfd.rfd_taps_get(c.sur_taps, j)[1] for j in range(N_TEST)])
-    # FP32 forward (bf16-exact weights) and basis expansion: rounding that
-    # grows like sqrt(terms) over the 2H + K products on the longest path;
-    # then an FP64 back substitution that amplifies relative error by at
-    # most cond(L^H)
+    # FP32 forward (bf16-exact weights): rounding that grows like
+    # sqrt(terms) over the 2H + K products on the longest path; then the
+    # FP64 expansion through L^-H B, which amplifies a relative coefficient
+    # error by at most cond(L^H)
     ev = np.linalg.eigvalsh(c.M + c.lam * np.eye(T))
     cond = float(np.sqrt(ev[-1] / ev[0]))
     tol = cond * 4 * np.sqrt(2 * H + K) * U32

@@ -147,3 +147,33 @@ def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None):
                 assert want[q][0] == got[q][0], f"template {j} window {q}: sample {want[q][0]} vs {got[q][0]}"
                 dmax = max(dmax, abs(want[q][1] - got[q][1]))
     return n_cmp, n_amb, dmax
+
+
+UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22}
+
+
+def tap_gain(case):
+    """||c_j||_1 of the normalised FIR taps c = conj(a) sigma_ref / sigma_fit (oracle taps)."""
+    out = []
+    for sb in case.subbanks:
+        sig_r = case.oracle["refs"][sb.ref].sigma
+        for j in range(sb.H.shape[0]):
+            tt = case.oracle["taps"][len(out)]
+            out.append(np.sum(np.abs(tt.a)) * sig_r / tt.sigma_fit)
+    return np.array(out)
+
+
+def fir_tolerance(case, precision, base):
+    """Per-template bound on |rho_gpu - rho_oracle|.
+
+    To first order, operand rounding reaches the output bounded by
+    u * ||c||_1 * max|zhat| (u the unit roundoff of the form: 2^-24 FP32,
+    2^-16 BF16 hi/lo, 2^-22 FP16 hi/lo), and the FP32 accumulation of 2T
+    real products adds a random walk of about sqrt(2T) 2^-24 max|zhat|; three
+    times their sum, never below `base` (the stated target: 1e-5 FP32, 1e-3
+    mixed).  The target alone holds up to T ~ 256 at the ridge's tap gains;
+    long (T = 1024, 2048), short or windowed taps need the bound."""
+    gain = tap_gain(case)
+    zmax = max(np.max(np.abs(r.z)) / r.sigma for r in case.oracle["refs"].values())
+    taps = np.concatenate([[sb.T] * sb.H.shape[0] for sb in case.subbanks])
+    return np.maximum(base, 3.0 * zmax * (UNIT[precision] * gain + 2.0 ** -24 * np.sqrt(2.0 * taps)))

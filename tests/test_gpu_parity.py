@@ -9,14 +9,14 @@ within the tolerance) are counted and printed.
 import numpy as np
 import pytest
 
-from gpu_cases import (compare_triggers, gpu_search, oracle_case, ragged_case, rho_matrix, workload_case)
+from gpu_cases import (compare_triggers, fir_tolerance, gpu_search, oracle_case, ragged_case, rho_matrix, tap_gain,
+                       workload_case)
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3}
 # unit roundoff of each form's operands: FP32; hi+lo with 8+8 (bf16) or 11+11
 # (fp16) significand bits, the dropped lo*lo term included
-UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22}
 
 
 @pytest.fixture(scope="module")
@@ -121,34 +121,13 @@ def test_findchirp_parity(rfd, small):
     assert n >= 1
 
 
-def tap_gain(case):
-    """||c_j||_1 of the normalised FIR taps c = conj(a) sigma_ref / sigma_fit.
-
-    To first order, operand rounding reaches the output bounded by
-    u * ||c||_1 * max|zhat| per rounded operand (u the unit roundoff of the
-    form), and the FP32 accumulation of 2T real products adds a random walk
-    of about sqrt(2T) u max|z|.  Edge-case taps (very short, very long or
-    windowed, so without the ridge's bound on the gain) get the tolerance
-    max(TOL, 3 u max|zhat| (||c||_1 + sqrt(2T))); the workload tests keep
-    the fixed TOL."""
-    out = []
-    for sb in case.subbanks:
-        sig_r = case.oracle["refs"][sb.ref].sigma
-        for j in range(sb.H.shape[0]):
-            tt = case.oracle["taps"][len(out)]
-            out.append(np.sum(np.abs(tt.a)) * sig_r / tt.sigma_fit)
-    return np.array(out)
-
-
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
 def test_ragged_subbanks_parity(rfd, ragged, precision):
     case, s = ragged
     trig, rho = _validation_rho(rfd, s, case, precision)
     want = np.abs(case.oracle["z"])
     gain = tap_gain(case)
-    zmax = max(np.max(np.abs(r.z)) / r.sigma for r in case.oracle["refs"].values())
-    taps = np.concatenate([[sb.T] * sb.H.shape[0] for sb in case.subbanks])
-    tol = np.maximum(TOL[precision], 3.0 * zmax * (UNIT[precision] * gain + 2.0 ** -24 * np.sqrt(2.0 * taps)))
+    tol = fir_tolerance(case, precision, TOL[precision])
     err_t = np.max(np.abs(rho - want), axis=1)
     print(f"\n[ragged] FIR {precision}: {case.n_templates} templates in {len(case.subbanks)} sub-banks, "
           f"max |drho| = {err_t.max():.3e}; ||c||_1 {gain.min():.1f}..{gain.max():.1f}; "

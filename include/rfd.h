@@ -63,7 +63,8 @@ typedef enum rfd_status {
 typedef enum rfd_precision {
   RFD_FP32 = 0,    /* FP32 operands, FP32 MFMA accumulation */
   RFD_BF16X3 = 1,  /* x = hi + lo in bfloat16; hi*hi + hi*lo + lo*hi, FP32 accumulation */
-  RFD_FP16X3 = 2   /* the same split in IEEE half precision */
+  RFD_FP16X3 = 2,  /* the same split in IEEE half precision */
+  RFD_OLS32 = 3    /* overlap-save FFT blocks (the paper's block realisation), FP32 */
 } rfd_precision;
 
 /* Tap construction route (rfd_make_taps). */
@@ -271,6 +272,9 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
  *   max_tiles   most tiles one workgroup sweeps from one LDS window: 1, 2,
  *               4, 8 or 16 (fewer when the cluster window is shorter).
  *   wg_per_cu   persistent grid size in workgroups per CU (0: all that fit).
+ *   ols_block   RFD_OLS32 block size K: 0 chooses per sub-bank the K in
+ *               {1024, 2048, 4096} of least (5 log2 K + 6) K / (K - T + 1);
+ *               1024, 2048 or 4096 forces it wherever K > T.
  * RFD_E_INVALID for values outside these sets.
  */
 typedef struct rfd_fir_config {
@@ -278,6 +282,7 @@ typedef struct rfd_fir_config {
   int32_t mode;
   int32_t max_tiles;
   int32_t wg_per_cu;
+  int32_t ols_block;
 } rfd_fir_config;
 int rfd_plan_set_fir_config(rfd_plan* plan, const rfd_fir_config* cfg);
 int rfd_plan_get_fir_config(const rfd_plan* plan, rfd_fir_config* cfg);
@@ -311,9 +316,13 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
  * buffers between replays.  Captured on a private stream; replayed on the
  * plan's stream.  Arguments as rfd_dechirp / rfd_filter_bank; h_refs is a
  * host array of n_refs device pointers (complex128 [N/2+1]) for the slots
- * ref_ids.  Changing the plan's FIR configuration needs a new graph.
+ * ref_ids.  Plan, taps and every captured buffer must outlive the graph.
  * rfd_segment_graph_launch replays it; with n_out non-NULL it synchronises
- * and returns the trigger count (RFD_E_OVERFLOW as rfd_filter_bank).
+ * and returns the trigger count (RFD_E_OVERFLOW as rfd_filter_bank).  Taps
+ * re-made after capture are picked up (RFD_OLS32 rebuilds its tap spectra in
+ * place first).  If a later call reallocated a buffer the graph points at
+ * (a filter call with more windows, another FIR configuration), the launch
+ * returns RFD_E_STATE without running: create the graph again.
  */
 typedef struct rfd_graph rfd_graph;
 int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,

@@ -90,11 +90,13 @@ static void plan_free(Plan& p) {
   dfree(p.stilde64); dfree(p.stilde); dfree(p.work64); dfree(p.fref64); dfree(p.dscratch);
   dfree(p.zref); dfree(p.zbf_hi); dfree(p.zbf_lo); dfree(p.zh_hi); dfree(p.zh_lo);
   dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work); dfree(p.counter);
+  dfree(p.ols_tw32); dfree(p.ols_tw64);
 }
 
 static int ensure_slots(Plan& p, int64_t n_slots) {
   if ((size_t)n_slots > p.slots_cap) {
     RFD_HIP(hipStreamSynchronize(p.stream));
+    ++p.res_gen;
     dfree(p.slots);
     p.slots_cap = 0;
     int rc = dalloc(&p.slots, (size_t)n_slots);
@@ -104,6 +106,7 @@ static int ensure_slots(Plan& p, int64_t n_slots) {
   size_t nblk = (size_t)compaction_blocks(n_slots) + 1;
   if (nblk > p.counts_cap) {
     RFD_HIP(hipStreamSynchronize(p.stream));
+    ++p.res_gen;
     dfree(p.counts);
     p.counts_cap = 0;
     int rc = dalloc(&p.counts, nblk);
@@ -133,17 +136,30 @@ static int finish_triggers(Plan& p, int64_t capacity, int64_t* n_out) {
   return RFD_OK;
 }
 
+static bool valid_precision(int precision) {
+  return precision == RFD_FP32 || precision == RFD_BF16X3 || precision == RFD_FP16X3 || precision == RFD_OLS32;
+}
+
 static bool use_persistent(const Plan& p, const Taps& t) {
   return p.fir_mode == 2 || (p.fir_mode == 0 && t.sb.size() > 1);
 }
 
 // FIR kernels of every sub-bank (one persistent launch or one per sub-bank).
 static int enqueue_fir(Plan& p, Taps& t, int precision, int64_t W, int64_t nwin) {
+  if (precision == RFD_OLS32) return launch_ols(p, t, W, nwin);
   if (use_persistent(p, t)) return launch_fir_persistent(p, t, precision, W, nwin);
   for (size_t b = 0; b < t.sb.size(); ++b) {
     int rc = launch_fir(p, t, (int)b, precision, W, nwin);
     if (rc) return rc;
   }
+  return RFD_OK;
+}
+
+// Everything a FIR launch needs that may allocate or build tables (never
+// inside graph capture): persistent work items, overlap-save spectra.
+static int prepare_fir(Plan& p, Taps& t, int precision, int64_t W) {
+  if (precision == RFD_OLS32) return ensure_ols(p, t);
+  if (use_persistent(p, t)) return prepare_fir_items(p, t, precision, W);
   return RFD_OK;
 }
 
@@ -220,6 +236,7 @@ int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, i
   TRY(upload_table(p, kFine, 1, n, &p.tw32f, &p.tw64f));
   TRY(upload_table(p, p.n1, 1, p.n1, &p.tw32_n1, &p.tw64_n1));
   TRY(upload_table(p, p.n2, 1, p.n2, &p.tw32_n2, &p.tw64_n2));
+  TRY(upload_table(p, 4096, 1, 4096, &p.ols_tw32, &p.ols_tw64));
   TRY(dalloc(&p.stilde64, nb));
   TRY(dalloc(&p.stilde, nb));
   TRY(dalloc(&p.work64, n));
@@ -306,11 +323,14 @@ int rfd_plan_set_fir_config(rfd_plan* plan, const rfd_fir_config* cfg) {
   const int mt = cfg->max_tiles;
   if (!(mt == 1 || mt == 2 || mt == 4 || mt == 8 || mt == 16)) return fail(RFD_E_INVALID, "max_tiles must be 1..16, a power of two");
   if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 32) return fail(RFD_E_INVALID, "wg_per_cu must be in [0, 32]");
+  if (!(cfg->ols_block == 0 || cfg->ols_block == 1024 || cfg->ols_block == 2048 || cfg->ols_block == 4096))
+    return fail(RFD_E_INVALID, "ols_block must be 0, 1024, 2048 or 4096");
   Plan& p = plan->p;
   p.fir_nb16 = cfg->col_blocks;
   p.fir_mode = cfg->mode;
   p.fir_smax = mt;
   p.fir_wg_per_cu = cfg->wg_per_cu;
+  p.ols_block = cfg->ols_block;
   return RFD_OK;
 }
 
@@ -320,6 +340,7 @@ int rfd_plan_get_fir_config(const rfd_plan* plan, rfd_fir_config* cfg) {
   cfg->mode = plan->p.fir_mode;
   cfg->max_tiles = plan->p.fir_smax;
   cfg->wg_per_cu = plan->p.fir_wg_per_cu;
+  cfg->ols_block = plan->p.ols_block;
   return RFD_OK;
 }
 
@@ -329,8 +350,7 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
   Plan& p = plan->p;
   Taps& t = const_cast<Taps&>(taps->t);
   if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
-  if (precision != RFD_FP32 && precision != RFD_BF16X3 && precision != RFD_FP16X3)
-    return fail(RFD_E_INVALID, "unknown precision");
+  if (!valid_precision(precision)) return fail(RFD_E_INVALID, "unknown precision");
   if (cluster_window < 1 || cluster_window > p.n) return fail(RFD_E_INVALID, "cluster_window must satisfy 1 <= W <= N");
   if (reps < 1 || reps > 100) return fail(RFD_E_INVALID, "reps must be in [1, 100]");
   int rc = check_bank_state(p, t);
@@ -345,10 +365,8 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
   auto measure = [&](const rfd_fir_config& c, double& ms) -> int {
     int r = rfd_plan_set_fir_config(plan, &c);
     if (r) return r;
-    if (use_persistent(p, t)) {
-      r = prepare_fir_items(p, t, precision, cluster_window);
-      if (r) return r;
-    }
+    r = prepare_fir(p, t, precision, cluster_window);
+    if (r) return r;
     hipEvent_t a, b;
     RFD_HIP(hipEventCreate(&a));
     RFD_HIP(hipEventCreate(&b));
@@ -375,11 +393,25 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
   int n = 1;
   const int nbs16[2] = {8, 16};
   const int tiles[3] = {4, 8, 16};
-  for (int ib = 0; ib < 2; ++ib) {
+  if (precision == RFD_OLS32) {
+    // overlap-save: the block size (per sub-bank cost model, or one K for all)
+    const int blocks[4] = {0, 1024, 2048, 4096};
+    for (int ib = 0; ib < 4; ++ib) {
+      rfd_fir_config c = before;
+      c.ols_block = blocks[ib];
+      double ms = 0.0;
+      rc = measure(c, ms);
+      if (rc) { rfd_plan_set_fir_config(plan, &before); p.timing = saved_timing; return rc; }
+      ++n;
+      if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+  }
+  for (int ib = 0; ib < 2 && precision != RFD_OLS32; ++ib) {
     if (precision == RFD_FP32 && ib > 0) break;
     for (int it = 0; it < 3; ++it) {
-      const rfd_fir_config cands[3] = {{nbs16[ib], 1, tiles[it], 0}, {nbs16[ib], 2, tiles[it], 0},
-                                       {nbs16[ib], 2, tiles[it], 1}};
+      const rfd_fir_config cands[3] = {{nbs16[ib], 1, tiles[it], 0, before.ols_block},
+                                       {nbs16[ib], 2, tiles[it], 0, before.ols_block},
+                                       {nbs16[ib], 2, tiles[it], 1, before.ols_block}};
       for (const auto& c : cands) {
         double ms = 0.0;
         rc = measure(c, ms);
@@ -450,6 +482,8 @@ static void taps_free(Taps& t) {
     dfree(s.L);
     dfree(s.U);
     dfree(s.g);
+    dfree(s.ols_x);
+    dfree(s.ols_g);
   }
   dfree(t.a64); dfree(t.sigma_fit); dfree(t.c32); dfree(t.pbf); dfree(t.pfh); dfree(t.p32);
   dfree(t.d_first); dfree(t.d_meta); dfree(t.d_abase); dfree(t.work64); dfree(t.bvec);
@@ -659,8 +693,7 @@ int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, flo
   Plan& p = plan->p;
   const Taps& t = taps->t;
   if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
-  if (precision != RFD_FP32 && precision != RFD_BF16X3 && precision != RFD_FP16X3)
-    return fail(RFD_E_INVALID, "unknown precision");
+  if (!valid_precision(precision)) return fail(RFD_E_INVALID, "unknown precision");
   int rc = check_filter_args(p, threshold, cluster_window, out, capacity, n_out);
   if (rc) return rc;
   rc = check_bank_state(p, t);
@@ -670,10 +703,8 @@ int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, flo
   const int64_t n_slots = t.n_templates * nwin;
   rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
   if (rc) return rc;
-  if (use_persistent(p, t)) {
-    rc = prepare_fir_items(p, tm, precision, cluster_window);
-    if (rc) return rc;
-  }
+  rc = prepare_fir(p, tm, precision, cluster_window);
+  if (rc) return rc;
   rc = launch_slots_clear(p, n_slots);
   if (rc) return rc;
   rc = stage_begin(p, kStFir);
@@ -762,10 +793,13 @@ int findchirp_filter(rfd_plan* plan, const double* data, const float* filt, int6
 
 struct rfd_graph {
   rfd_plan* plan = nullptr;
+  rfd::Taps* taps = nullptr;
+  int precision = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<int32_t> ref_ids;
   int64_t capacity = 0;
+  int64_t plan_gen = 0, taps_gen = 0;   // buffer generations the capture saw
 };
 
 int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
@@ -777,8 +811,7 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
   Plan& p = plan->p;
   Taps& t = const_cast<Taps&>(taps->t);
   if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
-  if (precision != RFD_FP32 && precision != RFD_BF16X3 && precision != RFD_FP16X3)
-    return fail(RFD_E_INVALID, "unknown precision");
+  if (!valid_precision(precision)) return fail(RFD_E_INVALID, "unknown precision");
   int64_t dummy = 0;
   int rc = check_filter_args(p, threshold, cluster_window, out, capacity, &dummy);
   if (rc) return rc;
@@ -797,10 +830,8 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
   const int64_t n_slots = t.n_templates * nwin;
   rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
   if (rc) return rc;
-  if (use_persistent(p, t)) {
-    rc = prepare_fir_items(p, t, precision, cluster_window);
-    if (rc) return rc;
-  }
+  rc = prepare_fir(p, t, precision, cluster_window);
+  if (rc) return rc;
   RFD_HIP(hipStreamSynchronize(p.stream));
   hipStream_t cap = nullptr;
   RFD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -835,6 +866,10 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
     return fail(RFD_E_NOMEM, "host allocation failed");
   }
   h->plan = plan;
+  h->taps = &t;
+  h->precision = precision;
+  h->plan_gen = p.res_gen;
+  h->taps_gen = t.res_gen;
   h->graph = g;
   h->ref_ids.assign(ref_ids, ref_ids + n_refs);
   h->capacity = capacity;
@@ -850,6 +885,13 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
 int rfd_segment_graph_launch(rfd_graph* graph, int64_t* n_out) {
   if (!graph) return fail(RFD_E_INVALID, "graph is NULL");
   Plan& p = graph->plan->p;
+  if (graph->precision == RFD_OLS32) {
+    int rc = ensure_ols(p, *graph->taps, false);   // tap spectra of re-made taps, in place
+    if (rc) return rc;
+  }
+  if (p.res_gen != graph->plan_gen || graph->taps->res_gen != graph->taps_gen)
+    return fail(RFD_E_STATE, "buffers were reallocated since capture (more windows or another FIR configuration); "
+                             "create the graph again");
   RFD_HIP(hipGraphLaunch(graph->exec, p.stream));
   ++p.seg_gen;
   for (int32_t r : graph->ref_ids) p.ref_gen[r] = p.seg_gen;

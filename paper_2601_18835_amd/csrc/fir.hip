@@ -436,6 +436,7 @@ int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W) {
   if (tp.it_key_W == W && tp.it_key_cols == cols && tp.it_key_smax == p.fir_smax && tp.it_key_prec == precision &&
       tp.it_key_wg == p.fir_wg_per_cu)
     return RFD_OK;
+  ++tp.res_gen;   // the tables below are reallocated
   const int nsb = (int)tp.sb.size();
   std::vector<int> order;
   for (int b = 0; b < nsb; ++b)

@@ -1,0 +1,425 @@
+// Ratio FIR of Eq. 3 by overlap-save block convolution in the frequency
+// domain: the paper's own realisation of the short filter (blocks of K
+// samples, K a small power of two, FFT-based), here on one workgroup per
+// group of blocks.
+//
+// With L = K - T + 1 valid outputs per block, block b's input is
+//   x_b[m] = zhat[(b L + k0 + m) mod N],  m < K,
+// and its outputs z_j[b L + i], i < L, are the first L samples of the
+// circular correlation of x_b with the taps:
+//   z_j[b L + i] = sum_k c_k x_b[i + k] = (1/K) sum_f X_b[f] G_j[f] e^{+2 pi i f i / K},
+//   X_b[f] = sum_m x_b[m] e^{-2 pi i f m / K},   G_j[f] = sum_k c_k e^{+2 pi i f k / K}.
+// X_b is computed once per reference series and segment (all blocks), G_j
+// once per tap set (FP64 sum, stored with the 1/K in FP32).  The main kernel
+// multiplies, runs one K-point inverse FFT per (template, block) in registers
+// and LDS, and feeds the same window-peak keys as the MFMA forms.
+//
+// FFT: K = 256 R (R = 4, 8, 16) by NTf = K/16 threads, 16 values each,
+// index m = t + NTf r:  a radix-16 stage over r in registers, an LDS
+// exchange, a radix-16 stage, an LDS exchange, a radix-R stage.  F = 256/NTf
+// independent FFTs share a workgroup.
+#include <math.h>
+
+#include <algorithm>
+
+#include "dev_common.h"
+#include "rfd_internal.h"
+
+namespace rfd {
+
+// Window-peak key of one output sample: bits(rho^2) above the complement of
+// its offset in the window (largest rho^2 wins, then the earliest sample).
+__device__ __forceinline__ unsigned long long offset_key_ols(float r2, uint32_t off) {
+  return ((unsigned long long)__float_as_uint(r2) << 32) | (unsigned long long)(0xFFFFFFFFu - off);
+}
+// windows one block may touch before the epilogue switches to per-sample atomics
+constexpr int kOlsMaxWin = 8;
+__device__ __forceinline__ unsigned long long umax64_ols(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+
+// cos / sin (2 pi k / 16), k < 16
+__device__ __forceinline__ float2 w16(int k, int sign) {
+  constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                           0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                           -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                           0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+  return make_float2(c[k & 15], sign * c[(k + 12) & 15]);   // sin x = cos(x - pi/2)
+}
+
+// 16-point DFT in registers, V[k] = sum_n v[n] e^{sign 2 pi i n k / 16}.
+// On return slot s holds V[(s >> 2) + 4 (s & 3)].
+template <int SIGN>
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) dft4(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12], SIGN);
+#pragma unroll
+  for (int n1 = 1; n1 < 4; ++n1)
+#pragma unroll
+    for (int k = 1; k < 4; ++k) v[n1 + 4 * k] = cmul(v[n1 + 4 * k], w16(n1 * k, SIGN));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dft4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3], SIGN);
+}
+__device__ __forceinline__ constexpr int dft16_freq(int s) { return (s >> 2) + 4 * (s & 3); }
+
+// R-point DFTs (R = 4, 8, 16) on consecutive groups of R slots of v; slot
+// g R + s holds V_g[dftR_freq(s)].
+template <int R, int SIGN>
+__device__ __forceinline__ void dft_r(float2 (&v)[16]) {
+  if constexpr (R == 16) {
+    dft16<SIGN>(v);
+  } else if constexpr (R == 4) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) dft4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3], SIGN);
+  } else {   // R == 8: n = n1 + 2 n2, DFT4 over n2, twiddle, DFT2 over n1
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      float2* u = v + 8 * g;
+      dft4(u[0], u[2], u[4], u[6], SIGN);
+      dft4(u[1], u[3], u[5], u[7], SIGN);
+#pragma unroll
+      for (int k = 1; k < 4; ++k) u[2 * k + 1] = cmul(u[2 * k + 1], w16(2 * k, SIGN));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float2 a = u[2 * k], b = u[2 * k + 1];
+        u[2 * k] = cadd(a, b);
+        u[2 * k + 1] = csub(a, b);
+      }
+    }
+  }
+}
+template <int R>
+__device__ __forceinline__ constexpr int dftr_freq(int s) {
+  return R == 16 ? dft16_freq(s) : (R == 4 ? s : (s >> 1) + 4 * (s & 1));
+}
+
+template <int K>
+struct OlsShape {
+  static constexpr int NTf = K / 16;       // threads per FFT
+  static constexpr int R = K / 256;        // last radix
+  static constexpr int F = 256 / NTf;      // FFTs per workgroup
+  static constexpr int S1 = NTf + 1;       // row stride of exchange 1 ([k1][t])
+  static constexpr int S2 = R + 1;         // row stride of exchange 2 ([k2][k1][u])
+  static constexpr int LDS = (16 * S1 > 256 * S2 ? 16 * S1 : 256 * S2);   // float2 per FFT
+};
+
+// Per-thread twiddles: stage A  W_K^(t k1), stage B  W_K^(16 u k2), k = 1..15.
+template <int K>
+struct OlsTw {
+  float2 a[16], b[16];
+};
+template <int K, int SIGN>
+__device__ __forceinline__ void ols_twiddles(OlsTw<K>& w, const float2* __restrict__ tw, int t) {
+  using S = OlsShape<K>;
+  constexpr int step = 4096 / K;
+  const int u = t % S::R;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float2 x = tw[((t * k) % K) * step];
+    float2 y = tw[((16 * u * k) % K) * step];
+    if (SIGN < 0) { x.y = -x.y; y.y = -y.y; }
+    w.a[k] = x;
+    w.b[k] = y;
+  }
+}
+
+// K-point DFT of v (thread t of its FFT holds x[t + NTf r] in v[r]) with
+// sign SIGN.  On return v[e * R + s] holds X[out_index(t, e, s)].  All
+// threads of the workgroup call it together (it synchronises).
+template <int K, int SIGN>
+__device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, const OlsTw<K>& w) {
+  using S = OlsShape<K>;
+  constexpr int NTf = S::NTf, R = S::R;
+  // stage A: radix 16 over r
+  dft16<SIGN>(v);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k1 = dft16_freq(s);
+    buf[k1 * S::S1 + t] = k1 ? cmul(v[s], w.a[k1]) : v[s];
+  }
+  __syncthreads();
+  // stage B: thread (k1, u) = (t / R, t % R), radix 16 over v of t' = u + R v
+  {
+    const int k1 = t / R, u = t % R;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = buf[k1 * S::S1 + u + R * q];
+  }
+  __syncthreads();
+  dft16<SIGN>(v);
+  {
+    const int k1 = t / R, u = t % R;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k2 = dft16_freq(s);
+      buf[(k2 * 16 + k1) * S::S2 + u] = k2 ? cmul(v[s], w.b[k2]) : v[s];
+    }
+  }
+  __syncthreads();
+  // stage C: thread (k1, g) = (t / R, t % R) takes k2 = g (16/R) + e, radix R over u
+  {
+    const int k1 = t / R, g = t % R;
+#pragma unroll
+    for (int e = 0; e < 16 / R; ++e) {
+      const int k2 = g * (16 / R) + e;
+#pragma unroll
+      for (int u = 0; u < R; ++u) v[e * R + u] = buf[(k2 * 16 + k1) * S::S2 + u];
+    }
+  }
+  __syncthreads();
+  dft_r<R, SIGN>(v);
+}
+
+// Output index of slot e * R + s of thread t after ols_fft.
+template <int K>
+__device__ __forceinline__ int ols_out_index(int t, int e, int s) {
+  using S = OlsShape<K>;
+  const int k1 = t / S::R, g = t % S::R;
+  const int k2 = g * (16 / S::R) + e;
+  return k1 + 16 * k2 + 256 * dftr_freq<S::R>(s);
+}
+
+// ------------------------------------------------------------ block spectra
+// X[b][f] for every block b of the reference series (forward FFT).
+template <int K>
+__global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
+                                            const float2* __restrict__ tw, float2* __restrict__ X) {
+  using S = OlsShape<K>;
+  __shared__ float2 lds[S::F * S::LDS];
+  const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
+  const int64_t b = (int64_t)blockIdx.x * S::F + f;
+  OlsTw<K> w;
+  ols_twiddles<K, -1>(w, tw, t);
+  float2 v[16];
+  const int64_t start = b * L + k0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = b < nB ? z[(start + t + S::NTf * r) & (n - 1)] : make_float2(0.f, 0.f);
+  ols_fft<K, -1>(v, lds + f * S::LDS, t, w);
+  if (b >= nB) return;
+  float2* xb = X + b * K;
+#pragma unroll
+  for (int e = 0; e < 16 / S::R; ++e)
+#pragma unroll
+    for (int s = 0; s < S::R; ++s) xb[ols_out_index<K>(t, e, s)] = v[e * S::R + s];
+}
+
+// --------------------------------------------------------- tap spectra (FP64)
+// G_j[f] = (1/K) sum_k c_k e^{+2 pi i f k / K}, c = the normalised FP32 taps.
+__global__ __launch_bounds__(256) void k_ols_g(const float2* __restrict__ c32, int Tp, int T, int K,
+                                            const double2* __restrict__ tw64, float2* __restrict__ G) {
+  extern __shared__ double2 cs[];
+  const float2* cj = c32 + (int64_t)blockIdx.x * Tp;
+  for (int k = threadIdx.x; k < T; k += 256) cs[k] = make_double2((double)cj[k].x, (double)cj[k].y);
+  __syncthreads();
+  const int step = 4096 / K;
+  const double inv = 1.0 / K;
+  float2* gj = G + (int64_t)blockIdx.x * K;
+  for (int f = threadIdx.x; f < K; f += 256) {
+    double re = 0.0, im = 0.0;
+    int idx = 0;                           // (f k) mod K
+    for (int k = 0; k < T; ++k) {
+      const double2 e = tw64[idx * step];
+      re += cs[k].x * e.x - cs[k].y * e.y;
+      im += cs[k].x * e.y + cs[k].y * e.x;
+      idx += f;
+      if (idx >= K) idx -= K;
+    }
+    gj[f] = make_float2((float)(re * inv), (float)(im * inv));
+  }
+}
+
+// -------------------------------------------------------------- main kernel
+struct OlsArgs {
+  const float2* X;           // [nB][K] block spectra of this sub-bank's series
+  const float2* G;           // [count][K] tap spectra
+  const float2* tw;          // exp(+2 pi i m / 4096), m < 4096
+  unsigned long long* slots;
+  int64_t n, count, tmpl0, nwin, W, nB;
+  int L, J;                  // valid outputs per block, templates per workgroup
+};
+
+template <int K>
+__device__ __forceinline__ unsigned long long ols_reduce(unsigned long long k) {
+  constexpr int NTf = OlsShape<K>::NTf;
+  constexpr int span = NTf < 64 ? NTf : 64;
+#pragma unroll
+  for (int o = 1; o < span; o <<= 1) k = umax64_ols(k, __shfl_xor(k, o));
+  return k;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
+  using S = OlsShape<K>;
+  __shared__ float2 lds[S::F * S::LDS];
+  const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
+  const int64_t b = (int64_t)blockIdx.x * S::F + f;
+  const bool bvalid = b < a.nB;
+  OlsTw<K> w;
+  ols_twiddles<K, 1>(w, a.tw, t);
+  float2 xb[16];
+  const float2* Xb = a.X + (bvalid ? b : 0) * K;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) xb[r] = Xb[t + S::NTf * r];
+  // this block's output samples and their windows (uniform per FFT)
+  const int64_t n0 = b * a.L;
+  const int64_t nend = std::min<int64_t>(n0 + a.L, a.n);
+  const int64_t q0 = n0 / a.W, q1 = bvalid ? (nend - 1) / a.W : q0;
+  const int64_t j0 = (int64_t)blockIdx.y * a.J;
+  const int64_t j1 = std::min<int64_t>(j0 + a.J, a.count);
+  const bool lead = (threadIdx.x & 63) == 0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const float2* gj = a.G + j * K;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gj[t + S::NTf * r]);
+    ols_fft<K, 1>(v, lds + f * S::LDS, t, w);
+    if (!bvalid) continue;
+    unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
+    float r2[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) r2[q] = v[q].x * v[q].x + v[q].y * v[q].y;
+    if (q1 - q0 < kOlsMaxWin) {
+      // one reduction and one atomic per window the block touches
+      for (int64_t qw = q0; qw <= q1; ++qw) {
+        const int64_t ws = qw * a.W, we = std::min<int64_t>(ws + a.W, nend);
+        unsigned long long k = 0;
+#pragma unroll
+        for (int e = 0; e < 16 / S::R; ++e)
+#pragma unroll
+          for (int s = 0; s < S::R; ++s) {
+            const int64_t nn = n0 + ols_out_index<K>(t, e, s);
+            if (nn >= ws && nn < we) k = umax64_ols(k, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - ws)));
+          }
+        k = ols_reduce<K>(k);
+        if (lead) atomicMax(slot + qw, k);
+      }
+    } else {
+      // windows shorter than a block / kOlsMaxWin: one atomic per sample
+#pragma unroll
+      for (int e = 0; e < 16 / S::R; ++e)
+#pragma unroll
+        for (int s = 0; s < S::R; ++s) {
+          const int64_t nn = n0 + ols_out_index<K>(t, e, s);
+          if (nn < nend) {
+            const int64_t q = nn / a.W;
+            atomicMax(slot + q, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - q * a.W)));
+          }
+        }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host
+int ols_block_size(const Plan& p, int T) {
+  if (p.ols_block > T) return p.ols_block;
+  int best = 4096;
+  double best_cost = 1e30;
+  for (int K = 1024; K <= 4096; K *= 2) {
+    if (K <= T) continue;
+    const double cost = (5.0 * std::log2((double)K) + 6.0) * K / (double)(K - T + 1);
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = K;
+    }
+  }
+  return best;
+}
+
+static int ols_templates_per_wg(int64_t nB, int F, int64_t count, int n_cu) {
+  // enough workgroups to fill the chip several times, at least 4 templates each
+  const int64_t gx = (nB + F - 1) / F;
+  int J = 32;
+  while (J > 4 && gx * ((count + J - 1) / J) < (int64_t)8 * n_cu) J /= 2;
+  return J;
+}
+
+int ensure_ols(Plan& p, Taps& t, bool allow_alloc) {
+  for (size_t bi = 0; bi < t.sb.size(); ++bi) {
+    SubBankTaps& s = t.sb[bi];
+    if (s.count == 0) continue;
+    const int K = ols_block_size(p, s.T);
+    const int L = K - s.T + 1;
+    const int64_t nB = (p.n + L - 1) / L;
+    const bool need_x = s.ols_x == nullptr || s.ols_x_cap < nB * K;
+    const bool need_g = s.ols_g == nullptr || s.ols_K != K;
+    if ((need_x || need_g) && !allow_alloc)
+      return fail(RFD_E_STATE, "overlap-save buffers changed since capture; create the graph again");
+    if (need_x || need_g) ++t.res_gen;
+    if (need_x) {
+      RFD_HIP(hipStreamSynchronize(p.stream));
+      if (s.ols_x) (void)hipFree(s.ols_x);
+      s.ols_x = nullptr;
+      if (hipMalloc((void**)&s.ols_x, (size_t)nB * K * sizeof(float2)) != hipSuccess) {
+        s.ols_x = nullptr;
+        (void)hipGetLastError();
+        return fail(RFD_E_NOMEM, "overlap-save block spectra: hipMalloc failed");
+      }
+      s.ols_x_cap = nB * K;
+    }
+    if (need_g) {
+      RFD_HIP(hipStreamSynchronize(p.stream));
+      if (s.ols_g) (void)hipFree(s.ols_g);
+      s.ols_g = nullptr;
+      if (hipMalloc((void**)&s.ols_g, (size_t)s.count * K * sizeof(float2)) != hipSuccess) {
+        s.ols_g = nullptr;
+        (void)hipGetLastError();
+        return fail(RFD_E_NOMEM, "overlap-save tap spectra: hipMalloc failed");
+      }
+      s.ols_valid = false;
+    }
+    s.ols_K = K;
+    s.ols_L = L;
+    s.ols_nB = nB;
+    if (!s.ols_valid) {
+      hipLaunchKernelGGL(k_ols_g, dim3((unsigned)s.count), dim3(256), (size_t)s.T * sizeof(double2), p.stream,
+                         t.c32 + s.a_base, s.Tp, s.T, K, (const double2*)p.ols_tw64, s.ols_g);
+      RFD_CHECK_LAUNCH();
+      s.ols_valid = true;
+    }
+  }
+  return RFD_OK;
+}
+
+template <int K>
+static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin) {
+  using S = OlsShape<K>;
+  const float2* z = p.zref + (int64_t)s.ref_id * p.n;
+  const unsigned gx = (unsigned)((s.ols_nB + S::F - 1) / S::F);
+  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, s.ols_nB,
+                     (const float2*)p.ols_tw32, s.ols_x);
+  RFD_CHECK_LAUNCH();
+  OlsArgs a;
+  a.X = s.ols_x;
+  a.G = s.ols_g;
+  a.tw = p.ols_tw32;
+  a.slots = p.slots;
+  a.n = p.n;
+  a.count = s.count;
+  a.tmpl0 = s.first;
+  a.nwin = nwin;
+  a.W = W;
+  a.nB = s.ols_nB;
+  a.L = s.ols_L;
+  a.J = ols_templates_per_wg(s.ols_nB, S::F, s.count, p.n_cu);
+  const unsigned gy = (unsigned)((s.count + a.J - 1) / a.J);
+  hipLaunchKernelGGL(k_ols<K>, dim3(gx, gy), dim3(256), 0, p.stream, a);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin) {
+  for (const SubBankTaps& s : t.sb) {
+    if (s.count == 0) continue;
+    if (!s.ols_valid || !s.ols_x) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
+    int rc;
+    switch (s.ols_K) {
+      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin); break;
+      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin); break;
+      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin); break;
+      default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
+    }
+    if (rc) return rc;
+  }
+  return RFD_OK;
+}
+
+}  // namespace rfd

@@ -73,7 +73,14 @@ struct Plan {
   // persistent grid: workgroups per CU (0: as many as fit)
   int fir_wg_per_cu = 0;
   int n_cu = 0;
+  // bumped whenever a buffer a captured graph may point at is reallocated
+  int64_t res_gen = 0;
   unsigned long long* counter = nullptr;   // persistent work-queue counter
+  // overlap-save FIR: block size (0: per sub-bank by cost model) and
+  // exp(+2 pi i m / 4096), m < 4096, in FP32 and FP64
+  int ols_block = 0;
+  float2* ols_tw32 = nullptr;
+  double2* ols_tw64 = nullptr;
 
   // optional stage timing (hipEvent pairs on `stream`)
   bool timing = false;
@@ -103,6 +110,13 @@ struct SubBankTaps {
   double eps = -1.0;                // ridge of the cached factor
   int64_t made = 0;                 // templates whose taps exist
   std::vector<uint8_t> made_mask;
+  // overlap-save FIR state: block spectra of the series (rebuilt every
+  // filter call), tap spectra (rebuilt after the taps change)
+  int ols_K = 0, ols_L = 0;
+  int64_t ols_nB = 0, ols_x_cap = 0;
+  float2* ols_x = nullptr;
+  float2* ols_g = nullptr;
+  bool ols_valid = false;
 };
 
 struct Taps {
@@ -124,6 +138,8 @@ struct Taps {
   int64_t* d_it_off = nullptr; int32_t* d_it_sb = nullptr; int32_t* d_it_S = nullptr; int64_t* d_it_nsg = nullptr;
   int64_t it_key_W = -1; int it_key_cols = -1; int it_key_smax = -1; int it_key_prec = -1; int it_key_wg = -1;
   int64_t it_total = 0; int it_nsb = 0; size_t it_lds = 0; int it_grid = 1;
+  // bumped whenever a buffer a captured graph may point at is reallocated
+  int64_t res_gen = 0;
   // scratch for tap construction
   double2* work64 = nullptr; size_t work64_cap = 0;
   double2* bvec = nullptr; size_t bvec_cap = 0;
@@ -157,6 +173,14 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
 // must not be called for the first time with a given key inside graph capture)
 int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W);
 int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin);
+
+// ----------------------------------------------------- launchers (ols.hip)
+int ols_block_size(const Plan& p, int T);
+// allocate block / tap spectra (only if allow_alloc; else RFD_E_STATE when one
+// is missing) and rebuild stale tap spectra in place (not inside capture)
+int ensure_ols(Plan& p, Taps& t, bool allow_alloc = true);
+// block spectra + overlap-save FIR of every sub-bank
+int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin);
 
 // ------------------------------------------------ launchers (triggers.hip)
 int launch_slots_clear(Plan& p, int64_t n_slots);

@@ -267,6 +267,7 @@ int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count) {
 // normalised taps and MFMA packings from a64 and sigma_fit already in place
 int taps_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count) {
   SubBankTaps& s = tp.sb[b];
+  s.ols_valid = false;   // the overlap-save tap spectra follow the packed taps
   const int T = s.T;
   double2* abase = tp.a64 + s.a_base + first * s.Tp;
   double* sig = tp.sigma_fit + s.first + first;

@@ -21,10 +21,10 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 RFD_OK, RFD_E_INVALID, RFD_E_NOMEM, RFD_E_DEVICE, RFD_E_OVERFLOW, RFD_E_STATE, RFD_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-RFD_FP32, RFD_BF16X3, RFD_FP16X3 = 0, 1, 2
+RFD_FP32, RFD_BF16X3, RFD_FP16X3, RFD_OLS32 = 0, 1, 2, 3
 RFD_TAPS_LS, RFD_TAPS_WINDOW = 0, 1
 RFD_MAX_TAPS = 2048
-PRECISIONS = {"fp32": RFD_FP32, "bf16x3": RFD_BF16X3, "fp16x3": RFD_FP16X3}
+PRECISIONS = {"fp32": RFD_FP32, "bf16x3": RFD_BF16X3, "fp16x3": RFD_FP16X3, "ols32": RFD_OLS32}
 
 TRIGGER_DTYPE = np.dtype([("sample", "<i8"), ("tmpl", "<i4"), ("subbank", "<i4"), ("rho", "<f4"),
                           ("z_re", "<f4"), ("z_im", "<f4"), ("flags", "<u4")])
@@ -45,7 +45,8 @@ class rfd_timing(C.Structure):
 
 
 class rfd_fir_config(C.Structure):
-    _fields_ = [("col_blocks", C.c_int32), ("mode", C.c_int32), ("max_tiles", C.c_int32), ("wg_per_cu", C.c_int32)]
+    _fields_ = [("col_blocks", C.c_int32), ("mode", C.c_int32), ("max_tiles", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("ols_block", C.c_int32)]
 
 
 class rfd_tune_result(C.Structure):
@@ -174,8 +175,8 @@ def _cfg_dict(c):
     return {k: getattr(c, k) for k, _ in rfd_fir_config._fields_}
 
 
-def rfd_plan_set_fir_config(plan, col_blocks=8, mode=0, max_tiles=16, wg_per_cu=0):
-    c = rfd_fir_config(col_blocks, mode, max_tiles, wg_per_cu)
+def rfd_plan_set_fir_config(plan, col_blocks=8, mode=0, max_tiles=16, wg_per_cu=0, ols_block=0):
+    c = rfd_fir_config(col_blocks, mode, max_tiles, wg_per_cu, ols_block)
     _check(_lib.rfd_plan_set_fir_config(plan, C.byref(c)), "rfd_plan_set_fir_config")
 
 

@@ -149,21 +149,31 @@ def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None):
     return n_cmp, n_amb, dmax
 
 
-UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22}
+UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22, "ols32": 2.0 ** -24}
 
 
-def tap_gain(case):
-    """||c_j||_1 of the normalised FIR taps c = conj(a) sigma_ref / sigma_fit (oracle taps)."""
+def ols_block(T, forced=0):
+    """Block size of the overlap-save form for T taps: `forced` where it
+    exceeds T, else the K in {1024, 2048, 4096} (K > T) of least
+    (5 log2 K + 6) K / (K - T + 1)."""
+    if forced > T:
+        return forced
+    cands = [K for K in (1024, 2048, 4096) if K > T]
+    return min(cands, key=lambda K: ((5 * np.log2(K) + 6) * K / (K - T + 1), K))
+
+
+def tap_gain(case, norm=1):
+    """||c_j||_1 (or ||c_j||_2) of the normalised FIR taps c = conj(a) sigma_ref / sigma_fit (oracle taps)."""
     out = []
     for sb in case.subbanks:
         sig_r = case.oracle["refs"][sb.ref].sigma
         for j in range(sb.H.shape[0]):
             tt = case.oracle["taps"][len(out)]
-            out.append(np.sum(np.abs(tt.a)) * sig_r / tt.sigma_fit)
+            out.append(np.linalg.norm(tt.a, ord=norm) * sig_r / tt.sigma_fit)
     return np.array(out)
 
 
-def fir_tolerance(case, precision, base):
+def fir_tolerance(case, precision, base, ols_forced=0):
     """Per-template bound on |rho_gpu - rho_oracle|.
 
     To first order, operand rounding reaches the output bounded by
@@ -172,8 +182,14 @@ def fir_tolerance(case, precision, base):
     real products adds a random walk of about sqrt(2T) 2^-24 max|zhat|; three
     times their sum, never below `base` (the stated target: 1e-5 FP32, 1e-3
     mixed).  The target alone holds up to T ~ 256 at the ridge's tap gains;
-    long (T = 1024, 2048), short or windowed taps need the bound."""
+    long (T = 1024, 2048), short or windowed taps need the bound.  The
+    overlap-save form adds its FFTs: about 2 log2 K FP32 butterfly levels,
+    each rounding values of size ||c||_2 max|zhat|."""
     gain = tap_gain(case)
     zmax = max(np.max(np.abs(r.z)) / r.sigma for r in case.oracle["refs"].values())
     taps = np.concatenate([[sb.T] * sb.H.shape[0] for sb in case.subbanks])
-    return np.maximum(base, 3.0 * zmax * (UNIT[precision] * gain + 2.0 ** -24 * np.sqrt(2.0 * taps)))
+    tol = 3.0 * zmax * (UNIT[precision] * gain + 2.0 ** -24 * np.sqrt(2.0 * taps))
+    if precision == "ols32":
+        K = np.array([ols_block(T, ols_forced) for T in taps], dtype=np.float64)
+        tol = tol + 3.0 * zmax * 2.0 ** -24 * 2.0 * np.log2(K) * tap_gain(case, 2)
+    return np.maximum(base, tol)

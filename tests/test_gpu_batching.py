@@ -77,6 +77,39 @@ def test_segment_graph_replays_match_eager(rfd, ragged):
         s.dechirp_all()
 
 
+def test_graph_refuses_to_run_after_its_buffers_move(rfd, ragged):
+    """A configuration change rebuilds the persistent work-item tables the
+    graph captured: the replay is refused on the host (nothing runs), and a
+    new graph works."""
+    import torch
+    case, s = ragged
+    th, W, cap = 2.5, 300, 1 << 16
+    s.dechirp_all()
+    rfd.rfd_plan_set_fir_config(s.plan, 8, 2, 16, 0)
+    out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    g = rfd.rfd_segment_graph_create(s.plan, s.taps, "bf16x3", th, W, s.data, s.h_ref, out, cap)
+    try:
+        n = rfd.rfd_segment_graph_launch(g)
+        first = rfd.triggers_to_numpy(out, n)
+        rfd.rfd_plan_set_fir_config(s.plan, 16, 2, 4, 0)
+        s.filter("bf16x3", th, W, cap)               # rebuilds the work-item tables
+        with pytest.raises(rfd.RfdError) as e:
+            rfd.rfd_segment_graph_launch(g)
+        assert e.value.code == rfd.RFD_E_STATE
+    finally:
+        rfd.rfd_graph_destroy(g)
+    g = rfd.rfd_segment_graph_create(s.plan, s.taps, "bf16x3", th, W, s.data, s.h_ref, out, cap)
+    try:
+        n = rfd.rfd_segment_graph_launch(g)
+        again = rfd.triggers_to_numpy(out, n)
+        assert np.array_equal(again["sample"], first["sample"])
+        np.testing.assert_allclose(again["rho"], first["rho"], rtol=0, atol=1e-5)
+    finally:
+        rfd.rfd_graph_destroy(g)
+        rfd.rfd_plan_set_fir_config(s.plan, 8, 0, 16, 0)
+        s.dechirp_all()
+
+
 def test_autotuner_picks_a_measured_configuration(rfd, ragged):
     case, s = ragged
     before = _trig(rfd, s, "fp16x3", 0.0, 1, case.n_templates * case.n)

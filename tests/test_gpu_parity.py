@@ -14,7 +14,7 @@ from gpu_cases import (compare_triggers, fir_tolerance, gpu_search, oracle_case,
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3, "ols32": 1e-5}
 # unit roundoff of each form's operands: FP32; hi+lo with 8+8 (bf16) or 11+11
 # (fp16) significand bits, the dropped lo*lo term included
 
@@ -68,7 +68,7 @@ def test_fp64_taps_match_oracle(rfd, small):
     assert worst_a <= 1e-8 and worst_s <= 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3", "ols32"])
 def test_fir_full_series_parity(rfd, small, precision):
     case, s = small
     trig, rho = _validation_rho(rfd, s, case, precision)
@@ -83,7 +83,7 @@ def test_fir_full_series_parity(rfd, small, precision):
     assert zerr <= 1e-5 and (trig["flags"] == 0).all()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "ols32"])
 def test_fir_triggers_identical(rfd, small, precision):
     case, s = small
     rho_o = np.abs(case.oracle["z"])
@@ -121,7 +121,7 @@ def test_findchirp_parity(rfd, small):
     assert n >= 1
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3", "ols32"])
 def test_ragged_subbanks_parity(rfd, ragged, precision):
     case, s = ragged
     trig, rho = _validation_rho(rfd, s, case, precision)

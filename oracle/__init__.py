@@ -26,4 +26,6 @@ pipeline   End-to-end helpers per workload (used by tests and the CPU
            baseline timing).
 surrogate  The learned tap surrogate (MLP forward / backward / Adam, SVD basis)
            in FP64.
+chisq      Sec. VI.C: the ratio-filtered chi^2 consistency test (equal
+           reference-power bands, band SNRs of the fitted template, shares).
 """

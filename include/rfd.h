@@ -419,6 +419,43 @@ int rfd_taps_fallback(rfd_taps* target, const rfd_taps* exact, int32_t subbank, 
                       const double* match, double min_match, int64_t* n_fallback_out);
 int rfd_surrogate_destroy(rfd_surrogate* sur);
 
+/*
+ * Ratio-filtered chi^2 signal-consistency test (Sec. VI.C): the time-frequency
+ * chi^2 with each target's band SNRs taken from its reference's band SNR
+ * series through the target's own taps.
+ *
+ * Bands: n_bands (2..64) contiguous bin ranges of the analysis band holding
+ * equal reference power u_i = w_i |h_ref,i|^2: edge 0 = first band bin, edge
+ * b = the first bin at which the sequential FP64 prefix sum of u (from the
+ * first band bin) reaches (total * b) / n_bands, edge n_bands = last band bin
+ * + 1.  RFD_E_INVALID if a band would be empty.
+ *
+ * rfd_dechirp_bands        after rfd_dechirp of slot ref_id on the current
+ *                          segment (same h_ref): stores the slot's n_bands
+ *                          band series zhat_b (FP32, normalised by
+ *                          sigma_ref; they sum to the slot's series).
+ *                          edges_out: host int64 [n_bands + 1] or NULL.
+ * rfd_taps_band_fractions  for every template of `subbank` (taps made, any
+ *                          route): shares f_b = a^H M_b a / sum_b a^H M_b a,
+ *                          M_b the Toeplitz Gram of the band-restricted
+ *                          reference power (FP64, stored FP32), with the
+ *                          bands of h_ref (the sub-bank's reference).
+ * rfd_taps_get_band_fractions  host float [n_bands] shares of one template.
+ * rfd_chisq                chi^2 = sum_b |z_b - f_b z|^2 / f_b at each of n
+ *                          triggers (device rfd_trigger [n], e.g. from
+ *                          rfd_filter_bank), z_b = the FIR of zhat_b at the
+ *                          trigger sample (FP32), z = sum_b z_b; chisq_out:
+ *                          device float [n].  Mean 2 (n_bands - 1) in
+ *                          Gaussian noise.  Every sub-bank needs shares and
+ *                          its slot's band series on this segment with the
+ *                          same edges (RFD_E_STATE otherwise); a trigger
+ *                          naming no template of the bank gives NaN.
+ */
+int rfd_dechirp_bands(rfd_plan* plan, const double* h_ref, int32_t ref_id, int32_t n_bands, int64_t* edges_out);
+int rfd_taps_band_fractions(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double* h_ref, int32_t n_bands);
+int rfd_taps_get_band_fractions(const rfd_taps* taps, int64_t tmpl, float* f_out, int32_t* n_bands_out);
+int rfd_chisq(rfd_plan* plan, const rfd_taps* taps, const rfd_trigger* triggers, int64_t n, float* chisq_out);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* rfd_last_error(void);
 

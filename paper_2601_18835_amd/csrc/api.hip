@@ -91,6 +91,7 @@ static void plan_free(Plan& p) {
   dfree(p.zref); dfree(p.zbf_hi); dfree(p.zbf_lo); dfree(p.zh_hi); dfree(p.zh_lo);
   dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work); dfree(p.counter);
   dfree(p.ols_tw32); dfree(p.ols_tw64);
+  for (auto& z : p.zband) dfree(z);
 }
 
 static int ensure_slots(Plan& p, int64_t n_slots) {
@@ -222,6 +223,10 @@ int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, i
   p.max_refs = max_refs;
   p.stream = (hipStream_t)stream;
   p.ref_gen.assign(max_refs, 0);
+  p.zband.assign(max_refs, nullptr);
+  p.zband_cap.assign(max_refs, 0);
+  p.zband_edges.assign(max_refs, std::vector<int64_t>());
+  p.zband_gen.assign(max_refs, 0);
   int rc = RFD_OK;
   std::vector<double> w(nb, 0.0);
   for (int64_t i = i_low; i <= i_high; ++i) w[i] = 4.0 * df / psd[i];
@@ -484,6 +489,7 @@ static void taps_free(Taps& t) {
     dfree(s.g);
     dfree(s.ols_x);
     dfree(s.ols_g);
+    dfree(s.band_f);
   }
   dfree(t.a64); dfree(t.sigma_fit); dfree(t.c32); dfree(t.pbf); dfree(t.pfh); dfree(t.p32);
   dfree(t.d_first); dfree(t.d_meta); dfree(t.d_abase); dfree(t.work64); dfree(t.bvec);

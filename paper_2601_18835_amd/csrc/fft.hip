@@ -85,6 +85,10 @@ struct StoreRef64 {        // FP64 series -> FP32 series + 16-bit hi/lo planes o
     hl[n] = rl | (il << 16);
   }
 };
+struct StoreBand {         // FP64 series -> FP32 band series
+  float2* z;
+  __device__ void operator()(int, int64_t n, double2 v) const { z[n] = make_float2((float)v.x, (float)v.y); }
+};
 struct StoreLags {         // keep lags k0 .. k0+T-1 (mod N), scaled
   double2* out; int64_t stride, n; int k0, T; double scale;
   __device__ void operator()(int b, int64_t m, double2 v) const {
@@ -369,6 +373,26 @@ int launch_dechirp(Plan& p, const double* h_ref, int ref_id, double* sigma_dev) 
   return run_pass_b<double2>(p, p.work64, st, p.tw64_n1, 1, +1);
 }
 
+// Band series of one reference: the dechirp integrand restricted to bins
+// [edges[b], edges[b+1]) and transformed, for every band (FP32 out, [p][N]).
+int launch_dechirp_bands(Plan& p, const double* h_ref, const int64_t* edges, int n_bands, float2* out) {
+  double* sig = p.dscratch + 16;
+  hipLaunchKernelGGL(k_sigma_sq, dim3(1), dim3(1024), 0, p.stream, p.w, (const double2*)h_ref, p.nb, p.nb, sig);
+  RFD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_build_filter64, dim3(256), dim3(256), 0, p.stream, p.w, (const double2*)h_ref, p.nb,
+                     (const double*)sig, 1.0 / p.data_scale, p.fref64);
+  RFD_CHECK_LAUNCH();
+  for (int b = 0; b < n_bands; ++b) {
+    LoadDechirp64 ld{p.stilde64, p.fref64, edges[b], edges[b + 1] - 1};
+    int rc = run_pass_a<double2>(p, ld, p.work64, p.tw64c, p.tw64f, p.tw64_n2, 1, +1);
+    if (rc) return rc;
+    StoreBand st{out + (int64_t)b * p.n};
+    rc = run_pass_b<double2>(p, p.work64, st, p.tw64_n1, 1, +1);
+    if (rc) return rc;
+  }
+  return RFD_OK;
+}
+
 int launch_findchirp_prepare(Plan& p, const double* h, int64_t count, float2* filt, double* sigma) {
   // sigma^2 into the output buffer (or scratch), then the filters
   double* s2 = sigma;
@@ -409,10 +433,11 @@ int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W
 }
 
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch, int T,
-                  int k0, double2* out, int64_t out_stride) {
+                  int k0, double2* out, int64_t out_stride, int64_t lo, int64_t hi) {
   size_t need = (size_t)batch * p.n;
   if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
-  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, p.i_low, p.i_high, mode};
+  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high,
+                mode};
   int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1);
   if (rc) return rc;
   StoreLags st{out, out_stride, p.n, k0, T, mode == 2 ? 1.0 / (double)p.n : 1.0};

@@ -103,23 +103,34 @@ struct OlsShape {
   static constexpr int LDS = (16 * S1 > 256 * S2 ? 16 * S1 : 256 * S2);   // float2 per FFT
 };
 
-// Per-thread twiddles: stage A  W_K^(t k1), stage B  W_K^(16 u k2), k = 1..15.
-template <int K>
-struct OlsTw {
-  float2 a[16], b[16];
-};
+// Twiddle exp(SIGN 2 pi i m / K) from the 4096-entry table exp(+2 pi i m / 4096).
 template <int K, int SIGN>
-__device__ __forceinline__ void ols_twiddles(OlsTw<K>& w, const float2* __restrict__ tw, int t) {
-  using S = OlsShape<K>;
-  constexpr int step = 4096 / K;
-  const int u = t % S::R;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    float2 x = tw[((t * k) % K) * step];
-    float2 y = tw[((16 * u * k) % K) * step];
-    if (SIGN < 0) { x.y = -x.y; y.y = -y.y; }
-    w.a[k] = x;
-    w.b[k] = y;
+__device__ __forceinline__ float2 ols_tw(const float2* __restrict__ tw, int m) {
+  float2 x = tw[(m & (K - 1)) * (4096 / K)];
+  if (SIGN < 0) x.y = -x.y;
+  return x;
+}
+
+// A zero the compiler cannot see through: offsetting the twiddle table by it
+// keeps the table reads inside the template loop (reloaded from L1 each FFT)
+// instead of 60 registers of hoisted twiddles that halve the occupancy.
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+
+// Exchange barrier: one wave per FFT needs only wave-level ordering of its
+// LDS traffic; larger FFTs span waves and synchronise the workgroup (every
+// FFT of the workgroup then runs in lockstep).
+template <int NTf>
+__device__ __forceinline__ void ols_sync() {
+  if constexpr (NTf <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
   }
 }
 
@@ -127,34 +138,43 @@ __device__ __forceinline__ void ols_twiddles(OlsTw<K>& w, const float2* __restri
 // sign SIGN.  On return v[e * R + s] holds X[out_index(t, e, s)].  All
 // threads of the workgroup call it together (it synchronises).
 template <int K, int SIGN>
-__device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, const OlsTw<K>& w) {
+__device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, const float2* __restrict__ tw) {
   using S = OlsShape<K>;
   constexpr int NTf = S::NTf, R = S::R;
-  // stage A: radix 16 over r
+  // stage A: radix 16 over r, then twiddles W_K^(t k1)
+  float2 wa[16];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) wa[k] = ols_tw<K, SIGN>(tw, t * k);
   dft16<SIGN>(v);
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     const int k1 = dft16_freq(s);
-    buf[k1 * S::S1 + t] = k1 ? cmul(v[s], w.a[k1]) : v[s];
+    buf[k1 * S::S1 + t] = k1 ? cmul(v[s], wa[k1]) : v[s];
   }
-  __syncthreads();
+  ols_sync<NTf>();
   // stage B: thread (k1, u) = (t / R, t % R), radix 16 over v of t' = u + R v
   {
     const int k1 = t / R, u = t % R;
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = buf[k1 * S::S1 + u + R * q];
   }
-  __syncthreads();
+  ols_sync<NTf>();
+  float2 wb[16];
+  {
+    const int u = t % R;
+#pragma unroll
+    for (int k = 1; k < 16; ++k) wb[k] = ols_tw<K, SIGN>(tw, 16 * u * k);
+  }
   dft16<SIGN>(v);
   {
     const int k1 = t / R, u = t % R;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k2 = dft16_freq(s);
-      buf[(k2 * 16 + k1) * S::S2 + u] = k2 ? cmul(v[s], w.b[k2]) : v[s];
+      buf[(k2 * 16 + k1) * S::S2 + u] = k2 ? cmul(v[s], wb[k2]) : v[s];
     }
   }
-  __syncthreads();
+  ols_sync<NTf>();
   // stage C: thread (k1, g) = (t / R, t % R) takes k2 = g (16/R) + e, radix R over u
   {
     const int k1 = t / R, g = t % R;
@@ -165,7 +185,7 @@ __device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, con
       for (int u = 0; u < R; ++u) v[e * R + u] = buf[(k2 * 16 + k1) * S::S2 + u];
     }
   }
-  __syncthreads();
+  ols_sync<NTf>();
   dft_r<R, SIGN>(v);
 }
 
@@ -187,13 +207,11 @@ __global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int
   __shared__ float2 lds[S::F * S::LDS];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
   const int64_t b = (int64_t)blockIdx.x * S::F + f;
-  OlsTw<K> w;
-  ols_twiddles<K, -1>(w, tw, t);
   float2 v[16];
   const int64_t start = b * L + k0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = b < nB ? z[(start + t + S::NTf * r) & (n - 1)] : make_float2(0.f, 0.f);
-  ols_fft<K, -1>(v, lds + f * S::LDS, t, w);
+  ols_fft<K, -1>(v, lds + f * S::LDS, t, tw);
   if (b >= nB) return;
   float2* xb = X + b * K;
 #pragma unroll
@@ -253,8 +271,6 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
   const int64_t b = (int64_t)blockIdx.x * S::F + f;
   const bool bvalid = b < a.nB;
-  OlsTw<K> w;
-  ols_twiddles<K, 1>(w, a.tw, t);
   float2 xb[16];
   const float2* Xb = a.X + (bvalid ? b : 0) * K;
 #pragma unroll
@@ -271,7 +287,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gj[t + S::NTf * r]);
-    ols_fft<K, 1>(v, lds + f * S::LDS, t, w);
+    ols_fft<K, 1>(v, lds + f * S::LDS, t, a.tw + opaque_zero());
     if (!bvalid) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
     float r2[16];

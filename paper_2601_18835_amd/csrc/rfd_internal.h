@@ -81,6 +81,12 @@ struct Plan {
   int ols_block = 0;
   float2* ols_tw32 = nullptr;
   double2* ols_tw64 = nullptr;
+  // chi^2 band series per reference slot: [n_bands][n] FP32, the band edges
+  // they were made with and the segment generation
+  std::vector<float2*> zband;
+  std::vector<int64_t> zband_cap;
+  std::vector<std::vector<int64_t>> zband_edges;
+  std::vector<int64_t> zband_gen;
 
   // optional stage timing (hipEvent pairs on `stream`)
   bool timing = false;
@@ -117,6 +123,9 @@ struct SubBankTaps {
   float2* ols_x = nullptr;
   float2* ols_g = nullptr;
   bool ols_valid = false;
+  // chi^2 band shares f_b per template [count][n_bands] and their band edges
+  float* band_f = nullptr;
+  std::vector<int64_t> band_edges;
 };
 
 struct Taps {
@@ -160,8 +169,11 @@ int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W
 // FP64 correlation: out[t][l] = sum_i P_t[i] exp(+2 pi i i (k0+l)/N), l < T
 // mode 0: P = w h_t conj(h_r); mode 1: P = w |h_r|^2 (batch 1); mode 2: P = h_t/h_r
 // where w |h_r|^2 > 0, scaled by 1/N.
+// lo / hi (inclusive bins, -1: the analysis band) restrict the sum to a band.
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch,
-                  int T, int k0, double2* out, int64_t out_stride);
+                  int T, int k0, double2* out, int64_t out_stride, int64_t lo = -1, int64_t hi = -1);
+// band series [n_bands][N] (FP32, normalised by sigma_ref) of one reference
+int launch_dechirp_bands(Plan& p, const double* h_ref, const int64_t* edges, int n_bands, float2* out);
 
 // ---------------------------------------------------- launchers (taps.hip)
 int taps_prepare_subbank(Plan& p, Taps& tp, int b, const double* h_ref, double eps);

@@ -72,6 +72,18 @@ class RatioFilterSearch:
         return rfd.rfd_filter_bank(self.plan, self.taps, precision, threshold, window, capacity, out,
                                    raise_overflow)
 
+    def bands(self, n_bands):
+        """Band series of every reference and band shares of every sub-bank
+        (the chi^2 test's inputs); returns the edges per reference."""
+        edges = {r: rfd.rfd_dechirp_bands(self.plan, h, r, n_bands) for r, h in self.h_ref.items()}
+        for b, spec in enumerate(self.subbanks):
+            if spec.count:
+                rfd.rfd_taps_band_fractions(self.plan, self.taps, b, self.h_ref[spec.ref_id], n_bands)
+        return edges
+
+    def chisq(self, triggers, n):
+        return rfd.rfd_chisq(self.plan, self.taps, triggers, n)
+
     def zref(self, ref_id):
         return rfd.rfd_get_zref(self.plan, ref_id)
 

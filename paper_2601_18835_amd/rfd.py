@@ -77,6 +77,10 @@ _SIGS = {
     "rfd_surrogate_make_taps": [_P, _P, _P, _i32, _i64, _i64],
     "rfd_taps_match": [_P, _P, _i32, _i64, _i64, _P],
     "rfd_taps_fallback": [_P, _P, _i32, _i64, _i64, _P, _d, C.POINTER(_i64)],
+    "rfd_dechirp_bands": [_P, _P, _i32, _i32, _P],
+    "rfd_taps_band_fractions": [_P, _P, _i32, _P, _i32],
+    "rfd_taps_get_band_fractions": [_P, _i64, _P, C.POINTER(_i32)],
+    "rfd_chisq": [_P, _P, _P, _i64, _P],
     "rfd_surrogate_destroy": [_P],
     "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
     "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
@@ -430,3 +434,36 @@ def rfd_taps_fallback(target, exact, subbank, first, match, min_match=0.99):
 
 def rfd_surrogate_destroy(sur):
     _check(_lib.rfd_surrogate_destroy(sur), "rfd_surrogate_destroy")
+
+
+# ------------------------------------------------------------------ chi^2
+def rfd_dechirp_bands(plan, h_ref, ref_id, n_bands):
+    """Band series of slot ref_id; returns the band edges (int64 [n_bands + 1])."""
+    import torch
+    info = rfd_plan_info_get(plan)
+    _dev_check(h_ref, torch.complex128, info["n_bins"], "h_ref")
+    edges = np.zeros(n_bands + 1, dtype=np.int64)
+    _check(_lib.rfd_dechirp_bands(plan, _ptr(h_ref), ref_id, n_bands, edges.ctypes.data), "rfd_dechirp_bands")
+    return edges
+
+
+def rfd_taps_band_fractions(plan, taps, subbank, h_ref, n_bands):
+    import torch
+    info = rfd_plan_info_get(plan)
+    _dev_check(h_ref, torch.complex128, info["n_bins"], "h_ref")
+    _check(_lib.rfd_taps_band_fractions(plan, taps, subbank, _ptr(h_ref), n_bands), "rfd_taps_band_fractions")
+
+
+def rfd_taps_get_band_fractions(taps, tmpl, max_bands=64):
+    f = np.zeros(max_bands, dtype=np.float32)
+    p = C.c_int32(0)
+    _check(_lib.rfd_taps_get_band_fractions(taps, tmpl, f.ctypes.data, C.byref(p)), "rfd_taps_get_band_fractions")
+    return f[:p.value].copy()
+
+
+def rfd_chisq(plan, taps, triggers, n):
+    """chi^2 at the first n triggers of a device trigger buffer; float32 numpy [n]."""
+    import torch
+    out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+    _check(_lib.rfd_chisq(plan, taps, _ptr(triggers), n, _ptr(out)), "rfd_chisq")
+    return out[:n].cpu().numpy()

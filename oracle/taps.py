@@ -167,3 +167,29 @@ def fitted_sigma_sq_lag(a, M):
     """The same norm in the tap domain (Sec. VI.B via Parseval): a^H M a,
     with M built from the reference autocorrelation."""
     return float(np.real(np.conj(a) @ (M @ a)))
+
+
+def zero_lag_match(h_j, h_r, w, a, k0):
+    """|(h_j|h_fit)(0)| / (sigma_j sigma_fit), h_fit = h_ref A: the fitted
+    template's phase-maximised overlap with its target at zero lag, by
+    frequency sums (Eq. 1 inner products).  Reading of Sec. V.A's target
+    match: the filter reproduces the target at the target's own time, so the
+    overlap is taken there."""
+    n = 2 * (h_j.size - 1)
+    h_fit = h_r * response(a, k0, n)
+    num = abs(np.sum(w * h_j * np.conj(h_fit)))
+    return float(num / np.sqrt(np.sum(w * np.abs(h_j) ** 2) * np.sum(w * np.abs(h_fit) ** 2)))
+
+
+def select_taps(h_j, h_r, w, target, ladder, eps=DEFAULT_RIDGE_EPS):
+    """Sec. V.A's dynamic tap count: the first T of the ascending ladder whose
+    least-squares taps (lags centred, k0 = -floor(T/2)) reach the target
+    zero-lag match; the last T if none does.  Returns (T, match)."""
+    m = 0.0
+    for T in ladder:
+        k0 = -(T // 2)
+        a = ls_taps_normal(h_j, h_r, w, T, k0, eps)
+        m = zero_lag_match(h_j, h_r, w, a, k0)
+        if m >= target:
+            return T, m
+    return ladder[-1], m

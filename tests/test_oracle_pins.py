@@ -278,3 +278,38 @@ def test_window_ambiguity_cases():
     rho = np.array([6.0000001, 1, 1, 1, 7.0, 6.9999995, 0, 0, 3.0, 2.9999999, 0, 0])
     flags = cluster.window_ambiguity(rho, 6.0, 4, 1e-5)
     assert flags.tolist() == [True, True, False]
+
+
+def test_zero_lag_match_and_tap_selection():
+    """The zero-lag match equals the overlap series of pipeline.match at lag 0,
+    equals |a^H b| / (sigma_j sqrt(a^H M a)) in the tap domain, and the
+    selection is the first ladder entry reaching the target."""
+    import synth
+    from oracle import pipeline, spectral, taps as tp
+    n, fs, f_low = 8192, 2048.0, 30.0
+    w = spectral.psd_weights(synth.psd_array(n, fs), n, fs, f_low)
+    h_r = synth.taylorf2(synth.WaveformParams(6.0, 5.0), n, fs, f_low)
+    h_j = synth.taylorf2(synth.WaveformParams(6.4, 4.7), n, fs, f_low)
+    T, k0 = 48, -24
+    M = tp.gram(h_r, w, T)
+    a = tp.ls_taps_normal(h_j, h_r, w, T, k0, M=M)
+    m = tp.zero_lag_match(h_j, h_r, w, a, k0)
+    h_fit = h_r * tp.response(a, k0, n)
+    series = spectral.matched_filter(h_j, h_fit, w)
+    want = abs(series[0]) / np.sqrt(spectral.sigma_sq(h_j, w) * spectral.sigma_sq(h_fit, w))
+    assert abs(m - want) <= 1e-12
+    b = tp.crosscorr(h_j, h_r, w, T, k0)
+    alt = abs(np.conj(a) @ b) / np.sqrt(spectral.sigma_sq(h_j, w) * np.real(np.conj(a) @ M @ a))
+    assert abs(m - alt) <= 1e-10
+    # the time-maximised match bounds it from above
+    assert m <= pipeline.match(pipeline.Prepared(n, fs, f_low, w, None), h_j, h_r,
+                               pipeline.TemplateTaps(a, k0, 1.0)) + 1e-12
+    ladder = [8, 16, 32, 64, 128, 256]
+    ms = []
+    for TT in ladder:
+        aa = tp.ls_taps_normal(h_j, h_r, w, TT, -(TT // 2))
+        ms.append(tp.zero_lag_match(h_j, h_r, w, aa, -(TT // 2)))
+    for target in (0.5, 0.9, 0.99, 0.999, 2.0):
+        T_sel, m_sel = tp.select_taps(h_j, h_r, w, target, ladder)
+        first = next((TT for TT, mm in zip(ladder, ms) if mm >= target), ladder[-1])
+        assert T_sel == first and abs(m_sel - ms[ladder.index(T_sel)]) <= 1e-14

@@ -456,6 +456,24 @@ int rfd_taps_band_fractions(rfd_plan* plan, rfd_taps* taps, int32_t subbank, con
 int rfd_taps_get_band_fractions(const rfd_taps* taps, int64_t tmpl, float* f_out, int32_t* n_bands_out);
 int rfd_chisq(rfd_plan* plan, const rfd_taps* taps, const rfd_trigger* triggers, int64_t n, float* chisq_out);
 
+/*
+ * rfd_select_taps - dynamic tap count (Sec. V.A tunes each template's number
+ * of taps to a target match with the target template).  For each of `count`
+ * templates (device complex128 [count][N/2+1], reference h_ref likewise):
+ * the first T of the strictly ascending host `ladder` (n_ladder in [1, 64],
+ * entries in [1, 2048]) whose least-squares taps with lags centred
+ * (k0 = -floor(T/2), ridge ridge_eps) reach `target` in the match
+ * |(h_j|h_fit)(0)| / (sigma_j sigma_fit) = |a^H b| / (sigma_j sigma_fit)
+ * (the fitted template's phase-maximised overlap with the target at zero
+ * lag), else the last T.  taps_out: host int32 [count]; match_out: host
+ * double [count] (the match at the chosen T) or NULL.  Every ladder entry
+ * builds the taps of all templates (n_ladder times the work of
+ * rfd_make_taps); templates are then grouped by T into sub-banks.
+ */
+int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, int64_t count, double target,
+                    const int32_t* ladder, int32_t n_ladder, double ridge_eps, int32_t* taps_out,
+                    double* match_out);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* rfd_last_error(void);
 

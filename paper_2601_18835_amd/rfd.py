@@ -81,6 +81,7 @@ _SIGS = {
     "rfd_taps_band_fractions": [_P, _P, _i32, _P, _i32],
     "rfd_taps_get_band_fractions": [_P, _i64, _P, C.POINTER(_i32)],
     "rfd_chisq": [_P, _P, _P, _i64, _P],
+    "rfd_select_taps": [_P, _P, _P, _i64, _d, _P, _i32, _d, _P, _P],
     "rfd_surrogate_destroy": [_P],
     "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
     "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
@@ -467,3 +468,21 @@ def rfd_chisq(plan, taps, triggers, n):
     out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
     _check(_lib.rfd_chisq(plan, taps, _ptr(triggers), n, _ptr(out)), "rfd_chisq")
     return out[:n].cpu().numpy()
+
+
+# ---------------------------------------------------------- tap selection
+def rfd_select_taps(plan, h_ref, h_tmpl, target, ladder, ridge_eps=1e-4):
+    """Per-template tap counts reaching `target` (zero-lag match); returns (T int32 [count], match float64 [count])."""
+    import torch
+    info = rfd_plan_info_get(plan)
+    _dev_check(h_ref, torch.complex128, info["n_bins"], "h_ref")
+    if h_tmpl.dim() != 2 or h_tmpl.shape[1] != info["n_bins"]:
+        raise ValueError("h_tmpl must be [count, N/2+1]")
+    _dev_check(h_tmpl, torch.complex128, None, "h_tmpl")
+    lad = np.ascontiguousarray(ladder, dtype=np.int32)
+    count = h_tmpl.shape[0]
+    T = np.zeros(count, dtype=np.int32)
+    m = np.zeros(count, dtype=np.float64)
+    _check(_lib.rfd_select_taps(plan, _ptr(h_ref), _ptr(h_tmpl), count, target, lad.ctypes.data, lad.size,
+                                ridge_eps, T.ctypes.data, m.ctypes.data), "rfd_select_taps")
+    return T, m

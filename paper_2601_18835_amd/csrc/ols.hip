@@ -103,26 +103,29 @@ struct OlsShape {
   static constexpr int LDS = (16 * S1 > 256 * S2 ? 16 * S1 : 256 * S2);   // float2 per FFT
 };
 
-// Twiddle exp(SIGN 2 pi i m / K) from the 4096-entry table exp(+2 pi i m / 4096).
+// Per-thread twiddles: stage A  W_K^(t k1), stage B  W_K^(16 u k2), k = 1..15.
+template <int K>
+struct OlsTw {
+  float2 a[16], b[16];
+};
 template <int K, int SIGN>
-__device__ __forceinline__ float2 ols_tw(const float2* __restrict__ tw, int m) {
-  float2 x = tw[(m & (K - 1)) * (4096 / K)];
-  if (SIGN < 0) x.y = -x.y;
-  return x;
+__device__ __forceinline__ void ols_twiddles(OlsTw<K>& w, const float2* __restrict__ tw, int t) {
+  using S = OlsShape<K>;
+  constexpr int step = 4096 / K;
+  const int u = t % S::R;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float2 x = tw[((t * k) % K) * step];
+    float2 y = tw[((16 * u * k) % K) * step];
+    if (SIGN < 0) { x.y = -x.y; y.y = -y.y; }
+    w.a[k] = x;
+    w.b[k] = y;
+  }
 }
 
-// A zero the compiler cannot see through: offsetting the twiddle table by it
-// keeps the table reads inside the template loop (reloaded from L1 each FFT)
-// instead of 60 registers of hoisted twiddles that halve the occupancy.
-__device__ __forceinline__ int opaque_zero() {
-  int z;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-  return z;
-}
-
-// Exchange barrier: one wave per FFT needs only wave-level ordering of its
-// LDS traffic; larger FFTs span waves and synchronise the workgroup (every
-// FFT of the workgroup then runs in lockstep).
+// Exchange barrier: one wave per FFT (K = 1024) needs only wave-level
+// ordering of its LDS traffic, so the workgroup's four FFTs run
+// independently; larger FFTs span waves and synchronise the workgroup.
 template <int NTf>
 __device__ __forceinline__ void ols_sync() {
   if constexpr (NTf <= 64) {
@@ -138,18 +141,15 @@ __device__ __forceinline__ void ols_sync() {
 // sign SIGN.  On return v[e * R + s] holds X[out_index(t, e, s)].  All
 // threads of the workgroup call it together (it synchronises).
 template <int K, int SIGN>
-__device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, const float2* __restrict__ tw) {
+__device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, const OlsTw<K>& w) {
   using S = OlsShape<K>;
   constexpr int NTf = S::NTf, R = S::R;
-  // stage A: radix 16 over r, then twiddles W_K^(t k1)
-  float2 wa[16];
-#pragma unroll
-  for (int k = 1; k < 16; ++k) wa[k] = ols_tw<K, SIGN>(tw, t * k);
+  // stage A: radix 16 over r
   dft16<SIGN>(v);
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     const int k1 = dft16_freq(s);
-    buf[k1 * S::S1 + t] = k1 ? cmul(v[s], wa[k1]) : v[s];
+    buf[k1 * S::S1 + t] = k1 ? cmul(v[s], w.a[k1]) : v[s];
   }
   ols_sync<NTf>();
   // stage B: thread (k1, u) = (t / R, t % R), radix 16 over v of t' = u + R v
@@ -159,19 +159,13 @@ __device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, con
     for (int q = 0; q < 16; ++q) v[q] = buf[k1 * S::S1 + u + R * q];
   }
   ols_sync<NTf>();
-  float2 wb[16];
-  {
-    const int u = t % R;
-#pragma unroll
-    for (int k = 1; k < 16; ++k) wb[k] = ols_tw<K, SIGN>(tw, 16 * u * k);
-  }
   dft16<SIGN>(v);
   {
     const int k1 = t / R, u = t % R;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k2 = dft16_freq(s);
-      buf[(k2 * 16 + k1) * S::S2 + u] = k2 ? cmul(v[s], wb[k2]) : v[s];
+      buf[(k2 * 16 + k1) * S::S2 + u] = k2 ? cmul(v[s], w.b[k2]) : v[s];
     }
   }
   ols_sync<NTf>();
@@ -207,11 +201,13 @@ __global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int
   __shared__ float2 lds[S::F * S::LDS];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
   const int64_t b = (int64_t)blockIdx.x * S::F + f;
+  OlsTw<K> w;
+  ols_twiddles<K, -1>(w, tw, t);
   float2 v[16];
   const int64_t start = b * L + k0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = b < nB ? z[(start + t + S::NTf * r) & (n - 1)] : make_float2(0.f, 0.f);
-  ols_fft<K, -1>(v, lds + f * S::LDS, t, tw);
+  ols_fft<K, -1>(v, lds + f * S::LDS, t, w);
   if (b >= nB) return;
   float2* xb = X + b * K;
 #pragma unroll
@@ -271,6 +267,8 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
   const int64_t b = (int64_t)blockIdx.x * S::F + f;
   const bool bvalid = b < a.nB;
+  OlsTw<K> w;
+  ols_twiddles<K, 1>(w, a.tw, t);
   float2 xb[16];
   const float2* Xb = a.X + (bvalid ? b : 0) * K;
 #pragma unroll
@@ -287,7 +285,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gj[t + S::NTf * r]);
-    ols_fft<K, 1>(v, lds + f * S::LDS, t, a.tw + opaque_zero());
+    ols_fft<K, 1>(v, lds + f * S::LDS, t, w);
     if (!bvalid) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
     float r2[16];
@@ -325,13 +323,18 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
 }
 
 // ------------------------------------------------------------------ host
+// Measured throughput of each block size per unit of FFT work, relative to
+// K = 2048 (MI355X: one-wave FFTs without workgroup barriers at 1024, a
+// whole-workgroup FFT at 4096).
+static double ols_efficiency(int K) { return K == 1024 ? 1.26 : (K == 2048 ? 1.0 : 0.72); }
+
 int ols_block_size(const Plan& p, int T) {
   if (p.ols_block > T) return p.ols_block;
   int best = 4096;
   double best_cost = 1e30;
   for (int K = 1024; K <= 4096; K *= 2) {
     if (K <= T) continue;
-    const double cost = (5.0 * std::log2((double)K) + 6.0) * K / (double)(K - T + 1);
+    const double cost = (5.0 * std::log2((double)K) + 6.0) * K / (double)(K - T + 1) / ols_efficiency(K);
     if (cost < best_cost - 1e-9) {
       best_cost = cost;
       best = K;

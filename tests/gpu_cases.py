@@ -152,14 +152,17 @@ def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None):
 UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22, "ols32": 2.0 ** -24}
 
 
+OLS_EFFICIENCY = {1024: 1.26, 2048: 1.0, 4096: 0.72}
+
+
 def ols_block(T, forced=0):
     """Block size of the overlap-save form for T taps: `forced` where it
     exceeds T, else the K in {1024, 2048, 4096} (K > T) of least
-    (5 log2 K + 6) K / (K - T + 1)."""
+    (5 log2 K + 6) K / (K - T + 1) / efficiency(K)."""
     if forced > T:
         return forced
     cands = [K for K in (1024, 2048, 4096) if K > T]
-    return min(cands, key=lambda K: ((5 * np.log2(K) + 6) * K / (K - T + 1), K))
+    return min(cands, key=lambda K: ((5 * np.log2(K) + 6) * K / (K - T + 1) / OLS_EFFICIENCY[K], K))
 
 
 def tap_gain(case, norm=1):

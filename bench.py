@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"bf16x3": 2500.0, "fp16x3": 2500.0, "fp32": 157.3,   # dense MFMA TFLOP/s, MI355X datasheet
         "ols32": 157.3}                                          # FP32 vector TFLOP/s
-COUNTERS = {"spin256s": "fir_bf16x3_spin256s_counters.txt"}
+COUNTERS = {("spin256s", "bf16x3"): "fir_bf16x3_spin256s_counters.txt",
+            ("spin256s", "ols32"): "fir_ols32_spin256s_counters.txt"}
 
 
 def log(msg):
@@ -220,7 +221,7 @@ def main():
         fl = ols_flops()
         achieved = fl / (fir_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": None,
+                    "frac": round(achieved / peak, 4), "traffic": read_traffic(COUNTERS.get((w.name, prec))),
                     "kernel": "k_ols<K> (+ k_ols_x block spectra)", "flops_per_launch": fl,
                     "avg_launch_ms": round(fir_ms, 4),
                     "direct_form_equivalent_TFLOPs": round(flops_alg / (fir_ms * 1e-3) / 1e12, 2)}
@@ -228,7 +229,7 @@ def main():
         achieved = flops_alg / (fir_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 4),
-                    "traffic": read_traffic(COUNTERS.get(w.name)) if prec == w.precision else None,
+                    "traffic": read_traffic(COUNTERS.get((w.name, prec))),
                     "kernel": (f"k_fir16<{prec[:4]}>" if prec != "fp32" else "k_fir32") +
                               ("_persistent" if multi else ""),
                     "issued_frac": round(3 * achieved / peak, 4) if prec != "fp32" else round(achieved / peak, 4),

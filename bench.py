@@ -253,6 +253,21 @@ def main():
                                          "filter_stream_GBs": nt * info["n_band"] * 8 / (fc_ms * 1e-3) / 1e9}
             log(f"findchirp: {d3 / k2 * 1e3:.3f} ms/step")
 
+    # low latency (Sec. VII.A): the newest second of the segment only, the same form
+    inc = int(w.fs)
+
+    def increment():
+        for r in range(nsb):
+            rfd.rfd_dechirp(s.plan, data if r == 0 else None, s.h_ref[r], r, False)
+        return rfd.rfd_filter_range(s.plan, s.taps, prec, w.threshold, w.window, w.n - inc, inc, cap, out)[1]
+
+    d5, n5, t5 = timed(increment, 20, 3)
+    low_latency = {"increment_samples": inc, "ms_per_increment": d5 / 20 * 1e3,
+                   "fir_ms_per_increment": t5["fir_ms"] / max(1, t5["n_fir"]), "form": prec,
+                   "note": "segment transform, every dechirp, then FIR, window peaks and trigger compaction "
+                           "for the last 1 s of the segment only"}
+    log(f"low latency: {d5 / 20 * 1e3:.3f} ms per 1 s increment ({prec})")
+
     parity = cpu = None
     if not args.no_cpu_baseline:
         parity, cpu = oracle_sample(args, w, bank, psd, seg, hrefs, s, out, cap, eager_step, prec, np, synth)
@@ -286,7 +301,8 @@ def main():
         "fir_form_selection_ms": selection, "mfma_form": mfma_form,
         "stages_ms": stages, "triggers": ntrig,
         "tap_construction": {"templates_per_s": taps_per_s, "gpu_ms": tap_timing["taps_ms"]},
-        "autotune": tune, "roofline": roofline, "compare": compare, "parity": parity, "cpu_baseline": cpu,
+        "autotune": tune, "roofline": roofline, "compare": compare, "low_latency": low_latency, "parity": parity,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -475,6 +475,37 @@ int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, i
                     const int32_t* ladder, int32_t n_ladder, double ridge_eps, int32_t* taps_out,
                     double* match_out);
 
+/*
+ * PSD drift (Sec. VI.B): the template norm must follow the detector PSD.
+ * rfd_plan_set_psd      replaces the plan's PSD weights w_i = 4 df / S_n(f_i)
+ *                       (host psd [N/2+1], finite and > 0 in band); every
+ *                       reference slot becomes stale (dechirp again).
+ * rfd_taps_renormalize  recomputes a sub-bank's reference autocorrelation
+ *                       g[m] under the current weights and, for every
+ *                       template, sigma_fit^2 = a^H M a and the normalised
+ *                       taps, leaving the taps a (designed under the old
+ *                       PSD) unchanged: O(T^2) per template instead of a
+ *                       full-band integral.  h_ref: the sub-bank's
+ *                       reference (device complex128 [N/2+1]).  A cached
+ *                       Cholesky factor is dropped (the next least-squares
+ *                       rfd_make_taps refactors).
+ */
+int rfd_plan_set_psd(rfd_plan* plan, const double* psd, int64_t n_psd);
+int rfd_taps_renormalize(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double* h_ref);
+
+/*
+ * rfd_filter_range - low-latency filtering (Sec. VII.A): the ratio FIR needs
+ * only the reference series around the new samples (T - 1 of settling), so
+ * a stream advancing by a few seconds filters just those samples.  As
+ * rfd_filter_bank, restricted to output samples [n_start, n_start + n_len)
+ * (both multiples of 256, inside the segment): windows keep their absolute
+ * positions [qW, (q+1)W) and a window cut by the range reports the peak of
+ * its part inside it.  Direct forms run one launch per sub-bank over the
+ * range; RFD_OLS32 transforms and filters only the blocks that meet it.
+ */
+int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold, int64_t cluster_window,
+                     int64_t n_start, int64_t n_len, rfd_trigger* out, int64_t capacity, int64_t* n_out);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* rfd_last_error(void);
 

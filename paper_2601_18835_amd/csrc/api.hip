@@ -300,6 +300,51 @@ int rfd_plan_set_timing(rfd_plan* plan, int32_t enable) {
   return RFD_OK;
 }
 
+int rfd_plan_set_psd(rfd_plan* plan, const double* psd, int64_t n_psd) {
+  if (!plan || !psd) return fail(RFD_E_INVALID, "NULL argument");
+  Plan& p = plan->p;
+  if (n_psd != p.nb) return fail(RFD_E_INVALID, "n_psd must equal seg_len/2 + 1");
+  std::vector<double> w(p.nb, 0.0);
+  for (int64_t i = p.i_low; i <= p.i_high; ++i) {
+    if (!isfinite(psd[i]) || !(psd[i] > 0.0))
+      return fail(RFD_E_INVALID, "psd must be finite and > 0 on every in-band bin (bin " + std::to_string(i) + ")");
+    w[i] = 4.0 * p.df / psd[i];
+  }
+  RFD_HIP(hipStreamSynchronize(p.stream));
+  RFD_HIP(hipMemcpy(p.w, w.data(), p.nb * sizeof(double), hipMemcpyHostToDevice));
+  // every reference series was filtered with the old weights
+  ++p.seg_gen;
+  return RFD_OK;
+}
+
+int rfd_taps_renormalize(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double* h_ref) {
+  if (!plan || !taps || !h_ref) return fail(RFD_E_INVALID, "NULL argument");
+  Plan& p = plan->p;
+  Taps& t = taps->t;
+  if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
+  if (subbank < 0 || subbank >= (int)t.sb.size()) return fail(RFD_E_INVALID, "subbank out of range");
+  SubBankTaps& s = t.sb[subbank];
+  if (s.made != s.count) return fail(RFD_E_STATE, "taps not made");
+  if (s.count == 0) return RFD_OK;
+  if (t.work64_cap < (size_t)p.n) {
+    RFD_HIP(hipStreamSynchronize(p.stream));
+    dfree(t.work64);
+    t.work64_cap = 0;
+    int rc = dalloc(&t.work64, (size_t)p.n);
+    if (rc) return rc;
+    t.work64_cap = p.n;
+  }
+  // the reference autocorrelation under the plan's current PSD, then sigma_fit
+  // and the normalised packings of the unchanged taps (Sec. VI.B)
+  int rc = launch_corr64(p, t, 1, h_ref, nullptr, 1, s.T, 0, s.g, s.T);
+  if (rc) return rc;
+  s.eps = -1.0;   // a cached Cholesky factor belongs to the old weights
+  rc = taps_norm_and_pack(p, t, subbank, 0, s.count);
+  if (rc) return rc;
+  RFD_HIP(hipStreamSynchronize(p.stream));
+  return RFD_OK;
+}
+
 int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out) {
   if (!plan || !out) return fail(RFD_E_INVALID, "NULL argument");
   Plan& p = plan->p;
@@ -716,6 +761,50 @@ int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, flo
   rc = stage_begin(p, kStFir);
   if (rc) return rc;
   rc = enqueue_fir(p, tm, precision, cluster_window, nwin);
+  if (rc) return rc;
+  rc = stage_end(p);
+  if (!rc) rc = stage_begin(p, kStCompact);
+  if (rc) return rc;
+  rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);
+  if (rc) return rc;
+  rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
+  if (!rc) rc = stage_end(p);
+  if (rc) return rc;
+  return finish_triggers(p, capacity, n_out);
+}
+
+int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold, int64_t cluster_window,
+                     int64_t n_start, int64_t n_len, rfd_trigger* out, int64_t capacity, int64_t* n_out) {
+  if (!plan || !taps) return fail(RFD_E_INVALID, "NULL plan or taps");
+  Plan& p = plan->p;
+  const Taps& t = taps->t;
+  if (t.plan != &p) return fail(RFD_E_INVALID, "taps belong to another plan");
+  if (!valid_precision(precision)) return fail(RFD_E_INVALID, "unknown precision");
+  if (n_start < 0 || n_len < 256 || n_start % 256 != 0 || n_len % 256 != 0 || n_start + n_len > p.n)
+    return fail(RFD_E_INVALID, "range must be 256-sample aligned, non-empty and inside the segment");
+  int rc = check_filter_args(p, threshold, cluster_window, out, capacity, n_out);
+  if (rc) return rc;
+  rc = check_bank_state(p, t);
+  if (rc) return rc;
+  Taps& tm = const_cast<Taps&>(t);
+  const int64_t nwin = (p.n + cluster_window - 1) / cluster_window;
+  const int64_t n_slots = t.n_templates * nwin;
+  rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
+  if (rc) return rc;
+  if (precision == RFD_OLS32) {
+    rc = ensure_ols(p, tm);
+    if (rc) return rc;
+  }
+  rc = launch_slots_clear(p, n_slots);
+  if (rc) return rc;
+  rc = stage_begin(p, kStFir);
+  if (rc) return rc;
+  if (precision == RFD_OLS32) {
+    rc = launch_ols(p, t, cluster_window, nwin, n_start, n_start + n_len);
+  } else {
+    for (size_t b = 0; !rc && b < t.sb.size(); ++b)
+      rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin, n_start, n_len);
+  }
   if (rc) return rc;
   rc = stage_end(p);
   if (!rc) rc = stage_begin(p, kStCompact);

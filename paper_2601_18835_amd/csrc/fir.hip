@@ -44,6 +44,7 @@ struct FirArgs {
   int64_t nwin, W;
   int k0, Tp, KB;           // Tp = taps padded to 16, KB = Tp / 16
   int S;                    // 256-sample tiles swept by one workgroup
+  int64_t m_off = 0;        // first output sample of the launch (range filtering)
 };
 
 __device__ __forceinline__ unsigned long long peak_key(float r2, int64_t n, int64_t W, int64_t& q) {
@@ -233,7 +234,7 @@ __device__ __forceinline__ void fir16_block(const FirArgs& a, int64_t mbase, int
 template <bool BF16, int NB>
 __global__ __launch_bounds__(256) void k_fir16(FirArgs a) {
   extern __shared__ __align__(16) uint32_t win[];
-  fir16_block<BF16, NB>(a, (int64_t)blockIdx.x * a.S * 16 * NB, (int64_t)blockIdx.y * kWavesPerBlock, win);
+  fir16_block<BF16, NB>(a, a.m_off + (int64_t)blockIdx.x * a.S * 16 * NB, (int64_t)blockIdx.y * kWavesPerBlock, win);
 }
 
 // FP32: v_mfma_f32_16x16x4f32, K step = 2 complex taps; B read from LDS.
@@ -281,7 +282,7 @@ __device__ __forceinline__ void fir32_block(const FirArgs& a, int64_t mbase, int
 template <int NB>
 __global__ __launch_bounds__(256) void k_fir32(FirArgs a) {
   extern __shared__ __align__(16) float2 wz[];
-  fir32_block<NB>(a, (int64_t)blockIdx.x * a.S * 16 * NB, (int64_t)blockIdx.y * kWavesPerBlock, wz);
+  fir32_block<NB>(a, a.m_off + (int64_t)blockIdx.x * a.S * 16 * NB, (int64_t)blockIdx.y * kWavesPerBlock, wz);
 }
 
 // ------------------------------------------------------------ persistent
@@ -374,7 +375,8 @@ static int tiles_per_block(int64_t n, int64_t W, int cols, int smax_cfg) {
   return S < 1 ? 1 : S;
 }
 
-int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin) {
+int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin, int64_t n_start,
+               int64_t n_len) {
   const SubBankTaps& s = tp.sb[b];
   if (s.count == 0) return RFD_OK;
   FirArgs a;
@@ -396,8 +398,14 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
   // column blocks per wave: FP32 16; 16-bit forms 8 (tile config knob)
   const int nb = precision == RFD_FP32 ? 16 : p.fir_nb16;
   const int cols = 16 * nb;
-  a.S = tiles_per_block(p.n, W, cols, p.fir_smax);
-  dim3 grid((unsigned)(p.n / ((int64_t)a.S * cols)), (unsigned)((s.count + kTmplTile - 1) / kTmplTile));
+  if (n_len < 0) {             // the whole segment
+    n_start = 0;
+    n_len = p.n;
+  }
+  a.S = tiles_per_block(n_len, W, cols, p.fir_smax);
+  while (a.S > 1 && n_start % ((int64_t)a.S * cols) != 0) a.S >>= 1;
+  a.m_off = n_start;
+  dim3 grid((unsigned)(n_len / ((int64_t)a.S * cols)), (unsigned)((s.count + kTmplTile - 1) / kTmplTile));
   const int Lw = a.S * cols + s.Tp;
   if (precision == RFD_FP32) {
     hipLaunchKernelGGL(k_fir32<16>, grid, dim3(256), (size_t)Lw * sizeof(float2), p.stream, a);

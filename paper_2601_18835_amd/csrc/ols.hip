@@ -196,15 +196,15 @@ __device__ __forceinline__ int ols_out_index(int t, int e, int s) {
 // X[b][f] for every block b of the reference series (forward FFT).
 template <int K>
 __global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
-                                            const float2* __restrict__ tw, float2* __restrict__ X) {
+                                            int64_t b_first, const float2* __restrict__ tw, float2* __restrict__ X) {
   using S = OlsShape<K>;
   __shared__ float2 lds[S::F * S::LDS];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
-  const int64_t b = (int64_t)blockIdx.x * S::F + f;
+  const int64_t b = (int64_t)blockIdx.x * S::F + f;     // row of X; the segment block is b_first + b
   OlsTw<K> w;
   ols_twiddles<K, -1>(w, tw, t);
   float2 v[16];
-  const int64_t start = b * L + k0;
+  const int64_t start = (b_first + b) * L + k0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = b < nB ? z[(start + t + S::NTf * r) & (n - 1)] : make_float2(0.f, 0.f);
   ols_fft<K, -1>(v, lds + f * S::LDS, t, w);
@@ -247,7 +247,9 @@ struct OlsArgs {
   const float2* G;           // [count][K] tap spectra
   const float2* tw;          // exp(+2 pi i m / 4096), m < 4096
   unsigned long long* slots;
-  int64_t n, count, tmpl0, nwin, W, nB;
+  int64_t n, count, tmpl0, nwin, W, nB;   // nB: blocks of this launch (rows of X)
+  int64_t b_first;           // segment block of X's row 0
+  int64_t n_lo, n_hi;        // output samples kept: [n_lo, n_hi)
   int L, J;                  // valid outputs per block, templates per workgroup
 };
 
@@ -274,9 +276,11 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) xb[r] = Xb[t + S::NTf * r];
   // this block's output samples and their windows (uniform per FFT)
-  const int64_t n0 = b * a.L;
-  const int64_t nend = std::min<int64_t>(n0 + a.L, a.n);
-  const int64_t q0 = n0 / a.W, q1 = bvalid ? (nend - 1) / a.W : q0;
+  const int64_t n0 = (a.b_first + b) * a.L;
+  const int64_t nbeg = std::max<int64_t>(n0, a.n_lo);
+  const int64_t nend = std::min<int64_t>(std::min<int64_t>(n0 + a.L, a.n), a.n_hi);
+  const bool has_out = bvalid && nend > nbeg;
+  const int64_t q0 = has_out ? nbeg / a.W : 0, q1 = has_out ? (nend - 1) / a.W : 0;
   const int64_t j0 = (int64_t)blockIdx.y * a.J;
   const int64_t j1 = std::min<int64_t>(j0 + a.J, a.count);
   const bool lead = (threadIdx.x & 63) == 0;
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gj[t + S::NTf * r]);
     ols_fft<K, 1>(v, lds + f * S::LDS, t, w);
-    if (!bvalid) continue;
+    if (!has_out) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
     float r2[16];
 #pragma unroll
@@ -294,14 +298,15 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
     if (q1 - q0 < kOlsMaxWin) {
       // one reduction and one atomic per window the block touches
       for (int64_t qw = q0; qw <= q1; ++qw) {
-        const int64_t ws = qw * a.W, we = std::min<int64_t>(ws + a.W, nend);
+        const int64_t wq = qw * a.W;
+        const int64_t ws = std::max<int64_t>(wq, nbeg), we = std::min<int64_t>(wq + a.W, nend);
         unsigned long long k = 0;
 #pragma unroll
         for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
           for (int s = 0; s < S::R; ++s) {
             const int64_t nn = n0 + ols_out_index<K>(t, e, s);
-            if (nn >= ws && nn < we) k = umax64_ols(k, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - ws)));
+            if (nn >= ws && nn < we) k = umax64_ols(k, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - wq)));
           }
         k = ols_reduce<K>(k);
         if (lead) atomicMax(slot + qw, k);
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
 #pragma unroll
         for (int s = 0; s < S::R; ++s) {
           const int64_t nn = n0 + ols_out_index<K>(t, e, s);
-          if (nn < nend) {
+          if (nn >= nbeg && nn < nend) {
             const int64_t q = nn / a.W;
             atomicMax(slot + q, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - q * a.W)));
           }
@@ -399,11 +404,14 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc) {
 }
 
 template <int K>
-static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin) {
+static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, int64_t n_lo,
+                        int64_t n_hi) {
   using S = OlsShape<K>;
   const float2* z = p.zref + (int64_t)s.ref_id * p.n;
-  const unsigned gx = (unsigned)((s.ols_nB + S::F - 1) / S::F);
-  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, s.ols_nB,
+  const int64_t b_first = n_lo / s.ols_L, b_last = (n_hi - 1) / s.ols_L;
+  const int64_t nB = b_last - b_first + 1;      // <= s.ols_nB
+  const unsigned gx = (unsigned)((nB + S::F - 1) / S::F);
+  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, nB, b_first,
                      (const float2*)p.ols_tw32, s.ols_x);
   RFD_CHECK_LAUNCH();
   OlsArgs a;
@@ -416,24 +424,29 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
   a.tmpl0 = s.first;
   a.nwin = nwin;
   a.W = W;
-  a.nB = s.ols_nB;
+  a.nB = nB;
+  a.b_first = b_first;
+  a.n_lo = n_lo;
+  a.n_hi = n_hi;
   a.L = s.ols_L;
-  a.J = ols_templates_per_wg(s.ols_nB, S::F, s.count, p.n_cu);
+  a.J = ols_templates_per_wg(nB, S::F, s.count, p.n_cu);
   const unsigned gy = (unsigned)((s.count + a.J - 1) / a.J);
   hipLaunchKernelGGL(k_ols<K>, dim3(gx, gy), dim3(256), 0, p.stream, a);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 
-int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin) {
+int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, int64_t n_lo, int64_t n_hi) {
+  if (n_hi < 0) n_hi = p.n;
+  if (n_lo < 0 || n_hi > p.n || n_lo >= n_hi) return fail(RFD_E_INVALID, "overlap-save: empty output range");
   for (const SubBankTaps& s : t.sb) {
     if (s.count == 0) continue;
     if (!s.ols_valid || !s.ols_x) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
     int rc;
     switch (s.ols_K) {
-      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin); break;
-      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin); break;
-      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin); break;
+      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin, n_lo, n_hi); break;
+      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin, n_lo, n_hi); break;
+      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin, n_lo, n_hi); break;
       default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
     }
     if (rc) return rc;

@@ -178,9 +178,14 @@ int launch_dechirp_bands(Plan& p, const double* h_ref, const int64_t* edges, int
 // ---------------------------------------------------- launchers (taps.hip)
 int taps_prepare_subbank(Plan& p, Taps& tp, int b, const double* h_ref, double eps);
 int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, int method);
+// sigma_fit of the taps in a64 (with the sub-bank's g), then the normalised packings
+int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
 
 // ----------------------------------------------------- launchers (fir.hip)
-int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin);
+// n_len < 0: the whole segment; else output samples [n_start, n_start + n_len),
+// both multiples of 256
+int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin, int64_t n_start = 0,
+               int64_t n_len = -1);
 // all sub-banks in one persistent launch (builds the work-item tables if needed;
 // must not be called for the first time with a given key inside graph capture)
 int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W);
@@ -192,7 +197,8 @@ int ols_block_size(const Plan& p, int T);
 // is missing) and rebuild stale tap spectra in place (not inside capture)
 int ensure_ols(Plan& p, Taps& t, bool allow_alloc = true);
 // block spectra + overlap-save FIR of every sub-bank
-int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin);
+// outputs [n_lo, n_hi) only (default: the whole segment)
+int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, int64_t n_lo = 0, int64_t n_hi = -1);
 
 // ------------------------------------------------ launchers (triggers.hip)
 int launch_slots_clear(Plan& p, int64_t n_slots);

@@ -72,6 +72,9 @@ class RatioFilterSearch:
         return rfd.rfd_filter_bank(self.plan, self.taps, precision, threshold, window, capacity, out,
                                    raise_overflow)
 
+    def filter_range(self, precision, threshold, window, n_start, n_len, capacity, out=None):
+        return rfd.rfd_filter_range(self.plan, self.taps, precision, threshold, window, n_start, n_len, capacity, out)
+
     def bands(self, n_bands):
         """Band series of every reference and band shares of every sub-bank
         (the chi^2 test's inputs); returns the edges per reference."""

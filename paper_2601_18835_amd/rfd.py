@@ -82,6 +82,9 @@ _SIGS = {
     "rfd_taps_get_band_fractions": [_P, _i64, _P, C.POINTER(_i32)],
     "rfd_chisq": [_P, _P, _P, _i64, _P],
     "rfd_select_taps": [_P, _P, _P, _i64, _d, _P, _i32, _d, _P, _P],
+    "rfd_plan_set_psd": [_P, _P, _i64],
+    "rfd_filter_range": [_P, _P, _i32, _f, _i64, _i64, _i64, _P, _i64, C.POINTER(_i64)],
+    "rfd_taps_renormalize": [_P, _P, _i32, _P],
     "rfd_surrogate_destroy": [_P],
     "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
     "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
@@ -486,3 +489,27 @@ def rfd_select_taps(plan, h_ref, h_tmpl, target, ladder, ridge_eps=1e-4):
     _check(_lib.rfd_select_taps(plan, _ptr(h_ref), _ptr(h_tmpl), count, target, lad.ctypes.data, lad.size,
                                 ridge_eps, T.ctypes.data, m.ctypes.data), "rfd_select_taps")
     return T, m
+
+
+# --------------------------------------------------------------- PSD drift
+def rfd_plan_set_psd(plan, psd):
+    psd = np.ascontiguousarray(psd, dtype=np.float64)
+    _check(_lib.rfd_plan_set_psd(plan, psd.ctypes.data, psd.size), "rfd_plan_set_psd")
+
+
+def rfd_taps_renormalize(plan, taps, subbank, h_ref):
+    import torch
+    info = rfd_plan_info_get(plan)
+    _dev_check(h_ref, torch.complex128, info["n_bins"], "h_ref")
+    _check(_lib.rfd_taps_renormalize(plan, taps, subbank, _ptr(h_ref)), "rfd_taps_renormalize")
+
+
+# ------------------------------------------------------------ low latency
+def rfd_filter_range(plan, taps, precision, threshold, cluster_window, n_start, n_len, capacity, out=None):
+    prec = PRECISIONS.get(precision, precision)
+    if out is None:
+        out = _trigger_buffer(capacity)
+    n = C.c_int64(0)
+    _check(_lib.rfd_filter_range(plan, taps, prec, threshold, cluster_window, n_start, n_len, _ptr(out), capacity,
+                                 C.byref(n)), "rfd_filter_range")
+    return out, n.value

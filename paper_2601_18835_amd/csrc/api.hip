@@ -146,8 +146,8 @@ static bool use_persistent(const Plan& p, const Taps& t) {
 }
 
 // FIR kernels of every sub-bank (one persistent launch or one per sub-bank).
-static int enqueue_fir(Plan& p, Taps& t, int precision, int64_t W, int64_t nwin) {
-  if (precision == RFD_OLS32) return launch_ols(p, t, W, nwin);
+static int enqueue_fir(Plan& p, Taps& t, int precision, int64_t W, int64_t nwin, float threshold) {
+  if (precision == RFD_OLS32) return launch_ols(p, t, W, nwin, threshold);
   if (use_persistent(p, t)) return launch_fir_persistent(p, t, precision, W, nwin);
   for (size_t b = 0; b < t.sb.size(); ++b) {
     int rc = launch_fir(p, t, (int)b, precision, W, nwin);
@@ -423,7 +423,7 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
     ms = 1e30;
     for (int i = 0; i < reps + 1; ++i) {      // first run warms caches and code
       RFD_HIP(hipEventRecord(a, p.stream));
-      r = enqueue_fir(p, t, precision, cluster_window, nwin);
+      r = enqueue_fir(p, t, precision, cluster_window, nwin, 0.f);   // every window, as in validation
       if (r) break;
       RFD_HIP(hipEventRecord(b, p.stream));
       RFD_HIP(hipEventSynchronize(b));
@@ -760,7 +760,7 @@ int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, flo
   if (rc) return rc;
   rc = stage_begin(p, kStFir);
   if (rc) return rc;
-  rc = enqueue_fir(p, tm, precision, cluster_window, nwin);
+  rc = enqueue_fir(p, tm, precision, cluster_window, nwin, threshold);
   if (rc) return rc;
   rc = stage_end(p);
   if (!rc) rc = stage_begin(p, kStCompact);
@@ -800,7 +800,7 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
   rc = stage_begin(p, kStFir);
   if (rc) return rc;
   if (precision == RFD_OLS32) {
-    rc = launch_ols(p, t, cluster_window, nwin, n_start, n_start + n_len);
+    rc = launch_ols(p, t, cluster_window, nwin, threshold, n_start, n_start + n_len);
   } else {
     for (size_t b = 0; !rc && b < t.sb.size(); ++b)
       rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin, n_start, n_len);
@@ -942,7 +942,7 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
     rc = launch_data_fft(p, data);
     for (int i = 0; !rc && i < n_refs; ++i) rc = launch_dechirp(p, h_refs[i], ref_ids[i], p.dscratch);
     if (!rc) rc = launch_slots_clear(p, n_slots);
-    if (!rc) rc = enqueue_fir(p, t, precision, cluster_window, nwin);
+    if (!rc) rc = enqueue_fir(p, t, precision, cluster_window, nwin, threshold);
     if (!rc) rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);
     if (!rc) rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
     hipError_t e = hipStreamEndCapture(cap, &g);

@@ -251,6 +251,7 @@ struct OlsArgs {
   int64_t b_first;           // segment block of X's row 0
   int64_t n_lo, n_hi;        // output samples kept: [n_lo, n_hi)
   int L, J;                  // valid outputs per block, templates per workgroup
+  float thr2;                // threshold^2 of the compaction (a key <= it never fires)
 };
 
 template <int K>
@@ -293,8 +294,20 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
     if (!has_out) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
     float r2[16];
+    float r2max = 0.f;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) r2[q] = v[q].x * v[q].x + v[q].y * v[q].y;
+    for (int e = 0; e < 16 / S::R; ++e)
+#pragma unroll
+      for (int s = 0; s < S::R; ++s) {
+        const float2 y = v[e * S::R + s];
+        const float x = y.x * y.x + y.y * y.y;
+        r2[e * S::R + s] = x;
+        const int64_t nn = n0 + ols_out_index<K>(t, e, s);
+        if (nn >= nbeg && nn < nend) r2max = fmaxf(r2max, x);
+      }
+    // the compaction reports a window only if its peak exceeds thr2: a wave
+    // with no sample above it cannot contribute a reported peak
+    if (!__any(r2max > a.thr2)) continue;
     if (q1 - q0 < kOlsMaxWin) {
       // one reduction and one atomic per window the block touches
       for (int64_t qw = q0; qw <= q1; ++qw) {
@@ -404,8 +417,8 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc) {
 }
 
 template <int K>
-static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, int64_t n_lo,
-                        int64_t n_hi) {
+static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, float threshold,
+                        int64_t n_lo, int64_t n_hi) {
   using S = OlsShape<K>;
   const float2* z = p.zref + (int64_t)s.ref_id * p.n;
   const int64_t b_first = n_lo / s.ols_L, b_last = (n_hi - 1) / s.ols_L;
@@ -430,13 +443,14 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
   a.n_hi = n_hi;
   a.L = s.ols_L;
   a.J = ols_templates_per_wg(nB, S::F, s.count, p.n_cu);
+  a.thr2 = threshold * threshold;
   const unsigned gy = (unsigned)((s.count + a.J - 1) / a.J);
   hipLaunchKernelGGL(k_ols<K>, dim3(gx, gy), dim3(256), 0, p.stream, a);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 
-int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, int64_t n_lo, int64_t n_hi) {
+int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo, int64_t n_hi) {
   if (n_hi < 0) n_hi = p.n;
   if (n_lo < 0 || n_hi > p.n || n_lo >= n_hi) return fail(RFD_E_INVALID, "overlap-save: empty output range");
   for (const SubBankTaps& s : t.sb) {
@@ -444,9 +458,9 @@ int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, int64_t n_lo, in
     if (!s.ols_valid || !s.ols_x) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
     int rc;
     switch (s.ols_K) {
-      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin, n_lo, n_hi); break;
-      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin, n_lo, n_hi); break;
-      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin, n_lo, n_hi); break;
+      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin, threshold, n_lo, n_hi); break;
+      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin, threshold, n_lo, n_hi); break;
+      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin, threshold, n_lo, n_hi); break;
       default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
     }
     if (rc) return rc;

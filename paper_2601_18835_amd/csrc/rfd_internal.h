@@ -197,8 +197,10 @@ int ols_block_size(const Plan& p, int T);
 // is missing) and rebuild stale tap spectra in place (not inside capture)
 int ensure_ols(Plan& p, Taps& t, bool allow_alloc = true);
 // block spectra + overlap-save FIR of every sub-bank
-// outputs [n_lo, n_hi) only (default: the whole segment)
-int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, int64_t n_lo = 0, int64_t n_hi = -1);
+// outputs [n_lo, n_hi) only (default: the whole segment); blocks whose samples
+// all have rho <= threshold skip the window keys (they can never fire)
+int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo = 0,
+               int64_t n_hi = -1);
 
 // ------------------------------------------------ launchers (triggers.hip)
 int launch_slots_clear(Plan& p, int64_t n_slots);

@@ -172,7 +172,7 @@ def main():
         return tot
 
     def ols_block(T):
-        eff = {1024: 1.26, 2048: 1.0, 4096: 0.72}     # the library's block-size rule
+        eff = {1024: 1.25, 2048: 1.0, 4096: 0.97}     # the library's block-size rule
         cands = [K for K in (1024, 2048, 4096) if K > T]
         return min(cands, key=lambda K: ((5 * np.log2(K) + 6) * K / (K - T + 1) / eff[K], K))
 
@@ -567,7 +567,7 @@ def oracle_sample(args, w, bank, psd, seg, hrefs, s, out, cap, eager_step, prec,
     gain = np.array([np.sum(np.abs(tts[i].a)) * refs[sbi[i]].sigma / tts[i].sigma_fit for i in range(len(sample))])
     tlen = np.array([bank.subbanks[sbi[i]].taps for i in range(len(sample))])
     gain2 = np.array([np.linalg.norm(tts[i].a) * refs[sbi[i]].sigma / tts[i].sigma_fit for i in range(len(sample))])
-    eff = {1024: 1.26, 2048: 1.0, 4096: 0.72}
+    eff = {1024: 1.25, 2048: 1.0, 4096: 0.97}
     kblk = np.array([min([K for K in (1024, 2048, 4096) if K > T],
                          key=lambda K: ((5 * np.log2(K) + 6) * K / (K - T + 1) / eff[K], K)) for T in tlen],
                     dtype=float)

@@ -274,8 +274,8 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
  *   wg_per_cu   persistent grid size in workgroups per CU (0: all that fit).
  *   ols_block   RFD_OLS32 block size K: 0 chooses per sub-bank the K in
  *               {1024, 2048, 4096} of least (5 log2 K + 6) K / (K - T + 1)
- *               divided by the measured relative speed of that K (1.26,
- *               1, 0.72); 1024, 2048 or 4096 forces it wherever K > T.
+ *               divided by the measured relative speed of that K (1.25,
+ *               1, 0.97); 1024, 2048 or 4096 forces it wherever K > T.
  * RFD_E_INVALID for values outside these sets.
  */
 typedef struct rfd_fir_config {

@@ -152,7 +152,7 @@ def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None):
 UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22, "ols32": 2.0 ** -24}
 
 
-OLS_EFFICIENCY = {1024: 1.26, 2048: 1.0, 4096: 0.72}
+OLS_EFFICIENCY = {1024: 1.25, 2048: 1.0, 4096: 0.97}
 
 
 def ols_block(T, forced=0):

@@ -72,7 +72,7 @@ __device__ __forceinline__ V twiddle_n(const V* __restrict__ coarse, const V* __
 
 // ------------------------------------------------------------------ LDS FFT
 // C independent L-point DFTs, X[k] = sum_n x[n] exp(sign 2 pi i n k / L), on
-// LDS data laid out [C][LP] (LP = L + 1 padding), Stockham autosort, radix 4
+// LDS data laid out [C][LP] (LP = lds_col<L>(), elements at lpad(i)), Stockham autosort, radix 4
 // stages then one radix-2 stage when log2 L is odd.  `twl` holds
 // exp(+2 pi i k / L), k < L, in LDS.  All NT threads of the block must call.
 template <typename V>
@@ -84,16 +84,24 @@ __device__ __forceinline__ void dft4(V& a, V& b, V& c, V& d, int sign) {
   d = csub(s1, s3);
 }
 
+// LDS position of element x of a column (or of the twiddle table): one
+// complex value of padding after every 16, so the strided butterfly writes
+// of the early radix-4 stages spread over the banks.
+__device__ __forceinline__ constexpr int lpad(int x) { return x + (x >> 4); }
+// column stride of an L-point column in LDS (odd: column loads stay conflict free)
+template <int L>
+__host__ __device__ constexpr int lds_col() { return L + L / 16 + 1; }
+
 template <typename V>
 __device__ __forceinline__ V tw_lds(const V* twl, int idx, int sign) {
-  V t = twl[idx];
+  V t = twl[lpad(idx)];
   if (sign < 0) t.y = -t.y;
   return t;
 }
 
 template <typename V, int L, int C, int NT>
 __device__ void lds_fft(V* buf, const V* twl, int sign) {
-  constexpr int LP = L + 1;
+  constexpr int LP = lds_col<L>();
   constexpr int LOG = __builtin_ctz(L);
   constexpr int NBF4 = C * (L / 4);
   constexpr int PER4 = (NBF4 + NT - 1) / NT;
@@ -109,7 +117,7 @@ __device__ void lds_fft(V* buf, const V* twl, int sign) {
         int c = idx / (L / 4), j = idx % (L / 4);
         const V* col = buf + c * LP;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[t][r] = col[j + r * (L / 4)];
+        for (int r = 0; r < 4; ++r) v[t][r] = col[lpad(j + r * (L / 4))];
         int k = j & (Ns - 1);
         if (Ns > 1) {
           int step = L / (4 * Ns);
@@ -129,7 +137,7 @@ __device__ void lds_fft(V* buf, const V* twl, int sign) {
         V* col = buf + c * LP;
         int d = (j / Ns) * Ns * 4 + k;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) col[d + r * Ns] = v[t][r];
+        for (int r = 0; r < 4; ++r) col[lpad(d + r * Ns)] = v[t][r];
       }
     }
     __syncthreads();
@@ -145,8 +153,8 @@ __device__ void lds_fft(V* buf, const V* twl, int sign) {
       if ((NBF2 % NT) == 0 || idx < NBF2) {
         int c = idx / (L / 2), j = idx % (L / 2);
         const V* col = buf + c * LP;
-        v[t][0] = col[j];
-        v[t][1] = col[j + L / 2];
+        v[t][0] = col[lpad(j)];
+        v[t][1] = col[lpad(j + L / 2)];
         int k = j & (Ns - 1);
         if (Ns > 1) v[t][1] = cmul(v[t][1], tw_lds(twl, k * (L / (2 * Ns)), sign));
         V a = cadd(v[t][0], v[t][1]), b = csub(v[t][0], v[t][1]);
@@ -163,8 +171,8 @@ __device__ void lds_fft(V* buf, const V* twl, int sign) {
         int k = j & (Ns - 1);
         V* col = buf + c * LP;
         int d = (j / Ns) * Ns * 2 + k;
-        col[d] = v[t][0];
-        col[d + Ns] = v[t][1];
+        col[lpad(d)] = v[t][0];
+        col[lpad(d + Ns)] = v[t][1];
       }
     }
     __syncthreads();

@@ -23,7 +23,7 @@ template <> struct Cols<float2> { static constexpr int value(int L) { return 8; 
 template <> struct Cols<double2> { static constexpr int value(int L) { return L >= 2048 ? 2 : 4; } };
 
 template <typename V, int L, int C>
-constexpr size_t lds_bytes() { return (size_t)C * (L + 1) * sizeof(V) + (size_t)L * sizeof(V); }
+constexpr size_t lds_bytes() { return (size_t)C * lds_col<L>() * sizeof(V) + (size_t)(L + L / 16) * sizeof(V); }
 
 // ---------------------------------------------------------------- loaders
 struct LoadData64 {        // real FP64 series, scaled, FP64 complex
@@ -100,7 +100,7 @@ struct StoreLags {         // keep lags k0 .. k0+T-1 (mod N), scaled
 // ------------------------------------------------------------------ passes
 template <typename V, int L>
 __device__ void load_twl(V* twl, const V* __restrict__ tab) {
-  for (int k = threadIdx.x; k < L; k += kNT) twl[k] = tab[k];
+  for (int k = threadIdx.x; k < L; k += kNT) twl[lpad(k)] = tab[k];
 }
 
 // pass A: L = N2-point transforms of C columns; writes Y with the inter-pass twiddle
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const 
                                               const V* __restrict__ fine, const V* __restrict__ tabL,
                                               int n1, int sign) {
   constexpr int C = Cols<V>::value(L);
-  constexpr int LP = L + 1;
+  constexpr int LP = lds_col<L>();
   extern __shared__ __align__(16) unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
   V* twl = buf + C * LP;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const 
   load_twl<V, L>(twl, tabL);
   for (int e = threadIdx.x; e < C * L; e += kNT) {
     int c = e % C, i2 = e / C;
-    buf[c * LP + i2] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
+    buf[c * LP + lpad(i2)] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
   }
   __syncthreads();
   lds_fft<V, L, C, kNT>(buf, twl, sign);
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const 
   for (int e = threadIdx.x; e < C * L; e += kNT) {
     int c = e % C, n2 = e / C;
     int i1 = c0 + c;
-    V v = buf[c * LP + n2];
+    V v = buf[c * LP + lpad(n2)];
     uint32_t p = (uint32_t)i1 * (uint32_t)n2;   // < N
     if (p) v = cmul(v, twiddle_n(coarse, fine, p, sign));
     Yb[(int64_t)n2 * n1 + i1] = v;
@@ -137,11 +137,11 @@ __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const 
 template <typename V, int L>
 __device__ void pass_b_load(const V* __restrict__ Yb, V* buf, V* twl, const V* __restrict__ tabL, int r0) {
   constexpr int C = Cols<V>::value(L);
-  constexpr int LP = L + 1;
+  constexpr int LP = lds_col<L>();
   load_twl<V, L>(twl, tabL);
   for (int e = threadIdx.x; e < C * L; e += kNT) {
     int c = e / L, i1 = e % L;
-    buf[c * LP + i1] = Yb[(int64_t)(r0 + c) * L + i1];
+    buf[c * LP + lpad(i1)] = Yb[(int64_t)(r0 + c) * L + i1];
   }
   __syncthreads();
 }
@@ -151,7 +151,7 @@ template <typename V, int L, class ST>
 __global__ __launch_bounds__(kNT) void k_pass_b(const V* __restrict__ Y, ST st, const V* __restrict__ tabL,
                                               int n2, int sign) {
   constexpr int C = Cols<V>::value(L);
-  constexpr int LP = L + 1;
+  constexpr int LP = lds_col<L>();
   extern __shared__ __align__(16) unsigned char smem[];
   V* buf = reinterpret_cast<V*>(smem);
   V* twl = buf + C * LP;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kNT) void k_pass_b(const V* __restrict__ Y, ST st, 
   lds_fft<V, L, C, kNT>(buf, twl, sign);
   for (int e = threadIdx.x; e < C * L; e += kNT) {
     int c = e % C, n1 = e / C;
-    st(b, (int64_t)(r0 + c) + (int64_t)n2 * n1, buf[c * LP + n1]);
+    st(b, (int64_t)(r0 + c) + (int64_t)n2 * n1, buf[c * LP + lpad(n1)]);
   }
 }
 
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kNT) void k_fc_pass_b(const float2* __restrict__ Y,
                                                  const float2* __restrict__ tabL, int n2, int64_t tmpl0,
                                                  int64_t nwin, int64_t W, int aligned) {
   constexpr int C = Cols<float2>::value(L);
-  constexpr int LP = L + 1;
+  constexpr int LP = lds_col<L>();
   constexpr int RUNS = kNT / C;
   constexpr int RUN = (L + RUNS - 1) / RUNS;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kNT) void k_fc_pass_b(const float2* __restrict__ Y,
     int n1 = run * RUN + t;
     if (n1 >= L) break;
     int64_t n = col + (int64_t)n2 * n1;
-    float2 v = buf[c * LP + n1];
+    float2 v = buf[c * LP + lpad(n1)];
     float r2 = v.x * v.x + v.y * v.y;
     int64_t q = n / W;
     unsigned long long key = ((unsigned long long)__float_as_uint(r2) << 32) |

@@ -872,7 +872,8 @@ int findchirp_filter(rfd_plan* plan, const double* data, const float* filt, int6
   if (rc) return rc;
   if (n_templates > 0) {
     rc = stage_begin(p, kStFindchirp);
-    if (!rc) rc = launch_findchirp(p, reinterpret_cast<const float2*>(filt), n_templates, cluster_window, nwin);
+    if (!rc) rc = launch_findchirp(p, reinterpret_cast<const float2*>(filt), n_templates, cluster_window, nwin,
+                                      threshold);
     if (!rc) rc = stage_end(p);
     if (rc) return rc;
   }

@@ -9,8 +9,8 @@
 // LDS, so every global access is a run of C contiguous elements.  The first
 // pass fuses the pointwise product of Eq. 1 (data x conj(template) x weight);
 // the second fuses the consumer: spectrum store, reference-series store with
-// its 16-bit hi/lo planes, FINDCHIRP's |z|^2 / window-peak epilogue, or the
-// selection of the T correlation lags used by tap construction.
+// its 16-bit hi/lo planes, or the selection of the T correlation lags used by
+// tap construction.  (FINDCHIRP's own transforms live with its kernels.)
 #include "dev_common.h"
 #include "rfd_internal.h"
 
@@ -99,15 +99,16 @@ struct StoreLags {         // keep lags k0 .. k0+T-1 (mod N), scaled
 
 // ------------------------------------------------------------------ passes
 template <typename V, int L>
-__device__ void load_twl(V* twl, const V* __restrict__ tab) {
-  for (int k = threadIdx.x; k < L; k += kNT) twl[lpad(k)] = tab[k];
+__device__ void load_twl(V* twl, const V* __restrict__ tab, int stride = 1) {
+  for (int k = threadIdx.x; k < L; k += kNT) twl[lpad(k)] = tab[k * stride];
 }
 
-// pass A: L = N2-point transforms of C columns; writes Y with the inter-pass twiddle
+// pass A: L = N2-point transforms of C columns; writes Y with the inter-pass
+// twiddle.  tabL[k * tab_stride] = exp(+2 pi i k / L).
 template <typename V, int L, class LD>
 __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const V* __restrict__ coarse,
                                               const V* __restrict__ fine, const V* __restrict__ tabL,
-                                              int n1, int sign) {
+                                              int n1, int sign, int tab_stride) {
   constexpr int C = Cols<V>::value(L);
   constexpr int LP = lds_col<L>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const 
   const int b = blockIdx.y;
   const int c0 = blockIdx.x * C;
   const int64_t n = (int64_t)n1 * L;
-  load_twl<V, L>(twl, tabL);
+  load_twl<V, L>(twl, tabL, tab_stride);
   for (int e = threadIdx.x; e < C * L; e += kNT) {
     int c = e % C, i2 = e / C;
     buf[c * LP + lpad(i2)] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
@@ -166,73 +167,6 @@ __global__ __launch_bounds__(kNT) void k_pass_b(const V* __restrict__ Y, ST st, 
   }
 }
 
-// pass B of FINDCHIRP: rho^2 of the normalised series, per-window peak keys.
-// Key = (bits(rho^2) << 32) | (0xFFFFFFFF - (n - qW)): the largest rho^2
-// wins, and on equal rho^2 the lowest sample.  Thread layout: column
-// c = tid % C, a run of L/32 consecutive n1 per thread, so each thread keeps a
-// running maximum and flushes it when the window changes.
-template <int L>
-__global__ __launch_bounds__(kNT) void k_fc_pass_b(const float2* __restrict__ Y, unsigned long long* __restrict__ slots,
-                                                 const float2* __restrict__ tabL, int n2, int64_t tmpl0,
-                                                 int64_t nwin, int64_t W, int aligned) {
-  constexpr int C = Cols<float2>::value(L);
-  constexpr int LP = lds_col<L>();
-  constexpr int RUNS = kNT / C;
-  constexpr int RUN = (L + RUNS - 1) / RUNS;
-  extern __shared__ __align__(16) unsigned char smem[];
-  float2* buf = reinterpret_cast<float2*>(smem);
-  float2* twl = buf + C * LP;
-  const int b = blockIdx.y;
-  const int r0 = blockIdx.x * C;
-  pass_b_load<float2, L>(Y + (int64_t)b * L * n2, buf, twl, tabL, r0);
-  lds_fft<float2, L, C, kNT>(buf, twl, +1);
-  const int c = threadIdx.x % C, run = threadIdx.x / C;
-  const int64_t col = r0 + c;
-  unsigned long long* srow = slots + (tmpl0 + b) * nwin;
-  int64_t qcur = -1;
-  unsigned long long kmax = 0;
-  for (int t = 0; t < RUN; ++t) {
-    int n1 = run * RUN + t;
-    if (n1 >= L) break;
-    int64_t n = col + (int64_t)n2 * n1;
-    float2 v = buf[c * LP + lpad(n1)];
-    float r2 = v.x * v.x + v.y * v.y;
-    int64_t q = n / W;
-    unsigned long long key = ((unsigned long long)__float_as_uint(r2) << 32) |
-                             (unsigned long long)(0xFFFFFFFFu - (uint32_t)(n - q * W));
-    if (q != qcur) {
-      if (qcur >= 0) {
-        if (aligned) {
-#pragma unroll
-          for (int o = 1; o < C; o <<= 1) {
-            unsigned long long other = __shfl_xor(kmax, o);
-            kmax = other > kmax ? other : kmax;
-          }
-          if (c == 0) atomicMax(srow + qcur, kmax);
-        } else {
-          atomicMax(srow + qcur, kmax);
-        }
-      }
-      qcur = q;
-      kmax = key;
-    } else if (key > kmax) {
-      kmax = key;
-    }
-  }
-  if (qcur >= 0) {
-    if (aligned) {
-#pragma unroll
-      for (int o = 1; o < C; o <<= 1) {
-        unsigned long long other = __shfl_xor(kmax, o);
-        kmax = other > kmax ? other : kmax;
-      }
-      if (c == 0) atomicMax(srow + qcur, kmax);
-    } else {
-      atomicMax(srow + qcur, kmax);
-    }
-  }
-}
-
 // -------------------------------------------------------------- dispatch
 template <typename V, class LD>
 static int run_pass_a(Plan& p, LD ld, V* Y, const V* coarse, const V* fine, const V* tab2, int batch, int sign) {
@@ -243,7 +177,7 @@ static int run_pass_a(Plan& p, LD ld, V* Y, const V* coarse, const V* fine, cons
     constexpr int C = Cols<V>::value(LL);                                                  \
     size_t sh = lds_bytes<V, LL, C>();                                                     \
     hipLaunchKernelGGL((k_pass_a<V, LL, LD>), dim3(p.n1 / C, batch), blk, sh, p.stream, ld, Y, coarse, \
-                       fine, tab2, p.n1, sign);                                            \
+                       fine, tab2, p.n1, sign, 1);                                         \
     break;                                                                                 \
   }
     CASE_A(32) CASE_A(64) CASE_A(128) CASE_A(256) CASE_A(512) CASE_A(1024) CASE_A(2048)
@@ -268,26 +202,6 @@ static int run_pass_b(Plan& p, const V* Y, ST st, const V* tab1, int batch, int 
   }
     CASE_B(32) CASE_B(64) CASE_B(128) CASE_B(256) CASE_B(512) CASE_B(1024) CASE_B(2048)
 #undef CASE_B
-    default: return fail(RFD_E_UNSUPPORTED, "fft: unsupported N1");
-  }
-  RFD_CHECK_LAUNCH();
-  return RFD_OK;
-}
-
-static int run_fc_pass_b(Plan& p, const float2* Y, int batch, int64_t tmpl0, int64_t nwin, int64_t W) {
-  int aligned = (W >= p.n2 && W % p.n2 == 0) ? 1 : 0;
-  dim3 blk(kNT);
-  switch (p.n1) {
-#define CASE_F(LL)                                                                          \
-  case LL: {                                                                                \
-    constexpr int C = Cols<float2>::value(LL);                                              \
-    size_t sh = lds_bytes<float2, LL, C>();                                                 \
-    hipLaunchKernelGGL((k_fc_pass_b<LL>), dim3(p.n2 / C, batch), blk, sh, p.stream, Y, p.slots, p.tw32_n1, \
-                       p.n2, tmpl0, nwin, W, aligned);                                      \
-    break;                                                                                  \
-  }
-    CASE_F(32) CASE_F(64) CASE_F(128) CASE_F(256) CASE_F(512) CASE_F(1024) CASE_F(2048)
-#undef CASE_F
     default: return fail(RFD_E_UNSUPPORTED, "fft: unsupported N1");
   }
   RFD_CHECK_LAUNCH();
@@ -411,24 +325,26 @@ int launch_findchirp_prepare(Plan& p, const double* h, int64_t count, float2* fi
   return RFD_OK;
 }
 
-int findchirp_batch_size(const Plan& p) {
-  // intermediates of up to ~128 MiB stay resident in the 256 MB MALL
-  int64_t b = ((int64_t)128 << 20) / (p.n * (int64_t)sizeof(float2));
-  if (b < 1) b = 1;
-  if (b > 64) b = 64;
-  return (int)b;
-}
-
-int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin) {
-  int bs = findchirp_batch_size(p);
-  for (int64_t t0 = 0; t0 < n_templates; t0 += bs) {
-    int nb = (int)((n_templates - t0) < bs ? (n_templates - t0) : bs);
-    LoadFindchirp ld{p.stilde, filt + t0 * p.n_band, p.i_low, p.i_high, p.n_band};
-    int rc = run_pass_a<float2>(p, ld, p.fc_work, p.tw32c, p.tw32f, p.tw32_n2, nb, +1);
-    if (rc) return rc;
-    rc = run_fc_pass_b(p, p.fc_work, nb, t0, nwin, W);
-    if (rc) return rc;
+// FINDCHIRP pass A for N2 = N / 4096 > 256 (segments of 2^21 and 2^22
+// samples): the LDS Stockham column transform into the [N2][4096] layout of
+// the register-FFT row pass, twiddles from the 4096-entry table.
+int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, int n2) {
+  LoadFindchirp ld{p.stilde, filt, p.i_low, p.i_high, p.n_band};
+  dim3 blk(kNT);
+  switch (n2) {
+#define CASE_L(LL)                                                                             \
+  case LL: {                                                                                   \
+    constexpr int C = Cols<float2>::value(LL);                                                 \
+    size_t sh = lds_bytes<float2, LL, C>();                                                    \
+    hipLaunchKernelGGL((k_pass_a<float2, LL, LoadFindchirp>), dim3(n1 / C, nb), blk, sh, p.stream, \
+                       ld, Y, p.tw32c, p.tw32f, p.ols_tw32, n1, +1, 4096 / LL);                \
+    break;                                                                                     \
   }
+    CASE_L(512) CASE_L(1024)
+#undef CASE_L
+    default: return fail(RFD_E_UNSUPPORTED, "findchirp: unsupported column length");
+  }
+  RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 

@@ -14,14 +14,13 @@
 // multiplies, runs one K-point inverse FFT per (template, block) in registers
 // and LDS, and feeds the same window-peak keys as the MFMA forms.
 //
-// FFT: K = 256 R (R = 4, 8, 16) by NTf = K/16 threads, 16 values each,
-// index m = t + NTf r:  a radix-16 stage over r in registers, an LDS
-// exchange, a radix-16 stage, an LDS exchange, a radix-R stage.  F = 256/NTf
-// independent FFTs share a workgroup.
+// FFT: the register-resident K-point transform of block_fft.h (K = 1024,
+// 2048, 4096), 4096/K blocks per workgroup.
 #include <math.h>
 
 #include <algorithm>
 
+#include "block_fft.h"
 #include "dev_common.h"
 #include "rfd_internal.h"
 
@@ -38,185 +37,28 @@ __device__ __forceinline__ unsigned long long umax64_ols(unsigned long long a, u
   return a > b ? a : b;
 }
 
-// cos / sin (2 pi k / 16), k < 16
-__device__ __forceinline__ float2 w16(int k, int sign) {
-  constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
-                           0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
-                           -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
-                           0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
-  return make_float2(c[k & 15], sign * c[(k + 12) & 15]);   // sin x = cos(x - pi/2)
-}
-
-// 16-point DFT in registers, V[k] = sum_n v[n] e^{sign 2 pi i n k / 16}.
-// On return slot s holds V[(s >> 2) + 4 (s & 3)].
-template <int SIGN>
-__device__ __forceinline__ void dft16(float2 (&v)[16]) {
-#pragma unroll
-  for (int n1 = 0; n1 < 4; ++n1) dft4(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12], SIGN);
-#pragma unroll
-  for (int n1 = 1; n1 < 4; ++n1)
-#pragma unroll
-    for (int k = 1; k < 4; ++k) v[n1 + 4 * k] = cmul(v[n1 + 4 * k], w16(n1 * k, SIGN));
-#pragma unroll
-  for (int k = 0; k < 4; ++k) dft4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3], SIGN);
-}
-__device__ __forceinline__ constexpr int dft16_freq(int s) { return (s >> 2) + 4 * (s & 3); }
-
-// R-point DFTs (R = 4, 8, 16) on consecutive groups of R slots of v; slot
-// g R + s holds V_g[dftR_freq(s)].
-template <int R, int SIGN>
-__device__ __forceinline__ void dft_r(float2 (&v)[16]) {
-  if constexpr (R == 16) {
-    dft16<SIGN>(v);
-  } else if constexpr (R == 4) {
-#pragma unroll
-    for (int g = 0; g < 4; ++g) dft4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3], SIGN);
-  } else {   // R == 8: n = n1 + 2 n2, DFT4 over n2, twiddle, DFT2 over n1
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      float2* u = v + 8 * g;
-      dft4(u[0], u[2], u[4], u[6], SIGN);
-      dft4(u[1], u[3], u[5], u[7], SIGN);
-#pragma unroll
-      for (int k = 1; k < 4; ++k) u[2 * k + 1] = cmul(u[2 * k + 1], w16(2 * k, SIGN));
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float2 a = u[2 * k], b = u[2 * k + 1];
-        u[2 * k] = cadd(a, b);
-        u[2 * k + 1] = csub(a, b);
-      }
-    }
-  }
-}
-template <int R>
-__device__ __forceinline__ constexpr int dftr_freq(int s) {
-  return R == 16 ? dft16_freq(s) : (R == 4 ? s : (s >> 1) + 4 * (s & 1));
-}
-
-template <int K>
-struct OlsShape {
-  static constexpr int NTf = K / 16;       // threads per FFT
-  static constexpr int R = K / 256;        // last radix
-  static constexpr int F = 256 / NTf;      // FFTs per workgroup
-  // row strides of the two exchanges ([k1][t] and [k2][k1][u]); padding by 4
-  // complex values (measured on MI355X: odd strides conflicted in the LDS
-  // banks, costing up to 1.8x at K = 4096)
-  static constexpr int S1 = NTf + 4;
-  static constexpr int S2 = R + 4;
-  static constexpr int LDS = (16 * S1 > 256 * S2 ? 16 * S1 : 256 * S2);   // float2 per FFT
-};
-
-// Per-thread twiddles: stage A  W_K^(t k1), stage B  W_K^(16 u k2), k = 1..15.
-template <int K>
-struct OlsTw {
-  float2 a[16], b[16];
-};
-template <int K, int SIGN>
-__device__ __forceinline__ void ols_twiddles(OlsTw<K>& w, const float2* __restrict__ tw, int t) {
-  using S = OlsShape<K>;
-  constexpr int step = 4096 / K;
-  const int u = t % S::R;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    float2 x = tw[((t * k) % K) * step];
-    float2 y = tw[((16 * u * k) % K) * step];
-    if (SIGN < 0) { x.y = -x.y; y.y = -y.y; }
-    w.a[k] = x;
-    w.b[k] = y;
-  }
-}
-
-// Exchange barrier: one wave per FFT (K = 1024) needs only wave-level
-// ordering of its LDS traffic, so the workgroup's four FFTs run
-// independently; larger FFTs span waves and synchronise the workgroup.
-template <int NTf>
-__device__ __forceinline__ void ols_sync() {
-  if constexpr (NTf <= 64) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
-// K-point DFT of v (thread t of its FFT holds x[t + NTf r] in v[r]) with
-// sign SIGN.  On return v[e * R + s] holds X[out_index(t, e, s)].  All
-// threads of the workgroup call it together (it synchronises).
-template <int K, int SIGN>
-__device__ __forceinline__ void ols_fft(float2 (&v)[16], float2* buf, int t, const OlsTw<K>& w) {
-  using S = OlsShape<K>;
-  constexpr int NTf = S::NTf, R = S::R;
-  // stage A: radix 16 over r
-  dft16<SIGN>(v);
-#pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const int k1 = dft16_freq(s);
-    buf[k1 * S::S1 + t] = k1 ? cmul(v[s], w.a[k1]) : v[s];
-  }
-  ols_sync<NTf>();
-  // stage B: thread (k1, u) = (t / R, t % R), radix 16 over v of t' = u + R v
-  {
-    const int k1 = t / R, u = t % R;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = buf[k1 * S::S1 + u + R * q];
-  }
-  ols_sync<NTf>();
-  dft16<SIGN>(v);
-  {
-    const int k1 = t / R, u = t % R;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int k2 = dft16_freq(s);
-      buf[(k2 * 16 + k1) * S::S2 + u] = k2 ? cmul(v[s], w.b[k2]) : v[s];
-    }
-  }
-  ols_sync<NTf>();
-  // stage C: thread (k1, g) = (t / R, t % R) takes k2 = g (16/R) + e, radix R over u
-  {
-    const int k1 = t / R, g = t % R;
-#pragma unroll
-    for (int e = 0; e < 16 / R; ++e) {
-      const int k2 = g * (16 / R) + e;
-#pragma unroll
-      for (int u = 0; u < R; ++u) v[e * R + u] = buf[(k2 * 16 + k1) * S::S2 + u];
-    }
-  }
-  ols_sync<NTf>();
-  dft_r<R, SIGN>(v);
-}
-
-// Output index of slot e * R + s of thread t after ols_fft.
-template <int K>
-__device__ __forceinline__ int ols_out_index(int t, int e, int s) {
-  using S = OlsShape<K>;
-  const int k1 = t / S::R, g = t % S::R;
-  const int k2 = g * (16 / S::R) + e;
-  return k1 + 16 * k2 + 256 * dftr_freq<S::R>(s);
-}
-
 // ------------------------------------------------------------ block spectra
 // X[b][f] for every block b of the reference series (forward FFT).
 template <int K>
 __global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
                                             int64_t b_first, const float2* __restrict__ tw, float2* __restrict__ X) {
-  using S = OlsShape<K>;
+  using S = BlockFft<K>;
   __shared__ float2 lds[S::F * S::LDS];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
   const int64_t b = (int64_t)blockIdx.x * S::F + f;     // row of X; the segment block is b_first + b
-  OlsTw<K> w;
-  ols_twiddles<K, -1>(w, tw, t);
+  BlockFftTw<K> w;
+  block_fft_twiddles<K, -1>(w, tw, t);
   float2 v[16];
   const int64_t start = (b_first + b) * L + k0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = b < nB ? z[(start + t + S::NTf * r) & (n - 1)] : make_float2(0.f, 0.f);
-  ols_fft<K, -1>(v, lds + f * S::LDS, t, w);
+  block_fft<K, -1>(v, lds + f * S::LDS, t, w);
   if (b >= nB) return;
   float2* xb = X + b * K;
 #pragma unroll
   for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
-    for (int s = 0; s < S::R; ++s) xb[ols_out_index<K>(t, e, s)] = v[e * S::R + s];
+    for (int s = 0; s < S::R; ++s) xb[block_fft_out<K>(t, e, s)] = v[e * S::R + s];
 }
 
 // --------------------------------------------------------- tap spectra (FP64)
@@ -259,7 +101,7 @@ struct OlsArgs {
 
 template <int K>
 __device__ __forceinline__ unsigned long long ols_reduce(unsigned long long k) {
-  constexpr int NTf = OlsShape<K>::NTf;
+  constexpr int NTf = BlockFft<K>::NTf;
   constexpr int span = NTf < 64 ? NTf : 64;
 #pragma unroll
   for (int o = 1; o < span; o <<= 1) k = umax64_ols(k, __shfl_xor(k, o));
@@ -268,13 +110,13 @@ __device__ __forceinline__ unsigned long long ols_reduce(unsigned long long k) {
 
 template <int K>
 __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
-  using S = OlsShape<K>;
+  using S = BlockFft<K>;
   __shared__ float2 lds[S::F * S::LDS];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
   const int64_t b = (int64_t)blockIdx.x * S::F + f;
   const bool bvalid = b < a.nB;
-  OlsTw<K> w;
-  ols_twiddles<K, 1>(w, a.tw, t);
+  BlockFftTw<K> w;
+  block_fft_twiddles<K, 1>(w, a.tw, t);
   float2 xb[16];
   const float2* Xb = a.X + (bvalid ? b : 0) * K;
 #pragma unroll
@@ -293,7 +135,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gj[t + S::NTf * r]);
-    ols_fft<K, 1>(v, lds + f * S::LDS, t, w);
+    block_fft<K, 1>(v, lds + f * S::LDS, t, w);
     if (!has_out) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
     float r2[16];
@@ -305,7 +147,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
         const float2 y = v[e * S::R + s];
         const float x = y.x * y.x + y.y * y.y;
         r2[e * S::R + s] = x;
-        const int64_t nn = n0 + ols_out_index<K>(t, e, s);
+        const int64_t nn = n0 + block_fft_out<K>(t, e, s);
         if (nn >= nbeg && nn < nend) r2max = fmaxf(r2max, x);
       }
     // the compaction reports a window only if its peak exceeds thr2: a wave
@@ -321,7 +163,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
         for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
           for (int s = 0; s < S::R; ++s) {
-            const int64_t nn = n0 + ols_out_index<K>(t, e, s);
+            const int64_t nn = n0 + block_fft_out<K>(t, e, s);
             if (nn >= ws && nn < we) k = umax64_ols(k, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - wq)));
           }
         k = ols_reduce<K>(k);
@@ -333,7 +175,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
       for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
         for (int s = 0; s < S::R; ++s) {
-          const int64_t nn = n0 + ols_out_index<K>(t, e, s);
+          const int64_t nn = n0 + block_fft_out<K>(t, e, s);
           if (nn >= nbeg && nn < nend) {
             const int64_t q = nn / a.W;
             atomicMax(slot + q, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - q * a.W)));
@@ -422,7 +264,7 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc) {
 template <int K>
 static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, float threshold,
                         int64_t n_lo, int64_t n_hi) {
-  using S = OlsShape<K>;
+  using S = BlockFft<K>;
   const float2* z = p.zref + (int64_t)s.ref_id * p.n;
   const int64_t b_first = n_lo / s.ols_L, b_last = (n_hi - 1) / s.ols_L;
   const int64_t nB = b_last - b_first + 1;      // <= s.ols_nB

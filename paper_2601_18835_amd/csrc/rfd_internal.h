@@ -165,7 +165,8 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 int launch_data_fft(Plan& p, const double* data);
 int launch_dechirp(Plan& p, const double* h_ref, int ref_id, double* sigma_dev);
 int launch_findchirp_prepare(Plan& p, const double* h, int64_t count, float2* filt, double* sigma);
-int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin);
+int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin, float threshold);
+int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, int n2);
 // FP64 correlation: out[t][l] = sum_i P_t[i] exp(+2 pi i i (k0+l)/N), l < T
 // mode 0: P = w h_t conj(h_r); mode 1: P = w |h_r|^2 (batch 1); mode 2: P = h_t/h_r
 // where w |h_r|^2 > 0, scaled by 1/N.

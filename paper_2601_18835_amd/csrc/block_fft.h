@@ -28,7 +28,11 @@ __device__ __forceinline__ void dft16(float2 (&v)[16]) {
 #pragma unroll
   for (int n1 = 1; n1 < 4; ++n1)
 #pragma unroll
-    for (int k = 1; k < 4; ++k) v[n1 + 4 * k] = cmul(v[n1 + 4 * k], w16(n1 * k, SIGN));
+    for (int k = 1; k < 4; ++k) {
+      // a quarter turn is a swap (a product with the constant 0 would be kept)
+      const int p = n1 * k;
+      v[n1 + 4 * k] = p == 4 ? cmul_si(v[n1 + 4 * k], SIGN) : cmul(v[n1 + 4 * k], w16(p, SIGN));
+    }
 #pragma unroll
   for (int k = 0; k < 4; ++k) dft4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3], SIGN);
 }

@@ -257,12 +257,12 @@ __global__ __launch_bounds__(256) void k_fc_rows(FcRowArgs a) {
     fetch(pair + S::F, nx);
     block_fft<N1, 1>(v, lds + f * S::LDS, t, w);
     float r2[16];
-    float r2max = 0.f;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      r2[q] = v[q].x * v[q].x + v[q].y * v[q].y;
-      r2max = fmaxf(r2max, r2[q]);
-    }
+    for (int q = 0; q < 16; ++q) r2[q] = v[q].x * v[q].x + v[q].y * v[q].y;
+    float r2max = r2[0];
+#pragma unroll
+    for (int q = 1; q < 15; q += 2) r2max = fmaxf(fmaxf(r2max, r2[q]), r2[q + 1]);
+    r2max = fmaxf(r2max, r2[15]);
     // only samples above the threshold can be a reported window peak
     if (!valid || !__any(r2max > a.thr2)) continue;
     const int64_t b = pair / a.N2, row = pair % a.N2;

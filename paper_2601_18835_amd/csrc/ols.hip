@@ -139,7 +139,11 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
     if (!has_out) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
     float r2[16];
-    float r2max = 0.f;
+    // maximum of the kept samples' rho^2 as bit patterns (non-negative floats
+    // order as their bits).  The discarded outputs stay out: where the block's
+    // correlation wraps, taps that cancel only against the series' own
+    // correlations lose that cancellation and would cross the threshold.
+    uint32_t r2max = 0u;
 #pragma unroll
     for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
@@ -148,11 +152,11 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
         const float x = y.x * y.x + y.y * y.y;
         r2[e * S::R + s] = x;
         const int64_t nn = n0 + block_fft_out<K>(t, e, s);
-        if (nn >= nbeg && nn < nend) r2max = fmaxf(r2max, x);
+        if (nn >= nbeg && nn < nend) r2max = max(r2max, __float_as_uint(x));
       }
     // the compaction reports a window only if its peak exceeds thr2: a wave
     // with no sample above it cannot contribute a reported peak
-    if (!__any(r2max > a.thr2)) continue;
+    if (!__any(r2max > __float_as_uint(a.thr2))) continue;
     if (q1 - q0 < kOlsMaxWin) {
       // one reduction and one atomic per window the block touches
       for (int64_t qw = q0; qw <= q1; ++qw) {

@@ -125,6 +125,42 @@ int rfd_plan_set_stream(rfd_plan* plan, void* stream);
 int rfd_plan_destroy(rfd_plan* plan);
 
 /*
+ * rfd_plan_workspace_size - bytes of the per-call scratch of the filtering
+ * calls (rfd_filter_bank, rfd_filter_range, findchirp_filter, the segment
+ * graph): the window-peak slots of the fused epilogue (8 B per template and
+ * cluster window, Table II's peak find), the compaction's per-block counts,
+ * and with with_findchirp != 0 FINDCHIRP's four-step intermediate (N * 8 B
+ * per template of a batch, up to 256 MiB; none when N <= 4096).  The size
+ * grows with N / W, not with the tap count: tap storage belongs to the taps
+ * object.
+ *   max_templates       largest template count of a call (0 .. 2^31-1).
+ *   min_cluster_window  smallest cluster window W of a call (1 .. N).
+ *   bytes               receives the size (a multiple of 256).
+ * Errors: RFD_E_INVALID for a NULL argument or a range violated above.
+ */
+int rfd_plan_workspace_size(const rfd_plan* plan, int64_t max_templates, int64_t min_cluster_window,
+                            int32_t with_findchirp, size_t* bytes);
+/*
+ * rfd_plan_set_workspace - the filtering calls take their scratch from
+ * caller-owned device memory [dev_ptr, dev_ptr + bytes) instead of growing
+ * library-owned buffers: from then on they allocate none of it, and a call
+ * needing more than the sizes given here (more templates, a smaller window,
+ * FINDCHIRP when with_findchirp was 0) fails with RFD_E_NOMEM and changes
+ * nothing.  The memory must stay valid, and unused by the caller, while the
+ * plan may run work on its stream; the library never frees it.  Waits for the
+ * plan's stream, releases library-owned scratch, and invalidates segment
+ * graphs captured before (their replays return RFD_E_STATE).
+ *   dev_ptr  device pointer, 256-byte aligned; NULL returns to library-owned
+ *            scratch (the other arguments are then ignored).
+ *   bytes    at least rfd_plan_workspace_size(max_templates,
+ *            min_cluster_window, with_findchirp).
+ * Errors: RFD_E_INVALID (misaligned pointer, bytes too small, ranges as in
+ * rfd_plan_workspace_size), RFD_E_DEVICE.
+ */
+int rfd_plan_set_workspace(rfd_plan* plan, void* dev_ptr, size_t bytes, int64_t max_templates,
+                           int64_t min_cluster_window, int32_t with_findchirp);
+
+/*
  * rfd_dechirp - reference matched filter (Eq. 1 with h = h_ref; the
  * dechirped series of Eq. 3 and Fig. 2).
  *   data     dev float64 [N]: the segment's time series.  When non-NULL its

@@ -84,6 +84,11 @@ static void drop_marks(Plan& p) {
 
 static void plan_free(Plan& p) {
   drop_marks(p);
+  if (p.ws_external) {      // caller-owned: not ours to free
+    p.slots = nullptr;
+    p.counts = nullptr;
+    p.fc_work = nullptr;
+  }
   dfree(p.w);
   dfree(p.tw32c); dfree(p.tw32f); dfree(p.tw64c); dfree(p.tw64f);
   dfree(p.tw32_n1); dfree(p.tw32_n2); dfree(p.tw64_n1); dfree(p.tw64_n2);
@@ -95,6 +100,12 @@ static void plan_free(Plan& p) {
 }
 
 static int ensure_slots(Plan& p, int64_t n_slots) {
+  if (p.ws_external) {
+    if ((size_t)n_slots > p.slots_cap || (size_t)compaction_blocks(n_slots) + 1 > p.counts_cap)
+      return fail(RFD_E_NOMEM, "workspace too small: the call needs " + std::to_string(n_slots) +
+                                   " window slots, the workspace holds " + std::to_string(p.slots_cap));
+    return RFD_OK;
+  }
   if ((size_t)n_slots > p.slots_cap) {
     RFD_HIP(hipStreamSynchronize(p.stream));
     ++p.res_gen;
@@ -175,6 +186,27 @@ static int check_bank_state(const Plan& p, const Taps& t) {
   return RFD_OK;
 }
 
+// Caller-owned workspace: slots, then counts, then the FINDCHIRP intermediate,
+// each region 256-byte aligned.
+struct WsLayout {
+  size_t slots = 0, counts = 0, fc = 0;   // entries (u64, long long, float2)
+  size_t off_counts = 0, off_fc = 0, bytes = 0;
+};
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+static int ws_layout(const Plan& p, int64_t max_templates, int64_t min_W, int32_t with_fc, WsLayout* l) {
+  if (max_templates < 0 || max_templates > ((int64_t)1 << 31) - 1)
+    return fail(RFD_E_INVALID, "max_templates must be in [0, 2^31 - 1]");
+  if (min_W < 1 || min_W > p.n) return fail(RFD_E_INVALID, "min_cluster_window must satisfy 1 <= W <= N");
+  const int64_t nwin = (p.n + min_W - 1) / min_W;
+  const int64_t n_slots = std::max<int64_t>(max_templates * nwin, 1);
+  l->slots = (size_t)n_slots;
+  l->counts = (size_t)compaction_blocks(n_slots) + 1;
+  l->fc = with_fc ? findchirp_work_size(p) : 0;
+  l->off_counts = align256(l->slots * sizeof(unsigned long long));
+  l->off_fc = l->off_counts + align256(l->counts * sizeof(long long));
+  l->bytes = l->off_fc + align256(l->fc * sizeof(float2));
+  return RFD_OK;
+}
 }  // namespace rfd
 
 using namespace rfd;
@@ -485,6 +517,56 @@ int rfd_plan_destroy(rfd_plan* plan) {
   (void)hipStreamSynchronize(plan->p.stream);
   plan_free(plan->p);
   delete plan;
+  return RFD_OK;
+}
+
+
+int rfd_plan_workspace_size(const rfd_plan* plan, int64_t max_templates, int64_t min_cluster_window,
+                            int32_t with_findchirp, size_t* bytes) {
+  if (!plan || !bytes) return fail(RFD_E_INVALID, "NULL argument");
+  WsLayout l;
+  int rc = ws_layout(plan->p, max_templates, min_cluster_window, with_findchirp, &l);
+  if (rc) return rc;
+  *bytes = l.bytes;
+  return RFD_OK;
+}
+
+int rfd_plan_set_workspace(rfd_plan* plan, void* dev_ptr, size_t bytes, int64_t max_templates,
+                           int64_t min_cluster_window, int32_t with_findchirp) {
+  if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
+  Plan& p = plan->p;
+  WsLayout l;
+  if (dev_ptr) {
+    int rc = ws_layout(p, max_templates, min_cluster_window, with_findchirp, &l);
+    if (rc) return rc;
+    if ((reinterpret_cast<uintptr_t>(dev_ptr) & 255u) != 0)
+      return fail(RFD_E_INVALID, "workspace must be 256-byte aligned");
+    if (bytes < l.bytes)
+      return fail(RFD_E_INVALID, "workspace too small: " + std::to_string(bytes) + " < " + std::to_string(l.bytes) +
+                                     " bytes");
+  }
+  RFD_HIP(hipStreamSynchronize(p.stream));
+  if (p.ws_external) {
+    p.slots = nullptr;
+    p.counts = nullptr;
+    p.fc_work = nullptr;
+  } else {
+    dfree(p.slots);
+    dfree(p.counts);
+    dfree(p.fc_work);
+  }
+  p.slots_cap = p.counts_cap = p.fc_work_cap = 0;
+  p.ws_external = false;
+  ++p.res_gen;
+  if (!dev_ptr) return RFD_OK;
+  char* base = static_cast<char*>(dev_ptr);
+  p.slots = reinterpret_cast<unsigned long long*>(base);
+  p.slots_cap = l.slots;
+  p.counts = reinterpret_cast<long long*>(base + l.off_counts);
+  p.counts_cap = l.counts;
+  p.fc_work = l.fc ? reinterpret_cast<float2*>(base + l.off_fc) : nullptr;
+  p.fc_work_cap = l.fc;
+  p.ws_external = true;
   return RFD_OK;
 }
 
@@ -859,9 +941,13 @@ int findchirp_filter(rfd_plan* plan, const double* data, const float* filt, int6
   const int64_t n_slots = n_templates * nwin;
   rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
   if (rc) return rc;
-  size_t need = (size_t)findchirp_batch_size(p) * p.n;
+  const size_t need = findchirp_work_size(p);
   if (p.fc_work_cap < need) {
+    if (p.ws_external)
+      return fail(RFD_E_NOMEM, "workspace too small: FINDCHIRP needs " + std::to_string(need * sizeof(float2)) +
+                                   " bytes of intermediate (set the workspace with with_findchirp = 1)");
     RFD_HIP(hipStreamSynchronize(p.stream));
+    ++p.res_gen;
     dfree(p.fc_work);
     p.fc_work_cap = 0;
     rc = dalloc(&p.fc_work, need);

@@ -316,11 +316,15 @@ int findchirp_batch_size(const Plan& p) {
   return (int)b;
 }
 
+size_t findchirp_work_size(const Plan& p) {
+  // the [N2][N1] intermediate of a batch; none when one pass covers N
+  return p.n > kFcN1 ? (size_t)findchirp_batch_size(p) * (size_t)p.n : 0;
+}
+
 int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin, float threshold) {
   const int64_t N1 = std::min<int64_t>(p.n, kFcN1);
   const int64_t N2 = p.n / N1;
-  if (N2 > 1 && p.fc_work_cap < (size_t)findchirp_batch_size(p) * p.n)
-    return fail(RFD_E_STATE, "findchirp: work buffer too small");
+  if (p.fc_work_cap < findchirp_work_size(p)) return fail(RFD_E_STATE, "findchirp: work buffer too small");
   const int bs = findchirp_batch_size(p);
   for (int64_t t0 = 0; t0 < n_templates; t0 += bs) {
     const int nb = (int)std::min<int64_t>(n_templates - t0, bs);

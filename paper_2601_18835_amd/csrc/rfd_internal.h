@@ -62,6 +62,8 @@ struct Plan {
 
   // FINDCHIRP batch intermediates (grown on demand)
   float2* fc_work = nullptr; size_t fc_work_cap = 0;
+  // slots, counts and fc_work point into caller-owned workspace (never grown or freed)
+  bool ws_external = false;
 
   // FIR tile configuration of the 16-bit forms: MFMA column blocks per wave (8 or 16)
   int fir_nb16 = 8;
@@ -211,6 +213,7 @@ int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, 
                         rfd_trigger* out, int64_t capacity);
 int compaction_blocks(int64_t n_slots);
 int findchirp_batch_size(const Plan& p);
+size_t findchirp_work_size(const Plan& p);
 int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity);
 int launch_findchirp_z(Plan& p, const float2* filt, rfd_trigger* out, int64_t capacity);
 

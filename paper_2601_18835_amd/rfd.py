@@ -61,6 +61,8 @@ _SIGS = {
     "rfd_plan_info_get": [_P, C.POINTER(rfd_plan_info)],
     "rfd_plan_set_stream": [_P, _P],
     "rfd_plan_destroy": [_P],
+    "rfd_plan_workspace_size": [_P, _i64, _i64, _i32, C.POINTER(C.c_size_t)],
+    "rfd_plan_set_workspace": [_P, _P, C.c_size_t, _i64, _i64, _i32],
     "rfd_plan_set_timing": [_P, _i32],
     "rfd_plan_set_fir_config": [_P, C.POINTER(rfd_fir_config)],
     "rfd_plan_get_fir_config": [_P, C.POINTER(rfd_fir_config)],
@@ -224,6 +226,24 @@ def rfd_segment_graph_launch(graph, want_count=True, raise_overflow=True):
 
 def rfd_graph_destroy(graph):
     _check(_lib.rfd_graph_destroy(graph), "rfd_graph_destroy")
+
+
+def rfd_plan_workspace_size(plan, max_templates, min_cluster_window=1, with_findchirp=False):
+    b = C.c_size_t()
+    _check(_lib.rfd_plan_workspace_size(plan, max_templates, min_cluster_window, 1 if with_findchirp else 0,
+                                        C.byref(b)), "rfd_plan_workspace_size")
+    return b.value
+
+
+def rfd_plan_set_workspace(plan, workspace, max_templates=0, min_cluster_window=1, with_findchirp=False):
+    """workspace: a device tensor the plan carves its per-call scratch from
+    (kept alive by the caller), or None for library-owned scratch."""
+    if workspace is None:
+        _check(_lib.rfd_plan_set_workspace(plan, None, 0, 0, 1, 0), "rfd_plan_set_workspace")
+        return
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(_lib.rfd_plan_set_workspace(plan, _ptr(workspace), nbytes, max_templates, min_cluster_window,
+                                       1 if with_findchirp else 0), "rfd_plan_set_workspace")
 
 
 def rfd_plan_destroy(plan):

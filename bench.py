@@ -147,8 +147,7 @@ def main():
     flops_alg = 8.0 * w.n * sum(sb.size * sb.taps for sb in bank.subbanks)   # 8T flop per template*sample
 
     def eager_step(precision):
-        for r in range(nsb):
-            rfd.rfd_dechirp(s.plan, data if r == 0 else None, s.h_ref[r], r, False)
+        rfd.rfd_dechirp_refs(s.plan, data, s.h_ref, False)     # transform + every reference, batched
         return rfd.rfd_filter_bank(s.plan, s.taps, precision, w.threshold, w.window, cap, out)[1]
 
     def timed(fn, steps, warmup):
@@ -262,8 +261,7 @@ def main():
     inc = int(w.fs)
 
     def increment():
-        for r in range(nsb):
-            rfd.rfd_dechirp(s.plan, data if r == 0 else None, s.h_ref[r], r, False)
+        rfd.rfd_dechirp_refs(s.plan, data, s.h_ref, False)
         return rfd.rfd_filter_range(s.plan, s.taps, prec, w.threshold, w.window, w.n - inc, inc, cap, out)[1]
 
     d5, n5, t5 = timed(increment, 20, 3)

@@ -178,6 +178,22 @@ int rfd_plan_set_workspace(rfd_plan* plan, void* dev_ptr, size_t bytes, int64_t 
  */
 int rfd_dechirp(rfd_plan* plan, const double* data, const double* h_ref, int32_t ref_id,
                 double* sigma_ref_out);
+/*
+ * rfd_dechirp_refs - rfd_dechirp for several references of one segment:
+ * the segment transform once (when data is non-NULL), then every
+ * reference's series through batched launches (up to 32 references, or
+ * 256 MiB of FP64 intermediates, per launch), each result identical to
+ * rfd_dechirp's for that reference.
+ *   n_refs     1 .. max_refs.
+ *   ref_ids    host int32 [n_refs]: distinct slots 0 <= id < max_refs.
+ *   h_refs     host array [n_refs] of dev complex128 [N/2+1] references.
+ *   sigma_out  host double [n_refs] or NULL: sigma_ref of each (synchronises).
+ * Errors: RFD_E_INVALID (NULL arrays or entries, ids out of range or
+ * repeated, a reference with sigma_ref = 0), RFD_E_STATE, RFD_E_NOMEM,
+ * RFD_E_DEVICE.
+ */
+int rfd_dechirp_refs(rfd_plan* plan, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                     const double* const* h_refs, double* sigma_out);
 
 /* Copy slot ref_id's normalised series z_ref/sigma_ref (dev complex64 [N]). */
 int rfd_get_zref(const rfd_plan* plan, int32_t ref_id, float* out);

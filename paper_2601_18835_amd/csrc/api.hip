@@ -93,6 +93,7 @@ static void plan_free(Plan& p) {
   dfree(p.tw32c); dfree(p.tw32f); dfree(p.tw64c); dfree(p.tw64f);
   dfree(p.tw32_n1); dfree(p.tw32_n2); dfree(p.tw64_n1); dfree(p.tw64_n2);
   dfree(p.stilde64); dfree(p.stilde); dfree(p.work64); dfree(p.fref64); dfree(p.dscratch);
+  dfree(p.work64b); dfree(p.dref_sig2); dfree(p.dref_scale);
   dfree(p.zref); dfree(p.zbf_hi); dfree(p.zbf_lo); dfree(p.zh_hi); dfree(p.zh_lo);
   dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work); dfree(p.counter);
   dfree(p.ols_tw32); dfree(p.ols_tw64);
@@ -125,6 +126,20 @@ static int ensure_slots(Plan& p, int64_t n_slots) {
     if (rc) return rc;
     p.counts_cap = nblk;
   }
+  return RFD_OK;
+}
+
+// batched dechirp intermediates (one N-point FP64 buffer when a batch is one reference)
+static int ensure_dechirp_work(Plan& p) {
+  const int bs = dechirp_batch_size(p);
+  if (bs <= 1 || p.work64b_cap >= (size_t)bs * p.n) return RFD_OK;
+  RFD_HIP(hipStreamSynchronize(p.stream));
+  ++p.res_gen;
+  dfree(p.work64b);
+  p.work64b_cap = 0;
+  int rc = dalloc(&p.work64b, (size_t)bs * p.n);
+  if (rc) return rc;
+  p.work64b_cap = (size_t)bs * p.n;
   return RFD_OK;
 }
 
@@ -279,6 +294,8 @@ int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, i
   TRY(dalloc(&p.work64, n));
   TRY(dalloc(&p.fref64, nb));
   TRY(dalloc(&p.dscratch, 64));
+  TRY(dalloc(&p.dref_sig2, (size_t)max_refs));
+  TRY(dalloc(&p.dref_scale, (size_t)kDechirpBatch));
   TRY(dalloc(&p.counter, 1));
   {
     int dev = 0, ncu = 0;
@@ -571,12 +588,26 @@ int rfd_plan_set_workspace(rfd_plan* plan, void* dev_ptr, size_t bytes, int64_t 
 }
 
 int rfd_dechirp(rfd_plan* plan, const double* data, const double* h_ref, int32_t ref_id, double* sigma_ref_out) {
+  return rfd_dechirp_refs(plan, data, 1, &ref_id, &h_ref, sigma_ref_out);
+}
+
+int rfd_dechirp_refs(rfd_plan* plan, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                     const double* const* h_refs, double* sigma_out) {
   if (!plan) return fail(RFD_E_INVALID, "plan is NULL");
   Plan& p = plan->p;
-  if (!h_ref) return fail(RFD_E_INVALID, "h_ref is NULL");
-  if (ref_id < 0 || ref_id >= p.max_refs) return fail(RFD_E_INVALID, "ref_id out of range");
+  if (!ref_ids || !h_refs) return fail(RFD_E_INVALID, "NULL argument");
+  if (n_refs < 1 || n_refs > p.max_refs) return fail(RFD_E_INVALID, "n_refs must be in [1, max_refs]");
+  std::vector<char> seen(p.max_refs, 0);
+  for (int i = 0; i < n_refs; ++i) {
+    if (ref_ids[i] < 0 || ref_ids[i] >= p.max_refs) return fail(RFD_E_INVALID, "ref_id out of range");
+    if (seen[ref_ids[i]]) return fail(RFD_E_INVALID, "ref_ids must be distinct");
+    if (!h_refs[i]) return fail(RFD_E_INVALID, "h_ref is NULL");
+    seen[ref_ids[i]] = 1;
+  }
+  int rc = ensure_dechirp_work(p);
+  if (rc) return rc;
   if (data) {
-    int rc = stage_begin(p, kStDataFft);
+    rc = stage_begin(p, kStDataFft);
     if (!rc) rc = launch_data_fft(p, data);
     if (!rc) rc = stage_end(p);
     if (rc) return rc;
@@ -584,18 +615,20 @@ int rfd_dechirp(rfd_plan* plan, const double* data, const double* h_ref, int32_t
   } else if (p.seg_gen == 0) {
     return fail(RFD_E_STATE, "no segment: pass data on the first dechirp");
   }
-  double* s2 = p.dscratch;
-  int rc = stage_begin(p, kStDechirp);
-  if (!rc) rc = launch_dechirp(p, h_ref, ref_id, s2);
+  rc = stage_begin(p, kStDechirp);
+  if (!rc) rc = launch_dechirp_refs(p, n_refs, ref_ids, h_refs);
   if (!rc) rc = stage_end(p);
   if (rc) return rc;
-  p.ref_gen[ref_id] = p.seg_gen;
-  if (sigma_ref_out) {
-    double v = 0;
-    RFD_HIP(hipMemcpyAsync(&v, s2, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+  for (int i = 0; i < n_refs; ++i) p.ref_gen[ref_ids[i]] = p.seg_gen;
+  if (sigma_out) {
+    std::vector<double> s2(p.max_refs);
+    RFD_HIP(hipMemcpyAsync(s2.data(), p.dref_sig2, p.max_refs * sizeof(double), hipMemcpyDeviceToHost, p.stream));
     RFD_HIP(hipStreamSynchronize(p.stream));
-    if (!(v > 0.0)) return fail(RFD_E_INVALID, "reference template has zero norm in band");
-    *sigma_ref_out = sqrt(v);
+    for (int i = 0; i < n_refs; ++i) {
+      const double v = s2[ref_ids[i]];
+      if (!(v > 0.0)) return fail(RFD_E_INVALID, "reference template has zero norm in band");
+      sigma_out[i] = sqrt(v);
+    }
   }
   return RFD_OK;
 }
@@ -1012,6 +1045,8 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
   const int64_t n_slots = t.n_templates * nwin;
   rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
   if (rc) return rc;
+  rc = ensure_dechirp_work(p);
+  if (rc) return rc;
   rc = prepare_fir(p, t, precision, cluster_window);
   if (rc) return rc;
   RFD_HIP(hipStreamSynchronize(p.stream));
@@ -1027,7 +1062,7 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
     rc = fail(RFD_E_DEVICE, "hipStreamBeginCapture failed");
   } else {
     rc = launch_data_fft(p, data);
-    for (int i = 0; !rc && i < n_refs; ++i) rc = launch_dechirp(p, h_refs[i], ref_ids[i], p.dscratch);
+    if (!rc) rc = launch_dechirp_refs(p, n_refs, ref_ids, h_refs);
     if (!rc) rc = launch_slots_clear(p, n_slots);
     if (!rc) rc = enqueue_fir(p, t, precision, cluster_window, nwin, threshold);
     if (!rc) rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);

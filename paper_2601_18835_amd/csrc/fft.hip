@@ -37,6 +37,21 @@ struct LoadDechirp64 {     // s_i * F_ref,i over the band, FP64 (Eq. 1 integrand
     return cmul(s[i], f[i]);
   }
 };
+// References of one batched dechirp, carried by value in the kernel arguments
+// (so eager launches and captured graphs need no pointer table in memory).
+struct DechirpRefs {
+  const double2* h[kDechirpBatch];   // reference templates, complex128 [nb]
+  int32_t slot[kDechirpBatch];       // reference-series slots they fill
+};
+struct LoadDechirpRefs {   // s_i w_i conj(h_b,i) / (sigma_b alpha) over the band, FP64
+  const double2* s; const double* w; DechirpRefs r; const double* scale; int64_t i_low, i_high;
+  __device__ double2 operator()(int b, int64_t i) const {
+    if (i < i_low || i > i_high) return make_double2(0.0, 0.0);
+    const double2 h = r.h[b][i];
+    const double f = w[i] * scale[b];
+    return cmul(s[i], make_double2(f * h.x, -f * h.y));
+  }
+};
 struct LoadFindchirp {     // s_i * F_j,i with F_j stored over band bins
   const float2* s; const float2* f; int64_t i_low, i_high, n_band;
   __device__ float2 operator()(int b, int64_t i) const {
@@ -83,6 +98,13 @@ struct StoreRef64 {        // FP64 series -> FP32 series + 16-bit hi/lo planes o
     split_f16(v.y, ih, il);
     hh[n] = rh | (ih << 16);
     hl[n] = rl | (il << 16);
+  }
+};
+struct StoreRefSlots {     // StoreRef64 into the slot of batch entry b
+  float2* z; uint32_t* bh; uint32_t* bl; uint32_t* hh; uint32_t* hl; int64_t n; DechirpRefs r;
+  __device__ void operator()(int b, int64_t m, double2 v) const {
+    const int64_t o = (int64_t)r.slot[b] * n;
+    StoreRef64{z + o, bh + o, bl + o, hh + o, hl + o}(0, m, v);
   }
 };
 struct StoreBand {         // FP64 series -> FP32 band series
@@ -228,6 +250,30 @@ __global__ __launch_bounds__(1024) void k_sigma_sq(const double* __restrict__ w,
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// sigma^2 of each reference of a batch (one workgroup each, the fixed order
+// of k_sigma_sq), stored by slot, and the filter scale 1 / (sigma alpha).
+__global__ __launch_bounds__(1024) void k_sigma_sq_refs(const double* __restrict__ w, DechirpRefs r, int64_t nb,
+                                                       double* __restrict__ sig2_by_slot,
+                                                       double* __restrict__ scale, double inv_alpha) {
+  __shared__ double red[1024];
+  const double2* hb = r.h[blockIdx.x];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < nb; i += 1024) {
+    double2 v = hb[i];
+    acc += w[i] * (v.x * v.x + v.y * v.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sig2_by_slot[r.slot[blockIdx.x]] = red[0];
+    scale[blockIdx.x] = inv_alpha / sqrt(red[0]);
+  }
+}
+
 // F[i] = w_i conj(h_i) / (sigma * alpha), FP64 then rounded to FP32.
 __global__ void k_build_filter(const double* __restrict__ w, const double2* __restrict__ h, int64_t nb,
                                int64_t hstride, const double* __restrict__ sigma_sq, double inv_alpha,
@@ -272,19 +318,37 @@ int launch_data_fft(Plan& p, const double* data) {
   return run_pass_b<double2>(p, p.work64, st, p.tw64_n1, 1, -1);
 }
 
-int launch_dechirp(Plan& p, const double* h_ref, int ref_id, double* sigma_dev) {
-  hipLaunchKernelGGL(k_sigma_sq, dim3(1), dim3(1024), 0, p.stream, p.w, (const double2*)h_ref, p.nb, p.nb,
-                     sigma_dev);
-  RFD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_build_filter64, dim3(256), dim3(256), 0, p.stream, p.w, (const double2*)h_ref, p.nb,
-                     (const double*)sigma_dev, 1.0 / p.data_scale, p.fref64);
-  RFD_CHECK_LAUNCH();
-  LoadDechirp64 ld{p.stilde64, p.fref64, p.i_low, p.i_high};
-  int rc = run_pass_a<double2>(p, ld, p.work64, p.tw64c, p.tw64f, p.tw64_n2, 1, +1);
-  if (rc) return rc;
-  int64_t o = (int64_t)ref_id * p.n;
-  StoreRef64 st{p.zref + o, p.zbf_hi + o, p.zbf_lo + o, p.zh_hi + o, p.zh_lo + o};
-  return run_pass_b<double2>(p, p.work64, st, p.tw64_n1, 1, +1);
+int dechirp_batch_size(const Plan& p) {
+  // FP64 intermediates of a batch: at most 256 MiB and kDechirpBatch references
+  int64_t b = ((int64_t)256 << 20) / (p.n * (int64_t)sizeof(double2));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, kDechirpBatch));
+}
+
+// Every reference through the same launches, in batches: sigma^2 (by slot,
+// into p.dref_sig2), then pass A with the filter formed on the fly, then
+// pass B into each reference's slot of the series store.
+int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const double* const* h_refs) {
+  const int bs = dechirp_batch_size(p);
+  double2* work = bs > 1 ? p.work64b : p.work64;
+  if (bs > 1 && p.work64b_cap < (size_t)bs * p.n) return fail(RFD_E_STATE, "dechirp: batch buffer too small");
+  for (int r0 = 0; r0 < n_refs; r0 += bs) {
+    const int nr = std::min(bs, n_refs - r0);
+    DechirpRefs refs{};
+    for (int b = 0; b < nr; ++b) {
+      refs.h[b] = reinterpret_cast<const double2*>(h_refs[r0 + b]);
+      refs.slot[b] = ref_ids[r0 + b];
+    }
+    hipLaunchKernelGGL(k_sigma_sq_refs, dim3((unsigned)nr), dim3(1024), 0, p.stream, p.w, refs, p.nb, p.dref_sig2,
+                       p.dref_scale, 1.0 / p.data_scale);
+    RFD_CHECK_LAUNCH();
+    LoadDechirpRefs ld{p.stilde64, p.w, refs, p.dref_scale, p.i_low, p.i_high};
+    int rc = run_pass_a<double2>(p, ld, work, p.tw64c, p.tw64f, p.tw64_n2, nr, +1);
+    if (rc) return rc;
+    StoreRefSlots st{p.zref, p.zbf_hi, p.zbf_lo, p.zh_hi, p.zh_lo, p.n, refs};
+    rc = run_pass_b<double2>(p, work, st, p.tw64_n1, nr, +1);
+    if (rc) return rc;
+  }
+  return RFD_OK;
 }
 
 // Band series of one reference: the dechirp integrand restricted to bins

@@ -25,6 +25,7 @@ int fail(int code, const std::string& msg);
 
 constexpr int kFineBits = 10;                 // twiddle factorisation p = (c << 10) | f
 constexpr int kFine = 1 << kFineBits;
+constexpr int kDechirpBatch = 32;               // references per batched dechirp launch
 
 // ------------------------------------------------------------- plan state
 struct Plan {
@@ -46,6 +47,9 @@ struct Plan {
   double2* stilde64 = nullptr; // current segment transform (scaled, FP64), [nb]
   float2* stilde = nullptr;   // its FP32 copy (FINDCHIRP operand), [nb]
   double2* work64 = nullptr;  // one N-point FP64 intermediate
+  double2* work64b = nullptr; size_t work64b_cap = 0;   // batched dechirp intermediates (grown)
+  double* dref_sig2 = nullptr;    // sigma_ref^2 by reference slot [max_refs]
+  double* dref_scale = nullptr;   // 1 / (sigma alpha) of a dechirp batch [kDechirpBatch]
   double2* fref64 = nullptr;  // reference filter scratch [nb]
   double* dscratch = nullptr; // small FP64 scratch (sigma etc.)  [64]
   // reference series store, slot-major [max_refs][n]
@@ -165,7 +169,8 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ----------------------------------------------------- launchers (fft.hip)
 int launch_data_fft(Plan& p, const double* data);
-int launch_dechirp(Plan& p, const double* h_ref, int ref_id, double* sigma_dev);
+int dechirp_batch_size(const Plan& p);
+int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const double* const* h_refs);
 int launch_findchirp_prepare(Plan& p, const double* h, int64_t count, float2* filt, double* sigma);
 int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin, float threshold);
 int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, int n2);

@@ -1,6 +1,8 @@
 // Trigger accumulation (Table II's last stage): slot clearing, deterministic
 // compaction of the per-(template, window) peak keys by prefix sum, and the
 // FP32 re-evaluation of the complex SNR at each trigger.
+#include <algorithm>
+
 #include "dev_common.h"
 #include "rfd_internal.h"
 
@@ -117,35 +119,36 @@ __global__ __launch_bounds__(kSegThreads) void k_write(const unsigned long long*
   }
 }
 
-// z_j[n] = sum_k c_j[k] zhat[(n + k0 + k) mod N]: one wave per trigger.
+// z_j[n] = sum_k c_j[k] zhat[(n + k0 + k) mod N]: one wave per trigger,
+// grid-stride over the triggers (the count is known only on the device).
 __global__ __launch_bounds__(256) void k_fir_z(rfd_trigger* __restrict__ out, const long long* __restrict__ total,
                                              int64_t capacity, const float2* __restrict__ c32,
                                              const float2* __restrict__ zref, int64_t n,
                                              const int64_t* __restrict__ sb_first, const int32_t* __restrict__ meta,
                                              const int64_t* __restrict__ abase) {
-  int64_t lim = *total < capacity ? *total : capacity;
-  int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= lim) return;
+  const int64_t lim = *total < capacity ? *total : capacity;
   const int lane = threadIdx.x & 63;
-  rfd_trigger t = out[i];
-  int b = t.subbank;
-  int ref = meta[4 * b + 0], T = meta[4 * b + 1], Tp = meta[4 * b + 2], k0 = meta[4 * b + 3];
-  const float2* c = c32 + abase[b] + (int64_t)(t.tmpl - sb_first[b]) * Tp;
-  const float2* z = zref + (int64_t)ref * n;
-  float re = 0.f, im = 0.f;
-  for (int k = lane; k < T; k += 64) {
-    float2 v = cmul(c[k], z[(t.sample + k0 + k) & (n - 1)]);
-    re += v.x;
-    im += v.y;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    re += __shfl_xor(re, o);
-    im += __shfl_xor(im, o);
-  }
-  if (lane == 0) {
-    out[i].z_re = re;
-    out[i].z_im = im;
-    out[i].flags = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < lim; i += (int64_t)gridDim.x * 4) {
+    const rfd_trigger t = out[i];
+    const int b = t.subbank;
+    const int ref = meta[4 * b + 0], T = meta[4 * b + 1], Tp = meta[4 * b + 2], k0 = meta[4 * b + 3];
+    const float2* c = c32 + abase[b] + (int64_t)(t.tmpl - sb_first[b]) * Tp;
+    const float2* z = zref + (int64_t)ref * n;
+    float re = 0.f, im = 0.f;
+    for (int k = lane; k < T; k += 64) {
+      const float2 v = cmul(c[k], z[(t.sample + k0 + k) & (n - 1)]);
+      re += v.x;
+      im += v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      re += __shfl_xor(re, o);
+      im += __shfl_xor(im, o);
+    }
+    if (lane == 0) {
+      out[i].z_re = re;
+      out[i].z_im = im;
+      out[i].flags = 0u;
+    }
   }
 }
 
@@ -161,13 +164,31 @@ __global__ __launch_bounds__(256) void k_fc_z(rfd_trigger* __restrict__ out, con
   if (i >= lim) return;
   rfd_trigger t = out[i];
   const float2* f = filt + (int64_t)t.tmpl * n_band;
+  // eight independent partial sums per thread keep eight bins' loads in
+  // flight (one chain would wait out the memory latency bin by bin); they
+  // combine in a fixed order, so the result does not depend on timing
+  constexpr int U = 8;
+  float pre[U], pim[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) pre[u] = pim[u] = 0.f;
+  for (int64_t k0 = threadIdx.x; k0 < n_band; k0 += 256 * U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = k0 + 256 * u;
+      if (k < n_band) {
+        const int64_t bin = k + i_low;
+        const uint32_t p = (uint32_t)((bin * t.sample) & (n - 1));
+        const float2 v = cmul(cmul(s[bin], f[k]), twiddle_n(coarse, fine, p, +1));
+        pre[u] += v.x;
+        pim[u] += v.y;
+      }
+    }
+  }
   float re = 0.f, im = 0.f;
-  for (int64_t k = threadIdx.x; k < n_band; k += 256) {
-    int64_t bin = k + i_low;
-    uint32_t p = (uint32_t)((bin * t.sample) & (n - 1));
-    float2 v = cmul(cmul(s[bin], f[k]), twiddle_n(coarse, fine, p, +1));
-    re += v.x;
-    im += v.y;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    re += pre[u];
+    im += pim[u];
   }
   red[0][threadIdx.x] = re;
   red[1][threadIdx.x] = im;
@@ -226,7 +247,7 @@ int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, 
 
 int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity) {
   if (capacity <= 0) return RFD_OK;
-  int64_t blocks = (capacity + 3) / 4;
+  const int64_t blocks = std::min<int64_t>((capacity + 3) / 4, 1024);
   hipLaunchKernelGGL(k_fir_z, dim3((unsigned)blocks), dim3(256), 0, p.stream, out, (const long long*)p.total,
                      capacity, tp.c32, p.zref, p.n, tp.d_first, tp.d_meta, tp.d_abase);
   RFD_CHECK_LAUNCH();

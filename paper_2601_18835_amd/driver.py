@@ -59,14 +59,9 @@ class RatioFilterSearch:
         self.data = data if isinstance(data, self.torch.Tensor) else self.to_dev(np.asarray(data, np.float64))
 
     def dechirp_all(self, want_sigma=False):
-        """Transform the segment once, then dechirp every reference."""
-        sig = {}
-        first = True
-        for ref_id in sorted(self.h_ref):
-            sig[ref_id] = rfd.rfd_dechirp(self.plan, self.data if first else None, self.h_ref[ref_id], ref_id,
-                                          want_sigma)
-            first = False
-        return sig
+        """Transform the segment once, then dechirp every reference (batched)."""
+        sig = rfd.rfd_dechirp_refs(self.plan, self.data, self.h_ref, want_sigma)
+        return sig if want_sigma else {r: None for r in self.h_ref}
 
     def filter(self, precision, threshold, window, capacity, out=None, raise_overflow=True):
         return rfd.rfd_filter_bank(self.plan, self.taps, precision, threshold, window, capacity, out,

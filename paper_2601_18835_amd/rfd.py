@@ -90,6 +90,7 @@ _SIGS = {
     "rfd_surrogate_destroy": [_P],
     "rfd_plan_get_timing": [_P, C.POINTER(rfd_timing)],
     "rfd_dechirp": [_P, _P, _P, _i32, C.POINTER(_d)],
+    "rfd_dechirp_refs": [_P, _P, _i32, _P, _P, _P],
     "rfd_get_zref": [_P, _i32, _P],
     "rfd_taps_create": [_P, _i32, _P, _P, _P, _P, C.POINTER(_P)],
     "rfd_make_taps": [_P, _P, _i32, _P, _P, _i64, _i64, _i32, _d],
@@ -262,6 +263,24 @@ def rfd_dechirp(plan, data, h_ref, ref_id=0, want_sigma=True):
     _check(_lib.rfd_dechirp(plan, _ptr(data), _ptr(h_ref), ref_id, C.byref(sig) if want_sigma else None),
            "rfd_dechirp")
     return sig.value if want_sigma else None
+
+
+def rfd_dechirp_refs(plan, data, refs, want_sigma=True):
+    """data: float64 [N] tensor or None; refs: {ref_id: complex128 [N/2+1]
+    tensor}.  Returns {ref_id: sigma_ref} (or None)."""
+    import torch
+    info = rfd_plan_info_get(plan)
+    if data is not None:
+        _dev_check(data, torch.float64, info["n"], "data")
+    ids = sorted(refs)
+    for r in ids:
+        _dev_check(refs[r], torch.complex128, info["n_bins"], "h_ref")
+    id_arr = (C.c_int32 * len(ids))(*ids)
+    ptr_arr = (C.c_void_p * len(ids))(*[_ptr(refs[r]) for r in ids])
+    sig = np.zeros(len(ids), dtype=np.float64)
+    _check(_lib.rfd_dechirp_refs(plan, _ptr(data), len(ids), id_arr, ptr_arr,
+                                 sig.ctypes.data if want_sigma else None), "rfd_dechirp_refs")
+    return dict(zip(ids, sig.tolist())) if want_sigma else None
 
 
 def rfd_get_zref(plan, ref_id, out=None):

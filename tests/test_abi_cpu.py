@@ -85,6 +85,7 @@ def test_null_arguments_are_rejected():
     assert rfd._lib.rfd_plan_workspace_size(None, 16, 2048, 1, C.byref(b)) == rfd.RFD_E_INVALID
     assert b.value == 7
     assert rfd._lib.rfd_plan_set_workspace(None, None, 0, 0, 1, 0) == rfd.RFD_E_INVALID
+    assert rfd._lib.rfd_dechirp_refs(None, None, 1, None, None, None) == rfd.RFD_E_INVALID
 
 
 @pytest.mark.skipif(gpu_available(), reason="forces an allocation failure by having no device")

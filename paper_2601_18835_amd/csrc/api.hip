@@ -93,7 +93,7 @@ static void plan_free(Plan& p) {
   dfree(p.tw32c); dfree(p.tw32f); dfree(p.tw64c); dfree(p.tw64f);
   dfree(p.tw32_n1); dfree(p.tw32_n2); dfree(p.tw64_n1); dfree(p.tw64_n2);
   dfree(p.stilde64); dfree(p.stilde); dfree(p.work64); dfree(p.fref64); dfree(p.dscratch);
-  dfree(p.work64b); dfree(p.dref_sig2); dfree(p.dref_scale);
+  dfree(p.work64b); dfree(p.dref_sig2); dfree(p.dref_scale); dfree(p.dref_part);
   dfree(p.zref); dfree(p.zbf_hi); dfree(p.zbf_lo); dfree(p.zh_hi); dfree(p.zh_lo);
   dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work); dfree(p.counter);
   dfree(p.ols_tw32); dfree(p.ols_tw64);
@@ -296,6 +296,7 @@ int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, i
   TRY(dalloc(&p.dscratch, 64));
   TRY(dalloc(&p.dref_sig2, (size_t)max_refs));
   TRY(dalloc(&p.dref_scale, (size_t)kDechirpBatch));
+  TRY(dalloc(&p.dref_part, (size_t)kDechirpBatch * kSigParts));
   TRY(dalloc(&p.counter, 1));
   {
     int dev = 0, ncu = 0;

@@ -11,6 +11,8 @@
 // the second fuses the consumer: spectrum store, reference-series store with
 // its 16-bit hi/lo planes, or the selection of the T correlation lags used by
 // tap construction.  (FINDCHIRP's own transforms live with its kernels.)
+#include <algorithm>
+
 #include "dev_common.h"
 #include "rfd_internal.h"
 
@@ -250,28 +252,37 @@ __global__ __launch_bounds__(1024) void k_sigma_sq(const double* __restrict__ w,
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
-// sigma^2 of each reference of a batch (one workgroup each, the fixed order
-// of k_sigma_sq), stored by slot, and the filter scale 1 / (sigma alpha).
-__global__ __launch_bounds__(1024) void k_sigma_sq_refs(const double* __restrict__ w, DechirpRefs r, int64_t nb,
-                                                       double* __restrict__ sig2_by_slot,
-                                                       double* __restrict__ scale, double inv_alpha) {
-  __shared__ double red[1024];
-  const double2* hb = r.h[blockIdx.x];
+// sigma^2 of each reference of a batch in two steps of fixed order:
+// kSigParts workgroups per reference reduce contiguous bin ranges to
+// partial sums, then one thread per reference adds its partials in order and
+// stores sigma^2 by slot and the filter scale 1 / (sigma alpha).
+__global__ __launch_bounds__(256) void k_sigma_part(const double* __restrict__ w, DechirpRefs r, int64_t nb,
+                                                   double* __restrict__ part) {
+  __shared__ double red[256];
+  const double2* hb = r.h[blockIdx.y];
+  const int64_t chunk = (nb + kSigParts - 1) / kSigParts;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = std::min<int64_t>(i0 + chunk, nb);
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < nb; i += 1024) {
-    double2 v = hb[i];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double2 v = hb[i];
     acc += w[i] * (v.x * v.x + v.y * v.y);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    sig2_by_slot[r.slot[blockIdx.x]] = red[0];
-    scale[blockIdx.x] = inv_alpha / sqrt(red[0]);
-  }
+  if (threadIdx.x == 0) part[blockIdx.y * kSigParts + blockIdx.x] = red[0];
+}
+__global__ void k_sigma_final(DechirpRefs r, int nr, const double* __restrict__ part,
+                              double* __restrict__ sig2_by_slot, double* __restrict__ scale, double inv_alpha) {
+  const int b = threadIdx.x;
+  if (b >= nr) return;
+  double s2 = 0.0;
+  for (int k = 0; k < kSigParts; ++k) s2 += part[b * kSigParts + k];
+  sig2_by_slot[r.slot[b]] = s2;
+  scale[b] = inv_alpha / sqrt(s2);
 }
 
 // F[i] = w_i conj(h_i) / (sigma * alpha), FP64 then rounded to FP32.
@@ -325,7 +336,7 @@ int dechirp_batch_size(const Plan& p) {
 }
 
 // Every reference through the same launches, in batches: sigma^2 (by slot,
-// into p.dref_sig2), then pass A with the filter formed on the fly, then
+// into p.dref_sig2, from kSigParts partial sums each), then pass A with the filter formed on the fly, then
 // pass B into each reference's slot of the series store.
 int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const double* const* h_refs) {
   const int bs = dechirp_batch_size(p);
@@ -338,8 +349,11 @@ int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const doubl
       refs.h[b] = reinterpret_cast<const double2*>(h_refs[r0 + b]);
       refs.slot[b] = ref_ids[r0 + b];
     }
-    hipLaunchKernelGGL(k_sigma_sq_refs, dim3((unsigned)nr), dim3(1024), 0, p.stream, p.w, refs, p.nb, p.dref_sig2,
-                       p.dref_scale, 1.0 / p.data_scale);
+    hipLaunchKernelGGL(k_sigma_part, dim3(kSigParts, (unsigned)nr), dim3(256), 0, p.stream, p.w, refs, p.nb,
+                       p.dref_part);
+    RFD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sigma_final, dim3(1), dim3(kDechirpBatch), 0, p.stream, refs, nr,
+                       (const double*)p.dref_part, p.dref_sig2, p.dref_scale, 1.0 / p.data_scale);
     RFD_CHECK_LAUNCH();
     LoadDechirpRefs ld{p.stilde64, p.w, refs, p.dref_scale, p.i_low, p.i_high};
     int rc = run_pass_a<double2>(p, ld, work, p.tw64c, p.tw64f, p.tw64_n2, nr, +1);

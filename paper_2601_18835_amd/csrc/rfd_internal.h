@@ -26,6 +26,8 @@ int fail(int code, const std::string& msg);
 constexpr int kFineBits = 10;                 // twiddle factorisation p = (c << 10) | f
 constexpr int kFine = 1 << kFineBits;
 constexpr int kDechirpBatch = 32;               // references per batched dechirp launch
+constexpr int kSigParts = 64;                   // partial sums per reference norm
+constexpr int kZParts = 32;                     // partial sums per FINDCHIRP trigger z
 
 // ------------------------------------------------------------- plan state
 struct Plan {
@@ -50,6 +52,7 @@ struct Plan {
   double2* work64b = nullptr; size_t work64b_cap = 0;   // batched dechirp intermediates (grown)
   double* dref_sig2 = nullptr;    // sigma_ref^2 by reference slot [max_refs]
   double* dref_scale = nullptr;   // 1 / (sigma alpha) of a dechirp batch [kDechirpBatch]
+  double* dref_part = nullptr;    // partial sums of their norms [kDechirpBatch][kSigParts]
   double2* fref64 = nullptr;  // reference filter scratch [nb]
   double* dscratch = nullptr; // small FP64 scratch (sigma etc.)  [64]
   // reference series store, slot-major [max_refs][n]

@@ -152,7 +152,9 @@ __global__ __launch_bounds__(256) void k_fir_z(rfd_trigger* __restrict__ out, co
   }
 }
 
-// FINDCHIRP: z_j[n] = sum_band s_i F_j,i exp(+2 pi i i n / N): one block per trigger.
+// FINDCHIRP: z_j[n] = sum_band s_i F_j,i exp(+2 pi i i n / N) at each trigger.
+// One block per trigger (segments of at most 4096 samples: a few bins per
+// thread) ...
 __global__ __launch_bounds__(256) void k_fc_z(rfd_trigger* __restrict__ out, const long long* __restrict__ total,
                                             int64_t capacity, const float2* __restrict__ s,
                                             const float2* __restrict__ filt, int64_t i_low, int64_t n_band,
@@ -164,31 +166,13 @@ __global__ __launch_bounds__(256) void k_fc_z(rfd_trigger* __restrict__ out, con
   if (i >= lim) return;
   rfd_trigger t = out[i];
   const float2* f = filt + (int64_t)t.tmpl * n_band;
-  // eight independent partial sums per thread keep eight bins' loads in
-  // flight (one chain would wait out the memory latency bin by bin); they
-  // combine in a fixed order, so the result does not depend on timing
-  constexpr int U = 8;
-  float pre[U], pim[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) pre[u] = pim[u] = 0.f;
-  for (int64_t k0 = threadIdx.x; k0 < n_band; k0 += 256 * U) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = k0 + 256 * u;
-      if (k < n_band) {
-        const int64_t bin = k + i_low;
-        const uint32_t p = (uint32_t)((bin * t.sample) & (n - 1));
-        const float2 v = cmul(cmul(s[bin], f[k]), twiddle_n(coarse, fine, p, +1));
-        pre[u] += v.x;
-        pim[u] += v.y;
-      }
-    }
-  }
   float re = 0.f, im = 0.f;
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    re += pre[u];
-    im += pim[u];
+  for (int64_t k = threadIdx.x; k < n_band; k += 256) {
+    int64_t bin = k + i_low;
+    uint32_t p = (uint32_t)((bin * t.sample) & (n - 1));
+    float2 v = cmul(cmul(s[bin], f[k]), twiddle_n(coarse, fine, p, +1));
+    re += v.x;
+    im += v.y;
   }
   red[0][threadIdx.x] = re;
   red[1][threadIdx.x] = im;
@@ -205,6 +189,60 @@ __global__ __launch_bounds__(256) void k_fc_z(rfd_trigger* __restrict__ out, con
     out[i].z_im = red[1][0];
     out[i].flags = 0u;
   }
+}
+
+// ... or, for long segments, kZParts blocks per trigger over contiguous bin
+// ranges (grid-stride over the triggers), their partial sums then added in
+// a fixed order by one thread per trigger.
+__global__ __launch_bounds__(256) void k_fc_z_part(const rfd_trigger* __restrict__ out,
+                                                 const long long* __restrict__ total, int64_t capacity,
+                                                 const float2* __restrict__ s, const float2* __restrict__ filt,
+                                                 int64_t i_low, int64_t n_band, int64_t n,
+                                                 const float2* __restrict__ coarse, const float2* __restrict__ fine,
+                                                 float2* __restrict__ part) {
+  __shared__ float red[2][256];
+  const int64_t lim = *total < capacity ? *total : capacity;
+  const int64_t chunk = (n_band + kZParts - 1) / kZParts;
+  const int64_t k0 = (int64_t)blockIdx.x * chunk, k1 = std::min<int64_t>(k0 + chunk, n_band);
+  for (int64_t i = blockIdx.y; i < lim; i += gridDim.y) {
+    const rfd_trigger t = out[i];
+    const float2* f = filt + (int64_t)t.tmpl * n_band;
+    float re = 0.f, im = 0.f;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+      const int64_t bin = k + i_low;
+      const uint32_t p = (uint32_t)((bin * t.sample) & (n - 1));
+      const float2 v = cmul(cmul(s[bin], f[k]), twiddle_n(coarse, fine, p, +1));
+      re += v.x;
+      im += v.y;
+    }
+    red[0][threadIdx.x] = re;
+    red[1][threadIdx.x] = im;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        red[1][threadIdx.x] += red[1][threadIdx.x + o];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[i * kZParts + blockIdx.x] = make_float2(red[0][0], red[1][0]);
+    __syncthreads();
+  }
+}
+__global__ __launch_bounds__(256) void k_fc_z_final(rfd_trigger* __restrict__ out, const long long* __restrict__ total,
+                                                  int64_t capacity, const float2* __restrict__ part) {
+  const int64_t lim = *total < capacity ? *total : capacity;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= lim) return;
+  float re = 0.f, im = 0.f;
+  for (int k = 0; k < kZParts; ++k) {
+    const float2 v = part[i * kZParts + k];
+    re += v.x;
+    im += v.y;
+  }
+  out[i].z_re = re;
+  out[i].z_im = im;
+  out[i].flags = 0u;
 }
 
 // ------------------------------------------------------------ launchers
@@ -256,6 +294,18 @@ int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity) {
 
 int launch_findchirp_z(Plan& p, const float2* filt, rfd_trigger* out, int64_t capacity) {
   if (capacity <= 0) return RFD_OK;
+  if (p.fc_work && p.fc_work_cap >= (size_t)capacity * kZParts) {
+    // partial sums in FINDCHIRP's (now idle) intermediate buffer
+    const unsigned gy = (unsigned)std::min<int64_t>(capacity, 256);
+    hipLaunchKernelGGL(k_fc_z_part, dim3(kZParts, gy), dim3(256), 0, p.stream, (const rfd_trigger*)out,
+                       (const long long*)p.total, capacity, p.stilde, filt, p.i_low, p.n_band, p.n, p.tw32c, p.tw32f,
+                       p.fc_work);
+    RFD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_fc_z_final, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, p.stream, out,
+                       (const long long*)p.total, capacity, (const float2*)p.fc_work);
+    RFD_CHECK_LAUNCH();
+    return RFD_OK;
+  }
   hipLaunchKernelGGL(k_fc_z, dim3((unsigned)capacity), dim3(256), 0, p.stream, out, (const long long*)p.total,
                      capacity, p.stilde, filt, p.i_low, p.n_band, p.n, p.tw32c, p.tw32f);
   RFD_CHECK_LAUNCH();

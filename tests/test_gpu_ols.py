@@ -105,5 +105,10 @@ def test_autotuner_picks_a_block_size(rfd, ragged):
     buf, n = s.filter("ols32", 0.0, 1, case.n_templates * case.n)
     after = rfd.triggers_to_numpy(buf, n)
     assert np.array_equal(after["sample"], before["sample"])
-    np.testing.assert_allclose(after["rho"], before["rho"], rtol=0, atol=2e-5)
+    # the tuned block size may differ from the automatic one: both lie within
+    # their own bounds of the oracle, so within the sum of the two of each other
+    both = fir_tolerance(case, "ols32", 1e-5) + fir_tolerance(case, "ols32", 1e-5,
+                                                              ols_forced=res["best"]["ols_block"])
+    assert np.all(np.abs(after["rho"] - before["rho"]) <= both[after["tmpl"]])
     rfd.rfd_plan_set_fir_config(s.plan)
+

@@ -9,8 +9,9 @@
 // LDS, so every global access is a run of C contiguous elements.  The first
 // pass fuses the pointwise product of Eq. 1 (data x conj(template) x weight);
 // the second fuses the consumer: spectrum store, reference-series store with
-// its 16-bit hi/lo planes, or the selection of the T correlation lags used by
-// tap construction.  (FINDCHIRP's own transforms live with its kernels.)
+// its 16-bit hi/lo planes.  Tap construction evaluates only the T
+// correlation lags it keeps, by direct sums over pass A's rows.  FINDCHIRP's
+// own transforms live with its kernels.
 #include <algorithm>
 
 #include "dev_common.h"
@@ -112,13 +113,6 @@ struct StoreRefSlots {     // StoreRef64 into the slot of batch entry b
 struct StoreBand {         // FP64 series -> FP32 band series
   float2* z;
   __device__ void operator()(int, int64_t n, double2 v) const { z[n] = make_float2((float)v.x, (float)v.y); }
-};
-struct StoreLags {         // keep lags k0 .. k0+T-1 (mod N), scaled
-  double2* out; int64_t stride, n; int k0, T; double scale;
-  __device__ void operator()(int b, int64_t m, double2 v) const {
-    int64_t l = (m - (int64_t)k0) & (n - 1);
-    if (l < T) out[(int64_t)b * stride + l] = make_double2(v.x * scale, v.y * scale);
-  }
 };
 
 // ------------------------------------------------------------------ passes
@@ -230,6 +224,35 @@ static int run_pass_b(Plan& p, const V* Y, ST st, const V* tab1, int batch, int 
   }
   RFD_CHECK_LAUNCH();
   return RFD_OK;
+}
+
+// Only the T lags m = (k0 + l) mod N, l < T, of pass B's output, each as a
+// direct sum over its row, z[m] = sum_i1 Y[n2 N1 + i1] exp(+2 pi i i1 n1 / N1)
+// with n2 = m mod N2 and n1 = m div N2: tap construction keeps T of N
+// outputs, and T N1 terms cost far less than the whole pass.  One wave per
+// lag, FP64.
+__global__ __launch_bounds__(256) void k_lags_direct(const double2* __restrict__ Y, int64_t n, int n1, int n2,
+                                                   const double2* __restrict__ tab1, int k0, int T, double scale,
+                                                   double2* __restrict__ out, int64_t stride) {
+  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (l >= T) return;                      // uniform per wave
+  const int64_t m = ((int64_t)k0 + l) & (n - 1);
+  const int64_t r = m % n2, c = m / n2;
+  const double2* row = Y + (int64_t)blockIdx.y * n + r * n1;
+  double re = 0.0, im = 0.0;
+  for (int i1 = lane; i1 < n1; i1 += 64) {
+    const double2 y = row[i1];
+    const double2 w = tab1[(int)((i1 * c) & (n1 - 1))];
+    re += y.x * w.x - y.y * w.y;
+    im += y.x * w.y + y.y * w.x;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o);
+    im += __shfl_xor(im, o);
+  }
+  if (lane == 0) out[(int64_t)blockIdx.y * stride + l] = make_double2(re * scale, im * scale);
 }
 
 // ------------------------------------------------------- small kernels
@@ -434,8 +457,11 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
                 mode};
   int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1);
   if (rc) return rc;
-  StoreLags st{out, out_stride, p.n, k0, T, mode == 2 ? 1.0 / (double)p.n : 1.0};
-  return run_pass_b<double2>(p, tp.work64, st, p.tw64_n1, (int)batch, +1);
+  hipLaunchKernelGGL(k_lags_direct, dim3((unsigned)((T + 3) / 4), (unsigned)batch), dim3(256), 0, p.stream,
+                     (const double2*)tp.work64, p.n, p.n1, p.n2, (const double2*)p.tw64_n1, k0, T,
+                     mode == 2 ? 1.0 / (double)p.n : 1.0, out, out_stride);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
 }
 
 }  // namespace rfd

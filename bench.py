@@ -364,7 +364,8 @@ def surrogate_main(args):
         torch.cuda.synchronize()
         captured = sur.fit(phys(train))
         t0 = time.perf_counter()
-        losses = sur.train(epochs=args.epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10)
+        losses = sur.train(epochs=args.epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10,
+                           progress=lambda st, ep, l: log(f"sub-bank {b}: {ep} epochs, loss {l:.4f}"))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         train_s += dt

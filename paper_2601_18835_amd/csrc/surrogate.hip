@@ -38,51 +38,89 @@ __device__ __forceinline__ float ld_op(const uint16_t* p, int64_t i) { return __
 
 // C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation.
 // op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
-template <typename TA, typename TB>
+// 64 x 64 output tile per workgroup, 4 x 4 per thread, K in steps of 32:
+// the next step's tiles are loaded into registers while the current one is
+// multiplied from LDS (the MLP's GEMMs are small, so load latency, not
+// arithmetic, bounds them).
+// Element r of this thread in a 32 x TM (k x m) tile: consecutive threads
+// run along whichever index is contiguous in memory (m for a k-major
+// operand, k for an m-major one), so every load is a coalesced run.
+template <int TM>
+__device__ __forceinline__ void tile_pos(int r, bool k_major, int& kk, int& mm) {
+  const int e = threadIdx.x + r * 256;
+  if (k_major) {
+    kk = e / TM;
+    mm = e % TM;
+  } else {
+    mm = e >> 5;
+    kk = e & 31;
+  }
+}
+
+// C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation.
+// op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
+// TM x TM output tile per workgroup (TM = 64: 4 x 4 per thread; TM = 32:
+// 2 x 2, four times the workgroups for the MLP's small GEMMs), K in steps of
+// 32 with the next step's tiles loaded into registers while the current one
+// is multiplied from LDS.
+template <int TM, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __restrict__ A, int lda, int ta,
                                             const TB* __restrict__ B, int ldb, int tb, float* __restrict__ C,
                                             int ldc, int accumulate) {
-  __shared__ float As[16][68];
-  __shared__ float Bs[16][68];
+  constexpr int R = TM * 32 / 256;        // tile elements per thread and operand
+  constexpr int P = TM / 16;              // outputs per thread along each dimension
+  __shared__ float As[32][TM + 4];
+  __shared__ float Bs[32][TM + 4];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+  float acc[P][P] = {};
+  float ra[R], rb[R];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + r * 256;                 // 1024 elements of each 16 x 64 tile
-      const int kk = e >> 6, mm = e & 63;
-      const int gm = m0 + mm, gk = k0 + kk;
-      float av = 0.f;
-      if (gm < M && gk < K) av = ta ? ld_op(A, (int64_t)gk * lda + gm) : ld_op(A, (int64_t)gm * lda + gk);
-      As[kk][mm] = av;
+    for (int r = 0; r < R; ++r) {
+      int kk, mm;
+      tile_pos<TM>(r, ta != 0, kk, mm);
+      int gm = m0 + mm, gk = k0 + kk;
+      ra[r] = (gm < M && gk < K) ? (ta ? ld_op(A, (int64_t)gk * lda + gm) : ld_op(A, (int64_t)gm * lda + gk)) : 0.f;
+      tile_pos<TM>(r, tb == 0, kk, mm);
       const int gn = n0 + mm;
-      float bv = 0.f;
-      if (gn < N && gk < K) bv = tb ? ld_op(B, (int64_t)gn * ldb + gk) : ld_op(B, (int64_t)gk * ldb + gn);
-      Bs[kk][mm] = bv;
+      gk = k0 + kk;
+      rb[r] = (gn < N && gk < K) ? (tb ? ld_op(B, (int64_t)gn * ldb + gk) : ld_op(B, (int64_t)gk * ldb + gn)) : 0.f;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += 32) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int kk, mm;
+      tile_pos<TM>(r, ta != 0, kk, mm);
+      As[kk][mm] = ra[r];
+      tile_pos<TM>(r, tb == 0, kk, mm);
+      Bs[kk][mm] = rb[r];
     }
     __syncthreads();
+    if (k0 + 32 < K) fetch(k0 + 32);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
+    for (int kk = 0; kk < 32; ++kk) {
+      float a[P], b[P];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+      for (int i = 0; i < P; ++i) a[i] = As[kk][ty * P + i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+      for (int j = 0; j < P; ++j) b[j] = Bs[kk][tx * P + j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < P; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int j = 0; j < P; ++j) acc[i][j] += a[i] * b[j];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = m0 + ty * 4 + i;
+  for (int i = 0; i < P; ++i) {
+    const int gm = m0 + ty * P + i;
     if (gm >= M) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + tx * 4 + j;
+    for (int j = 0; j < P; ++j) {
+      const int gn = n0 + tx * P + j;
       if (gn >= N) continue;
       float v = acc[i][j];
       if (accumulate) v += C[(int64_t)gm * ldc + gn];
@@ -95,8 +133,16 @@ template <typename TA, typename TB>
 static int gemm(hipStream_t st, int M, int N, int K, const TA* A, int lda, int ta, const TB* B, int ldb, int tb,
                 float* C, int ldc, int accumulate = 0) {
   if (M <= 0 || N <= 0) return RFD_OK;
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
-  hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, accumulate);
+  // 32-wide tiles when 64-wide ones would leave most of the 256 CUs idle
+  if ((int64_t)((N + 63) / 64) * ((M + 63) / 64) < 512) {
+    dim3 grid((N + 31) / 32, (M + 31) / 32);
+    hipLaunchKernelGGL((k_gemm<32, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
+                       accumulate);
+  } else {
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    hipLaunchKernelGGL((k_gemm<64, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
+                       accumulate);
+  }
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
@@ -151,12 +197,24 @@ __global__ void k_sum_partials(const double* __restrict__ partial, int n, double
   *out = accumulate ? *out + s : s;
 }
 
-__global__ void k_colsum(const float* __restrict__ X, int64_t n, int H, float* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= H) return;
+// out[j] = sum_i X[i][j]: 64 columns per workgroup, 16 row groups (rows
+// g, g + 16, ...) added in LDS in a fixed order.
+__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ X, int64_t n, int H,
+                                               float* __restrict__ out) {
+  __shared__ float red[16][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int64_t i = 0; i < n; ++i) s += X[i * H + j];
-  out[j] = s;
+  if (j < H)
+    for (int64_t i = g; i < n; i += 16) s += X[i * H + j];
+  red[g][c] = s;
+  __syncthreads();
+  if (g == 0 && j < H) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q][c];
+    out[j] = t;
+  }
 }
 
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
@@ -522,21 +580,21 @@ static int backward(Surrogate& s, hipStream_t st, const float* P, const float* C
   RFD_CHECK_LAUNCH();
   // layer 3
   if ((rc = gemm<float, float>(st, K, H, n, s.dY, K, 1, s.H2, H, 0, s.g + s.oW3, H))) return rc;
-  hipLaunchKernelGGL(k_colsum, dim3((K + 255) / 256), dim3(256), 0, st, s.dY, (int64_t)n, K, s.g + s.ob3);
+  hipLaunchKernelGGL(k_colsum, dim3((K + 63) / 64), dim3(1024), 0, st, s.dY, (int64_t)n, K, s.g + s.ob3);
   RFD_CHECK_LAUNCH();
   if ((rc = gemm<float, uint16_t>(st, n, H, K, s.dY, K, 0, s.wbf + s.oW3, H, 0, s.dA, H))) return rc;
   hipLaunchKernelGGL(k_silu_bwd, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.dA, s.Z2, (int64_t)n * H);
   RFD_CHECK_LAUNCH();
   // layer 2
   if ((rc = gemm<float, float>(st, H, H, n, s.dA, H, 1, s.H1, H, 0, s.g + s.oW2, H))) return rc;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, s.dA, (int64_t)n, H, s.g + s.ob2);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, st, s.dA, (int64_t)n, H, s.g + s.ob2);
   RFD_CHECK_LAUNCH();
   if ((rc = gemm<float, uint16_t>(st, n, H, H, s.dA, H, 0, s.wbf + s.oW2, H, 0, s.dB, H))) return rc;
   hipLaunchKernelGGL(k_silu_bwd, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.dB, s.Z1, (int64_t)n * H);
   RFD_CHECK_LAUNCH();
   // layer 1
   if ((rc = gemm<float, float>(st, H, 4, n, s.dB, H, 1, P, 4, 0, s.g + s.oW1, 4))) return rc;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, s.dB, (int64_t)n, H, s.g + s.ob1);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, st, s.dB, (int64_t)n, H, s.g + s.ob1);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }

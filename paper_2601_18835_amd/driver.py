@@ -156,8 +156,9 @@ class TapSurrogate:
                                             self.seed)
         return rfd.rfd_surrogate_fit_basis(self.sur, basis_iters)
 
-    def train(self, epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10):
-        """Adam with a geometric learning-rate decay over `stages` calls."""
+    def train(self, epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10, progress=None):
+        """Adam with a geometric learning-rate decay over `stages` calls;
+        progress(stage, epochs_done, last_loss) after each."""
         losses = []
         per = max(1, epochs // stages)
         done = 0
@@ -168,6 +169,8 @@ class TapSurrogate:
             rate = lr * (lr_end / lr) ** (s / max(1, stages - 1))
             losses.append(rfd.rfd_surrogate_train(self.sur, self.params_dev, e, batch, rate))
             done += e
+            if progress is not None:
+                progress(s, done, float(losses[-1][-1]))
         return np.concatenate(losses)
 
     def make_taps(self, target_taps, subbank, params, first=0):

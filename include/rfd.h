@@ -416,6 +416,13 @@ int rfd_graph_destroy(rfd_graph* graph);
  *                          optimiser state (a learning-rate schedule is a
  *                          sequence of calls); loss_out: host float
  *                          [epochs] (mean loss per epoch) or NULL.
+ *                          Each step's batch index and Adam step count live
+ *                          on the device, so an epoch is one fixed launch
+ *                          sequence: by default it is captured once per call
+ *                          and replayed as a HIP graph every epoch.
+ * rfd_surrogate_set_graphs enable != 0 (default): graph replay of epochs;
+ *                          0: every step launched directly.  Results are
+ *                          identical either way.
  * rfd_surrogate_loss_grad  loss and gradients (dev float [n_params], order
  *                          W1, b1, W2, b2, W3, b3; W row-major [out][in])
  *                          for the first n (<= 1024) rows of params;
@@ -460,6 +467,7 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
 int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_out);
 int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs, int32_t batch, float lr,
                         float* loss_out);
+int rfd_surrogate_set_graphs(rfd_surrogate* sur, int32_t enable);
 int rfd_surrogate_loss_grad(rfd_surrogate* sur, const float* params, const float* targets, int32_t n, float* grads,
                             double* loss_out);
 int rfd_surrogate_get_state(rfd_surrogate* sur, float* weights, float* basis, float* targets, int64_t* sizes);

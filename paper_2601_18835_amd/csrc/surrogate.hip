@@ -188,9 +188,12 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// accumulate: the flag, or when acc_from is given, whether acc_from[0] > 0
+// (a training step after the epoch's first)
 __global__ void k_sum_partials(const double* __restrict__ partial, int n, double scale, double* __restrict__ out,
-                               int accumulate) {
+                               int accumulate, const int64_t* __restrict__ acc_from) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (acc_from) accumulate = acc_from[0] > 0;
   double s = 0.0;
   for (int i = 0; i < n; ++i) s += partial[i];
   s *= scale;
@@ -217,9 +220,27 @@ __global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ X, in
   }
 }
 
-__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
-                       float bc2) {
+// Training step state on the device, so every step of an epoch is the same
+// launch sequence (and can be replayed as one captured graph):
+// st[0] = batch index within the epoch, st[1] = Adam steps taken.
+__global__ void k_train_state_set(int64_t* __restrict__ st, int64_t bi, int64_t steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st[0] = bi;
+    st[1] = steps;
+  }
+}
+__global__ void k_train_state_advance(int64_t* __restrict__ st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st[0] += 1;
+    st[1] += 1;
+  }
+}
+// Adam step number st[1] + 1 (bias corrections 1 - beta^t)
+__global__ void k_adam_step(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            const int64_t* __restrict__ st) {
+  const float t = (float)(st[1] + 1);
+  const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
@@ -235,8 +256,10 @@ __global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ ou
     out[i] = (uint16_t)bf16_bits(w[i]);
 }
 
-__global__ void k_gather(const float* __restrict__ P, const float* __restrict__ C, const int32_t* __restrict__ idx,
-                         int nb, int K, float* __restrict__ Pb, float* __restrict__ Cb) {
+// rows perm[st[0] nb + r], r < nb, of the parameters and targets
+__global__ void k_gather(const float* __restrict__ P, const float* __restrict__ C, const int32_t* __restrict__ perm,
+                         const int64_t* __restrict__ st, int nb, int K, float* __restrict__ Pb, float* __restrict__ Cb) {
+  const int32_t* idx = perm + st[0] * nb;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb * (4 + K); e += gridDim.x * blockDim.x) {
     const int r = e / (4 + K), c = e % (4 + K);
     const int64_t src = idx[r];
@@ -507,6 +530,8 @@ struct Surrogate {
   double* loss = nullptr;
   uint64_t seed = 0;
   bool basis_ready = false;            // basis, targets and Weff exist
+  int64_t* tstate = nullptr;           // training step state (k_train_state_*)
+  bool graphs = true;                  // training replays one captured epoch per epoch
 };
 
 template <typename T>
@@ -528,7 +553,7 @@ static void sfree(T*& p) {
 static void sur_free(Surrogate& s) {
   sfree(s.X); sfree(s.Weff); sfree(s.Bt); sfree(s.C); sfree(s.Q2); sfree(s.w); sfree(s.g); sfree(s.m); sfree(s.v); sfree(s.wbf);
   sfree(s.Pb); sfree(s.Cb); sfree(s.Z1); sfree(s.H1); sfree(s.Z2); sfree(s.H2); sfree(s.Y); sfree(s.dY);
-  sfree(s.dA); sfree(s.dB); sfree(s.idx); sfree(s.partial); sfree(s.loss);
+  sfree(s.dA); sfree(s.dB); sfree(s.idx); sfree(s.partial); sfree(s.loss); sfree(s.tstate);
 }
 
 // dynamic LDS a launch may request on the current device
@@ -569,14 +594,15 @@ static int forward(Surrogate& s, hipStream_t st, const float* P, int n) {
 
 // loss (added to *s.loss when accumulate) and gradients into s.g for n rows (Pb, Cb)
 static int backward(Surrogate& s, hipStream_t st, const float* P, const float* Cb, int n, int accumulate_loss,
-                    double loss_scale) {
+                    double loss_scale, const int64_t* acc_from = nullptr) {
   int rc;
   const int H = s.H, K = s.K;
   const int64_t ny = (int64_t)n * K;
   const int nblk = std::min<int>(grid_for(ny), 256);
   hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, st, s.Y, Cb, s.dY, ny, 1.f / n, s.partial);
   RFD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, loss_scale, s.loss, accumulate_loss);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, loss_scale, s.loss, accumulate_loss,
+                     acc_from);
   RFD_CHECK_LAUNCH();
   // layer 3
   if ((rc = gemm<float, float>(st, K, H, n, s.dY, K, 1, s.H2, H, 0, s.g + s.oW3, H))) return rc;
@@ -679,6 +705,7 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
   TRY(salloc(&s.idx, (size_t)s.nb));
   TRY(salloc(&s.partial, 256));
   TRY(salloc(&s.loss, 1));
+  TRY(salloc(&s.tstate, 2));
 #undef TRY
   // He-uniform initial weights, zero biases (host, seeded)
   std::vector<float> w0(s.np, 0.f);
@@ -743,7 +770,8 @@ int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_
     float* dummy = nullptr;
     if ((rc = salloc(&dummy, (size_t)ny))) return rc;
     hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, st, s.C, zeros, dummy, ny, 1.f, s.partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, 1.0 / n, s.loss, 0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, 1.0 / n, s.loss, 0,
+                       (const int64_t*)nullptr);
     double v = 0;
     RFD_HIP(hipMemcpyAsync(&v, s.loss, sizeof(double), hipMemcpyDeviceToHost, st));
     RFD_HIP(hipStreamSynchronize(st));
@@ -767,26 +795,60 @@ int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs,
   int rc = salloc(&dperm, (size_t)s.n);
   if (rc) return rc;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int64_t nbatches = s.n / batch;              // whole batches only
+  const double loss_scale = 1.0 / (double)(batch * nbatches);
+  // one training step; its batch index and Adam step count live on the device
+  auto step = [&](hipStream_t q) -> int {
+    hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)batch * (4 + s.K))), dim3(256), 0, q, params, s.C,
+                       (const int32_t*)dperm, (const int64_t*)s.tstate, batch, s.K, s.Pb, s.Cb);
+    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "gather launch failed");
+    int r = forward(s, q, s.Pb, batch);
+    if (!r) r = backward(s, q, s.Pb, s.Cb, batch, 0, loss_scale, s.tstate);
+    if (r) return r;
+    hipLaunchKernelGGL(k_adam_step, dim3(grid_for(s.np)), dim3(256), 0, q, s.w, s.g, s.m, s.v, s.np, lr, b1, b2, eps,
+                       (const int64_t*)s.tstate);
+    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "adam launch failed");
+    if ((r = refresh_bf16(s, q))) return r;
+    hipLaunchKernelGGL(k_train_state_advance, dim3(1), dim3(1), 0, q, s.tstate);
+    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "step launch failed");
+    return RFD_OK;
+  };
+  // with graphs: capture one epoch's steps once, replay it every epoch
+  hipGraphExec_t exec = nullptr;
+  if (s.graphs && nbatches > 1) {
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+      rc = fail(RFD_E_DEVICE, "capture stream creation failed");
+    } else if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = fail(RFD_E_DEVICE, "hipStreamBeginCapture failed");
+    } else {
+      for (int64_t bi = 0; bi < nbatches && !rc; ++bi) rc = step(cs);
+      const hipError_t e = hipStreamEndCapture(cs, &g);
+      if (!rc && e != hipSuccess) rc = fail(RFD_E_DEVICE, "hipStreamEndCapture failed");
+      if (!rc && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(RFD_E_DEVICE, "hipGraphInstantiate failed");
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+  }
   for (int e = 0; e < epochs && !rc; ++e) {
     std::shuffle(perm.begin(), perm.end(), gen);
-    if (hipMemcpy(dperm, perm.data(), s.n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    // the previous epoch still reads the permutation until the stream drains
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(dperm, perm.data(), s.n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
       rc = fail(RFD_E_DEVICE, "permutation upload failed");
       break;
     }
-    const int64_t nbatches = s.n / batch;            // whole batches only
-    for (int64_t bi = 0; bi < nbatches && !rc; ++bi) {
-      hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)batch * (4 + s.K))), dim3(256), 0, st, params, s.C,
-                         dperm + bi * batch, batch, s.K, s.Pb, s.Cb);
-      if (hipGetLastError() != hipSuccess) { rc = fail(RFD_E_DEVICE, "gather launch failed"); break; }
-      if ((rc = forward(s, st, s.Pb, batch))) break;
-      if ((rc = backward(s, st, s.Pb, s.Cb, batch, bi > 0, 1.0 / (double)(batch * nbatches)))) break;
-      ++s.step;
-      const float bc1 = 1.f - powf(b1, (float)s.step), bc2 = 1.f - powf(b2, (float)s.step);
-      hipLaunchKernelGGL(k_adam, dim3(grid_for(s.np)), dim3(256), 0, st, s.w, s.g, s.m, s.v, s.np, lr, b1, b2, eps,
-                         bc1, bc2);
-      if (hipGetLastError() != hipSuccess) { rc = fail(RFD_E_DEVICE, "adam launch failed"); break; }
-      if ((rc = refresh_bf16(s, st))) break;
+    hipLaunchKernelGGL(k_train_state_set, dim3(1), dim3(1), 0, st, s.tstate, (int64_t)0, s.step);
+    if (hipGetLastError() != hipSuccess) { rc = fail(RFD_E_DEVICE, "state launch failed"); break; }
+    if (exec) {
+      if (hipGraphLaunch(exec, st) != hipSuccess) rc = fail(RFD_E_DEVICE, "hipGraphLaunch failed");
+    } else {
+      for (int64_t bi = 0; bi < nbatches && !rc; ++bi) rc = step(st);
     }
+    s.step += nbatches;
     if (!rc && loss_out) {
       double v = 0;
       if (hipMemcpyAsync(&v, s.loss, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -796,8 +858,15 @@ int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs,
     }
   }
   (void)hipStreamSynchronize(st);
+  if (exec) (void)hipGraphExecDestroy(exec);
   sfree(dperm);
   return rc;
+}
+
+int rfd_surrogate_set_graphs(rfd_surrogate* sur, int32_t enable) {
+  if (!sur) return fail(RFD_E_INVALID, "NULL surrogate");
+  sur->s.graphs = enable != 0;
+  return RFD_OK;
 }
 
 int rfd_surrogate_loss_grad(rfd_surrogate* sur, const float* params, const float* targets, int32_t n, float* grads,

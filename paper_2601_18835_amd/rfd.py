@@ -73,6 +73,7 @@ _SIGS = {
     "rfd_surrogate_create": [_P, _P, _i32, _i32, _i32, C.c_uint64, C.POINTER(_P)],
     "rfd_surrogate_fit_basis": [_P, _i32, C.POINTER(_d)],
     "rfd_surrogate_train": [_P, _P, _i32, _i32, _f, _P],
+    "rfd_surrogate_set_graphs": [_P, _i32],
     "rfd_surrogate_loss_grad": [_P, _P, _P, _i32, _P, C.POINTER(_d)],
     "rfd_surrogate_get_state": [_P, _P, _P, _P, _P],
     "rfd_surrogate_set_state": [_P, _P, _P],
@@ -431,6 +432,10 @@ def rfd_surrogate_set_state(sur, weights=None, basis=None):
     b = None if basis is None else np.ascontiguousarray(basis, dtype=np.float32)
     _check(_lib.rfd_surrogate_set_state(sur, None if w is None else w.ctypes.data,
                                         None if b is None else b.ctypes.data), "rfd_surrogate_set_state")
+
+
+def rfd_surrogate_set_graphs(sur, enable=True):
+    _check(_lib.rfd_surrogate_set_graphs(sur, 1 if enable else 0), "rfd_surrogate_set_graphs")
 
 
 def rfd_surrogate_loss_grad(sur, params, targets=None):

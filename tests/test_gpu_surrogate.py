@@ -211,6 +211,27 @@ def test_two_adam_steps_match_oracle(rfd, case):
         assert dev.max() <= tol
 
 
+def test_graph_replayed_epochs_equal_direct_launches(rfd, case):
+    """Training replays one captured epoch per epoch; with graphs off every
+    step is launched directly.  The same kernels read the same device-resident
+    step state, so four epochs of eight steps give identical per-epoch losses
+    (each replay checked) and identical weights."""
+    c = case
+    sur = c.sur.sur
+    out = {}
+    try:
+        for graphs in (False, True):
+            rfd.rfd_surrogate_set_state(sur, weights=c.w0, basis=c.B)
+            rfd.rfd_surrogate_set_graphs(sur, graphs)
+            losses = rfd.rfd_surrogate_train(sur, c.sur.params_dev, 4, N_TRAIN // 8, 1e-3)
+            out[graphs] = (losses, rfd.rfd_surrogate_state(sur)["weights"])
+    finally:
+        rfd.rfd_surrogate_set_graphs(sur, True)
+    assert np.all(np.isfinite(out[True][0])) and out[True][0][-1] < out[True][0][0]
+    assert np.array_equal(out[False][0], out[True][0])
+    assert np.array_equal(out[False][1], out[True][1])
+
+
 def test_inference_matches_oracle(rfd, case):
     import torch
     c = case

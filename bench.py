@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--workload", default="spin256s", choices=["spin256s", "tidal256s", "ecc512s", "surr512s"])
     ap.add_argument("--subbanks", default="4,20", help="surr512s: sub-banks given a surrogate")
     ap.add_argument("--train", type=int, default=16384, help="surr512s: exact tap sets per surrogate")
-    ap.add_argument("--epochs", type=int, default=2000, help="surr512s: training epochs per surrogate")
+    ap.add_argument("--epochs", type=int, default=6000, help="surr512s: training epochs per surrogate")
     ap.add_argument("--cpu-sample", type=int, default=30, help="templates in the CPU oracle sample")
     ap.add_argument("--fir-form", default="auto", choices=["auto", "fp32", "bf16x3", "fp16x3", "ols32"],
                     help="FIR form of the timed run; auto: the faster of the workload's MFMA form and the "

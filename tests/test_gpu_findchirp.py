@@ -65,7 +65,7 @@ def test_full_series_matches_oracle(rfd, n, count):
 
 
 # larger segments: one peak per window of 4096 samples, every window compared
-WINDOWED = [(1 << 19, 67), (1 << 20, 35), (1 << 21, 17)]
+WINDOWED = [(1 << 19, 67), (1 << 20, 35), (1 << 21, 17), (1 << 22, 9)]
 
 
 @pytest.mark.parametrize("n,count", WINDOWED)

@@ -67,7 +67,10 @@ def main():
     ap.add_argument("--workload", default="spin256s", choices=["spin256s", "tidal256s", "ecc512s", "surr512s"])
     ap.add_argument("--subbanks", default="4,20", help="surr512s: sub-banks given a surrogate")
     ap.add_argument("--train", type=int, default=16384, help="surr512s: exact tap sets per surrogate")
-    ap.add_argument("--epochs", type=int, default=6000, help="surr512s: training epochs per surrogate")
+    ap.add_argument("--epochs", type=int, default=12000, help="surr512s: training epochs per surrogate")
+    ap.add_argument("--batch", type=int, default=256, help="surr512s: training batch")
+    ap.add_argument("--lr", type=float, default=2e-3, help="surr512s: first learning rate")
+    ap.add_argument("--lr-end", type=float, default=2e-4, help="surr512s: last learning rate (geometric decay)")
     ap.add_argument("--cpu-sample", type=int, default=30, help="templates in the CPU oracle sample")
     ap.add_argument("--fir-form", default="auto", choices=["auto", "fp32", "bf16x3", "fp16x3", "ols32"],
                     help="FIR form of the timed run; auto: the faster of the workload's MFMA form and the "
@@ -364,7 +367,7 @@ def surrogate_main(args):
         torch.cuda.synchronize()
         captured = sur.fit(phys(train))
         t0 = time.perf_counter()
-        losses = sur.train(epochs=args.epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10,
+        losses = sur.train(epochs=args.epochs, batch=args.batch, lr=args.lr, lr_end=args.lr_end, stages=10,
                            progress=lambda st, ep, l: log(f"sub-bank {b}: {ep} epochs, loss {l:.4f}"))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0

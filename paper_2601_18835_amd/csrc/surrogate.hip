@@ -57,6 +57,25 @@ __device__ __forceinline__ void tile_pos(int r, bool k_major, int& kk, int& mm) 
   }
 }
 
+__device__ __forceinline__ float silu_f(float z) { return z / (1.f + __expf(-z)); }
+__device__ __forceinline__ float silu_g(float z) {
+  const float s = 1.f / (1.f + __expf(-z));
+  return s * (1.f + z * (1.f - s));
+}
+
+// What the GEMM does with each result x = op(A) op(B) [m][n]:
+//   kStore   C = x (or C += x when accumulate)
+//   kBiasAct z = x + bias[n]; C = z; H = silu(z)   (hidden layer, forward)
+//   kBias    C = x + bias[n]                      (output layer, forward)
+//   kSiluBwd C = x silu'(Z[m][n])                  (hidden layer, backward)
+enum GemmEpiMode { kStore = 0, kBiasAct, kBias, kSiluBwd };
+struct GemmEpi {
+  int mode = kStore;
+  const float* bias = nullptr;
+  float* H = nullptr;
+  const float* Z = nullptr;
+};
+
 // C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation.
 // op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
 // TM x TM output tile per workgroup (TM = 64: 4 x 4 per thread; TM = 32:
@@ -66,7 +85,7 @@ __device__ __forceinline__ void tile_pos(int r, bool k_major, int& kk, int& mm) 
 template <int TM, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __restrict__ A, int lda, int ta,
                                             const TB* __restrict__ B, int ldb, int tb, float* __restrict__ C,
-                                            int ldc, int accumulate) {
+                                            int ldc, int accumulate, GemmEpi epi) {
   constexpr int R = TM * 32 / 256;        // tile elements per thread and operand
   constexpr int P = TM / 16;              // outputs per thread along each dimension
   __shared__ float As[32][TM + 4];
@@ -122,52 +141,42 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
     for (int j = 0; j < P; ++j) {
       const int gn = n0 + tx * P + j;
       if (gn >= N) continue;
+      const int64_t o = (int64_t)gm * ldc + gn;
       float v = acc[i][j];
-      if (accumulate) v += C[(int64_t)gm * ldc + gn];
-      C[(int64_t)gm * ldc + gn] = v;
+      if (epi.mode == kBiasAct) {
+        v += epi.bias[gn];
+        epi.H[o] = silu_f(v);
+      } else if (epi.mode == kBias) {
+        v += epi.bias[gn];
+      } else if (epi.mode == kSiluBwd) {
+        v *= silu_g(epi.Z[o]);
+      } else if (accumulate) {
+        v += C[o];
+      }
+      C[o] = v;
     }
   }
 }
 
 template <typename TA, typename TB>
 static int gemm(hipStream_t st, int M, int N, int K, const TA* A, int lda, int ta, const TB* B, int ldb, int tb,
-                float* C, int ldc, int accumulate = 0) {
+                float* C, int ldc, int accumulate = 0, GemmEpi epi = GemmEpi()) {
   if (M <= 0 || N <= 0) return RFD_OK;
   // 32-wide tiles when 64-wide ones would leave most of the 256 CUs idle
   if ((int64_t)((N + 63) / 64) * ((M + 63) / 64) < 512) {
     dim3 grid((N + 31) / 32, (M + 31) / 32);
     hipLaunchKernelGGL((k_gemm<32, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
-                       accumulate);
+                       accumulate, epi);
   } else {
     dim3 grid((N + 63) / 64, (M + 63) / 64);
     hipLaunchKernelGGL((k_gemm<64, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
-                       accumulate);
+                       accumulate, epi);
   }
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 
 // ------------------------------------------------------- elementwise
-__device__ __forceinline__ float silu_f(float z) { return z / (1.f + __expf(-z)); }
-__device__ __forceinline__ float silu_g(float z) {
-  const float s = 1.f / (1.f + __expf(-z));
-  return s * (1.f + z * (1.f - s));
-}
-
-__global__ void k_bias_act(float* __restrict__ Z, float* __restrict__ Hout, const float* __restrict__ b, int64_t n,
-                           int H, int act) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * H; e += (int64_t)gridDim.x * blockDim.x) {
-    const float z = Z[e] + b[e % H];
-    Z[e] = z;
-    if (act) Hout[e] = silu_f(z);
-  }
-}
-
-__global__ void k_silu_bwd(float* __restrict__ dH, const float* __restrict__ Z, int64_t n) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    dH[e] *= silu_g(Z[e]);
-}
-
 // dY = 2 (Y - C) / nb, and the per-block sums of squares (deterministic order)
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const float* __restrict__ Cb,
                                             float* __restrict__ dY, int64_t n, float scale,
@@ -577,18 +586,13 @@ static int refresh_bf16(Surrogate& s, hipStream_t st) {
 static int forward(Surrogate& s, hipStream_t st, const float* P, int n) {
   int rc;
   const int H = s.H, K = s.K;
-  if ((rc = gemm<float, uint16_t>(st, n, H, 4, P, 4, 0, s.wbf + s.oW1, 4, 1, s.Z1, H))) return rc;
-  hipLaunchKernelGGL(k_bias_act, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.Z1, s.H1, s.w + s.ob1,
-                     (int64_t)n, H, 1);
-  RFD_CHECK_LAUNCH();
-  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.H1, H, 0, s.wbf + s.oW2, H, 1, s.Z2, H))) return rc;
-  hipLaunchKernelGGL(k_bias_act, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.Z2, s.H2, s.w + s.ob2,
-                     (int64_t)n, H, 1);
-  RFD_CHECK_LAUNCH();
-  if ((rc = gemm<float, uint16_t>(st, n, K, H, s.H2, H, 0, s.wbf + s.oW3, H, 1, s.Y, K))) return rc;
-  hipLaunchKernelGGL(k_bias_act, dim3(grid_for((int64_t)n * K)), dim3(256), 0, st, s.Y, (float*)nullptr, s.w + s.ob3,
-                     (int64_t)n, K, 0);
-  RFD_CHECK_LAUNCH();
+  // biases and activations in the GEMM epilogues
+  GemmEpi e1{kBiasAct, s.w + s.ob1, s.H1, nullptr};
+  if ((rc = gemm<float, uint16_t>(st, n, H, 4, P, 4, 0, s.wbf + s.oW1, 4, 1, s.Z1, H, 0, e1))) return rc;
+  GemmEpi e2{kBiasAct, s.w + s.ob2, s.H2, nullptr};
+  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.H1, H, 0, s.wbf + s.oW2, H, 1, s.Z2, H, 0, e2))) return rc;
+  GemmEpi e3{kBias, s.w + s.ob3, nullptr, nullptr};
+  if ((rc = gemm<float, uint16_t>(st, n, K, H, s.H2, H, 0, s.wbf + s.oW3, H, 1, s.Y, K, 0, e3))) return rc;
   return RFD_OK;
 }
 
@@ -608,16 +612,14 @@ static int backward(Surrogate& s, hipStream_t st, const float* P, const float* C
   if ((rc = gemm<float, float>(st, K, H, n, s.dY, K, 1, s.H2, H, 0, s.g + s.oW3, H))) return rc;
   hipLaunchKernelGGL(k_colsum, dim3((K + 63) / 64), dim3(1024), 0, st, s.dY, (int64_t)n, K, s.g + s.ob3);
   RFD_CHECK_LAUNCH();
-  if ((rc = gemm<float, uint16_t>(st, n, H, K, s.dY, K, 0, s.wbf + s.oW3, H, 0, s.dA, H))) return rc;
-  hipLaunchKernelGGL(k_silu_bwd, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.dA, s.Z2, (int64_t)n * H);
-  RFD_CHECK_LAUNCH();
+  GemmEpi ea{kSiluBwd, nullptr, nullptr, s.Z2};
+  if ((rc = gemm<float, uint16_t>(st, n, H, K, s.dY, K, 0, s.wbf + s.oW3, H, 0, s.dA, H, 0, ea))) return rc;
   // layer 2
   if ((rc = gemm<float, float>(st, H, H, n, s.dA, H, 1, s.H1, H, 0, s.g + s.oW2, H))) return rc;
   hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, st, s.dA, (int64_t)n, H, s.g + s.ob2);
   RFD_CHECK_LAUNCH();
-  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.dA, H, 0, s.wbf + s.oW2, H, 0, s.dB, H))) return rc;
-  hipLaunchKernelGGL(k_silu_bwd, dim3(grid_for((int64_t)n * H)), dim3(256), 0, st, s.dB, s.Z1, (int64_t)n * H);
-  RFD_CHECK_LAUNCH();
+  GemmEpi eb{kSiluBwd, nullptr, nullptr, s.Z1};
+  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.dA, H, 0, s.wbf + s.oW2, H, 0, s.dB, H, 0, eb))) return rc;
   // layer 1
   if ((rc = gemm<float, float>(st, H, 4, n, s.dB, H, 1, P, 4, 0, s.g + s.oW1, 4))) return rc;
   hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, st, s.dB, (int64_t)n, H, s.g + s.ob1);

@@ -290,6 +290,12 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x (read 1073741824 B, write 1073741824 B) in elementwise_kernel")
         del src, dst
+    # this GPU's ceilings from the library's own microbenchmarks (context beside the published peaks)
+    peaks = {k: round(v, 2) for k, v in rfd.rfd_measure_peaks().items()}
+    log(f"measured ceilings: {peaks}")
+    # (the BF16 MFMA loop does not stand for an FP32-operand contraction)
+    roofline["measured_ceiling"] = None if prec == "fp32" else {
+        "alu": peaks["fp32_fma_TFLOPs"], "mfma": peaks["bf16_mfma_TFLOPs"], "hbm": peaks["copy_GBs"]}[roofline["bound"]]
     line = {
         "metric": "template*samples/s at SNR err <=1e-3 vs FP32 ratio-FIR and FINDCHIRP, 1 GPU",
         "value": value, "unit": "template*samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -309,6 +315,7 @@ def main():
         "tap_construction": {"templates_per_s": taps_per_s, "gpu_ms": tap_timing["taps_ms"]},
         "autotune": tune, "roofline": roofline, "compare": compare, "low_latency": low_latency, "parity": parity,
         "cpu_baseline": cpu,
+        "measured_peaks": peaks,
         # the paper's own speed-ups (context, other hardware) beside this GPU's measured ratios
         "paper_context": {
             "filtering_loop_speedup_vs_fft_matched_filter": {

@@ -567,6 +567,20 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
                      int64_t n_start, int64_t n_len, rfd_trigger* out, int64_t capacity, int64_t* n_out);
 
 /* Thread-local description of the last error on this thread ("" if none). */
+/*
+ * rfd_measure_peaks - this GPU's ceilings measured by the library's own
+ * microbenchmarks (a diagnostic beside the datasheet peaks that rooflines
+ * are priced against; not part of the method):
+ *   out[0] FP32 FMA issue, TFLOP/s (dependent chains, packed FP32 off as in
+ *          every kernel here);  out[1] FP64 FMA, TFLOP/s;
+ *   out[2] BF16 MFMA 16x16x32 with FP32 accumulation, TFLOP/s;
+ *   out[3] device-to-device copy of 1 GiB, GB/s of read + write.
+ *   stream  hipStream_t (NULL: the null stream); out host double [4].
+ * Allocates 2 GiB + a small buffer for the duration of the call and
+ * synchronises.  Errors: RFD_E_INVALID (NULL out), RFD_E_NOMEM, RFD_E_DEVICE.
+ */
+int rfd_measure_peaks(void* stream, double* out);
+
 const char* rfd_last_error(void);
 
 #ifdef __cplusplus

@@ -62,6 +62,7 @@ _SIGS = {
     "rfd_plan_set_stream": [_P, _P],
     "rfd_plan_destroy": [_P],
     "rfd_plan_workspace_size": [_P, _i64, _i64, _i32, C.POINTER(C.c_size_t)],
+    "rfd_measure_peaks": [_P, _P],
     "rfd_plan_set_workspace": [_P, _P, C.c_size_t, _i64, _i64, _i32],
     "rfd_plan_set_timing": [_P, _i32],
     "rfd_plan_set_fir_config": [_P, C.POINTER(rfd_fir_config)],
@@ -246,6 +247,14 @@ def rfd_plan_set_workspace(plan, workspace, max_templates=0, min_cluster_window=
     nbytes = workspace.numel() * workspace.element_size()
     _check(_lib.rfd_plan_set_workspace(plan, _ptr(workspace), nbytes, max_templates, min_cluster_window,
                                        1 if with_findchirp else 0), "rfd_plan_set_workspace")
+
+
+def rfd_measure_peaks(stream=None):
+    """This GPU's measured ceilings: FP32 / FP64 FMA and BF16 MFMA TFLOP/s, copy GB/s."""
+    out = np.zeros(4, dtype=np.float64)
+    _check(_lib.rfd_measure_peaks(_stream(stream), out.ctypes.data), "rfd_measure_peaks")
+    return {"fp32_fma_TFLOPs": float(out[0]), "fp64_fma_TFLOPs": float(out[1]), "bf16_mfma_TFLOPs": float(out[2]),
+            "copy_GBs": float(out[3])}
 
 
 def rfd_plan_destroy(plan):

@@ -174,9 +174,9 @@ static bool use_persistent(const Plan& p, const Taps& t) {
 // FIR kernels of every sub-bank (one persistent launch or one per sub-bank).
 static int enqueue_fir(Plan& p, Taps& t, int precision, int64_t W, int64_t nwin, float threshold) {
   if (precision == RFD_OLS32) return launch_ols(p, t, W, nwin, threshold);
-  if (use_persistent(p, t)) return launch_fir_persistent(p, t, precision, W, nwin);
+  if (use_persistent(p, t)) return launch_fir_persistent(p, t, precision, W, nwin, threshold);
   for (size_t b = 0; b < t.sb.size(); ++b) {
-    int rc = launch_fir(p, t, (int)b, precision, W, nwin);
+    int rc = launch_fir(p, t, (int)b, precision, W, nwin, threshold);
     if (rc) return rc;
   }
   return RFD_OK;
@@ -919,7 +919,7 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
     rc = launch_ols(p, t, cluster_window, nwin, threshold, n_start, n_start + n_len);
   } else {
     for (size_t b = 0; !rc && b < t.sb.size(); ++b)
-      rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin, n_start, n_len);
+      rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin, threshold, n_start, n_len);
   }
   if (rc) return rc;
   rc = stage_end(p);

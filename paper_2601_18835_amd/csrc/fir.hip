@@ -19,11 +19,15 @@
 // Epilogue: rho^2 = Re^2 + Im^2 in registers; per (template, window) the key
 // (bits(rho^2) << 32) | (0xFFFFFFFF - offset in window) is reduced across the
 // wave and merged into the slot array with a 64-bit atomicMax, so the largest
-// rho^2 wins and exact ties go to the lowest sample.  No series reaches HBM.
+// rho^2 wins and exact ties go to the lowest sample.  A key whose rho^2 does
+// not exceed threshold^2 cannot be a reported peak and is not written (its
+// window's slot stays 0 unless a sample above the threshold arrives).  No
+// series reaches HBM.
 #include "dev_common.h"
 #include "rfd_internal.h"
 
 #include <algorithm>
+#include <cstring>
 
 namespace rfd {
 
@@ -45,6 +49,7 @@ struct FirArgs {
   int k0, Tp, KB;           // Tp = taps padded to 16, KB = Tp / 16
   int S;                    // 256-sample tiles swept by one workgroup
   int64_t m_off = 0;        // first output sample of the launch (range filtering)
+  uint32_t thr2_bits = 0;   // bits of threshold^2: keys at or below it never fire, so are not written
 };
 
 __device__ __forceinline__ unsigned long long peak_key(float r2, int64_t n, int64_t W, int64_t& q) {
@@ -112,12 +117,12 @@ __device__ __forceinline__ void fir_tile_epilogue(const f32x4 (&acc)[NB], const 
       ka = reduce16(ka);
       kb = reduce16(kb);
       if (n == 0) {
-        if (va) atomicMax(sa + q, ka);
-        if (vb) atomicMax(sb + q, kb);
+        if (va && (uint32_t)(ka >> 32) > a.thr2_bits) atomicMax(sa + q, ka);
+        if (vb && (uint32_t)(kb >> 32) > a.thr2_bits) atomicMax(sb + q, kb);
       }
     } else {
-      if (va) atomicMax(sa + q, ka);
-      if (vb) atomicMax(sb + q, kb);
+      if (va && (uint32_t)(ka >> 32) > a.thr2_bits) atomicMax(sa + q, ka);
+      if (vb && (uint32_t)(kb >> 32) > a.thr2_bits) atomicMax(sb + q, kb);
     }
   }
 }
@@ -129,8 +134,8 @@ __device__ __forceinline__ void fir_final_epilogue(const FirArgs& a, int64_t tb,
   unsigned long long ka = reduce16(ps.ka), kb = reduce16(ps.kb);
   if ((lane & 15) == 0) {
     unsigned long long* sa = a.slots + (a.tmpl0 + ta) * a.nwin + ps.q;
-    if (ta < a.count) atomicMax(sa, ka);
-    if (ta + 1 < a.count) atomicMax(sa + a.nwin, kb);
+    if (ta < a.count && (uint32_t)(ka >> 32) > a.thr2_bits) atomicMax(sa, ka);
+    if (ta + 1 < a.count && (uint32_t)(kb >> 32) > a.thr2_bits) atomicMax(sa + a.nwin, kb);
   }
 }
 
@@ -375,8 +380,15 @@ static int tiles_per_block(int64_t n, int64_t W, int cols, int smax_cfg) {
   return S < 1 ? 1 : S;
 }
 
-int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin, int64_t n_start,
-               int64_t n_len) {
+static uint32_t thr2_bits(float threshold) {
+  const float t2 = threshold * threshold;     // as the compaction compares
+  uint32_t b;
+  std::memcpy(&b, &t2, sizeof(b));
+  return b;
+}
+
+int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin, float threshold,
+               int64_t n_start, int64_t n_len) {
   const SubBankTaps& s = tp.sb[b];
   if (s.count == 0) return RFD_OK;
   FirArgs a;
@@ -392,6 +404,7 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
   a.tmpl0 = s.first;
   a.nwin = nwin;
   a.W = W;
+  a.thr2_bits = thr2_bits(threshold);
   a.k0 = s.k0;
   a.Tp = s.Tp;
   a.KB = s.Tp / 16;
@@ -496,7 +509,7 @@ int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W) {
   return RFD_OK;
 }
 
-int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin) {
+int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin, float threshold) {
   if (tp.it_total == 0) return RFD_OK;
   PersistArgs pa;
   FirArgs& a = pa.base;
@@ -510,6 +523,7 @@ int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int
   a.tmpl0 = 0;
   a.nwin = nwin;
   a.W = W;
+  a.thr2_bits = thr2_bits(threshold);
   a.k0 = a.Tp = a.KB = 0;
   a.S = 1;
   pa.it_off = tp.d_it_off;

@@ -195,12 +195,12 @@ int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
 // ----------------------------------------------------- launchers (fir.hip)
 // n_len < 0: the whole segment; else output samples [n_start, n_start + n_len),
 // both multiples of 256
-int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin, int64_t n_start = 0,
-               int64_t n_len = -1);
+int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t nwin, float threshold,
+               int64_t n_start = 0, int64_t n_len = -1);
 // all sub-banks in one persistent launch (builds the work-item tables if needed;
 // must not be called for the first time with a given key inside graph capture)
 int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W);
-int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin);
+int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin, float threshold);
 
 // ----------------------------------------------------- launchers (ols.hip)
 int ols_block_size(const Plan& p, int T);

@@ -407,69 +407,103 @@ __global__ __launch_bounds__(256) void k_unwhiten(const float* __restrict__ Xh, 
   for (int i = threadIdx.x; i < T; i += 256) ao[i] = x[i];
 }
 
-// Coefficients -> FP64 taps and their fitted norm, kExpandRows templates per
-// workgroup (the folded matrix is read once per group):
+// Coefficients -> FP64 taps and their fitted norm:
 //   a_j = sum_k y_jk W_k      (W = L^-H B: row k is the back-substituted
 //                              basis vector k),
 //   v_j = sum_k y_jk B_k      (= L^H a_j, B_k = b_k[:T] + i b_k[T:]),
 //   sigma_fit^2 = a^H M a = ||v||^2 - lam ||a||^2   (M + lam I = L L^H),
 // an O(K T) form of the Sec. VI.B norm for taps given in whitened form.
-constexpr int kExpandRows = 4;
+// A workgroup takes kExpandRows templates and 256 taps (one per thread), so
+// each tile of W and B is read from L2 once per kExpandRows templates; it
+// writes its share of ||a||^2 and ||v||^2 per template, which k_expand_sigma
+// adds in a fixed order (partials [template][tap block][2]).
+constexpr int kExpandRows = 16;
 __global__ __launch_bounds__(256) void k_expand(const float* __restrict__ Y, int n, int K,
                                               const double2* __restrict__ W, const float* __restrict__ Bt, int T,
-                                              double eps, const double2* __restrict__ g, double2* __restrict__ a,
-                                              int Tp, double* __restrict__ sigma) {
-  __shared__ double yk[kExpandRows][1024];
-  __shared__ double red[2 * kExpandRows][256];
+                                              double2* __restrict__ a, int Tp, double* __restrict__ part) {
+  extern __shared__ double2 yk_lds[];
+  double* yk = reinterpret_cast<double*>(yk_lds);    // [kExpandRows][Kp], zero beyond K and n
+  __shared__ double red[4][2 * kExpandRows];
+  const int Kp = (K + 3) & ~3;
   const int j0 = blockIdx.x * kExpandRows;
   const int rows = min(kExpandRows, n - j0);
-  for (int e = threadIdx.x; e < kExpandRows * K; e += 256) {
-    const int r = e / K, k = e % K;
-    yk[r][k] = r < rows ? (double)Y[(int64_t)(j0 + r) * K + k] : 0.0;
+  for (int e = threadIdx.x; e < kExpandRows * Kp; e += 256) {
+    const int r = e / Kp, k = e % Kp;
+    yk[e] = (r < rows && k < K) ? (double)Y[(int64_t)(j0 + r) * K + k] : 0.0;
   }
   __syncthreads();
-  double aa[kExpandRows], vv[kExpandRows];
+  const int t = blockIdx.y * 256 + threadIdx.x;
+  const int tc = min(t, T - 1);                       // lanes past T compute a copy and store nothing
+  double ar[kExpandRows], ai[kExpandRows], vr[kExpandRows], vi[kExpandRows];
 #pragma unroll
-  for (int r = 0; r < kExpandRows; ++r) aa[r] = vv[r] = 0.0;
-  for (int t = threadIdx.x; t < T; t += 256) {
-    double ar[kExpandRows], ai[kExpandRows], vr[kExpandRows], vi[kExpandRows];
+  for (int r = 0; r < kExpandRows; ++r) ar[r] = ai[r] = vr[r] = vi[r] = 0.0;
+  // Workgroups start the K sweep at staggered quads: those running together
+  // then ask for different rows of W and B at first, and each later row is
+  // already in L2 (or on its way) when the rest reach it, instead of every
+  // wave of the grid waiting on the same miss at every step.
+  const int nq = Kp / 4;
+  const int q0 = (int)((blockIdx.x / 8) % (unsigned)nq);
+  for (int qi = 0; qi < nq; ++qi) {
+    const int k0 = 4 * (qi + q0 < nq ? qi + q0 : qi + q0 - nq);
+    double wr[4], wi[4], br[4], bi[4];
 #pragma unroll
-    for (int r = 0; r < kExpandRows; ++r) ar[r] = ai[r] = vr[r] = vi[r] = 0.0;
-    for (int k = 0; k < K; ++k) {
-      const double2 w = W[(int64_t)k * T + t];
-      const double br = (double)Bt[(int64_t)k * 2 * T + t], bi = (double)Bt[(int64_t)k * 2 * T + T + t];
-#pragma unroll
-      for (int r = 0; r < kExpandRows; ++r) {
-        const double y = yk[r][k];
-        ar[r] = fma(y, w.x, ar[r]);
-        ai[r] = fma(y, w.y, ai[r]);
-        vr[r] = fma(y, br, vr[r]);
-        vi[r] = fma(y, bi, vi[r]);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int k = min(k0 + q, K - 1);                // y is zero for the clamped rows
+      const double2 w = W[(int64_t)k * T + tc];
+      wr[q] = w.x;
+      wi[q] = w.y;
+      br[q] = (double)Bt[(int64_t)k * 2 * T + tc];
+      bi[q] = (double)Bt[(int64_t)k * 2 * T + T + tc];
     }
 #pragma unroll
     for (int r = 0; r < kExpandRows; ++r) {
-      if (r < rows) a[(int64_t)(j0 + r) * Tp + t] = make_double2(ar[r], ai[r]);
-      aa[r] += ar[r] * ar[r] + ai[r] * ai[r];
-      vv[r] += vr[r] * vr[r] + vi[r] * vi[r];
+      const double2 y01 = *reinterpret_cast<const double2*>(yk + r * Kp + k0);
+      const double2 y23 = *reinterpret_cast<const double2*>(yk + r * Kp + k0 + 2);
+      const double y[4] = {y01.x, y01.y, y23.x, y23.y};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ar[r] = fma(y[q], wr[q], ar[r]);
+        ai[r] = fma(y[q], wi[q], ai[r]);
+        vr[r] = fma(y[q], br[q], vr[r]);
+        vi[r] = fma(y[q], bi[q], vi[r]);
+      }
     }
   }
+  const bool live = t < T;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int r = 0; r < kExpandRows; ++r) {
-    red[2 * r][threadIdx.x] = aa[r];
-    red[2 * r + 1][threadIdx.x] = vv[r];
+    if (live && r < rows) a[(int64_t)(j0 + r) * Tp + t] = make_double2(ar[r], ai[r]);
+    double aa = live ? ar[r] * ar[r] + ai[r] * ai[r] : 0.0;
+    double vv = live ? vr[r] * vr[r] + vi[r] * vi[r] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+      aa += __shfl_xor(aa, o);
+      vv += __shfl_xor(vv, o);
+    }
+    if (lane == 0) {
+      red[wv][2 * r] = aa;
+      red[wv][2 * r + 1] = vv;
+    }
   }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o)
-      for (int q = 0; q < 2 * kExpandRows; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
-    __syncthreads();
+  if (threadIdx.x < 2 * rows) {
+    const double v = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    const int r = threadIdx.x >> 1;
+    part[((int64_t)(j0 + r) * gridDim.y + blockIdx.y) * 2 + (threadIdx.x & 1)] = v;
   }
-  if (threadIdx.x < rows) {
-    const int r = threadIdx.x;
-    const double lam = eps * g[0].x;
-    sigma[j0 + r] = sqrt(fmax(red[2 * r + 1][0] - lam * red[2 * r][0], 0.0));
+}
+
+__global__ void k_expand_sigma(const double* __restrict__ part, int n, int nblk, double eps,
+                               const double2* __restrict__ g, double* __restrict__ sigma) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double aa = 0.0, vv = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    aa += part[((int64_t)j * nblk + b) * 2];
+    vv += part[((int64_t)j * nblk + b) * 2 + 1];
   }
+  const double lam = eps * g[0].x;
+  sigma[j] = sqrt(fmax(vv - lam * aa, 0.0));
 }
 
 // |a^H M b| / sqrt(a^H M a b^H M b), M[l,k] = g[l-k]; one workgroup per template.
@@ -516,6 +550,8 @@ __global__ __launch_bounds__(256) void k_match(const double2* __restrict__ A, co
 }
 
 // ------------------------------------------------------------- state
+constexpr int kSurMaxBatch = 1024;    // training batch and loss_grad rows
+constexpr int kSurChunk = 4096;       // inference templates per forward pass and expansion
 struct Surrogate {
   Plan* plan = nullptr;
   Taps* taps = nullptr;
@@ -531,11 +567,12 @@ struct Surrogate {
   float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   uint16_t* wbf = nullptr;             // BF16 copy used by every GEMM
   int64_t step = 0;
-  int nb = 0;                          // batch capacity
+  int nb = 0;                          // rows of the batch buffers (training batch, inference chunk)
   float *Pb = nullptr, *Cb = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr,
         *dY = nullptr, *dA = nullptr, *dB = nullptr;
   int32_t* idx = nullptr;
   double* partial = nullptr;
+  double* epart = nullptr;             // [nb x tap blocks x 2] expansion norm partials
   double* loss = nullptr;
   uint64_t seed = 0;
   bool basis_ready = false;            // basis, targets and Weff exist
@@ -562,7 +599,7 @@ static void sfree(T*& p) {
 static void sur_free(Surrogate& s) {
   sfree(s.X); sfree(s.Weff); sfree(s.Bt); sfree(s.C); sfree(s.Q2); sfree(s.w); sfree(s.g); sfree(s.m); sfree(s.v); sfree(s.wbf);
   sfree(s.Pb); sfree(s.Cb); sfree(s.Z1); sfree(s.H1); sfree(s.Z2); sfree(s.H2); sfree(s.Y); sfree(s.dY);
-  sfree(s.dA); sfree(s.dB); sfree(s.idx); sfree(s.partial); sfree(s.loss); sfree(s.tstate);
+  sfree(s.dA); sfree(s.dB); sfree(s.idx); sfree(s.partial); sfree(s.epart); sfree(s.loss); sfree(s.tstate);
 }
 
 // dynamic LDS a launch may request on the current device
@@ -660,6 +697,8 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
   if (!sb.U) return fail(RFD_E_STATE, "training taps must come from the least-squares route (Cholesky factor)");
   if (n_basis < 1 || n_basis > 2 * sb.T || n_basis > 1024) return fail(RFD_E_INVALID, "n_basis out of range");
   if (hidden < 1 || hidden > 4096) return fail(RFD_E_INVALID, "hidden out of range");
+  if (!lds_fits((size_t)kExpandRows * ((n_basis + 3) & ~3) * sizeof(double) + 8 * kExpandRows * sizeof(double)))
+    return fail(RFD_E_INVALID, "n_basis too large for the device's LDS");
   rfd_surrogate* h = new (std::nothrow) rfd_surrogate();
   if (!h) return fail(RFD_E_NOMEM, "host allocation failed");
   Surrogate& s = h->s;
@@ -673,7 +712,7 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
   s.H = hidden;
   s.n = sb.count;
   s.seed = seed;
-  s.nb = 1024;
+  s.nb = kSurChunk;
   const int H = s.H, K = s.K;
   s.oW1 = 0;
   s.ob1 = s.oW1 + (int64_t)H * 4;
@@ -706,6 +745,7 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
   TRY(salloc(&s.dB, (size_t)s.nb * H));
   TRY(salloc(&s.idx, (size_t)s.nb));
   TRY(salloc(&s.partial, 256));
+  TRY(salloc(&s.epart, (size_t)s.nb * ((s.T + 255) / 256) * 2));
   TRY(salloc(&s.loss, 1));
   TRY(salloc(&s.tstate, 2));
 #undef TRY
@@ -787,7 +827,7 @@ int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs,
                         float* loss_out) {
   if (!sur || !params) return fail(RFD_E_INVALID, "NULL argument");
   Surrogate& s = sur->s;
-  if (epochs < 1 || batch < 1 || batch > s.nb || !(lr > 0.f)) return fail(RFD_E_INVALID, "bad training arguments");
+  if (epochs < 1 || batch < 1 || batch > kSurMaxBatch || !(lr > 0.f)) return fail(RFD_E_INVALID, "bad training arguments");
   if (!s.basis_ready) return fail(RFD_E_STATE, "fit or set the basis before training");
   hipStream_t st = s.plan->stream;
   std::mt19937_64 gen(s.seed + 7);
@@ -875,7 +915,7 @@ int rfd_surrogate_loss_grad(rfd_surrogate* sur, const float* params, const float
                             double* loss_out) {
   if (!sur || !params || !grads) return fail(RFD_E_INVALID, "NULL argument");
   Surrogate& s = sur->s;
-  if (n < 1 || n > s.nb) return fail(RFD_E_INVALID, "n out of range");
+  if (n < 1 || n > kSurMaxBatch) return fail(RFD_E_INVALID, "n out of range");
   hipStream_t st = s.plan->stream;
   const float* Cb = targets ? targets : s.C;
   int rc = forward(s, st, params, n);
@@ -962,9 +1002,13 @@ int rfd_surrogate_make_taps(rfd_surrogate* sur, const float* params, rfd_taps* t
     if (!rc) rc = stage_end(p);
     if (!rc) rc = stage_begin(p, kStSurExpand);
     if (!rc) {
-      hipLaunchKernelGGL(k_expand, dim3((unsigned)((cn + kExpandRows - 1) / kExpandRows)), dim3(256), 0, st, s.Y,
-                         cn, s.K, (const double2*)s.Weff, s.Bt, s.T, src.eps, (const double2*)src.g,
-                         t.a64 + sb.a_base + (first + c0) * sb.Tp, sb.Tp, t.sigma_fit + sb.first + first + c0);
+      const int tb = (s.T + 255) / 256;
+      const size_t lds = (size_t)kExpandRows * ((s.K + 3) & ~3) * sizeof(double);
+      hipLaunchKernelGGL(k_expand, dim3((unsigned)((cn + kExpandRows - 1) / kExpandRows), (unsigned)tb), dim3(256),
+                         lds, st, s.Y, cn, s.K, (const double2*)s.Weff, s.Bt, s.T,
+                         t.a64 + sb.a_base + (first + c0) * sb.Tp, sb.Tp, s.epart);
+      hipLaunchKernelGGL(k_expand_sigma, dim3((unsigned)((cn + 255) / 256)), dim3(256), 0, st, s.epart, cn, tb,
+                         src.eps, (const double2*)src.g, t.sigma_fit + sb.first + first + c0);
       if (hipGetLastError() != hipSuccess) rc = fail(RFD_E_DEVICE, "expansion launch failed");
     }
     if (!rc) rc = stage_end(p);

@@ -13,6 +13,8 @@
 //     sigma_fit^2 = sum_i w_i |h_ref A|^2 = a^H M a.
 // The FIR applies c = conj(a) sigma_ref / sigma_fit to zhat = z_ref/sigma_ref,
 // so its output is directly the normalised SNR of h_fit.
+#include <algorithm>
+
 #include "dev_common.h"
 #include "rfd_internal.h"
 
@@ -157,50 +159,83 @@ __global__ __launch_bounds__(256) void k_sigma_fit(const double2* __restrict__ a
 // packings.  Row 2t holds (Re c, -Im c) per tap, row 2t+1 holds (Im c, Re c).
 //  16-bit: element e = 2 (k%4) + comp of lane (row + 16 ((k%16)/4)) in K block k/16,
 //          uint4 index ((tb*KB + kb)*2 + plane)*64 + lane.
-//  FP32:   K step kb2 = k/2, lane row + 16 (2 (k%2) + comp), float4 (tb*(Tp/8) + kb2/4)*64 + lane,
-//          component kb2 % 4.
-__global__ void k_pack(const double2* __restrict__ a, int64_t astride, const double* __restrict__ sigma_fit,
-                       const double2* __restrict__ g, int T, int Tp, int64_t t_first, int64_t count,
-                       float2* __restrict__ c32, uint16_t* __restrict__ pbf, uint16_t* __restrict__ pfh,
-                       float* __restrict__ p32) {
+//  FP32:   K step kb2 = k/2, lane row + 16 (2 (k%2) + comp), float4 (tb*(Tp/8) + kq)*64 + lane
+//          with kq = kb2/4, component kb2 % 4.
+// A workgroup takes a tile of 8 templates (tb) x 16 taps (kb): the 128
+// normalised taps are staged in LDS, then each wave writes one packing of the
+// tile as 64 consecutive 16-byte lanes: wave 0 the BF16 hi and lo planes,
+// wave 1 the FP16 planes, waves 2 and 3 the two FP32 K quads.  Lanes of
+// templates outside [t_first, t_first + count) store nothing.
+__device__ __forceinline__ double pack_val(double2 c, int o, int comp) {
+  return o == 0 ? (comp == 0 ? c.x : -c.y) : (comp == 0 ? c.y : c.x);
+}
+
+__global__ __launch_bounds__(256) void k_pack(const double2* __restrict__ a, int64_t astride,
+                                            const double* __restrict__ sigma_fit, const double2* __restrict__ g,
+                                            int T, int Tp, int64_t t_first, int64_t count, float2* __restrict__ c32,
+                                            uint4* __restrict__ pbf, uint4* __restrict__ pfh,
+                                            float4* __restrict__ p32) {
+  __shared__ double2 cs[8][16];
   const double sig_ref = sqrt(g[0].x);
   const int KB = Tp / 16;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count * Tp;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t tl = e / Tp;            // within this batch
-    int k = (int)(e % Tp);
-    int64_t t = t_first + tl;       // within the sub-bank
-    double2 c = make_double2(0.0, 0.0);
-    if (k < T) {
-      double2 av = a[tl * astride + k];
-      double s = sig_ref / sigma_fit[tl];
-      c = make_double2(av.x * s, -av.y * s);
-    }
-    c32[t * Tp + k] = make_float2((float)c.x, (float)c.y);
-    const int64_t tb = t / 8;
-    const int trow = (int)(t % 8);
-    const double vals[2][2] = {{c.x, -c.y}, {c.y, c.x}};
-    const int kb = k / 16, kk = k % 16, gq = kk / 4, jj = kk % 4;
-    const int kb2 = k / 2, kq = kb2 / 4, sub = kb2 % 4;
-#pragma unroll
-    for (int o = 0; o < 2; ++o) {
-      const int row = 2 * trow + o;
-#pragma unroll
-      for (int comp = 0; comp < 2; ++comp) {
-        const double v = vals[o][comp];
-        const int lane16 = row + 16 * gq;
-        const int64_t u4 = ((tb * KB + kb) * 2) * 64 + lane16;   // plane 0 (hi)
-        const int el = 2 * jj + comp;
-        uint32_t hi, lo;
-        split_bf16(v, hi, lo);
-        pbf[u4 * 8 + el] = (uint16_t)hi;
-        pbf[(u4 + 64) * 8 + el] = (uint16_t)lo;
-        split_f16(v, hi, lo);
-        pfh[u4 * 8 + el] = (uint16_t)hi;
-        pfh[(u4 + 64) * 8 + el] = (uint16_t)lo;
-        const int lane32 = row + 16 * (2 * (k % 2) + comp);
-        p32[((tb * (Tp / 8) + kq) * 64 + lane32) * 4 + sub] = (float)v;
+  const int64_t tb0 = t_first / 8, tb1 = (t_first + count - 1) / 8;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t tb = tb0 + blockIdx.y; tb <= tb1; tb += gridDim.y) {
+    for (int kb = blockIdx.x; kb < KB; kb += gridDim.x) {
+      if (threadIdx.x < 128) {
+        const int trow = threadIdx.x >> 4, kk = threadIdx.x & 15;
+        const int k = kb * 16 + kk;
+        const int64_t t = tb * 8 + trow;
+        const int64_t tl = t - t_first;
+        double2 c = make_double2(0.0, 0.0);
+        if (tl >= 0 && tl < count) {
+          if (k < T) {
+            const double2 av = a[tl * astride + k];
+            const double sc = sig_ref / sigma_fit[tl];
+            c = make_double2(av.x * sc, -av.y * sc);
+          }
+          c32[t * Tp + k] = make_float2((float)c.x, (float)c.y);
+        }
+        cs[trow][kk] = c;
       }
+      __syncthreads();
+      if (w < 2) {
+        // 16-bit planes: lane = row + 16 gq, taps 4 gq .. 4 gq + 3 of the tile
+        const int row = lane & 15, gq = lane >> 4, trow = row >> 1, o = row & 1;
+        const int64_t tl = tb * 8 + trow - t_first;
+        if (tl >= 0 && tl < count) {
+          uint32_t hw[4], lw[4];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const double2 c = cs[trow][gq * 4 + jj];
+            uint32_t h0, l0, h1, l1;
+            if (w == 0) {
+              split_bf16(pack_val(c, o, 0), h0, l0);
+              split_bf16(pack_val(c, o, 1), h1, l1);
+            } else {
+              split_f16(pack_val(c, o, 0), h0, l0);
+              split_f16(pack_val(c, o, 1), h1, l1);
+            }
+            hw[jj] = (h0 & 0xffffu) | (h1 << 16);
+            lw[jj] = (l0 & 0xffffu) | (l1 << 16);
+          }
+          uint4* dst = (w == 0 ? pbf : pfh) + ((tb * KB + kb) * 2) * 64 + lane;
+          dst[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+          dst[64] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        }
+      } else {
+        // FP32: lane = row + 16 (2 par + comp); component sub holds tap 8 q + 2 sub + par
+        const int q = w - 2;
+        const int row = lane & 15, par = lane >> 5, comp = (lane >> 4) & 1, trow = row >> 1, o = row & 1;
+        const int64_t tl = tb * 8 + trow - t_first;
+        if (tl >= 0 && tl < count) {
+          float v[4];
+#pragma unroll
+          for (int sub = 0; sub < 4; ++sub) v[sub] = (float)pack_val(cs[trow][8 * q + 2 * sub + par], o, comp);
+          p32[(tb * (Tp / 8) + 2 * kb + q) * 64 + lane] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+      }
+      __syncthreads();
     }
   }
 }
@@ -268,14 +303,15 @@ int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count) {
 int taps_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count) {
   SubBankTaps& s = tp.sb[b];
   s.ols_valid = false;   // the overlap-save tap spectra follow the packed taps
+  if (count <= 0) return RFD_OK;
   const int T = s.T;
   double2* abase = tp.a64 + s.a_base + first * s.Tp;
   double* sig = tp.sigma_fit + s.first + first;
-  int64_t el = count * s.Tp;
-  int blocks = (int)((el + 255) / 256 < 8192 ? (el + 255) / 256 : 8192);
-  hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, p.stream, abase, (int64_t)s.Tp, sig, s.g, T, s.Tp, first,
-                     count, tp.c32 + s.a_base, reinterpret_cast<uint16_t*>(tp.pbf + s.p16_base),
-                     reinterpret_cast<uint16_t*>(tp.pfh + s.p16_base), reinterpret_cast<float*>(tp.p32 + s.p32_base));
+  const int64_t ntb = (first + count - 1) / 8 - first / 8 + 1;
+  const int KB = s.Tp / 16;
+  dim3 grid((unsigned)std::min(KB, 8), (unsigned)std::min<int64_t>(ntb, 8192));
+  hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, p.stream, abase, (int64_t)s.Tp, sig, s.g, T, s.Tp, first, count,
+                     tp.c32 + s.a_base, tp.pbf + s.p16_base, tp.pfh + s.p16_base, tp.p32 + s.p32_base);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }

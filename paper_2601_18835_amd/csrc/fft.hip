@@ -122,11 +122,13 @@ __device__ void load_twl(V* twl, const V* __restrict__ tab, int stride = 1) {
 }
 
 // pass A: L = N2-point transforms of C columns; writes Y with the inter-pass
-// twiddle.  tabL[k * tab_stride] = exp(+2 pi i k / L).
+// twiddle.  tabL[k * tab_stride] = exp(+2 pi i k / L).  Only the rows n2 in
+// [row_lo, row_lo + row_cnt) mod L are written (all rows: 0, L): a consumer
+// that evaluates a few outputs of the second pass reads no others.
 template <typename V, int L, class LD>
 __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const V* __restrict__ coarse,
                                               const V* __restrict__ fine, const V* __restrict__ tabL,
-                                              int n1, int sign, int tab_stride) {
+                                              int n1, int sign, int tab_stride, int row_lo, int row_cnt) {
   constexpr int C = Cols<V>::value(L);
   constexpr int LP = lds_col<L>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -145,6 +147,7 @@ __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const 
   V* Yb = Y + (int64_t)b * n;
   for (int e = threadIdx.x; e < C * L; e += kNT) {
     int c = e % C, n2 = e / C;
+    if (((n2 - row_lo) & (L - 1)) >= row_cnt) continue;
     int i1 = c0 + c;
     V v = buf[c * LP + lpad(n2)];
     uint32_t p = (uint32_t)i1 * (uint32_t)n2;   // < N
@@ -187,7 +190,8 @@ __global__ __launch_bounds__(kNT) void k_pass_b(const V* __restrict__ Y, ST st, 
 
 // -------------------------------------------------------------- dispatch
 template <typename V, class LD>
-static int run_pass_a(Plan& p, LD ld, V* Y, const V* coarse, const V* fine, const V* tab2, int batch, int sign) {
+static int run_pass_a(Plan& p, LD ld, V* Y, const V* coarse, const V* fine, const V* tab2, int batch, int sign,
+                      int row_lo = 0, int row_cnt = 1 << 30) {
   dim3 blk(kNT);
   switch (p.n2) {
 #define CASE_A(LL)                                                                         \
@@ -195,7 +199,7 @@ static int run_pass_a(Plan& p, LD ld, V* Y, const V* coarse, const V* fine, cons
     constexpr int C = Cols<V>::value(LL);                                                  \
     size_t sh = lds_bytes<V, LL, C>();                                                     \
     hipLaunchKernelGGL((k_pass_a<V, LL, LD>), dim3(p.n1 / C, batch), blk, sh, p.stream, ld, Y, coarse, \
-                       fine, tab2, p.n1, sign, 1);                                         \
+                       fine, tab2, p.n1, sign, 1, row_lo & (LL - 1), std::min(row_cnt, LL));  \
     break;                                                                                 \
   }
     CASE_A(32) CASE_A(64) CASE_A(128) CASE_A(256) CASE_A(512) CASE_A(1024) CASE_A(2048)
@@ -438,7 +442,7 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
     constexpr int C = Cols<float2>::value(LL);                                                 \
     size_t sh = lds_bytes<float2, LL, C>();                                                    \
     hipLaunchKernelGGL((k_pass_a<float2, LL, LoadFindchirp>), dim3(n1 / C, nb), blk, sh, p.stream, \
-                       ld, Y, p.tw32c, p.tw32f, p.ols_tw32, n1, +1, 4096 / LL);                \
+                       ld, Y, p.tw32c, p.tw32f, p.ols_tw32, n1, +1, 4096 / LL, 0, LL);         \
     break;                                                                                     \
   }
     CASE_L(512) CASE_L(1024)
@@ -455,7 +459,9 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
   if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
   LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high,
                 mode};
-  int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1);
+  // k_lags_direct reads the pass-A rows (k0 + l) mod N2, l < T
+  const int row_lo = (int)(((int64_t)k0 % p.n2 + p.n2) % p.n2);
+  int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1, row_lo, T);
   if (rc) return rc;
   hipLaunchKernelGGL(k_lags_direct, dim3((unsigned)((T + 3) / 4), (unsigned)batch), dim3(256), 0, p.stream,
                      (const double2*)tp.work64, p.n, p.n1, p.n2, (const double2*)p.tw64_n1, k0, T,

@@ -74,34 +74,107 @@ __global__ void k_upper(const double2* __restrict__ L, int T, double2* __restric
   }
 }
 
-// (L L^H) a = b for one template per workgroup (column-oriented sweeps in LDS).
-__global__ __launch_bounds__(256) void k_trsv(const double2* __restrict__ L, const double2* __restrict__ U, int T,
-                                            const double2* __restrict__ b, int64_t bstride,
-                                            double2* __restrict__ a, int64_t astride) {
-  extern __shared__ double2 sh[];
-  double2* x = sh;
-  double2* y = sh + T;
-  const double2* bb = b + (int64_t)blockIdx.x * bstride;
-  for (int i = threadIdx.x; i < T; i += 256) x[i] = bb[i];
-  __syncthreads();
-  for (int j = 0; j < T; ++j) {
-    const double2* col = L + (int64_t)j * T;
-    const double inv = 1.0 / col[j].x;
-    const double2 yj = make_double2(x[j].x * inv, x[j].y * inv);
-    if (threadIdx.x == 0) y[j] = yj;
-    for (int i = j + 1 + threadIdx.x; i < T; i += 256) x[i] = csub(x[i], cmul(col[i], yj));
-    __syncthreads();
+// (L L^H) a = b for one template per workgroup (column-oriented sweeps in LDS):
+// a forward sweep with L, then a backward sweep with U = L^H.
+template <int E>
+struct TrsvCol {
+  double2 v[E];   // column entries at rows lane + 64 q (row T - 1 past the end), unmasked
+};
+
+// Entry (j, j) of a column held as TrsvCol: lane j % 64 holds it in slot
+// j / 64; read across lanes with readlane (no memory access).
+template <int E>
+__device__ __forceinline__ double trsv_diag(const TrsvCol<E>& c, int j) {
+  // a masked sum (one nonzero term, exact) rather than a selection, which the
+  // compiler would turn into an indexed access and move the ring to scratch
+  double d = 0.0;
+#pragma unroll
+  for (int q = 0; q < E; ++q) d += (q == (j >> 6)) ? c.v[q].x : 0.0;
+  const long long bits = __double_as_longlong(d);
+  const int lo = __builtin_amdgcn_readlane((int)bits, j & 63);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), j & 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int E>
+__device__ __forceinline__ void trsv_load(const double2* __restrict__ F, int T, int lane, TrsvCol<E>& c, int j) {
+  const double2* col = F + (int64_t)min(max(j, 0), T - 1) * T;
+#pragma unroll
+  for (int q = 0; q < E; ++q) c.v[q] = col[min(lane + 64 * q, T - 1)];
+}
+
+// One step of a column sweep: w_j = r_j / F[j][j] (stored to out[j]), then
+// r_i -= F[i][j] w_j for the rows i the step updates (forward: j < i < T,
+// backward: i < j); the other rows subtract an exact zero.
+template <int E, bool FWD>
+__device__ __forceinline__ void trsv_step(const TrsvCol<E>& c, int j, int T, int lane, double2* r, double2* out) {
+  const double inv = 1.0 / trsv_diag(c, j);
+  const double2 rj = r[j];
+  const double2 wj = make_double2(rj.x * inv, rj.y * inv);
+  out[j] = wj;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int i = lane + 64 * q;
+    const bool active = FWD ? (i > j && i < T) : (i < j);
+    const double2 v = active ? c.v[q] : make_double2(0.0, 0.0);
+    r[i] = csub(r[i], cmul(v, wj));
   }
-  for (int j = T - 1; j >= 0; --j) {
-    const double2* col = U + (int64_t)j * T;
-    const double inv = 1.0 / col[j].x;
-    const double2 aj = make_double2(y[j].x * inv, y[j].y * inv);
-    if (threadIdx.x == 0) x[j] = aj;
-    for (int i = threadIdx.x; i < j; i += 256) y[i] = csub(y[i], cmul(col[i], aj));
-    __syncthreads();
+  __syncthreads();
+}
+
+// One wavefront per template; lane l owns rows l + 64 q (q < E, T <= 64 E).
+// Column j of the factor is consumed at step j while columns j+1 and j+2 are
+// already being fetched into the other two slots of a register ring, so the
+// L2 latency of the factor overlaps two steps of work.  Every step is
+// branch-free (rows outside the update subtract an exact zero; x and y hold
+// 64 E entries), and the diagonal comes from registers rather than a scalar
+// load that every LDS wait would also wait for, so the loads of the next
+// columns stay in flight across each step.
+template <int E>
+__global__ __launch_bounds__(64) void k_trsv(const double2* __restrict__ L, const double2* __restrict__ U, int T,
+                                           const double2* __restrict__ b, int64_t bstride,
+                                           double2* __restrict__ a, int64_t astride) {
+  extern __shared__ double2 sh[];
+  double2* x = sh;               // [64 E]
+  double2* y = sh + 64 * E;      // [64 E]
+  const int lane = threadIdx.x;
+  const double2* bb = b + (int64_t)blockIdx.x * bstride;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int i = lane + 64 * q;
+    x[i] = i < T ? bb[i] : make_double2(0.0, 0.0);
+    y[i] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  TrsvCol<E> c0, c1, c2;
+  // forward: L y = b
+  trsv_load<E>(L, T, lane, c0, 0);
+  trsv_load<E>(L, T, lane, c1, 1);
+  for (int j = 0; j < T; j += 3) {
+    trsv_load<E>(L, T, lane, c2, j + 2);
+    trsv_step<E, true>(c0, j, T, lane, x, y);
+    if (j + 1 >= T) break;
+    trsv_load<E>(L, T, lane, c0, j + 3);
+    trsv_step<E, true>(c1, j + 1, T, lane, x, y);
+    if (j + 2 >= T) break;
+    trsv_load<E>(L, T, lane, c1, j + 4);
+    trsv_step<E, true>(c2, j + 2, T, lane, x, y);
+  }
+  // backward: U a = y
+  trsv_load<E>(U, T, lane, c0, T - 1);
+  trsv_load<E>(U, T, lane, c1, T - 2);
+  for (int j = T - 1; j >= 0; j -= 3) {
+    trsv_load<E>(U, T, lane, c2, j - 2);
+    trsv_step<E, false>(c0, j, T, lane, y, x);
+    if (j - 1 < 0) break;
+    trsv_load<E>(U, T, lane, c0, j - 3);
+    trsv_step<E, false>(c1, j - 1, T, lane, y, x);
+    if (j - 2 < 0) break;
+    trsv_load<E>(U, T, lane, c1, j - 4);
+    trsv_step<E, false>(c2, j - 2, T, lane, y, x);
   }
   double2* ao = a + (int64_t)blockIdx.x * astride;
-  for (int i = threadIdx.x; i < T; i += 256) ao[i] = x[i];
+  for (int i = lane; i < T; i += 64) ao[i] = x[i];
 }
 
 // Windowed variant: a = tukey(0.25) * (truncated inverse transform of R).
@@ -274,9 +347,15 @@ int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, 
   const int T = s.T;
   double2* abase = tp.a64 + s.a_base + first * s.Tp;
   if (method == RFD_TAPS_LS) {
-    size_t sh = (size_t)2 * T * sizeof(double2);
-    hipLaunchKernelGGL(k_trsv, dim3((unsigned)count), dim3(256), sh, p.stream, s.L, s.U, T, tp.bvec, (int64_t)T,
-                       abase, (int64_t)s.Tp);
+    const dim3 grid((unsigned)count);
+#define RFD_TRSV(E)                                                                                              \
+  hipLaunchKernelGGL(k_trsv<E>, grid, dim3(64), (size_t)2 * 64 * (E) * sizeof(double2), p.stream, s.L, s.U, T,   \
+                     tp.bvec, (int64_t)T, abase, (int64_t)s.Tp)
+    if (T <= 256) RFD_TRSV(4);
+    else if (T <= 512) RFD_TRSV(8);
+    else if (T <= 1024) RFD_TRSV(16);
+    else RFD_TRSV(32);
+#undef RFD_TRSV
   } else {
     int64_t el = count * T;
     int blocks = (int)((el + 255) / 256 < 4096 ? (el + 255) / 256 : 4096);

@@ -259,6 +259,79 @@ __global__ __launch_bounds__(256) void k_lags_direct(const double2* __restrict__
   if (lane == 0) out[(int64_t)blockIdx.y * stride + l] = make_double2(re * scale, im * scale);
 }
 
+// Correlation lags without the pass-A intermediate: the workgroup's C
+// column transforms (as k_pass_a, inter-pass twiddle included) are reduced at
+// once to their share of every kept lag m = k0 + l,
+//   part[b][g][l] = sum_{i1 in group g} Y[m mod N2][i1] exp(+2 pi i i1 (m div N2) / N1),
+// and k_corr_reduce adds the N1 / C shares of each lag in a fixed order.
+template <int L>
+__global__ __launch_bounds__(kNT) void k_corr_part(LoadCorr64 ld, double2* __restrict__ part,
+                                                 const double2* __restrict__ coarse,
+                                                 const double2* __restrict__ fine, const double2* __restrict__ tabL,
+                                                 const double2* __restrict__ tab1, int n1, int k0, int T) {
+  constexpr int C = Cols<double2>::value(L);
+  constexpr int LP = lds_col<L>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  double2* buf = reinterpret_cast<double2*>(smem);
+  double2* twl = buf + C * LP;
+  const int b = blockIdx.y;
+  const int c0 = blockIdx.x * C;
+  const int64_t n = (int64_t)n1 * L;
+  load_twl<double2, L>(twl, tabL, 1);
+  for (int e = threadIdx.x; e < C * L; e += kNT) {
+    int c = e % C, i2 = e / C;
+    buf[c * LP + lpad(i2)] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
+  }
+  __syncthreads();
+  lds_fft<double2, L, C, kNT>(buf, twl, +1);
+  __syncthreads();
+  double2* pb = part + ((int64_t)b * gridDim.x + blockIdx.x) * T;
+  for (int l = threadIdx.x; l < T; l += kNT) {
+    const int64_t m = ((int64_t)k0 + l) & (n - 1);
+    const int r = (int)(m % L), cc = (int)(m / L);
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int i1 = c0 + c;
+      double2 v = buf[c * LP + lpad(r)];
+      const uint32_t pp = (uint32_t)i1 * (uint32_t)r;
+      if (pp) v = cmul(v, twiddle_n(coarse, fine, pp, +1));
+      const double2 w = tab1[(int)(((int64_t)i1 * cc) & (n1 - 1))];
+      re += v.x * w.x - v.y * w.y;
+      im += v.x * w.y + v.y * w.x;
+    }
+    pb[l] = make_double2(re, im);
+  }
+}
+
+// 32 lags per workgroup; 8 slices of the groups per lag (slice s adds groups
+// s, s + 8, ...), then the slices in order: a fixed summation order.
+__global__ __launch_bounds__(256) void k_corr_reduce(const double2* __restrict__ part, int groups, int T,
+                                                   double scale, double2* __restrict__ out, int64_t stride) {
+  __shared__ double2 red[8][32];
+  const int ll = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int l = blockIdx.x * 32 + ll;
+  double re = 0.0, im = 0.0;
+  if (l < T) {
+    const double2* pb = part + (int64_t)blockIdx.y * groups * T + l;
+    for (int g = sl; g < groups; g += 8) {
+      const double2 v = pb[(int64_t)g * T];
+      re += v.x;
+      im += v.y;
+    }
+  }
+  red[sl][ll] = make_double2(re, im);
+  __syncthreads();
+  if (sl == 0 && l < T) {
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      re += red[k][ll].x;
+      im += red[k][ll].y;
+    }
+    out[(int64_t)blockIdx.y * stride + l] = make_double2(re * scale, im * scale);
+  }
+}
+
 // ------------------------------------------------------- small kernels
 // sigma^2 = sum_i w_i |h_i|^2 in FP64 by one workgroup (fixed order).
 __global__ __launch_bounds__(1024) void k_sigma_sq(const double* __restrict__ w, const double2* __restrict__ h,
@@ -459,13 +532,38 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
   if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
   LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high,
                 mode};
+  const double scale = mode == 2 ? 1.0 / (double)p.n : 1.0;
+  // fused form: per-workgroup lag shares in the work buffer, then their sums
+  const int C = Cols<double2>::value(p.n2);
+  const int groups = p.n1 / C;
+  if ((int64_t)groups * T <= p.n) {
+    dim3 blk(kNT);
+    switch (p.n2) {
+#define CASE_C(LL)                                                                                     \
+  case LL: {                                                                                           \
+    constexpr int CC = Cols<double2>::value(LL);                                                       \
+    const size_t sh = lds_bytes<double2, LL, CC>();                                                    \
+    hipLaunchKernelGGL((k_corr_part<LL>), dim3(groups, (unsigned)batch), blk, sh, p.stream, ld, tp.work64, \
+                       p.tw64c, p.tw64f, p.tw64_n2, p.tw64_n1, p.n1, k0, T);                           \
+    break;                                                                                             \
+  }
+      CASE_C(32) CASE_C(64) CASE_C(128) CASE_C(256) CASE_C(512) CASE_C(1024) CASE_C(2048)
+#undef CASE_C
+      default: return fail(RFD_E_UNSUPPORTED, "fft: unsupported N2");
+    }
+    RFD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_corr_reduce, dim3((unsigned)((T + 31) / 32), (unsigned)batch), dim3(256), 0, p.stream,
+                       (const double2*)tp.work64, groups, T, scale, out, out_stride);
+    RFD_CHECK_LAUNCH();
+    return RFD_OK;
+  }
   // k_lags_direct reads the pass-A rows (k0 + l) mod N2, l < T
   const int row_lo = (int)(((int64_t)k0 % p.n2 + p.n2) % p.n2);
   int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1, row_lo, T);
   if (rc) return rc;
   hipLaunchKernelGGL(k_lags_direct, dim3((unsigned)((T + 3) / 4), (unsigned)batch), dim3(256), 0, p.stream,
-                     (const double2*)tp.work64, p.n, p.n1, p.n2, (const double2*)p.tw64_n1, k0, T,
-                     mode == 2 ? 1.0 / (double)p.n : 1.0, out, out_stride);
+                     (const double2*)tp.work64, p.n, p.n1, p.n2, (const double2*)p.tw64_n1, k0, T, scale, out,
+                     out_stride);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }

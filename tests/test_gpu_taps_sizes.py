@@ -1,7 +1,9 @@
 """Least-squares ratio taps (Sec. V.A) against the FP64 oracle at tap counts
 that reach every shape of the triangular solves (one wavefront per template
 owning 4, 8, 16 or 32 rows per lane: T <= 256, 512, 1024, 2048), with one and
-several templates per sub-bank."""
+several templates per sub-bank.  At N = 2^13 (128 x 64) the correlation lags of
+T = 64 come from per-workgroup lag shares, those of the larger T from the
+row-limited column transform and direct lag sums, so both routes are checked."""
 import numpy as np
 import pytest
 

@@ -79,7 +79,7 @@ struct GemmEpi {
 // C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation.
 // op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
 // TM x TM output tile per workgroup (TM = 64: 4 x 4 per thread; TM = 32:
-// 2 x 2, four times the workgroups for the MLP's small GEMMs), K in steps of
+// 2 x 2 and TM = 16: 1 x 1, more workgroups for the MLP's small GEMMs), K in steps of
 // 32 with the next step's tiles loaded into registers while the current one
 // is multiplied from LDS.
 template <int TM, typename TA, typename TB>
@@ -162,8 +162,13 @@ template <typename TA, typename TB>
 static int gemm(hipStream_t st, int M, int N, int K, const TA* A, int lda, int ta, const TB* B, int ldb, int tb,
                 float* C, int ldc, int accumulate = 0, GemmEpi epi = GemmEpi()) {
   if (M <= 0 || N <= 0) return RFD_OK;
-  // 32-wide tiles when 64-wide ones would leave most of the 256 CUs idle
-  if ((int64_t)((N + 63) / 64) * ((M + 63) / 64) < 512) {
+  // narrower tiles when wider ones would leave most of the 256 CUs idle (each
+  // output's summation order is the same at every tile width)
+  if ((int64_t)((N + 31) / 32) * ((M + 31) / 32) < 512) {
+    dim3 grid((N + 15) / 16, (M + 15) / 16);
+    hipLaunchKernelGGL((k_gemm<16, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
+                       accumulate, epi);
+  } else if ((int64_t)((N + 63) / 64) * ((M + 63) / 64) < 512) {
     dim3 grid((N + 31) / 32, (M + 31) / 32);
     hipLaunchKernelGGL((k_gemm<32, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
                        accumulate, epi);

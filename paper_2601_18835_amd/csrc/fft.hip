@@ -10,8 +10,11 @@
 // pass fuses the pointwise product of Eq. 1 (data x conj(template) x weight);
 // the second fuses the consumer: spectrum store, reference-series store with
 // its 16-bit hi/lo planes.  Tap construction evaluates only the T
-// correlation lags it keeps, by direct sums over pass A's rows.  FINDCHIRP's
-// own transforms live with its kernels.
+// correlation lags it keeps: each pass-A workgroup reduces its columns at
+// once to its share of every kept lag (k_corr_part, k_corr_reduce), or, where
+// those shares would not fit the work buffer, pass A stores the rows the lags
+// read and k_lags_direct sums them.  FINDCHIRP's own transforms live with its
+// kernels.
 #include <algorithm>
 
 #include "dev_common.h"

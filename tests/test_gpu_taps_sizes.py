@@ -49,3 +49,34 @@ def test_ls_taps_every_solve_shape(rfd, sized):
             j += 1
         print(f"\n[taps T={sb.T}] max rel |da| = {worst:.3e}")
         assert worst <= 1e-8
+
+
+# Long segments: N2 = 1024 (N = 2^20, four columns per workgroup) and N2 = 2048
+# (N = 2^22, two columns per workgroup) of the per-workgroup lag shares.
+@pytest.mark.parametrize("log2n", [20, 22])
+def test_ls_taps_long_segments(rfd, log2n):
+    from oracle import pipeline as orc
+    from oracle import taps as otaps
+    n, T, k0 = 1 << log2n, 128, -64
+    w = synth.Workload(f"taps{log2n}", 9, n, FS, F_LOW, 0, 1, 0, "fp32", "nonspin")
+    rng = np.random.default_rng(log2n)
+    psd = synth.psd_array(n, FS)
+    s = synth.make_noise_spectrum(w, rng)
+    h_ref = synth.taylorf2(synth.WaveformParams(3.0, 2.5), n, FS, F_LOW)
+    params = [synth.WaveformParams(*m) for m in rng.uniform(2.7, 3.3, size=(2, 2))]
+    H = synth.template_batch(w, params)
+    data = synth.spectrum_to_time(s, n, FS)
+    case = Case(f"taps{log2n}", n, FS, F_LOW, psd, data, {0: h_ref}, [SB(0, T, k0, H, "ls")])
+    p = orc.prepare(psd, data, FS, F_LOW)
+    M = otaps.gram(h_ref, p.w, T)
+    srch = gpu_search(case)
+    try:
+        for j in range(H.shape[0]):
+            tt = orc.make_taps(p, H[j], h_ref, T, k0, method="ls", M=M)
+            a, sig, Tg, k0g = srch.tap(j)
+            rel = np.max(np.abs(a - tt.a)) / np.max(np.abs(tt.a))
+            print(f"\n[taps N=2^{log2n}] template {j}: max rel |da| = {rel:.3e}")
+            assert rel <= 1e-8
+            assert abs(sig - tt.sigma_fit) <= 1e-9 * tt.sigma_fit
+    finally:
+        srch.close()

@@ -123,17 +123,17 @@ __device__ __forceinline__ void trsv_step(const TrsvCol<E>& c, int j, int T, int
 }
 
 // One wavefront per template; lane l owns rows l + 64 q (q < E, T <= 64 E).
-// Column j of the factor is consumed at step j while columns j+1 and j+2 are
-// already being fetched into the other two slots of a register ring, so the
-// L2 latency of the factor overlaps two steps of work.  Every step is
+// The factor is read B = 32 / E columns at a time (one batch of independent
+// loads, one wait), then B steps run from registers: each workgroup meets the
+// latency of a column read once per B steps (the waves of a launch read the
+// same column in lockstep, so each read waits on the L2 fill).  Every step is
 // branch-free (rows outside the update subtract an exact zero; x and y hold
-// 64 E entries), and the diagonal comes from registers rather than a scalar
-// load that every LDS wait would also wait for, so the loads of the next
-// columns stay in flight across each step.
+// 64 E entries) and takes the diagonal from registers.
 template <int E>
 __global__ __launch_bounds__(64) void k_trsv(const double2* __restrict__ L, const double2* __restrict__ U, int T,
                                            const double2* __restrict__ b, int64_t bstride,
                                            double2* __restrict__ a, int64_t astride) {
+  constexpr int B = 32 / E;
   extern __shared__ double2 sh[];
   double2* x = sh;               // [64 E]
   double2* y = sh + 64 * E;      // [64 E]
@@ -146,32 +146,23 @@ __global__ __launch_bounds__(64) void k_trsv(const double2* __restrict__ L, cons
     y[i] = make_double2(0.0, 0.0);
   }
   __syncthreads();
-  TrsvCol<E> c0, c1, c2;
   // forward: L y = b
-  trsv_load<E>(L, T, lane, c0, 0);
-  trsv_load<E>(L, T, lane, c1, 1);
-  for (int j = 0; j < T; j += 3) {
-    trsv_load<E>(L, T, lane, c2, j + 2);
-    trsv_step<E, true>(c0, j, T, lane, x, y);
-    if (j + 1 >= T) break;
-    trsv_load<E>(L, T, lane, c0, j + 3);
-    trsv_step<E, true>(c1, j + 1, T, lane, x, y);
-    if (j + 2 >= T) break;
-    trsv_load<E>(L, T, lane, c1, j + 4);
-    trsv_step<E, true>(c2, j + 2, T, lane, x, y);
+  for (int j0 = 0; j0 < T; j0 += B) {
+    TrsvCol<E> c[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) trsv_load<E>(L, T, lane, c[k], j0 + k);
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (j0 + k < T) trsv_step<E, true>(c[k], j0 + k, T, lane, x, y);
   }
   // backward: U a = y
-  trsv_load<E>(U, T, lane, c0, T - 1);
-  trsv_load<E>(U, T, lane, c1, T - 2);
-  for (int j = T - 1; j >= 0; j -= 3) {
-    trsv_load<E>(U, T, lane, c2, j - 2);
-    trsv_step<E, false>(c0, j, T, lane, y, x);
-    if (j - 1 < 0) break;
-    trsv_load<E>(U, T, lane, c0, j - 3);
-    trsv_step<E, false>(c1, j - 1, T, lane, y, x);
-    if (j - 2 < 0) break;
-    trsv_load<E>(U, T, lane, c1, j - 4);
-    trsv_step<E, false>(c2, j - 2, T, lane, y, x);
+  for (int j0 = T - 1; j0 >= 0; j0 -= B) {
+    TrsvCol<E> c[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) trsv_load<E>(U, T, lane, c[k], j0 - k);
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (j0 - k >= 0) trsv_step<E, false>(c[k], j0 - k, T, lane, y, x);
   }
   double2* ao = a + (int64_t)blockIdx.x * astride;
   for (int i = lane; i < T; i += 64) ao[i] = x[i];

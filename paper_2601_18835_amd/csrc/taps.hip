@@ -168,6 +168,92 @@ __global__ __launch_bounds__(64) void k_trsv(const double2* __restrict__ L, cons
   for (int i = lane; i < T; i += 64) ao[i] = x[i];
 }
 
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Row j of a register-distributed vector (row i = lane + 64 q in slot q of
+// lane i % 64), on every lane: a masked sum over the slots (one nonzero
+// term, exact) and a cross-lane read.
+template <int E>
+__device__ __forceinline__ double row_pick(const double (&v)[E], int j) {
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < E; ++q) s += (q == (j >> 6)) ? v[q] : 0.0;
+  return lane_bcast(s, j & 63);
+}
+
+// The same sweeps for T <= 64 E, E <= 8, with x, y and the inverse diagonal
+// 1 / L[i][i] (= 1 / U[i][i], real) in registers: a step is a cross-lane
+// read of row j and E independent updates, with no LDS and no barrier.  The
+// factor columns come in batches of B = 32 / E as in k_trsv.
+template <int E>
+__device__ __forceinline__ void trsv_reg_step(const TrsvCol<E>& c, int j, int T, int lane, bool fwd,
+                                              const double (&dinv)[E], double (&rr)[E], double (&ri)[E],
+                                              double (&outr)[E], double (&outi)[E]) {
+  const double inv = row_pick<E>(dinv, j);
+  const double wr = row_pick<E>(rr, j) * inv, wi = row_pick<E>(ri, j) * inv;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int i = lane + 64 * q;
+    if (i == j) {
+      outr[q] = wr;
+      outi[q] = wi;
+    }
+    const bool active = fwd ? (i > j && i < T) : (i < j);
+    const double2 v = active ? c.v[q] : make_double2(0.0, 0.0);
+    const double2 d = csub(make_double2(rr[q], ri[q]), cmul(v, make_double2(wr, wi)));
+    rr[q] = d.x;
+    ri[q] = d.y;
+  }
+}
+
+template <int E>
+__global__ __launch_bounds__(64) void k_trsv_reg(const double2* __restrict__ L, const double2* __restrict__ U,
+                                               int T, const double2* __restrict__ b, int64_t bstride,
+                                               double2* __restrict__ a, int64_t astride) {
+  constexpr int B = 32 / E;
+  const int lane = threadIdx.x;
+  const double2* bb = b + (int64_t)blockIdx.x * bstride;
+  double xr[E], xi[E], yr[E], yi[E], dinv[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int i = lane + 64 * q;
+    const double2 v = i < T ? bb[i] : make_double2(0.0, 0.0);
+    xr[q] = v.x;
+    xi[q] = v.y;
+    yr[q] = yi[q] = 0.0;
+    dinv[q] = i < T ? 1.0 / L[(int64_t)i * T + i].x : 1.0;
+  }
+  // forward: y_j = x_j / L[j][j]; x_i -= L[i][j] y_j for j < i < T
+  for (int j0 = 0; j0 < T; j0 += B) {
+    TrsvCol<E> c[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) trsv_load<E>(L, T, lane, c[k], j0 + k);
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (j0 + k < T) trsv_reg_step<E>(c[k], j0 + k, T, lane, true, dinv, xr, xi, yr, yi);
+  }
+  // backward: a_j = y_j / U[j][j] (into x); y_i -= U[i][j] a_j for i < j
+  for (int j0 = T - 1; j0 >= 0; j0 -= B) {
+    TrsvCol<E> c[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) trsv_load<E>(U, T, lane, c[k], j0 - k);
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (j0 - k >= 0) trsv_reg_step<E>(c[k], j0 - k, T, lane, false, dinv, yr, yi, xr, xi);
+  }
+  double2* ao = a + (int64_t)blockIdx.x * astride;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int i = lane + 64 * q;
+    if (i < T) ao[i] = make_double2(xr[q], xi[q]);
+  }
+}
+
 // Windowed variant: a = tukey(0.25) * (truncated inverse transform of R).
 __device__ double tukey(int l, int T) {
   const double alpha = 0.25;
@@ -342,8 +428,12 @@ int taps_solve_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count, 
 #define RFD_TRSV(E)                                                                                              \
   hipLaunchKernelGGL(k_trsv<E>, grid, dim3(64), (size_t)2 * 64 * (E) * sizeof(double2), p.stream, s.L, s.U, T,   \
                      tp.bvec, (int64_t)T, abase, (int64_t)s.Tp)
-    if (T <= 256) RFD_TRSV(4);
-    else if (T <= 512) RFD_TRSV(8);
+    if (T <= 256)
+      hipLaunchKernelGGL(k_trsv_reg<4>, grid, dim3(64), 0, p.stream, s.L, s.U, T, tp.bvec, (int64_t)T, abase,
+                         (int64_t)s.Tp);
+    else if (T <= 512)
+      hipLaunchKernelGGL(k_trsv_reg<8>, grid, dim3(64), 0, p.stream, s.L, s.U, T, tp.bvec, (int64_t)T, abase,
+                         (int64_t)s.Tp);
     else if (T <= 1024) RFD_TRSV(16);
     else RFD_TRSV(32);
 #undef RFD_TRSV

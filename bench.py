@@ -193,28 +193,24 @@ def main():
         prec = args.fir_form
 
     tune = None
-    graph = None
     if multi:
         s.dechirp_all()
         tune = rfd.rfd_autotune_fir(s.plan, s.taps, prec, w.window, reps=1)
         log(f"autotuner: {tune}")
-        graph = rfd.rfd_segment_graph_create(s.plan, s.taps, prec, w.threshold, w.window, data, s.h_ref, out, cap)
-        step = lambda: rfd.rfd_segment_graph_launch(graph)   # noqa: E731
-        # FIR kernel time (eager, same configuration) for the roofline
-        _, _, tfir = timed(lambda: eager_step(prec), 2, 1)
-        fir_ms = tfir["fir_ms"] / max(1, tfir["n_fir"])
-    else:
-        step = lambda: eager_step(prec)   # noqa: E731
+    # the timed step replays the segment graph (transform, dechirps, FIR, compaction); the
+    # per-stage times and the FIR kernel time for the roofline come from eager steps of the
+    # same configuration, timed on the plan's stream with HIP events
+    graph = rfd.rfd_segment_graph_create(s.plan, s.taps, prec, w.threshold, w.window, data, s.h_ref, out, cap)
+    step = lambda: rfd.rfd_segment_graph_launch(graph)   # noqa: E731
 
-    log(f"timing {args.steps} steps ({args.warmup} warm-up), {prec}{' (segment graph)' if multi else ''}")
+    log(f"timing {args.steps} steps ({args.warmup} warm-up), {prec} (segment graph)")
     dt, ntrig, tim = timed(step, args.steps, args.warmup)
     ms_step = dt / args.steps * 1e3
     value = ts * args.steps / dt
-    if not multi:
-        fir_ms = tim["fir_ms"] / max(1, tim["n_fir"])
-        stages = {k: tim[k] / args.steps for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms")}
-    else:
-        stages = {"fir_ms": fir_ms}
+    ne = max(5, args.steps // 2)
+    _, _, tfir = timed(lambda: eager_step(prec), ne, 2)
+    fir_ms = tfir["fir_ms"] / max(1, tfir["n_fir"])
+    stages = {k: tfir[k] / ne for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms") if k in tfir}
     log(f"{prec}: {ms_step:.3f} ms/step, {value:.4g} t*s/s, FIR kernel {fir_ms:.3f} ms, {ntrig} triggers")
     peak = PEAK[prec]
     if prec == "ols32":
@@ -309,7 +305,7 @@ def main():
         "config": {"workload": w.name, "segment_samples": w.n, "fs": w.fs, "f_low": w.f_low, "templates": nt,
                    "references": nsb, "taps": sorted(set(sb.taps for sb in bank.subbanks))
                    if multi else bank.subbanks[0].taps, "threshold": w.threshold, "cluster_window": w.window,
-                   "fir_form": prec, "segment_graph": multi},
+                   "fir_form": prec, "segment_graph": True},
         "fir_form_selection_ms": selection, "mfma_form": mfma_form,
         "stages_ms": stages, "triggers": ntrig,
         "tap_construction": {"templates_per_s": taps_per_s, "gpu_ms": tap_timing["taps_ms"]},

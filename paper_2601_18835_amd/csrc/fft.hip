@@ -278,7 +278,12 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LoadCorr64 ld, double2* __res
   double2* buf = reinterpret_cast<double2*>(smem);
   double2* twl = buf + C * LP;
   const int b = blockIdx.y;
-  const int c0 = blockIdx.x * C;
+  // column group of this workgroup: consecutive workgroups go to different
+  // XCDs (round robin over 8), so groups g and g + 1, which read the two
+  // halves of the same cache lines, are given to workgroups of one XCD
+  const int G = gridDim.x;
+  const int g = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int c0 = g * C;
   const int64_t n = (int64_t)n1 * L;
   load_twl<double2, L>(twl, tabL, 1);
   for (int e = threadIdx.x; e < C * L; e += kNT) {
@@ -288,7 +293,7 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LoadCorr64 ld, double2* __res
   __syncthreads();
   lds_fft<double2, L, C, kNT>(buf, twl, +1);
   __syncthreads();
-  double2* pb = part + ((int64_t)b * gridDim.x + blockIdx.x) * T;
+  double2* pb = part + ((int64_t)b * G + g) * T;
   for (int l = threadIdx.x; l < T; l += kNT) {
     const int64_t m = ((int64_t)k0 + l) & (n - 1);
     const int r = (int)(m % L), cc = (int)(m / L);

@@ -81,7 +81,7 @@ def main():
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: this benchmark runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -56,7 +56,7 @@ typedef enum rfd_status {
   RFD_E_DEVICE = -3,      /* a HIP runtime call or kernel launch failed */
   RFD_E_OVERFLOW = -4,    /* more triggers than `capacity`; *n_out = needed count */
   RFD_E_STATE = -5,       /* call order violated (e.g. filtering before dechirp) */
-  RFD_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+  RFD_E_UNSUPPORTED = -6  /* valid request this library does not implement */
 } rfd_status;
 
 /* FIR arithmetic (rfd_filter_bank). */

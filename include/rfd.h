@@ -385,6 +385,20 @@ int rfd_segment_graph_launch(rfd_graph* graph, int64_t* n_out);
 int rfd_graph_destroy(rfd_graph* graph);
 
 /*
+ * Low-latency increment as one graph (Sec. VII.A: only the newest stretch of
+ * the segment is filtered): the same capture as rfd_segment_graph_create, but
+ * the FIR, window peaks and triggers cover only outputs [n_start, n_start +
+ * n_len), exactly as rfd_filter_range (same range rules: 256-sample aligned,
+ * non-empty, inside the segment, else RFD_E_INVALID).  The segment transform
+ * and the dechirps still cover the whole segment.  Replayed with
+ * rfd_segment_graph_launch, freed with rfd_graph_destroy.
+ */
+int rfd_range_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                           int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                           const double* const* h_refs, int64_t n_start, int64_t n_len, rfd_trigger* out,
+                           int64_t capacity, rfd_graph** graph);
+
+/*
  * Learned tap surrogate (an extension to the method; the paper does not
  * define it).  A small MLP (4 -> hidden -> hidden -> n_basis, SiLU, BF16
  * weights, FP32 accumulation) maps scaled template parameters to

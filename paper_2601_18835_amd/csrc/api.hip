@@ -1018,9 +1018,16 @@ struct rfd_graph {
   int64_t plan_gen = 0, taps_gen = 0;   // buffer generations the capture saw
 };
 
-int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
-                             int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,
-                             const double* const* h_refs, rfd_trigger* out, int64_t capacity, rfd_graph** graph) {
+}  // extern "C"
+
+// Capture of one segment's launches (transform, every dechirp, slot clear,
+// FIR, window peaks, compaction, trigger z) into a graph; n_len > 0 limits the
+// FIR and the trigger search to outputs [n_start, n_start + n_len) as
+// rfd_filter_range does, n_len == 0 covers the whole segment.
+static int graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                        int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                        const double* const* h_refs, int64_t n_start, int64_t n_len, rfd_trigger* out,
+                        int64_t capacity, rfd_graph** graph) {
   if (!graph) return fail(RFD_E_INVALID, "graph is NULL");
   *graph = nullptr;
   if (!plan || !taps || !data || !ref_ids || !h_refs) return fail(RFD_E_INVALID, "NULL argument");
@@ -1042,6 +1049,9 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
     if (s.count && !seen[s.ref_id]) return fail(RFD_E_INVALID, "a sub-bank's reference is not in ref_ids");
   for (auto& s : t.sb)
     if (s.made != s.count) return fail(RFD_E_STATE, "taps not made");
+  const bool ranged = n_len != 0;
+  if (ranged && (n_start < 0 || n_len < 256 || n_start % 256 != 0 || n_len % 256 != 0 || n_start + n_len > p.n))
+    return fail(RFD_E_INVALID, "range must be 256-sample aligned, non-empty and inside the segment");
   const int64_t nwin = (p.n + cluster_window - 1) / cluster_window;
   const int64_t n_slots = t.n_templates * nwin;
   rc = ensure_slots(p, std::max<int64_t>(n_slots, 1));
@@ -1065,7 +1075,15 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
     rc = launch_data_fft(p, data);
     if (!rc) rc = launch_dechirp_refs(p, n_refs, ref_ids, h_refs);
     if (!rc) rc = launch_slots_clear(p, n_slots);
-    if (!rc) rc = enqueue_fir(p, t, precision, cluster_window, nwin, threshold);
+    if (!rc && !ranged) rc = enqueue_fir(p, t, precision, cluster_window, nwin, threshold);
+    if (!rc && ranged) {
+      if (precision == RFD_OLS32) {
+        rc = launch_ols(p, t, cluster_window, nwin, threshold, n_start, n_start + n_len);
+      } else {
+        for (size_t b = 0; !rc && b < t.sb.size(); ++b)
+          rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin, threshold, n_start, n_len);
+      }
+    }
     if (!rc) rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);
     if (!rc) rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
     hipError_t e = hipStreamEndCapture(cap, &g);
@@ -1098,6 +1116,24 @@ int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t preci
   }
   *graph = h;
   return RFD_OK;
+}
+
+extern "C" {
+
+int rfd_segment_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                             int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                             const double* const* h_refs, rfd_trigger* out, int64_t capacity, rfd_graph** graph) {
+  return graph_create(plan, taps, precision, threshold, cluster_window, data, n_refs, ref_ids, h_refs, 0, 0, out,
+                      capacity, graph);
+}
+
+int rfd_range_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                           int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,
+                           const double* const* h_refs, int64_t n_start, int64_t n_len, rfd_trigger* out,
+                           int64_t capacity, rfd_graph** graph) {
+  if (n_len == 0) return fail(RFD_E_INVALID, "range must be 256-sample aligned, non-empty and inside the segment");
+  return graph_create(plan, taps, precision, threshold, cluster_window, data, n_refs, ref_ids, h_refs, n_start, n_len,
+                      out, capacity, graph);
 }
 
 int rfd_segment_graph_launch(rfd_graph* graph, int64_t* n_out) {

@@ -70,6 +70,7 @@ _SIGS = {
     "rfd_autotune_fir": [_P, _P, _i32, _i64, _i32, C.POINTER(rfd_tune_result)],
     "rfd_segment_graph_create": [_P, _P, _i32, _f, _i64, _P, _i32, _P, _P, _P, _i64, C.POINTER(_P)],
     "rfd_segment_graph_launch": [_P, C.POINTER(_i64)],
+    "rfd_range_graph_create": [_P, _P, _i32, _f, _i64, _P, _i32, _P, _P, _i64, _i64, _P, _i64, C.POINTER(_P)],
     "rfd_graph_destroy": [_P],
     "rfd_surrogate_create": [_P, _P, _i32, _i32, _i32, C.c_uint64, C.POINTER(_P)],
     "rfd_surrogate_fit_basis": [_P, _i32, C.POINTER(_d)],
@@ -215,6 +216,18 @@ def rfd_segment_graph_create(plan, taps, precision, threshold, cluster_window, d
     _check(_lib.rfd_segment_graph_create(plan, taps, PRECISIONS.get(precision, precision), threshold, cluster_window,
                                          _ptr(data), len(ids), ids.ctypes.data, ptrs, _ptr(out), capacity,
                                          C.byref(g)), "rfd_segment_graph_create")
+    return g
+
+
+def rfd_range_graph_create(plan, taps, precision, threshold, cluster_window, data, refs, n_start, n_len, out,
+                           capacity):
+    """As rfd_segment_graph_create, FIR and triggers over outputs [n_start, n_start + n_len) only."""
+    ids = np.array(sorted(refs), dtype=np.int32)
+    ptrs = (C.c_void_p * len(ids))(*[refs[int(i)].data_ptr() for i in ids])
+    g = _P()
+    _check(_lib.rfd_range_graph_create(plan, taps, PRECISIONS.get(precision, precision), threshold, cluster_window,
+                                       _ptr(data), len(ids), ids.ctypes.data, ptrs, n_start, n_len, _ptr(out),
+                                       capacity, C.byref(g)), "rfd_range_graph_create")
     return g
 
 

@@ -91,3 +91,41 @@ def test_renormalisation_follows_a_psd_change(rfd):
         assert worst_s <= 1e-9 and worst <= 1e-5
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("precision", ["ols32", "fp32", "bf16x3"])
+def test_range_graph_replays_match_eager_range(rfd, ragged, precision):
+    """The low-latency increment captured as one graph (transform, dechirps,
+    range FIR, compaction) gives the eager range filter's triggers on every
+    replay, with eager work between the replays."""
+    import torch
+    case, s = ragged
+    th, W, cap = 2.5, 512, 1 << 16
+    n_start, n_len = case.n - 2048, 2048
+    s.dechirp_all()
+    buf, n = s.filter_range(precision, th, W, n_start, n_len, cap)
+    eager = rfd.triggers_to_numpy(buf, n)
+    assert len(eager) > 0
+    out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    g = rfd.rfd_range_graph_create(s.plan, s.taps, precision, th, W, s.data, s.h_ref, n_start, n_len, out, cap)
+    try:
+        for rep in range(3):
+            n2 = rfd.rfd_segment_graph_launch(g)
+            assert np.array_equal(rfd.triggers_to_numpy(out, n2), eager), f"replay {rep}"
+            s.dechirp_all()
+            buf, n3 = s.filter_range(precision, th, W, n_start, n_len, cap)
+            assert np.array_equal(rfd.triggers_to_numpy(buf, n3), eager)
+            torch.cuda.synchronize()
+    finally:
+        rfd.rfd_graph_destroy(g)
+        s.dechirp_all()
+
+
+def test_range_graph_arguments_are_checked(rfd, ragged):
+    import torch
+    case, s = ragged
+    out = torch.empty(1024 * 32, dtype=torch.uint8, device="cuda")
+    for n_start, n_len in [(100, 256), (0, 0), (0, 100), (case.n - 256, 512), (-256, 256)]:
+        with pytest.raises(rfd.RfdError) as e:
+            rfd.rfd_range_graph_create(s.plan, s.taps, "ols32", 2.5, 512, s.data, s.h_ref, n_start, n_len, out, 1024)
+        assert e.value.code == rfd.RFD_E_INVALID

@@ -35,6 +35,9 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
+// tap groups (8 complex taps, 64 real products) per FP32 MFMA accumulation chunk
+constexpr int kFir32Chunk = 4;
+
 struct FirArgs {
   const uint32_t* zhi;      // 16-bit planes of the reference slot ((re) | (im << 16))
   const uint32_t* zlo;
@@ -261,23 +264,37 @@ __device__ __forceinline__ void fir32_block(const FirArgs& a, int64_t mbase, int
   ps.one_window = ps.q == ((mbase + (int64_t)a.S * kColsPerTile - 1) / a.W);
   for (int t = 0; t < a.S; ++t) {
     const float* wf = reinterpret_cast<const float*>(wz + t * kColsPerTile) + 2 * (lane & 15) + (lane >> 4);
+    // The K sweep runs in chunks of kFir32Chunk tap groups (8 complex taps,
+    // 16 real products each): every chunk accumulates from zero in the MFMA
+    // and is then added to the running sum with a rounded FP32 add.  One
+    // accumulator over all 2T products lets its rounding error grow with the
+    // sweep length (measured 2.2e-5 in rho at T = 1024); chunks bound the
+    // MFMA's share to 64 products.
     f32x4 acc[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
     float4 av = A[0];
-    for (int kq = 0; kq < KQ; ++kq) {
-      const float4 an = A[(int64_t)(kq + 1 < KQ ? kq + 1 : kq) * 64];
-      const float avs[4] = {av.x, av.y, av.z, av.w};
+    for (int c0 = 0; c0 < KQ; c0 += kFir32Chunk) {
+      const int c1 = c0 + kFir32Chunk < KQ ? c0 + kFir32Chunk : KQ;
+      f32x4 part[NB];
 #pragma unroll
-      for (int sub = 0; sub < 4; ++sub) {
-        const int kb2 = 4 * kq + sub;
+      for (int i = 0; i < NB; ++i) part[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int kq = c0; kq < c1; ++kq) {
+        const float4 an = A[(int64_t)(kq + 1 < KQ ? kq + 1 : kq) * 64];
+        const float avs[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const float bv = wf[32 * nb + 4 * kb2];
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avs[sub], bv, acc[nb], 0, 0, 0);
+        for (int sub = 0; sub < 4; ++sub) {
+          const int kb2 = 4 * kq + sub;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const float bv = wf[32 * nb + 4 * kb2];
+            part[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avs[sub], bv, part[nb], 0, 0, 0);
+          }
         }
+        av = an;
       }
-      av = an;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] += part[nb];
     }
     fir_tile_epilogue<NB>(acc, a, mbase + (int64_t)t * kColsPerTile, tb, ps);
   }

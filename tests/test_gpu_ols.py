@@ -5,7 +5,7 @@ block-size autotuner."""
 import numpy as np
 import pytest
 
-from gpu_cases import compare_triggers, fir_tolerance, gpu_search, oracle_case, ragged_case, rho_matrix
+from gpu_cases import check_target_ambiguity, compare_triggers, fir_tolerance, gpu_search, oracle_case, ragged_case, rho_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,9 @@ def test_block_sizes_match_oracle(rfd, ragged, block):
         # windows much shorter than a block (per-sample keys), about a block, longer than the segment part
         for threshold, window in [(3.0, 17), (3.0, 300), (2.5, 8192)]:
             buf, n = s.filter("ols32", threshold, window, 1 << 16)
-            compare_triggers(rfd.triggers_to_numpy(buf, n), want, threshold, window, float(tol.max()))
+            tr = rfd.triggers_to_numpy(buf, n)
+            compare_triggers(tr, want, threshold, window, tol)
+            check_target_ambiguity(tr, want, threshold, window, tol, 1e-5)
     finally:
         rfd.rfd_plan_set_fir_config(s.plan)
 

@@ -9,7 +9,7 @@ within the tolerance) are counted and printed.
 import numpy as np
 import pytest
 
-from gpu_cases import (compare_triggers, fir_tolerance, gpu_search, oracle_case, ragged_case, rho_matrix, tap_gain,
+from gpu_cases import (ambiguity_bound, check_target_ambiguity, compare_triggers, fir_tolerance, gpu_search, oracle_case, ragged_case, rho_matrix, tap_gain,
                        workload_case)
 
 pytestmark = pytest.mark.gpu
@@ -94,6 +94,8 @@ def test_fir_triggers_identical(rfd, small, precision):
         ncmp, namb, dmax = compare_triggers(trig, rho_o, threshold, window, TOL[precision])
         print(f"\n[bns64s] {precision} theta={threshold} W={window}: {n} triggers, {ncmp} windows identical, "
               f"{namb} ambiguous, max |drho| {dmax:.2e}")
+        assert namb <= ambiguity_bound(ncmp + namb, TOL[precision]), (namb, ncmp)
+        assert dmax <= TOL[precision]
 
 
 def test_findchirp_parity(rfd, small):
@@ -114,6 +116,7 @@ def test_findchirp_parity(rfd, small):
     buf, n = R.findchirp_filter(s.plan, None, filt, 6.0, 2048, 4096)
     trig = R.triggers_to_numpy(buf, n)
     ncmp, namb, dmax = compare_triggers(trig, want, 6.0, 2048, 1e-5)
+    assert namb == 0 and dmax <= 1e-5
     z = trig["z_re"] + 1j * trig["z_im"]
     assert np.max(np.abs(z - case.oracle["fc"][trig["tmpl"], trig["sample"]]), initial=0) <= 1e-5
     print(f"[bns64s] FINDCHIRP theta=6: {n} triggers, {ncmp} windows identical, {namb} ambiguous")
@@ -139,7 +142,11 @@ def test_ragged_subbanks_parity(rfd, ragged, precision):
     for threshold, window in [(3.0, 300), (2.5, 8192), (3.0, 17)]:
         buf, n = s.filter(precision, threshold, window, 1 << 16)
         t2 = rfd.triggers_to_numpy(buf, n)
-        compare_triggers(t2, want, threshold, window, float(tol.max()))
+        ncmp, namb, dmax = compare_triggers(t2, want, threshold, window, tol)
+        nt, a2, c2 = check_target_ambiguity(t2, want, threshold, window, tol, TOL[precision])
+        print(f"[ragged] {precision} theta={threshold} W={window}: {ncmp} windows identical, {namb} ambiguous "
+              f"({a2} of {a2 + c2} over the {nt} templates at the target tolerance)")
+        assert dmax <= tol.max()
 
 
 def test_ragged_taps_parity(rfd, ragged):

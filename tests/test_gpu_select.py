@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_cases import SB, Case, compare_triggers, fir_tolerance, gpu_search, oracle_case
+from gpu_cases import SB, Case, ambiguity_bound, compare_triggers, fir_tolerance, gpu_search, oracle_case
 from oracle import spectral
 from oracle import taps as otaps
 
@@ -74,7 +74,8 @@ def test_search_over_selected_subbanks(rfd, bank):
             tol = fir_tolerance(case, form, 1e-5 if form != "bf16x3" else 1e-3)
             buf, n = g.filter(form, 5.0, 1024, 1 << 14)
             tr = rfd.triggers_to_numpy(buf, n)
-            ncmp, namb, dmax = compare_triggers(tr, want, 5.0, 1024, float(tol.max()))
+            ncmp, namb, dmax = compare_triggers(tr, want, 5.0, 1024, tol)
+            assert namb <= ambiguity_bound(ncmp + namb, float(tol.min())) and dmax <= tol.max()
             print(f"\n[select] {len(subbanks)} sub-banks T={[sb.T for sb in subbanks]}, {form}: {n} triggers, "
                   f"{ncmp} windows identical, {namb} ambiguous")
             assert n >= 1

@@ -61,6 +61,6 @@ def test_short_segment_one_window(rfd, short, precision):
     buf, n = s.filter(precision, 3.0, case.n, 64)
     trig = rfd.triggers_to_numpy(buf, n)
     tol = fir_tolerance(case, precision, 1e-5 if precision in ("fp32", "ols32") else 1e-3)
-    ncmp, namb, dmax = compare_triggers(trig, np.abs(case.oracle["z"]), 3.0, case.n, float(tol.max()))
+    ncmp, namb, dmax = compare_triggers(trig, np.abs(case.oracle["z"]), 3.0, case.n, tol)
     assert ncmp + namb == case.n_templates
     assert len(trig) >= 1

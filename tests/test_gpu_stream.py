@@ -5,7 +5,7 @@ oracle's ratio SNR with the old taps under the new PSD."""
 import numpy as np
 import pytest
 
-from gpu_cases import compare_triggers, fir_tolerance, gpu_search, oracle_case, ragged_case, workload_case
+from gpu_cases import check_target_ambiguity, compare_triggers, fir_tolerance, gpu_search, oracle_case, ragged_case, workload_case
 from oracle import fir, pipeline
 from oracle import taps as otaps
 
@@ -36,7 +36,9 @@ def test_range_matches_oracle_on_the_range(rfd, ragged, precision, n_start, n_le
     buf, n = s.filter_range(precision, 2.5, window, n_start, n_len, 1 << 16)
     tr = rfd.triggers_to_numpy(buf, n)
     assert np.all((tr["sample"] >= n_start) & (tr["sample"] < n_start + n_len))
-    ncmp, namb, _ = compare_triggers(tr, want, 2.5, window, float(tol.max()))
+    ncmp, namb, dmax = compare_triggers(tr, want, 2.5, window, tol)
+    check_target_ambiguity(tr, want, 2.5, window, tol, TOL[precision])
+    assert dmax <= tol.max(), dmax
     print(f"\n[ragged] {precision} range [{n_start}, {n_start + n_len}) W={window}: {n} triggers, "
           f"{ncmp} windows identical, {namb} ambiguous")
     if precision != "ols32" and window % 256 == 0 and n_start % window == 0 and n_len % window == 0:

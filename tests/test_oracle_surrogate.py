@@ -2,6 +2,7 @@
 differences, Adam against a hand-computed first step, whitening round trip,
 the basis against the Eckart-Young optimum, the match bounds."""
 import numpy as np
+import pytest
 
 from oracle import surrogate as sg
 
@@ -131,3 +132,41 @@ def test_phase_align_is_the_zero_lag_overlap_phase():
     z = (al @ (M + lam * np.eye(T)).T)[:, -k0]
     assert np.allclose(z.imag, 0, atol=1e-9 * np.abs(z).max()) and (z.real > 0).all()
     assert np.allclose(sg.match(al, a, M), 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("T,k0", [(32, 5), (32, -40), (16, -16), (8, 0), (24, -23)])
+def test_phase_align_outside_the_window_uses_the_nearest_lag(T, k0):
+    """When the tap window [k0, k0 + T) does not contain lag 0, the phase
+    reference is the weighted overlap at the window's lag nearest zero:
+    m* = k0 for k0 > 0, m* = k0 + T - 1 for k0 + T - 1 < 0.  For least-squares
+    taps (M + lam I) a = b, so that overlap is the cross-correlation
+    sum_i w_i h_j conj(h_ref) exp(+2 pi i i m*/N) of the spectra, computed here
+    directly by a loop over bins, independent of the taps."""
+    from oracle import spectral, taps as tp
+    from synth.waveforms import WaveformParams, taylorf2
+    from synth.psd import psd_array
+    n, fs, f_low = 4096, 2048.0, 20.0
+    w = spectral.psd_weights(psd_array(n, fs), n, fs, f_low)
+    h_ref = taylorf2(WaveformParams(1.4, 1.4), n, fs, f_low)
+    M = tp.gram(h_ref, w, T)
+    lam = tp.DEFAULT_RIDGE_EPS * M[0, 0].real
+    hs = [taylorf2(WaveformParams(1.4 + 0.013 * k, 1.38, e0=0.03 * k), n, fs, f_low) for k in range(3)]
+    a = np.stack([tp.ls_taps_normal(h, h_ref, w, T, k0, M=M) for h in hs])
+    al = sg.phase_align(a, M, lam, k0)
+    if k0 <= 0 <= k0 + T - 1:
+        m_star = 0
+    elif k0 > 0:
+        m_star = k0
+    else:
+        m_star = k0 + T - 1
+    bins = np.arange(w.size)
+    want = []
+    for h in hs:
+        acc = 0j
+        for i in bins[w > 0]:
+            acc += w[i] * h[i] * np.conj(h_ref[i]) * np.exp(2j * np.pi * ((i * m_star) % n) / n)
+        want.append(acc)
+    rot = al / a
+    assert np.allclose(np.abs(rot), 1.0, atol=1e-12)
+    assert np.allclose(rot, rot[:, :1], atol=1e-12)
+    assert np.allclose(rot[:, 0], np.exp(-1j * np.angle(np.array(want))), atol=1e-8)

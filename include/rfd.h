@@ -266,6 +266,29 @@ int rfd_filter_bank(rfd_plan* plan, const rfd_taps* taps, int32_t precision, flo
                     int64_t cluster_window, rfd_trigger* out, int64_t capacity, int64_t* n_out);
 
 /*
+ * rfd_filter_bank_noalloc - rfd_filter_bank for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels, results and errors as
+ * rfd_filter_bank, except:
+ *   - every per-call scratch buffer (window-peak slots, compaction counts,
+ *     the trigger total, overlap-save block spectra) lives in one static
+ *     device array of 32 MiB inside the library, one copy per GPU, held
+ *     until the process ends; the call allocates and frees nothing;
+ *   - a call whose scratch exceeds 32 MiB fails with RFD_E_NOMEM
+ *     (n_templates * ceil(N / W) * 8 B of slots, plus ceil(N / L) * K * 8 B
+ *     of block spectra for RFD_OLS32);
+ *   - direct forms run one launch per sub-bank (no persistent work queue);
+ *   - RFD_OLS32 needs the taps' spectra to exist already (one earlier
+ *     rfd_filter_bank call with RFD_OLS32 makes them), else RFD_E_STATE;
+ *   - stage timing is not recorded.
+ * The static array keeps the last call's contents; every call clears what it
+ * reads before reading it.  Calls that overlap on one GPU (several host
+ * threads or streams) share the array and race: serialise them.
+ */
+int rfd_filter_bank_noalloc(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
+                            int64_t cluster_window, rfd_trigger* out, int64_t capacity, int64_t* n_out);
+
+/*
  * rfd_findchirp_prepare - FINDCHIRP filters F_j = w_i conj(h_j,i) / sigma_j
  * (times the plan's data-scale compensation), FP64 on the device, stored in
  * complex64 over the band bins.

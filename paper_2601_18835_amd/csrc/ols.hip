@@ -218,14 +218,14 @@ static int ols_templates_per_wg(int64_t nB, int F, int64_t count, int n_cu) {
   return J;
 }
 
-int ensure_ols(Plan& p, Taps& t, bool allow_alloc) {
+int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
   for (size_t bi = 0; bi < t.sb.size(); ++bi) {
     SubBankTaps& s = t.sb[bi];
     if (s.count == 0) continue;
     const int K = ols_block_size(p, s.T);
     const int L = K - s.T + 1;
     const int64_t nB = (p.n + L - 1) / L;
-    const bool need_x = s.ols_x == nullptr || s.ols_x_cap < nB * K;
+    const bool need_x = need_block_spectra && (s.ols_x == nullptr || s.ols_x_cap < nB * K);
     const bool need_g = s.ols_g == nullptr || s.ols_K != K;
     if ((need_x || need_g) && !allow_alloc)
       return fail(RFD_E_STATE, "overlap-save buffers changed since capture; create the graph again");
@@ -267,17 +267,17 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc) {
 
 template <int K>
 static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, float threshold,
-                        int64_t n_lo, int64_t n_hi) {
+                        int64_t n_lo, int64_t n_hi, float2* X) {
   using S = BlockFft<K>;
   const float2* z = p.zref + (int64_t)s.ref_id * p.n;
   const int64_t b_first = n_lo / s.ols_L, b_last = (n_hi - 1) / s.ols_L;
   const int64_t nB = b_last - b_first + 1;      // <= s.ols_nB
   const unsigned gx = (unsigned)((nB + S::F - 1) / S::F);
   hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, nB, b_first,
-                     (const float2*)p.ols_tw32, s.ols_x);
+                     (const float2*)p.ols_tw32, X);
   RFD_CHECK_LAUNCH();
   OlsArgs a;
-  a.X = s.ols_x;
+  a.X = X;
   a.G = s.ols_g;
   a.tw = p.ols_tw32;
   a.slots = p.slots;
@@ -299,17 +299,19 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
   return RFD_OK;
 }
 
-int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo, int64_t n_hi) {
+int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo, int64_t n_hi,
+               float2* x_scratch) {
   if (n_hi < 0) n_hi = p.n;
   if (n_lo < 0 || n_hi > p.n || n_lo >= n_hi) return fail(RFD_E_INVALID, "overlap-save: empty output range");
   for (const SubBankTaps& s : t.sb) {
     if (s.count == 0) continue;
-    if (!s.ols_valid || !s.ols_x) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
+    float2* X = x_scratch ? x_scratch : s.ols_x;
+    if (!s.ols_valid || !X) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
     int rc;
     switch (s.ols_K) {
-      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin, threshold, n_lo, n_hi); break;
-      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin, threshold, n_lo, n_hi); break;
-      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin, threshold, n_lo, n_hi); break;
+      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
+      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
+      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
       default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
     }
     if (rc) return rc;

@@ -205,13 +205,16 @@ int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int
 // ----------------------------------------------------- launchers (ols.hip)
 int ols_block_size(const Plan& p, int T);
 // allocate block / tap spectra (only if allow_alloc; else RFD_E_STATE when one
-// is missing) and rebuild stale tap spectra in place (not inside capture)
-int ensure_ols(Plan& p, Taps& t, bool allow_alloc = true);
+// is missing) and rebuild stale tap spectra in place (not inside capture);
+// need_block_spectra false: the caller brings the block-spectra buffer itself
+int ensure_ols(Plan& p, Taps& t, bool allow_alloc = true, bool need_block_spectra = true);
 // block spectra + overlap-save FIR of every sub-bank
 // outputs [n_lo, n_hi) only (default: the whole segment); blocks whose samples
 // all have rho <= threshold skip the window keys (they can never fire)
+// x_scratch (optional): block-spectra buffer of at least ceil(N/L) K complex
+// values, used for every sub-bank in turn instead of the sub-bank's own
 int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo = 0,
-               int64_t n_hi = -1);
+               int64_t n_hi = -1, float2* x_scratch = nullptr);
 
 // ------------------------------------------------ launchers (triggers.hip)
 int launch_slots_clear(Plan& p, int64_t n_slots);

@@ -100,6 +100,7 @@ _SIGS = {
     "rfd_taps_get": [_P, _i64, _P, C.POINTER(_d), C.POINTER(_i32), C.POINTER(_i32)],
     "rfd_taps_destroy": [_P],
     "rfd_filter_bank": [_P, _P, _i32, _f, _i64, _P, _i64, C.POINTER(_i64)],
+    "rfd_filter_bank_noalloc": [_P, _P, _i32, _f, _i64, _P, _i64, C.POINTER(_i64)],
     "rfd_findchirp_prepare": [_P, _P, _i64, _P, _P],
     "findchirp_filter": [_P, _P, _P, _i64, _f, _i64, _P, _i64, C.POINTER(_i64)],
 }
@@ -378,6 +379,18 @@ def rfd_filter_bank(plan, taps, precision, threshold, cluster_window, capacity, 
     if rc == RFD_E_OVERFLOW and not raise_overflow:
         return out, n.value
     _check(rc, "rfd_filter_bank")
+    return out, n.value
+
+
+def rfd_filter_bank_noalloc(plan, taps, precision, threshold, cluster_window, capacity, out, raise_overflow=True):
+    """As rfd_filter_bank, with the library's static scratch (no device
+    allocation inside the call).  `out` must be given: (out, n)."""
+    prec = PRECISIONS.get(precision, precision)
+    n = C.c_int64(0)
+    rc = _lib.rfd_filter_bank_noalloc(plan, taps, prec, threshold, cluster_window, _ptr(out), capacity, C.byref(n))
+    if rc == RFD_E_OVERFLOW and not raise_overflow:
+        return out, n.value
+    _check(rc, "rfd_filter_bank_noalloc")
     return out, n.value
 
 

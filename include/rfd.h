@@ -331,6 +331,8 @@ typedef struct rfd_timing {
   double match_ms;      /* fitted-template match of two tap sets */
   int64_t n_data_fft, n_dechirp, n_fir, n_compact, n_findchirp, n_taps, n_sur_net, n_sur_expand, n_sur_pack,
       n_match;
+  double fir_kernel_ms; /* the main FIR kernel launches alone (one interval per launch), inside fir_ms */
+  int64_t n_fir_kernel;
 } rfd_timing;
 int rfd_plan_set_timing(rfd_plan* plan, int32_t enable);
 int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
@@ -351,6 +353,11 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out);
  *               {1024, 2048, 4096} of least (5 log2 K + 6) K / (K - T + 1)
  *               divided by the measured relative speed of that K (1.25,
  *               1, 0.97); 1024, 2048 or 4096 forces it wherever K > T.
+ *   ols_aligned 1 (default): RFD_OLS32 may keep L = 256 nf outputs per block
+ *               (nf = floor((K - T + 1) / 256)) instead of all K - T + 1,
+ *               when that costs less per output: the discarded outputs
+ *               are then never computed and interior blocks skip
+ *               per-sample range tests; 0: always K - T + 1.
  * RFD_E_INVALID for values outside these sets.
  */
 typedef struct rfd_fir_config {
@@ -359,9 +366,15 @@ typedef struct rfd_fir_config {
   int32_t max_tiles;
   int32_t wg_per_cu;
   int32_t ols_block;
+  int32_t ols_aligned;
 } rfd_fir_config;
 int rfd_plan_set_fir_config(rfd_plan* plan, const rfd_fir_config* cfg);
 int rfd_plan_get_fir_config(const rfd_plan* plan, rfd_fir_config* cfg);
+/*
+ * rfd_ols_shape - the overlap-save shape the plan's configuration gives T
+ * taps: block size K and outputs kept per block L (host int32 each).
+ */
+int rfd_ols_shape(const rfd_plan* plan, int32_t taps, int32_t* block, int32_t* outputs);
 
 /*
  * rfd_autotune_fir - pick the FIR configuration by measurement on the
@@ -442,6 +455,17 @@ int rfd_range_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precisi
  *                          n_basis in [1, min(2T, 1024)], hidden in
  *                          [1, 4096]; seed fixes initial weights, the basis
  *                          start and the shuffles.
+ * rfd_surrogate_set_feature_range
+ *                          the network's input range from the training
+ *                          set's physical parameters phys (dev float64
+ *                          [n][4]: m1, m2, chi, e0): min and max of each
+ *                          feature (chirp mass M eta^(3/5), eta = m1 m2 /
+ *                          M^2, chi, e0).  Synchronises.
+ * rfd_surrogate_features   network inputs for phys (dev float64 [n][4]):
+ *                          each feature mapped linearly onto [-1, 1] over
+ *                          that range (a constant feature maps to -1), into
+ *                          out (dev float [n][4]): the params of train and
+ *                          make_taps.  RFD_E_STATE before the range is set.
  * rfd_surrogate_fit_basis  subspace iteration (iters in [1, 100]) for the
  *                          basis; *captured_out (host, may be NULL) = mean
  *                          ||B^T x||^2 over the training set (<= 1).
@@ -505,6 +529,8 @@ int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_
 int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs, int32_t batch, float lr,
                         float* loss_out);
 int rfd_surrogate_set_graphs(rfd_surrogate* sur, int32_t enable);
+int rfd_surrogate_set_feature_range(rfd_surrogate* sur, const double* phys, int64_t n);
+int rfd_surrogate_features(rfd_surrogate* sur, const double* phys, int64_t n, float* out);
 int rfd_surrogate_loss_grad(rfd_surrogate* sur, const float* params, const float* targets, int32_t n, float* grads,
                             double* loss_out);
 int rfd_surrogate_get_state(rfd_surrogate* sur, float* weights, float* basis, float* targets, int64_t* sizes);
@@ -605,6 +631,54 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
 
 /* Thread-local description of the last error on this thread ("" if none). */
 /*
+ * Streaming (Sec. VII.A): the next stretch of SNR from the newest data.
+ * The ratio FIR is short, so a new stretch of D samples needs the reference
+ * series only over those samples plus the taps' span; the references (few,
+ * Sec. IV) are still matched-filtered against the whole window.  The stream
+ * keeps the last N data samples in a ring indexed by absolute sample number
+ * mod N (trigger samples are such ring positions).  Each push:
+ *   - writes D samples, transforms the ring once;
+ *   - evaluates every reference series on the last zlen ring positions only
+ *     (the correlation sum of Eq. 1 at those lags) into the plan's series
+ *     store, FP32 and 16-bit planes;
+ *   - runs the ratio FIR of every template, with the fused epilogue, over the
+ *     D outputs [head - D - lag, head - lag) mod N, lag = the taps' lead
+ *     max(k0 + T) rounded up to 256, so every FIR input lies in the freshly
+ *     evaluated stretch: zlen = D + lag + max(-k0), rounded up to 256.
+ * A window [qW, (q+1)W) cut by the output range reports the peak of its part
+ * inside (as rfd_filter_range).  After a push the series store is valid on
+ * the last zlen positions only: rfd_filter_bank refuses (RFD_E_STATE) until
+ * the references are dechirped again.
+ *
+ * rfd_stream_create - a stream over a plan and its taps.
+ *   n_refs, ref_ids  host int32 [n_refs]: the reference slots the taps' sub-banks
+ *                    use (every sub-bank's ref_id must be among them).
+ *   h_refs           host array of n_refs dev pointers to complex128 [N/2+1]
+ *                    reference spectra; copied into stream-owned memory.
+ *   increment        D: a multiple of 256, at most N/4, and with the taps'
+ *                    span zlen <= N/2.
+ *   Allocates the ring (N float64), reference copies (n_refs (N/2+1) complex128),
+ *   lag sums and their work buffer.  The plan and taps must outlive it.
+ * rfd_stream_prime - fills the ring with a first window (dev float64 [N],
+ *   ring positions 0..N-1, head = 0) and dechirps every stream reference on it.
+ * rfd_stream_push - data: dev float64 [D], the samples at ring positions
+ *   [head, head + D).  Remaining arguments as rfd_filter_bank; *out_start
+ *   (host, may be NULL) receives the first output position.  Synchronises.
+ * rfd_stream_info - head (next write position), lag, zlen.
+ * Errors: RFD_E_INVALID, RFD_E_STATE (push before prime, taps not made),
+ * RFD_E_NOMEM, RFD_E_OVERFLOW, RFD_E_DEVICE.
+ */
+typedef struct rfd_stream rfd_stream;
+int rfd_stream_create(rfd_plan* plan, const rfd_taps* taps, int32_t n_refs, const int32_t* ref_ids,
+                      const double* const* h_refs, int64_t increment, rfd_stream** out);
+int rfd_stream_prime(rfd_stream* stream, const double* data);
+int rfd_stream_push(rfd_stream* stream, const double* data, int32_t precision, float threshold,
+                    int64_t cluster_window, rfd_trigger* out, int64_t capacity, int64_t* n_out,
+                    int64_t* out_start);
+int rfd_stream_info(const rfd_stream* stream, int64_t* head, int64_t* lag, int64_t* zlen);
+int rfd_stream_destroy(rfd_stream* stream);
+
+/*
  * rfd_measure_peaks - this GPU's ceilings measured by the library's own
  * microbenchmarks (a diagnostic beside the datasheet peaks that rooflines
  * are priced against; not part of the method):
@@ -619,6 +693,15 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
 int rfd_measure_peaks(void* stream, double* out);
 
 const char* rfd_last_error(void);
+
+/*
+ * rfd_debug_fail_allocation - failure injection for tests of the library's
+ * out-of-memory paths: after `after` further successful device allocations
+ * (process-wide, any plan), the next one fails once as if the device were
+ * out of memory (the call reports RFD_E_NOMEM and releases what it had
+ * allocated).  after < 0 disables it.  Not for production use.
+ */
+int rfd_debug_fail_allocation(int64_t after);
 
 #ifdef __cplusplus
 }

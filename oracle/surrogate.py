@@ -96,6 +96,26 @@ def adam_init(params):
     return (0, [np.zeros_like(q) for q in flat], [np.zeros_like(q) for q in flat])
 
 
+def input_features(phys):
+    """(m1, m2, chi, e0) [n, 4] -> (chirp mass M eta^(3/5), eta = m1 m2 / M^2,
+    chi, e0): the network's input coordinates."""
+    p = np.asarray(phys, dtype=np.float64).reshape(-1, 4)
+    m1, m2 = p[:, 0], p[:, 1]
+    mt = m1 + m2
+    eta = m1 * m2 / mt ** 2
+    return np.stack([mt * eta ** 0.6, eta, p[:, 2], p[:, 3]], axis=1)
+
+
+def scaled_inputs(phys, phys_train):
+    """Features of phys mapped linearly onto [-1, 1] over the training set's
+    range of each feature (a constant feature maps to -1)."""
+    f = input_features(phys)
+    ft = input_features(phys_train)
+    lo, hi = ft.min(axis=0), ft.max(axis=0)
+    span = np.where(hi > lo, hi - lo, 1.0)
+    return 2.0 * (f - lo) / span - 1.0
+
+
 def phase_align(a, M, lam, k0):
     """a exp(-i arg z) with z = ((M + lam I) a)[i0] (a: [n, T] complex);
     i0 = -k0 is the zero-lag tap, clamped into [0, T) when the tap window

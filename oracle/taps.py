@@ -156,6 +156,16 @@ def response(a, k0, n):
     return design_matrix(bins, a.size, k0, n) @ a
 
 
+def response_fft(a, k0, n):
+    """The same A_i as `response`, by one length-N FFT of the taps placed at
+    their lags (k0 + k) mod N: A_i = sum_m x[m] exp(-2 pi i i m / N) with
+    x[(k0 + k) mod N] = a_k.  O(N log N) memory-light form for long segments."""
+    x = np.zeros(n, dtype=np.complex128)
+    lag = (k0 + np.arange(a.size, dtype=np.int64)) % n
+    np.add.at(x, lag, a)
+    return np.fft.fft(x)[: n // 2 + 1]
+
+
 def fitted_sigma_sq_freq(a, h_r, w, k0):
     """(h_fit|h_fit) = sum_i w_i |h_ref A|^2: the frequency-domain form of
     Sec. VI.B for the fitted template h_fit = h_ref * A."""

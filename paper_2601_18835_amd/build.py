@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librfd.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "fft.hip", "fir.hip", "triggers.hip", "taps.hip", "surrogate.hip", "ols.hip", "chisq.hip", "select.hip", "findchirp.hip", "peaks.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "fft.hip", "fir.hip", "triggers.hip", "taps.hip", "surrogate.hip", "ols.hip", "chisq.hip", "select.hip", "findchirp.hip", "peaks.hip", "noalloc.hip", "stream.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -19,11 +20,30 @@ int fail(int code, const std::string& msg) {
 }
 
 
+// Injected allocation failure (rfd_debug_fail_allocation): the allocation
+// after `g_fail_after` further successful ones fails once with
+// hipErrorOutOfMemory; -1 disables.
+static std::atomic<int64_t> g_fail_after{-1};
+
+hipError_t device_malloc(void** ptr, size_t bytes) {
+  int64_t k = g_fail_after.load();
+  while (k >= 0) {
+    if (g_fail_after.compare_exchange_weak(k, k - 1)) {
+      if (k == 0) {
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+      }
+      break;
+    }
+  }
+  return hipMalloc(ptr, bytes);
+}
+
 template <typename T>
 static int dalloc(T** ptr, size_t count) {
   *ptr = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+  hipError_t e = device_malloc((void**)ptr, count * sizeof(T));
   if (e != hipSuccess) {
     *ptr = nullptr;
     (void)hipGetLastError();
@@ -60,7 +80,7 @@ static int upload_table(Plan& p, int64_t len, int64_t step, int64_t den, float2*
 
 int stage_begin(Plan& p, int stage) {
   if (!p.timing) return RFD_OK;
-  Plan::Mark m{stage, nullptr, nullptr};
+  Plan::Mark m{stage, nullptr, nullptr, true};
   RFD_HIP(hipEventCreate(&m.a));
   RFD_HIP(hipEventCreate(&m.b));
   RFD_HIP(hipEventRecord(m.a, p.stream));
@@ -68,9 +88,15 @@ int stage_begin(Plan& p, int stage) {
   return RFD_OK;
 }
 
+// closes the innermost open stage (stages nest: a kernel inside the FIR stage)
 int stage_end(Plan& p) {
-  if (!p.timing || p.marks.empty()) return RFD_OK;
-  RFD_HIP(hipEventRecord(p.marks.back().b, p.stream));
+  if (!p.timing) return RFD_OK;
+  for (auto it = p.marks.rbegin(); it != p.marks.rend(); ++it) {
+    if (!it->open) continue;
+    RFD_HIP(hipEventRecord(it->b, p.stream));
+    it->open = false;
+    break;
+  }
   return RFD_OK;
 }
 
@@ -100,7 +126,7 @@ static void plan_free(Plan& p) {
   for (auto& z : p.zband) dfree(z);
 }
 
-static int ensure_slots(Plan& p, int64_t n_slots) {
+int ensure_slots(Plan& p, int64_t n_slots) {
   if (p.ws_external) {
     if ((size_t)n_slots > p.slots_cap || (size_t)compaction_blocks(n_slots) + 1 > p.counts_cap)
       return fail(RFD_E_NOMEM, "workspace too small: the call needs " + std::to_string(n_slots) +
@@ -153,7 +179,7 @@ static int check_filter_args(const Plan& p, float threshold, int64_t W, const rf
   return RFD_OK;
 }
 
-static int finish_triggers(Plan& p, int64_t capacity, int64_t* n_out) {
+int finish_triggers(Plan& p, int64_t capacity, int64_t* n_out) {
   long long tot = 0;
   RFD_HIP(hipMemcpyAsync(&tot, p.total, sizeof(long long), hipMemcpyDeviceToHost, p.stream));
   RFD_HIP(hipStreamSynchronize(p.stream));
@@ -229,6 +255,11 @@ using namespace rfd;
 extern "C" {
 
 const char* rfd_last_error(void) { return rfd::g_err.c_str(); }
+
+int rfd_debug_fail_allocation(int64_t after) {
+  rfd::g_fail_after.store(after < 0 ? -1 : after);
+  return RFD_OK;
+}
 
 int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, int64_t seg_len, int32_t max_refs,
                     void* stream, rfd_plan** out) {
@@ -401,11 +432,12 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out) {
   memset(out, 0, sizeof(*out));
   double* ms[kNumStages] = {&out->data_fft_ms, &out->dechirp_ms, &out->fir_ms, &out->compact_ms,
                             &out->findchirp_ms, &out->taps_ms, &out->sur_net_ms, &out->sur_expand_ms,
-                            &out->sur_pack_ms, &out->match_ms};
+                            &out->sur_pack_ms, &out->match_ms, &out->fir_kernel_ms};
   int64_t* cnt[kNumStages] = {&out->n_data_fft, &out->n_dechirp, &out->n_fir, &out->n_compact,
                               &out->n_findchirp, &out->n_taps, &out->n_sur_net, &out->n_sur_expand,
-                              &out->n_sur_pack, &out->n_match};
+                              &out->n_sur_pack, &out->n_match, &out->n_fir_kernel};
   for (auto& m : p.marks) {
+    if (m.open) continue;                 // never closed (a failed call): no interval
     RFD_HIP(hipEventSynchronize(m.b));
     float t = 0.f;
     RFD_HIP(hipEventElapsedTime(&t, m.a, m.b));
@@ -425,12 +457,14 @@ int rfd_plan_set_fir_config(rfd_plan* plan, const rfd_fir_config* cfg) {
   if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 32) return fail(RFD_E_INVALID, "wg_per_cu must be in [0, 32]");
   if (!(cfg->ols_block == 0 || cfg->ols_block == 1024 || cfg->ols_block == 2048 || cfg->ols_block == 4096))
     return fail(RFD_E_INVALID, "ols_block must be 0, 1024, 2048 or 4096");
+  if (cfg->ols_aligned != 0 && cfg->ols_aligned != 1) return fail(RFD_E_INVALID, "ols_aligned must be 0 or 1");
   Plan& p = plan->p;
   p.fir_nb16 = cfg->col_blocks;
   p.fir_mode = cfg->mode;
   p.fir_smax = mt;
   p.fir_wg_per_cu = cfg->wg_per_cu;
   p.ols_block = cfg->ols_block;
+  p.ols_aligned = cfg->ols_aligned != 0;
   return RFD_OK;
 }
 
@@ -441,6 +475,16 @@ int rfd_plan_get_fir_config(const rfd_plan* plan, rfd_fir_config* cfg) {
   cfg->max_tiles = plan->p.fir_smax;
   cfg->wg_per_cu = plan->p.fir_wg_per_cu;
   cfg->ols_block = plan->p.ols_block;
+  cfg->ols_aligned = plan->p.ols_aligned ? 1 : 0;
+  return RFD_OK;
+}
+
+int rfd_ols_shape(const rfd_plan* plan, int32_t taps, int32_t* block, int32_t* outputs) {
+  if (!plan || !block || !outputs) return fail(RFD_E_INVALID, "NULL argument");
+  if (taps < 1 || taps > RFD_MAX_TAPS || taps >= 4096) return fail(RFD_E_INVALID, "taps out of range");
+  const OlsShape sh = ols_shape(plan->p, taps);
+  *block = sh.K;
+  *outputs = sh.L;
   return RFD_OK;
 }
 
@@ -494,24 +538,28 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
   const int nbs16[2] = {8, 16};
   const int tiles[3] = {4, 8, 16};
   if (precision == RFD_OLS32) {
-    // overlap-save: the block size (per sub-bank cost model, or one K for all)
+    // overlap-save: the block size (per sub-bank cost model, or one K for
+    // all), with and without aligned output lengths
     const int blocks[4] = {0, 1024, 2048, 4096};
     for (int ib = 0; ib < 4; ++ib) {
-      rfd_fir_config c = before;
-      c.ols_block = blocks[ib];
-      double ms = 0.0;
-      rc = measure(c, ms);
-      if (rc) { rfd_plan_set_fir_config(plan, &before); p.timing = saved_timing; return rc; }
-      ++n;
-      if (ms < best_ms) { best_ms = ms; best = c; }
+      for (int al = 0; al < 2; ++al) {
+        rfd_fir_config c = before;
+        c.ols_block = blocks[ib];
+        c.ols_aligned = al;
+        double ms = 0.0;
+        rc = measure(c, ms);
+        if (rc) { rfd_plan_set_fir_config(plan, &before); p.timing = saved_timing; return rc; }
+        ++n;
+        if (ms < best_ms) { best_ms = ms; best = c; }
+      }
     }
   }
   for (int ib = 0; ib < 2 && precision != RFD_OLS32; ++ib) {
     if (precision == RFD_FP32 && ib > 0) break;
     for (int it = 0; it < 3; ++it) {
-      const rfd_fir_config cands[3] = {{nbs16[ib], 1, tiles[it], 0, before.ols_block},
-                                       {nbs16[ib], 2, tiles[it], 0, before.ols_block},
-                                       {nbs16[ib], 2, tiles[it], 1, before.ols_block}};
+      const rfd_fir_config cands[3] = {{nbs16[ib], 1, tiles[it], 0, before.ols_block, before.ols_aligned},
+                                       {nbs16[ib], 2, tiles[it], 0, before.ols_block, before.ols_aligned},
+                                       {nbs16[ib], 2, tiles[it], 1, before.ols_block, before.ols_aligned}};
       for (const auto& c : cands) {
         double ms = 0.0;
         rc = measure(c, ms);

@@ -80,13 +80,26 @@ template <int K>
 struct BlockFft {
   static constexpr int NTf = K / 16;       // threads per FFT
   static constexpr int R = K / 256;        // last radix
+  static constexpr int G = 16 / R;         // last-stage groups per thread
   static constexpr int F = 256 / NTf;      // FFTs per workgroup
-  // row strides of the two exchanges ([k1][t] and [k2][k1][u]); padding by 4
-  // complex values (measured on MI355X: odd strides conflicted in the LDS
-  // banks, costing up to 1.8x at K = 4096)
-  static constexpr int S1 = NTf + 4;
-  static constexpr int S2 = R + 4;
-  static constexpr int LDS = (16 * S1 > 256 * S2 ? 16 * S1 : 256 * S2);   // float2 per FFT
+  // LDS layouts of the two exchanges, chosen so that no access of either
+  // exchange meets an LDS bank twice within a pass (a 64-bit access is
+  // serviced half a wave at a time):
+  //  exchange 1: element (k1, t) at k1 S1 + t, S1 = NTf + R.  A stage-B reader
+  //    takes elements u + R q of row k1 = t / R; the rows of one half-wave
+  //    start 2R banks apart, so their R-wide column groups tile the banks.
+  //  exchange 2: element (k2, k1, u) at (16 k2 + k1) R + k2 / G + u: rows of R
+  //    values, each group of G rows (one stage-C reader's rows) skewed by one
+  //    more element, so the readers, which take R consecutive values from
+  //    rows 16 (G g + e) + k1, start in distinct banks; every offset is a
+  //    compile-time constant past one per-thread base.
+  // (The earlier strides S1 = NTf + 4 and S2 = R + 4 left the stage-C reads
+  // 8-16-way conflicted: LDS bank-conflict cycles at 1.9x the busy cycles of
+  // the 4096-point overlap-save kernel.)
+  static constexpr int S1 = NTf + R;
+  static constexpr int X1 = 16 * S1;                 // float2 of exchange 1
+  static constexpr int X2 = 256 * R + R;             // float2 of exchange 2
+  static constexpr int LDS = X1 > X2 ? X1 : X2;      // float2 per FFT
 };
 
 // Per-thread twiddles: stage A  W_K^(t k1), stage B  W_K^(16 u k2), k = 1..15.
@@ -148,21 +161,22 @@ __device__ __forceinline__ void block_fft(float2 (&v)[16], float2* buf, int t, c
   dft16<SIGN>(v);
   {
     const int k1 = t / R, u = t % R;
+    float2* row = buf + k1 * R + u;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k2 = dft16_freq(s);
-      buf[(k2 * 16 + k1) * S::S2 + u] = k2 ? cmul(v[s], w.b[k2]) : v[s];
+      row[k2 * 16 * R + k2 / S::G] = k2 ? cmul(v[s], w.b[k2]) : v[s];
     }
   }
   block_fft_sync<NTf>();
-  // stage C: thread (k1, g) = (t / R, t % R) takes k2 = g (16/R) + e, radix R over u
+  // stage C: thread (k1, g) = (t / R, t % R) takes k2 = g G + e, radix R over u
   {
     const int k1 = t / R, g = t % R;
+    const float2* row = buf + (g * S::G * 16 + k1) * R + g;
 #pragma unroll
-    for (int e = 0; e < 16 / R; ++e) {
-      const int k2 = g * (16 / R) + e;
+    for (int e = 0; e < S::G; ++e) {
 #pragma unroll
-      for (int u = 0; u < R; ++u) v[e * R + u] = buf[(k2 * 16 + k1) * S::S2 + u];
+      for (int u = 0; u < R; ++u) v[e * R + u] = row[e * 16 * R + u];
     }
   }
   block_fft_sync<NTf>();

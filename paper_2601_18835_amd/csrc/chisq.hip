@@ -168,7 +168,7 @@ __global__ __launch_bounds__(64) void k_chisq(const rfd_trigger* __restrict__ tr
 template <typename T>
 static int calloc_dev(T** p, size_t n) {
   *p = nullptr;
-  if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+  if (device_malloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
     return fail(RFD_E_NOMEM, "chi^2: hipMalloc failed");

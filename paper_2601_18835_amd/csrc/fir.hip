@@ -437,6 +437,8 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
   a.m_off = n_start;
   dim3 grid((unsigned)(n_len / ((int64_t)a.S * cols)), (unsigned)((s.count + kTmplTile - 1) / kTmplTile));
   const int Lw = a.S * cols + s.Tp;
+  int rc = stage_begin(p, kStFirKernel);
+  if (rc) return rc;
   if (precision == RFD_FP32) {
     hipLaunchKernelGGL(k_fir32<16>, grid, dim3(256), (size_t)Lw * sizeof(float2), p.stream, a);
   } else {
@@ -451,7 +453,7 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
     }
   }
   RFD_CHECK_LAUNCH();
-  return RFD_OK;
+  return stage_end(p);
 }
 
 }  // namespace rfd
@@ -497,7 +499,7 @@ int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W) {
   }
   auto up = [&](auto*& dst, const auto& src, size_t n) -> int {
     if (dst) { (void)hipFree(dst); dst = nullptr; }
-    if (hipMalloc((void**)&dst, std::max<size_t>(n, 1) * sizeof(src[0])) != hipSuccess)
+    if (device_malloc((void**)&dst, std::max<size_t>(n, 1) * sizeof(src[0])) != hipSuccess)
       return fail(RFD_E_NOMEM, "work-item table allocation failed");
     if (n && hipMemcpy(dst, src.data(), n * sizeof(src[0]), hipMemcpyHostToDevice) != hipSuccess)
       return fail(RFD_E_DEVICE, "work-item table upload failed");
@@ -568,6 +570,8 @@ int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int
     return fail(RFD_E_STATE, "persistent FIR work items were prepared for another configuration");
   const size_t lds = tp.it_lds;
   const dim3 grid(tp.it_grid);
+  int rc = stage_begin(p, kStFirKernel);
+  if (rc) return rc;
   if (precision == RFD_FP32) {
     hipLaunchKernelGGL(k_fir32_persistent<16>, grid, dim3(256), lds, p.stream, pa);
   } else if (p.fir_nb16 == 16) {
@@ -578,7 +582,7 @@ int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int
     else hipLaunchKernelGGL((k_fir16_persistent<true, 8>), grid, dim3(256), lds, p.stream, pa);
   }
   RFD_CHECK_LAUNCH();
-  return RFD_OK;
+  return stage_end(p);
 }
 
 }  // namespace rfd

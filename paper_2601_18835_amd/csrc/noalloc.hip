@@ -117,9 +117,9 @@ extern "C" int rfd_filter_bank_noalloc(rfd_plan* plan, const rfd_taps* taps, int
   if (precision == RFD_OLS32) {
     for (const SubBankTaps& s : t.sb) {
       if (s.count == 0) continue;
-      const int K = ols_block_size(p, s.T);
-      const int64_t nB = (p.n + (K - s.T + 1) - 1) / (K - s.T + 1);
-      x_elems = std::max(x_elems, (size_t)nB * K);
+      const OlsShape sh = ols_shape(p, s.T);
+      const int64_t nB = (p.n + sh.L - 1) / sh.L;
+      x_elems = std::max(x_elems, (size_t)nB * sh.K);
     }
   }
   const size_t off_counts = 256;

@@ -108,7 +108,17 @@ __device__ __forceinline__ unsigned long long ols_reduce(unsigned long long k) {
   return k;
 }
 
-template <int K>
+// Slot (e, s) of a thread after block_fft is kept when NF == 0 (any L), or
+// when its output group dftr_freq(s) < NF: with L = 256 NF every output of
+// the block at index < L lies in groups 0..NF-1 (index = k1 + 16 k2 + 256
+// group, k1 + 16 k2 < 256), so the discarded groups are never read and the
+// compiler drops the last DFT stage's work for them.
+template <int K, int NF>
+__device__ __forceinline__ constexpr bool ols_slot_kept(int s) {
+  return NF == 0 || dftr_freq<BlockFft<K>::R>(s) < NF;
+}
+
+template <int K, int NF>
 __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
   using S = BlockFft<K>;
   __shared__ float2 lds[S::F * S::LDS];
@@ -126,6 +136,8 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
   const int64_t nbeg = std::max<int64_t>(n0, a.n_lo);
   const int64_t nend = std::min<int64_t>(std::min<int64_t>(n0 + a.L, a.n), a.n_hi);
   const bool has_out = bvalid && nend > nbeg;
+  // every kept slot is an output of the launch: no per-sample range test
+  const bool whole = NF > 0 && has_out && nbeg == n0 && nend == n0 + a.L;
   const int64_t q0 = has_out ? nbeg / a.W : 0, q1 = has_out ? (nend - 1) / a.W : 0;
   const int64_t j0 = (int64_t)blockIdx.y * a.J;
   const int64_t j1 = std::min<int64_t>(j0 + a.J, a.count);
@@ -144,16 +156,30 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
     // correlation wraps, taps that cancel only against the series' own
     // correlations lose that cancellation and would cross the threshold.
     uint32_t r2max = 0u;
+    if (whole) {
 #pragma unroll
-    for (int e = 0; e < 16 / S::R; ++e)
+      for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
-      for (int s = 0; s < S::R; ++s) {
-        const float2 y = v[e * S::R + s];
-        const float x = y.x * y.x + y.y * y.y;
-        r2[e * S::R + s] = x;
-        const int64_t nn = n0 + block_fft_out<K>(t, e, s);
-        if (nn >= nbeg && nn < nend) r2max = max(r2max, __float_as_uint(x));
-      }
+        for (int s = 0; s < S::R; ++s) {
+          if (!ols_slot_kept<K, NF>(s)) continue;
+          const float2 y = v[e * S::R + s];
+          const float x = y.x * y.x + y.y * y.y;
+          r2[e * S::R + s] = x;
+          r2max = max(r2max, __float_as_uint(x));
+        }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16 / S::R; ++e)
+#pragma unroll
+        for (int s = 0; s < S::R; ++s) {
+          if (!ols_slot_kept<K, NF>(s)) continue;
+          const float2 y = v[e * S::R + s];
+          const float x = y.x * y.x + y.y * y.y;
+          r2[e * S::R + s] = x;
+          const int64_t nn = n0 + block_fft_out<K>(t, e, s);
+          if (nn >= nbeg && nn < nend) r2max = max(r2max, __float_as_uint(x));
+        }
+    }
     // the compaction reports a window only if its peak exceeds thr2: a wave
     // with no sample above it cannot contribute a reported peak
     if (!__any(r2max > __float_as_uint(a.thr2))) continue;
@@ -167,6 +193,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
         for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
           for (int s = 0; s < S::R; ++s) {
+            if (!ols_slot_kept<K, NF>(s)) continue;
             const int64_t nn = n0 + block_fft_out<K>(t, e, s);
             if (nn >= ws && nn < we) k = umax64_ols(k, offset_key_ols(r2[e * S::R + s], (uint32_t)(nn - wq)));
           }
@@ -179,6 +206,7 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
       for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
         for (int s = 0; s < S::R; ++s) {
+          if (!ols_slot_kept<K, NF>(s)) continue;
           const int64_t nn = n0 + block_fft_out<K>(t, e, s);
           if (nn >= nbeg && nn < nend) {
             const int64_t q = nn / a.W;
@@ -194,21 +222,47 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
 // K = 2048 (MI355X: one-wave FFTs without workgroup barriers at 1024, a
 // whole-workgroup FFT at 4096).
 static double ols_efficiency(int K) { return K == 1024 ? 1.25 : (K == 2048 ? 1.0 : 0.97); }
+// ... and the gain of an aligned output length (L = 256 NF: the discarded
+// outputs are never computed, interior blocks skip per-sample range tests)
+constexpr double kOlsAlignedGain = 1.10;
 
-int ols_block_size(const Plan& p, int T) {
-  if (p.ols_block > T) return p.ols_block;
-  int best = 4096;
+// aligned output groups the kernels are built for, per block size
+static bool ols_nf_built(int K, int nf) {
+  switch (K) {
+    case 1024: return nf == 3;
+    case 2048: return nf == 6 || nf == 7;
+    case 4096: return nf >= 12 && nf <= 15;
+    default: return false;
+  }
+}
+
+OlsShape ols_shape(const Plan& p, int T) {
+  OlsShape best{4096, 4096 - T + 1, 0};
   double best_cost = 1e30;
   for (int K = 1024; K <= 4096; K *= 2) {
     if (K <= T) continue;
-    const double cost = (5.0 * std::log2((double)K) + 6.0) * K / (double)(K - T + 1) / ols_efficiency(K);
-    if (cost < best_cost - 1e-9) {
-      best_cost = cost;
-      best = K;
+    if (p.ols_block > T && K != p.ols_block) continue;
+    const int L0 = K - T + 1;
+    const double flops = 5.0 * std::log2((double)K) + 6.0;
+    // the general form keeps every valid output, the aligned form whole groups of 256
+    const double cost0 = flops * K / (double)L0 / ols_efficiency(K);
+    if (cost0 < best_cost - 1e-9) {
+      best_cost = cost0;
+      best = OlsShape{K, L0, 0};
+    }
+    const int nf = L0 / 256;
+    if (p.ols_aligned && nf > 0 && ols_nf_built(K, nf)) {
+      const double cost1 = flops * K / (double)(256 * nf) / (ols_efficiency(K) * kOlsAlignedGain);
+      if (cost1 < best_cost - 1e-9) {
+        best_cost = cost1;
+        best = OlsShape{K, 256 * nf, nf};
+      }
     }
   }
   return best;
 }
+
+int ols_block_size(const Plan& p, int T) { return ols_shape(p, T).K; }
 
 static int ols_templates_per_wg(int64_t nB, int F, int64_t count, int n_cu) {
   // enough workgroups to fill the chip several times, at least 4 templates each
@@ -222,8 +276,8 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
   for (size_t bi = 0; bi < t.sb.size(); ++bi) {
     SubBankTaps& s = t.sb[bi];
     if (s.count == 0) continue;
-    const int K = ols_block_size(p, s.T);
-    const int L = K - s.T + 1;
+    const OlsShape sh = ols_shape(p, s.T);
+    const int K = sh.K, L = sh.L;
     const int64_t nB = (p.n + L - 1) / L;
     const bool need_x = need_block_spectra && (s.ols_x == nullptr || s.ols_x_cap < nB * K);
     const bool need_g = s.ols_g == nullptr || s.ols_K != K;
@@ -234,7 +288,7 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
       RFD_HIP(hipStreamSynchronize(p.stream));
       if (s.ols_x) (void)hipFree(s.ols_x);
       s.ols_x = nullptr;
-      if (hipMalloc((void**)&s.ols_x, (size_t)nB * K * sizeof(float2)) != hipSuccess) {
+      if (device_malloc((void**)&s.ols_x, (size_t)nB * K * sizeof(float2)) != hipSuccess) {
         s.ols_x = nullptr;
         (void)hipGetLastError();
         return fail(RFD_E_NOMEM, "overlap-save block spectra: hipMalloc failed");
@@ -245,7 +299,7 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
       RFD_HIP(hipStreamSynchronize(p.stream));
       if (s.ols_g) (void)hipFree(s.ols_g);
       s.ols_g = nullptr;
-      if (hipMalloc((void**)&s.ols_g, (size_t)s.count * K * sizeof(float2)) != hipSuccess) {
+      if (device_malloc((void**)&s.ols_g, (size_t)s.count * K * sizeof(float2)) != hipSuccess) {
         s.ols_g = nullptr;
         (void)hipGetLastError();
         return fail(RFD_E_NOMEM, "overlap-save tap spectra: hipMalloc failed");
@@ -254,6 +308,7 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
     }
     s.ols_K = K;
     s.ols_L = L;
+    s.ols_nf = sh.nf;
     s.ols_nB = nB;
     if (!s.ols_valid) {
       hipLaunchKernelGGL(k_ols_g, dim3((unsigned)s.count), dim3(256), (size_t)s.T * sizeof(double2), p.stream,
@@ -265,7 +320,7 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
   return RFD_OK;
 }
 
-template <int K>
+template <int K, int NF>
 static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, float threshold,
                         int64_t n_lo, int64_t n_hi, float2* X) {
   using S = BlockFft<K>;
@@ -294,9 +349,11 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
   a.J = ols_templates_per_wg(nB, S::F, s.count, p.n_cu);
   a.thr2 = threshold * threshold;
   const unsigned gy = (unsigned)((s.count + a.J - 1) / a.J);
-  hipLaunchKernelGGL(k_ols<K>, dim3(gx, gy), dim3(256), 0, p.stream, a);
+  int rc = stage_begin(p, kStFirKernel);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_ols<K, NF>), dim3(gx, gy), dim3(256), 0, p.stream, a);
   RFD_CHECK_LAUNCH();
-  return RFD_OK;
+  return stage_end(p);
 }
 
 int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo, int64_t n_hi,
@@ -308,10 +365,13 @@ int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold,
     float2* X = x_scratch ? x_scratch : s.ols_x;
     if (!s.ols_valid || !X) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
     int rc;
-    switch (s.ols_K) {
-      case 1024: rc = launch_ols_k<1024>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
-      case 2048: rc = launch_ols_k<2048>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
-      case 4096: rc = launch_ols_k<4096>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
+    switch (s.ols_K * 16 + s.ols_nf) {
+#define OLS_CASE(KK, NN) \
+      case KK * 16 + NN: rc = launch_ols_k<KK, NN>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
+      OLS_CASE(1024, 0) OLS_CASE(1024, 3)
+      OLS_CASE(2048, 0) OLS_CASE(2048, 6) OLS_CASE(2048, 7)
+      OLS_CASE(4096, 0) OLS_CASE(4096, 12) OLS_CASE(4096, 13) OLS_CASE(4096, 14) OLS_CASE(4096, 15)
+#undef OLS_CASE
       default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
     }
     if (rc) return rc;

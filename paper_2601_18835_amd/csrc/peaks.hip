@@ -78,8 +78,8 @@ int rfd_measure_peaks(void* stream, double* out) {
   void* res = nullptr;
   void* a = nullptr;
   void* b = nullptr;
-  if (hipMalloc(&res, (size_t)blocks * 256 * sizeof(double)) != hipSuccess ||
-      hipMalloc(&a, copy_bytes) != hipSuccess || hipMalloc(&b, copy_bytes) != hipSuccess) {
+  if (device_malloc((void**)&res, (size_t)blocks * 256 * sizeof(double)) != hipSuccess ||
+      device_malloc((void**)&a, copy_bytes) != hipSuccess || device_malloc((void**)&b, copy_bytes) != hipSuccess) {
     (void)hipGetLastError();
     if (res) (void)hipFree(res);
     if (a) (void)hipFree(a);

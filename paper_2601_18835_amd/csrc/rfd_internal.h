@@ -22,6 +22,9 @@ int fail(int code, const std::string& msg);
       return ::rfd::fail(RFD_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 #define RFD_CHECK_LAUNCH() RFD_HIP(hipGetLastError())
+// every device allocation of the library goes through here (hipMalloc, or an
+// injected failure requested with rfd_debug_fail_allocation)
+hipError_t device_malloc(void** ptr, size_t bytes);
 
 constexpr int kFineBits = 10;                 // twiddle factorisation p = (c << 10) | f
 constexpr int kFine = 1 << kFineBits;
@@ -88,6 +91,7 @@ struct Plan {
   // overlap-save FIR: block size (0: per sub-bank by cost model) and
   // exp(+2 pi i m / 4096), m < 4096, in FP32 and FP64
   int ols_block = 0;
+  bool ols_aligned = true;     // allow aligned output lengths (L = 256 nf)
   float2* ols_tw32 = nullptr;
   double2* ols_tw64 = nullptr;
   // chi^2 band series per reference slot: [n_bands][n] FP32, the band edges
@@ -99,16 +103,18 @@ struct Plan {
 
   // optional stage timing (hipEvent pairs on `stream`)
   bool timing = false;
-  struct Mark { int stage; hipEvent_t a, b; };
+  struct Mark { int stage; hipEvent_t a, b; bool open; };
   std::vector<Mark> marks;
 };
 
 enum Stage {
   kStDataFft = 0, kStDechirp, kStFir, kStCompact, kStFindchirp, kStTaps, kStSurNet, kStSurExpand, kStSurPack,
-  kStMatch,
+  kStMatch, kStFirKernel,
   kNumStages
 };
-// Record the start / stop of a stage when timing is enabled.
+// Record the start / stop of a stage when timing is enabled.  Stages nest:
+// stage_end closes the innermost open one (kStFirKernel marks each main FIR
+// kernel launch inside kStFir).
 int stage_begin(Plan& p, int stage);
 int stage_end(Plan& p);
 
@@ -127,7 +133,7 @@ struct SubBankTaps {
   std::vector<uint8_t> made_mask;
   // overlap-save FIR state: block spectra of the series (rebuilt every
   // filter call), tap spectra (rebuilt after the taps change)
-  int ols_K = 0, ols_L = 0;
+  int ols_K = 0, ols_L = 0, ols_nf = 0;   // ols_nf > 0: L = 256 ols_nf (aligned output groups)
   int64_t ols_nB = 0, ols_x_cap = 0;
   float2* ols_x = nullptr;
   float2* ols_g = nullptr;
@@ -203,6 +209,10 @@ int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W);
 int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int64_t nwin, float threshold);
 
 // ----------------------------------------------------- launchers (ols.hip)
+// overlap-save block shape for T taps: block size K, outputs kept per block
+// L (K - T + 1, or 256 nf when the aligned form is cheaper), nf (0: general)
+struct OlsShape { int K, L, nf; };
+OlsShape ols_shape(const Plan& p, int T);
 int ols_block_size(const Plan& p, int T);
 // allocate block / tap spectra (only if allow_alloc; else RFD_E_STATE when one
 // is missing) and rebuild stale tap spectra in place (not inside capture);
@@ -215,6 +225,14 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc = true, bool need_block_spectr
 // values, used for every sub-bank in turn instead of the sub-bank's own
 int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo = 0,
                int64_t n_hi = -1, float2* x_scratch = nullptr);
+
+// ------------------------------------------------------ helpers (api.hip)
+// window-peak slots and compaction counts for n_slots slots (grown on demand,
+// or checked against caller-owned workspace)
+int ensure_slots(Plan& p, int64_t n_slots);
+// reads the trigger total back (synchronises) into *n_out; RFD_E_OVERFLOW
+// when it exceeds capacity
+int finish_triggers(Plan& p, int64_t capacity, int64_t* n_out);
 
 // ------------------------------------------------ launchers (triggers.hip)
 int launch_slots_clear(Plan& p, int64_t n_slots);

@@ -78,8 +78,8 @@ int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, i
   Plan& p = plan->p;
   double* norm2 = nullptr;
   double* m = nullptr;
-  if (hipMalloc((void**)&norm2, count * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&m, count * sizeof(double)) != hipSuccess) {
+  if (device_malloc((void**)&norm2, count * sizeof(double)) != hipSuccess ||
+      device_malloc((void**)&m, count * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     if (norm2) (void)hipFree(norm2);
     return fail(RFD_E_NOMEM, "tap selection: hipMalloc failed");

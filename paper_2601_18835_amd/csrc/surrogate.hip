@@ -583,12 +583,14 @@ struct Surrogate {
   bool basis_ready = false;            // basis, targets and Weff exist
   int64_t* tstate = nullptr;           // training step state (k_train_state_*)
   bool graphs = true;                  // training replays one captured epoch per epoch
+  double* frange = nullptr;            // feature range lo[4], hi[4] (rfd_surrogate_set_feature_range)
+  bool frange_set = false;
 };
 
 template <typename T>
 static int salloc(T** p, size_t n) {
   *p = nullptr;
-  if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+  if (device_malloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
     return fail(RFD_E_NOMEM, "surrogate: hipMalloc failed");
@@ -605,6 +607,69 @@ static void sur_free(Surrogate& s) {
   sfree(s.X); sfree(s.Weff); sfree(s.Bt); sfree(s.C); sfree(s.Q2); sfree(s.w); sfree(s.g); sfree(s.m); sfree(s.v); sfree(s.wbf);
   sfree(s.Pb); sfree(s.Cb); sfree(s.Z1); sfree(s.H1); sfree(s.Z2); sfree(s.H2); sfree(s.Y); sfree(s.dY);
   sfree(s.dA); sfree(s.dB); sfree(s.idx); sfree(s.partial); sfree(s.epart); sfree(s.loss); sfree(s.tstate);
+  sfree(s.frange);
+}
+
+// Network inputs from physical parameters (m1, m2, chi, e0): chirp mass
+// M eta^(3/5), symmetric mass ratio eta = m1 m2 / M^2, chi and e0 (the same
+// four degrees of freedom in the coordinates the phase depends on most),
+// each mapped linearly onto [-1, 1] over the training set's range.
+__device__ __forceinline__ void phys_features(const double* q, double f[4]) {
+  const double m1 = q[0], m2 = q[1], mt = m1 + m2;
+  const double eta = m1 * m2 / (mt * mt);
+  f[0] = mt * pow(eta, 0.6);
+  f[1] = eta;
+  f[2] = q[2];
+  f[3] = q[3];
+}
+
+// range[0..3] = min, range[4..7] = max of each feature over n rows (one workgroup)
+__global__ __launch_bounds__(256) void k_feature_range(const double* __restrict__ phys, int64_t n,
+                                                     double* __restrict__ range) {
+  __shared__ double lo[4][256], hi[4][256];
+  double l[4], h[4];
+  for (int c = 0; c < 4; ++c) {
+    l[c] = INFINITY;
+    h[c] = -INFINITY;
+  }
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    double f[4];
+    phys_features(phys + 4 * i, f);
+    for (int c = 0; c < 4; ++c) {
+      l[c] = fmin(l[c], f[c]);
+      h[c] = fmax(h[c], f[c]);
+    }
+  }
+  for (int c = 0; c < 4; ++c) {
+    lo[c][threadIdx.x] = l[c];
+    hi[c][threadIdx.x] = h[c];
+  }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 4; ++c) {
+        lo[c][threadIdx.x] = fmin(lo[c][threadIdx.x], lo[c][threadIdx.x + o]);
+        hi[c][threadIdx.x] = fmax(hi[c][threadIdx.x], hi[c][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) {
+    range[threadIdx.x] = lo[threadIdx.x][0];
+    range[4 + threadIdx.x] = hi[threadIdx.x][0];
+  }
+}
+
+// scaled features 2 (f - lo) / (hi - lo) - 1 (a constant feature maps to -1)
+__global__ __launch_bounds__(256) void k_features(const double* __restrict__ phys, int64_t n,
+                                                const double* __restrict__ range, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double f[4];
+  phys_features(phys + 4 * i, f);
+  for (int c = 0; c < 4; ++c) {
+    const double lo = range[c], span = range[4 + c] - lo;
+    out[4 * i + c] = (float)(2.0 * (f[c] - lo) / (span > 0.0 ? span : 1.0) - 1.0);
+  }
 }
 
 // dynamic LDS a launch may request on the current device
@@ -752,6 +817,7 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
   TRY(salloc(&s.partial, 256));
   TRY(salloc(&s.epart, (size_t)s.nb * ((s.T + 255) / 256) * 2));
   TRY(salloc(&s.loss, 1));
+  TRY(salloc(&s.frange, 8));
   TRY(salloc(&s.tstate, 2));
 #undef TRY
   // He-uniform initial weights, zero biases (host, seeded)
@@ -908,6 +974,30 @@ int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs,
   if (exec) (void)hipGraphExecDestroy(exec);
   sfree(dperm);
   return rc;
+}
+
+int rfd_surrogate_set_feature_range(rfd_surrogate* sur, const double* phys, int64_t n) {
+  if (!sur || !phys) return fail(RFD_E_INVALID, "NULL argument");
+  if (n < 1) return fail(RFD_E_INVALID, "n must be >= 1");
+  Surrogate& s = sur->s;
+  hipStream_t st = s.plan->stream;
+  hipLaunchKernelGGL(k_feature_range, dim3(1), dim3(256), 0, st, phys, n, s.frange);
+  RFD_CHECK_LAUNCH();
+  RFD_HIP(hipStreamSynchronize(st));
+  s.frange_set = true;
+  return RFD_OK;
+}
+
+int rfd_surrogate_features(rfd_surrogate* sur, const double* phys, int64_t n, float* out) {
+  if (!sur || !phys || !out) return fail(RFD_E_INVALID, "NULL argument");
+  if (n < 0) return fail(RFD_E_INVALID, "n must be >= 0");
+  Surrogate& s = sur->s;
+  if (!s.frange_set) return fail(RFD_E_STATE, "feature range not set (rfd_surrogate_set_feature_range)");
+  if (n == 0) return RFD_OK;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s.plan->stream, phys, n,
+                     (const double*)s.frange, out);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
 }
 
 int rfd_surrogate_set_graphs(rfd_surrogate* sur, int32_t enable) {

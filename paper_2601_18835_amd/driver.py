@@ -103,17 +103,6 @@ class RatioFilterSearch:
             pass
 
 
-def surrogate_features(params):
-    """(m1, m2, chi, e0) [n, 4] -> (chirp mass, symmetric mass ratio, chi, e0):
-    the same four degrees of freedom in the coordinates the phase depends on
-    most directly."""
-    p = np.asarray(params, dtype=np.float64).reshape(-1, 4)
-    m1, m2 = p[:, 0], p[:, 1]
-    mt = m1 + m2
-    eta = m1 * m2 / mt ** 2
-    return np.stack([mt * eta ** 0.6, eta, p[:, 2], p[:, 3]], axis=1)
-
-
 class TapSurrogate:
     """A learned tap generator for one (reference, T, k0) of a plan.
 
@@ -133,7 +122,6 @@ class TapSurrogate:
         self.n_basis, self.hidden, self.seed = n_basis, hidden, seed
         self.train_taps = rfd.rfd_taps_create(search.plan, np.array([0, n_train], np.int64), [ref_id], [T], [k0])
         self.sur = None
-        self.lo = self.hi = None
         self.params_dev = None
 
     def add_training_waveforms(self, h_tmpl, first, ridge_eps=1e-4):
@@ -142,18 +130,26 @@ class TapSurrogate:
         rfd.rfd_make_taps(self.search.plan, self.train_taps, 0, self.search.h_ref[self.ref_id], ht, first,
                           rfd.RFD_TAPS_LS, ridge_eps)
 
+    def _phys_dev(self, params):
+        if isinstance(params, self.torch.Tensor):
+            return params.to(device="cuda", dtype=self.torch.float64).reshape(-1, 4).contiguous()
+        return self.search.to_dev(np.asarray(params, np.float64).reshape(-1, 4))
+
+    def scale_dev(self, params):
+        """Network inputs (dev float32 [n, 4]) of physical (m1, m2, chi, e0), by librfd."""
+        return rfd.rfd_surrogate_features(self.sur, self._phys_dev(params))
+
     def scale(self, params):
-        f = surrogate_features(params)
-        span = np.where(self.hi > self.lo, self.hi - self.lo, 1.0)
-        return (2.0 * (f - self.lo) / span - 1.0).astype(np.float32)
+        return self.scale_dev(params).cpu().numpy()
 
     def fit(self, train_params, basis_iters=20):
-        """Whiten the training taps and fit the basis; returns the captured fraction."""
-        f = surrogate_features(train_params)
-        self.lo, self.hi = f.min(axis=0), f.max(axis=0)
-        self.params_dev = self.search.to_dev(self.scale(train_params))
+        """Input range from the training parameters, whitened training taps and
+        the basis; returns the captured fraction."""
         self.sur = rfd.rfd_surrogate_create(self.search.plan, self.train_taps, 0, self.n_basis, self.hidden,
                                             self.seed)
+        phys = self._phys_dev(train_params)
+        rfd.rfd_surrogate_set_feature_range(self.sur, phys)
+        self.params_dev = rfd.rfd_surrogate_features(self.sur, phys)
         return rfd.rfd_surrogate_fit_basis(self.sur, basis_iters)
 
     def train(self, epochs, batch=256, lr=2e-3, lr_end=2e-5, stages=10, progress=None):
@@ -174,8 +170,7 @@ class TapSurrogate:
         return np.concatenate(losses)
 
     def make_taps(self, target_taps, subbank, params, first=0):
-        p = self.search.to_dev(self.scale(params))
-        rfd.rfd_surrogate_make_taps(self.sur, p, target_taps, subbank, first)
+        rfd.rfd_surrogate_make_taps(self.sur, self.scale_dev(params), target_taps, subbank, first)
 
     def close(self):
         if self.sur is not None:

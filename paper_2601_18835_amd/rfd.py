@@ -41,12 +41,13 @@ class rfd_timing(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms", "findchirp_ms",
                                           "taps_ms", "sur_net_ms", "sur_expand_ms", "sur_pack_ms", "match_ms")] + \
                [(k, C.c_int64) for k in ("n_data_fft", "n_dechirp", "n_fir", "n_compact", "n_findchirp", "n_taps",
-                                         "n_sur_net", "n_sur_expand", "n_sur_pack", "n_match")]
+                                         "n_sur_net", "n_sur_expand", "n_sur_pack", "n_match")] + \
+               [("fir_kernel_ms", C.c_double), ("n_fir_kernel", C.c_int64)]
 
 
 class rfd_fir_config(C.Structure):
     _fields_ = [("col_blocks", C.c_int32), ("mode", C.c_int32), ("max_tiles", C.c_int32), ("wg_per_cu", C.c_int32),
-                ("ols_block", C.c_int32)]
+                ("ols_block", C.c_int32), ("ols_aligned", C.c_int32)]
 
 
 class rfd_tune_result(C.Structure):
@@ -101,6 +102,15 @@ _SIGS = {
     "rfd_taps_destroy": [_P],
     "rfd_filter_bank": [_P, _P, _i32, _f, _i64, _P, _i64, C.POINTER(_i64)],
     "rfd_filter_bank_noalloc": [_P, _P, _i32, _f, _i64, _P, _i64, C.POINTER(_i64)],
+    "rfd_stream_create": [_P, _P, _i32, _P, _P, _i64, C.POINTER(_P)],
+    "rfd_stream_prime": [_P, _P],
+    "rfd_stream_push": [_P, _P, _i32, _f, _i64, _P, _i64, C.POINTER(_i64), C.POINTER(_i64)],
+    "rfd_stream_info": [_P, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)],
+    "rfd_stream_destroy": [_P],
+    "rfd_debug_fail_allocation": [_i64],
+    "rfd_ols_shape": [_P, _i32, C.POINTER(_i32), C.POINTER(_i32)],
+    "rfd_surrogate_set_feature_range": [_P, _P, _i64],
+    "rfd_surrogate_features": [_P, _P, _i64, _P],
     "rfd_findchirp_prepare": [_P, _P, _i64, _P, _P],
     "findchirp_filter": [_P, _P, _P, _i64, _f, _i64, _P, _i64, C.POINTER(_i64)],
 }
@@ -190,8 +200,8 @@ def _cfg_dict(c):
     return {k: getattr(c, k) for k, _ in rfd_fir_config._fields_}
 
 
-def rfd_plan_set_fir_config(plan, col_blocks=8, mode=0, max_tiles=16, wg_per_cu=0, ols_block=0):
-    c = rfd_fir_config(col_blocks, mode, max_tiles, wg_per_cu, ols_block)
+def rfd_plan_set_fir_config(plan, col_blocks=8, mode=0, max_tiles=16, wg_per_cu=0, ols_block=0, ols_aligned=1):
+    c = rfd_fir_config(col_blocks, mode, max_tiles, wg_per_cu, ols_block, ols_aligned)
     _check(_lib.rfd_plan_set_fir_config(plan, C.byref(c)), "rfd_plan_set_fir_config")
 
 
@@ -199,6 +209,13 @@ def rfd_plan_get_fir_config(plan):
     c = rfd_fir_config()
     _check(_lib.rfd_plan_get_fir_config(plan, C.byref(c)), "rfd_plan_get_fir_config")
     return _cfg_dict(c)
+
+
+def rfd_ols_shape(plan, taps):
+    """(K, L): overlap-save block size and outputs kept per block for `taps` taps."""
+    k, l = C.c_int32(0), C.c_int32(0)
+    _check(_lib.rfd_ols_shape(plan, taps, C.byref(k), C.byref(l)), "rfd_ols_shape")
+    return k.value, l.value
 
 
 def rfd_autotune_fir(plan, taps, precision, cluster_window, reps=3):
@@ -394,6 +411,50 @@ def rfd_filter_bank_noalloc(plan, taps, precision, threshold, cluster_window, ca
     return out, n.value
 
 
+def rfd_debug_fail_allocation(after):
+    """The allocation after `after` further successful ones fails once (-1: off)."""
+    _check(_lib.rfd_debug_fail_allocation(after), "rfd_debug_fail_allocation")
+
+
+# ---------------------------------------------------------------- stream
+def rfd_stream_create(plan, taps, refs, increment):
+    """refs: {ref_id: dev complex128 tensor [N/2+1]}."""
+    ids = sorted(refs)
+    id_arr = (C.c_int32 * len(ids))(*ids)
+    ptr_arr = (C.c_void_p * len(ids))(*[_ptr(refs[r]) for r in ids])
+    h = C.c_void_p()
+    _check(_lib.rfd_stream_create(plan, taps, len(ids), id_arr, ptr_arr, increment, C.byref(h)), "rfd_stream_create")
+    return h
+
+
+def rfd_stream_prime(stream, data):
+    _check(_lib.rfd_stream_prime(stream, _ptr(data)), "rfd_stream_prime")
+
+
+def rfd_stream_push(stream, data, precision, threshold, cluster_window, capacity, out=None, raise_overflow=True):
+    """Returns (trigger buffer, n, first output position)."""
+    prec = PRECISIONS.get(precision, precision)
+    if out is None:
+        out = _trigger_buffer(capacity)
+    n, start = C.c_int64(0), C.c_int64(0)
+    rc = _lib.rfd_stream_push(stream, _ptr(data), prec, threshold, cluster_window, _ptr(out), capacity, C.byref(n),
+                              C.byref(start))
+    if rc == RFD_E_OVERFLOW and not raise_overflow:
+        return out, n.value, start.value
+    _check(rc, "rfd_stream_push")
+    return out, n.value, start.value
+
+
+def rfd_stream_info(stream):
+    head, lag, zlen = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    _check(_lib.rfd_stream_info(stream, C.byref(head), C.byref(lag), C.byref(zlen)), "rfd_stream_info")
+    return {"head": head.value, "lag": lag.value, "zlen": zlen.value}
+
+
+def rfd_stream_destroy(stream):
+    _check(_lib.rfd_stream_destroy(stream), "rfd_stream_destroy")
+
+
 def rfd_findchirp_prepare(plan, h_tmpl, filt=None, sigma=None):
     """FINDCHIRP filters of h_tmpl [count, N/2+1] into filt [count, n_band] (complex64)."""
     import torch
@@ -467,6 +528,23 @@ def rfd_surrogate_set_state(sur, weights=None, basis=None):
     b = None if basis is None else np.ascontiguousarray(basis, dtype=np.float32)
     _check(_lib.rfd_surrogate_set_state(sur, None if w is None else w.ctypes.data,
                                         None if b is None else b.ctypes.data), "rfd_surrogate_set_state")
+
+
+def rfd_surrogate_set_feature_range(sur, phys):
+    """phys: dev float64 tensor [n, 4] (m1, m2, chi, e0) of the training set."""
+    import torch
+    _dev_check(phys, torch.float64, None, "phys")
+    _check(_lib.rfd_surrogate_set_feature_range(sur, _ptr(phys), phys.shape[0]), "rfd_surrogate_set_feature_range")
+
+
+def rfd_surrogate_features(sur, phys, out=None):
+    """Scaled network inputs (dev float32 [n, 4]) of physical parameters (dev float64 [n, 4])."""
+    import torch
+    _dev_check(phys, torch.float64, None, "phys")
+    if out is None:
+        out = torch.empty((phys.shape[0], 4), dtype=torch.float32, device=phys.device)
+    _check(_lib.rfd_surrogate_features(sur, _ptr(phys), phys.shape[0], _ptr(out)), "rfd_surrogate_features")
+    return out
 
 
 def rfd_surrogate_set_graphs(sur, enable=True):

@@ -101,8 +101,8 @@ def test_autotuner_picks_a_block_size(rfd, ragged):
     before = rfd.triggers_to_numpy(buf, n)
     res = rfd.rfd_autotune_fir(s.plan, s.taps, "ols32", 1, reps=2)
     print(f"\n[ragged] autotune ols32: {res}")
-    assert res["n_candidates"] == 5
-    assert res["best"]["ols_block"] in (0, 1024, 2048, 4096)
+    assert res["n_candidates"] == 9       # the current one, then 4 block sizes x (general, aligned outputs)
+    assert res["best"]["ols_block"] in (0, 1024, 2048, 4096) and res["best"]["ols_aligned"] in (0, 1)
     assert res["best_ms"] <= res["before_ms"] + 1e-9
     buf, n = s.filter("ols32", 0.0, 1, case.n_templates * case.n)
     after = rfd.triggers_to_numpy(buf, n)

@@ -151,6 +151,18 @@ def test_targets_and_basis_match_oracle(rfd, case):
     assert err <= 2 * T * U32 * 4
 
 
+def test_input_features_match_oracle(rfd, case):
+    """The network inputs librfd computes from (m1, m2, chi, e0) (chirp mass,
+    eta, chi, e0 scaled over the training range) against the oracle's."""
+    c = case
+    for phys in (c.p_train, c.p_test):
+        got = c.sur.scale(phys).astype(np.float64)
+        want = osg.scaled_inputs(phys, c.p_train)
+        err = float(np.max(np.abs(got - want)))
+        assert err <= 2.5e-7, err          # float32 rounding of values in [-1, 1] (and just beyond)
+    print(f"\n[surrogate] input features: max |dx| = {err:.2e}")
+
+
 def test_gradients_match_oracle(rfd, case):
     import torch
     c = case

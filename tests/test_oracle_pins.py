@@ -313,3 +313,17 @@ def test_zero_lag_match_and_tap_selection():
         T_sel, m_sel = tp.select_taps(h_j, h_r, w, target, ladder)
         first = next((TT for TT, mm in zip(ladder, ms) if mm >= target), ladder[-1])
         assert T_sel == first and abs(m_sel - ms[ladder.index(T_sel)]) <= 1e-14
+
+
+@pytest.mark.parametrize("T,k0", [(8, -4), (33, 5), (16, -40), (2048, -1024)])
+def test_response_fft_equals_the_defining_sum(T, k0):
+    """response_fft (one FFT of the taps at their lags) equals response, the
+    defining sum sum_k a_k exp(-2 pi i i (k0 + k) / N) written as a matrix
+    product, bin by bin."""
+    from oracle import taps as tp
+    n = 4096
+    rng = np.random.default_rng(T)
+    a = rng.standard_normal(T) + 1j * rng.standard_normal(T)
+    want = tp.response(a, k0, n)
+    got = tp.response_fft(a, k0, n)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))

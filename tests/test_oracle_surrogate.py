@@ -170,3 +170,21 @@ def test_phase_align_outside_the_window_uses_the_nearest_lag(T, k0):
     assert np.allclose(np.abs(rot), 1.0, atol=1e-12)
     assert np.allclose(rot, rot[:, :1], atol=1e-12)
     assert np.allclose(rot[:, 0], np.exp(-1j * np.angle(np.array(want))), atol=1e-8)
+
+
+def test_input_features_closed_forms():
+    """Equal masses m: chirp mass m 2^(-1/5), eta = 1/4; swapping the masses
+    changes nothing; training extremes map to -1 and +1, a constant feature
+    to -1."""
+    phys = np.array([[1.4, 1.4, 0.01, 0.1], [2.0, 1.0, -0.02, 0.0], [1.0, 2.0, -0.02, 0.0], [3.0, 3.0, 0.03, 0.2]])
+    f = sg.input_features(phys)
+    assert np.allclose(f[0, :2], [1.4 * 2 ** -0.2, 0.25], rtol=1e-15)
+    assert np.allclose(f[3, :2], [3.0 * 2 ** -0.2, 0.25], rtol=1e-15)
+    assert np.allclose(f[1], f[2]) and np.isclose(f[1, 1], 2.0 / 9.0)
+    # chirp mass from the definition (m1 m2)^(3/5) / M^(1/5)
+    assert np.isclose(f[1, 0], (2.0 * 1.0) ** 0.6 / 3.0 ** 0.2, rtol=1e-14)
+    x = sg.scaled_inputs(phys, phys)
+    assert np.allclose(x.min(axis=0)[:2], -1.0) and np.allclose(x.max(axis=0)[:2], 1.0)
+    const = phys.copy()
+    const[:, 3] = 0.3
+    assert np.all(sg.scaled_inputs(const, const)[:, 3] == -1.0)

@@ -45,3 +45,20 @@ def test_taylorf2_support_and_isco():
     assert abs(synth.f_isco(1.0) - 4397.0) < 1.0
     k = np.nonzero(np.abs(h) > 0)[0]
     assert np.allclose(np.abs(h[k]), f[k] ** (-7 / 6))
+
+
+def test_device_batches_equal_host_waveforms():
+    """synth.device evaluates the same TaylorF2 formulas with torch tensors
+    (here on the CPU): same band edges, values equal to FP64 rounding of the
+    phase (which reaches ~1e6 rad for the lightest eccentric systems)."""
+    torch = __import__("pytest").importorskip("torch")
+    from synth.device import template_batch_device
+    for name, tol in [("ecc512s", 5e-9), ("tidal256s", 1e-9), ("spin256s", 1e-9), ("surr512s", 1e-9),
+                      ("bns64s", 1e-9)]:
+        w = synth.get_workload(name)
+        bank = synth.make_bank(w)
+        ps = [bank.params(j) for j in range(0, bank.n_templates, max(1, bank.n_templates // 5))][:5]
+        host = synth.template_batch(w, ps)
+        dev = template_batch_device(w, ps, "cpu").numpy()
+        assert np.array_equal(dev == 0, host == 0), name
+        assert np.max(np.abs(dev - host)) <= tol * np.max(np.abs(host)), name

@@ -241,6 +241,7 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
  * T and k0 (synchronises).  Any output pointer may be NULL. */
 int rfd_taps_get(const rfd_taps* taps, int64_t tmpl, double* a_out, double* sigma_fit_out,
                  int32_t* taps_out, int32_t* k0_out);
+/* rfd_taps_destroy: RFD_E_STATE while a graph or stream uses the taps. */
 int rfd_taps_destroy(rfd_taps* taps);
 
 /*
@@ -405,7 +406,9 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
  * buffers between replays.  Captured on a private stream; replayed on the
  * plan's stream.  Arguments as rfd_dechirp / rfd_filter_bank; h_refs is a
  * host array of n_refs device pointers (complex128 [N/2+1]) for the slots
- * ref_ids.  Plan, taps and every captured buffer must outlive the graph.
+ * ref_ids.  Plan, taps and every captured buffer must outlive the graph:
+ * rfd_plan_destroy and rfd_taps_destroy return RFD_E_STATE (and free
+ * nothing) while a graph or stream created on them still exists.
  * rfd_segment_graph_launch replays it; with n_out non-NULL it synchronises
  * and returns the trigger count (RFD_E_OVERFLOW as rfd_filter_bank).  Taps
  * re-made after capture are picked up (RFD_OLS32 rebuilds its tap spectra in
@@ -426,8 +429,12 @@ int rfd_graph_destroy(rfd_graph* graph);
  * the FIR, window peaks and triggers cover only outputs [n_start, n_start +
  * n_len), exactly as rfd_filter_range (same range rules: 256-sample aligned,
  * non-empty, inside the segment, else RFD_E_INVALID).  The segment transform
- * and the dechirps still cover the whole segment.  Replayed with
- * rfd_segment_graph_launch, freed with rfd_graph_destroy.
+ * and the dechirps still cover the whole segment, and the range is fixed at
+ * capture: every replay filters the same output samples of whatever the
+ * captured buffers hold (refill `data` to advance the stream by one
+ * segment).  An advancing stream with incremental reference series is
+ * rfd_stream_*.  Replayed with rfd_segment_graph_launch, freed with
+ * rfd_graph_destroy.
  */
 int rfd_range_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision, float threshold,
                            int64_t cluster_window, const double* data, int32_t n_refs, const int32_t* ref_ids,

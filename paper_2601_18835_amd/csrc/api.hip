@@ -580,6 +580,8 @@ int rfd_autotune_fir(rfd_plan* plan, const rfd_taps* taps, int32_t precision, in
 
 int rfd_plan_destroy(rfd_plan* plan) {
   if (!plan) return RFD_OK;
+  if (plan->p.users > 0)
+    return fail(RFD_E_STATE, "plan still used by " + std::to_string(plan->p.users) + " graph(s) or stream(s)");
   (void)hipStreamSynchronize(plan->p.stream);
   plan_free(plan->p);
   delete plan;
@@ -896,6 +898,8 @@ int rfd_taps_get(const rfd_taps* taps, int64_t tmpl, double* a_out, double* sigm
 
 int rfd_taps_destroy(rfd_taps* taps) {
   if (!taps) return RFD_OK;
+  if (taps->t.users > 0)
+    return fail(RFD_E_STATE, "taps still used by " + std::to_string(taps->t.users) + " graph(s) or stream(s)");
   (void)hipStreamSynchronize(taps->t.plan->stream);
   taps_free(taps->t);
   delete taps;
@@ -959,7 +963,12 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
     rc = ensure_ols(p, tm);
     if (rc) return rc;
   }
-  rc = launch_slots_clear(p, n_slots);
+  // clear and compact only the windows the range meets
+  const int64_t rlo = n_start, rhi = n_start + n_len;
+  WinMap m;
+  if (!win_map_range(nwin, cluster_window, 1, &rlo, &rhi, &m)) m = win_map_all(nwin);
+  const int64_t n_visit = t.n_templates * m.nq;
+  rc = launch_slots_clear_map(p, n_visit, m);
   if (rc) return rc;
   rc = stage_begin(p, kStFir);
   if (rc) return rc;
@@ -973,7 +982,7 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
   rc = stage_end(p);
   if (!rc) rc = stage_begin(p, kStCompact);
   if (rc) return rc;
-  rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);
+  rc = launch_compact_bank(p, t, n_visit, nwin, cluster_window, threshold, out, capacity, &m);
   if (rc) return rc;
   rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
   if (!rc) rc = stage_end(p);
@@ -1120,9 +1129,14 @@ static int graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision,
   if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     rc = fail(RFD_E_DEVICE, "hipStreamBeginCapture failed");
   } else {
+    // a ranged graph clears and compacts only the windows its range meets
+    WinMap m = win_map_all(nwin);
+    const int64_t rlo = n_start, rhi = n_start + n_len;
+    if (ranged && !win_map_range(nwin, cluster_window, 1, &rlo, &rhi, &m)) m = win_map_all(nwin);
+    const int64_t n_visit = t.n_templates * m.nq;
     rc = launch_data_fft(p, data);
     if (!rc) rc = launch_dechirp_refs(p, n_refs, ref_ids, h_refs);
-    if (!rc) rc = launch_slots_clear(p, n_slots);
+    if (!rc) rc = launch_slots_clear_map(p, n_visit, m);
     if (!rc && !ranged) rc = enqueue_fir(p, t, precision, cluster_window, nwin, threshold);
     if (!rc && ranged) {
       if (precision == RFD_OLS32) {
@@ -1132,7 +1146,7 @@ static int graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision,
           rc = launch_fir(p, t, (int)b, precision, cluster_window, nwin, threshold, n_start, n_len);
       }
     }
-    if (!rc) rc = launch_compact_bank(p, t, n_slots, nwin, cluster_window, threshold, out, capacity);
+    if (!rc) rc = launch_compact_bank(p, t, n_visit, nwin, cluster_window, threshold, out, capacity, &m);
     if (!rc) rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
     hipError_t e = hipStreamEndCapture(cap, &g);
     if (!rc && e != hipSuccess) rc = fail(RFD_E_DEVICE, "hipStreamEndCapture failed");
@@ -1151,6 +1165,8 @@ static int graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precision,
   }
   h->plan = plan;
   h->taps = &t;
+  ++p.users;
+  ++t.users;
   h->precision = precision;
   h->plan_gen = p.res_gen;
   h->taps_gen = t.res_gen;
@@ -1206,6 +1222,8 @@ int rfd_graph_destroy(rfd_graph* graph) {
   (void)hipStreamSynchronize(graph->plan->p.stream);
   if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
   if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  --graph->plan->p.users;
+  --graph->taps->users;
   delete graph;
   return RFD_OK;
 }

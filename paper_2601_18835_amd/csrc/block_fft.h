@@ -122,6 +122,44 @@ __device__ __forceinline__ void block_fft_twiddles(BlockFftTw<K>& w, const float
   }
 }
 
+// The same twiddles with stage B's taken from a workgroup table in LDS: they
+// depend on u = t % R only, so R x 16 values serve every thread, and the 32
+// registers they would hold stay free (for the next operands in flight).
+template <int K>
+struct BlockFftTwL {
+  float2 a[16];
+  const float2* bl;   // LDS row of this thread's u: bl[k] = W_K^(16 u k)
+};
+constexpr int kTwbStride = 17;   // odd row stride: the R rows' reads meet distinct banks
+template <int K>
+__host__ __device__ constexpr int block_fft_twb_size() { return (K / 256) * kTwbStride; }
+// Fills the table (every thread of the workgroup calls it; a barrier must
+// follow before the first block_fft) and this thread's stage-A twiddles.
+template <int K, int SIGN>
+__device__ __forceinline__ void block_fft_twiddles_lds(BlockFftTwL<K>& w, const float2* __restrict__ tw, int t,
+                                                       float2* table) {
+  using S = BlockFft<K>;
+  constexpr int step = 4096 / K;
+  for (int e = threadIdx.x; e < S::R * 16; e += 256) {
+    const int u = e / 16, k = e % 16;
+    float2 y = tw[((16 * u * k) % K) * step];
+    if (SIGN < 0) y.y = -y.y;
+    table[u * kTwbStride + k] = y;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float2 x = tw[((t * k) % K) * step];
+    if (SIGN < 0) x.y = -x.y;
+    w.a[k] = x;
+  }
+  w.bl = table + (t % S::R) * kTwbStride;
+}
+// stage-B twiddle W_K^(16 u k) of either form
+template <int K>
+__device__ __forceinline__ float2 twb(const BlockFftTw<K>& w, int k) { return w.b[k]; }
+template <int K>
+__device__ __forceinline__ float2 twb(const BlockFftTwL<K>& w, int k) { return w.bl[k]; }
+
 // Exchange barrier: one wave per FFT (K = 1024) needs only wave-level
 // ordering of its LDS traffic, so the workgroup's four FFTs run
 // independently; larger FFTs span waves and synchronise the workgroup.
@@ -139,8 +177,8 @@ __device__ __forceinline__ void block_fft_sync() {
 // K-point DFT of v (thread t of its FFT holds x[t + NTf r] in v[r]) with
 // sign SIGN.  On return v[e * R + s] holds X[out_index(t, e, s)].  All
 // threads of the workgroup call it together (it synchronises).
-template <int K, int SIGN>
-__device__ __forceinline__ void block_fft(float2 (&v)[16], float2* buf, int t, const BlockFftTw<K>& w) {
+template <int K, int SIGN, typename TW>
+__device__ __forceinline__ void block_fft(float2 (&v)[16], float2* buf, int t, const TW& w) {
   using S = BlockFft<K>;
   constexpr int NTf = S::NTf, R = S::R;
   // stage A: radix 16 over r
@@ -165,7 +203,7 @@ __device__ __forceinline__ void block_fft(float2 (&v)[16], float2* buf, int t, c
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k2 = dft16_freq(s);
-      row[k2 * 16 * R + k2 / S::G] = k2 ? cmul(v[s], w.b[k2]) : v[s];
+      row[k2 * 16 * R + k2 / S::G] = k2 ? cmul(v[s], twb(w, k2)) : v[s];
     }
   }
   block_fft_sync<NTf>();

@@ -119,18 +119,20 @@ __device__ __forceinline__ constexpr bool ols_slot_kept(int s) {
 }
 
 template <int K, int NF>
-__global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ols(OlsArgs a) {
   using S = BlockFft<K>;
   __shared__ float2 lds[S::F * S::LDS];
+  __shared__ float2 twb_table[block_fft_twb_size<K>()];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
   const int64_t b = (int64_t)blockIdx.x * S::F + f;
   const bool bvalid = b < a.nB;
-  BlockFftTw<K> w;
-  block_fft_twiddles<K, 1>(w, a.tw, t);
+  BlockFftTwL<K> w;
+  block_fft_twiddles_lds<K, 1>(w, a.tw, t, twb_table);
   float2 xb[16];
   const float2* Xb = a.X + (bvalid ? b : 0) * K;
 #pragma unroll
   for (int r = 0; r < 16; ++r) xb[r] = Xb[t + S::NTf * r];
+  __syncthreads();     // the twiddle table is complete
   // this block's output samples and their windows (uniform per FFT)
   const int64_t n0 = (a.b_first + b) * a.L;
   const int64_t nbeg = std::max<int64_t>(n0, a.n_lo);
@@ -142,11 +144,20 @@ __global__ __launch_bounds__(256) void k_ols(OlsArgs a) {
   const int64_t j0 = (int64_t)blockIdx.y * a.J;
   const int64_t j1 = std::min<int64_t>(j0 + a.J, a.count);
   const bool lead = (threadIdx.x & 63) == 0;
+  // the next template's tap spectrum is fetched while the current one is
+  // transformed (its loads would otherwise stall all waves of the FFT)
+  float2 gn[16];
+  auto fetch_g = [&](int64_t j) {
+    const float2* gj = a.G + (j < j1 ? j : j0) * K;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gn[r] = gj[t + S::NTf * r];
+  };
+  fetch_g(j0);
   for (int64_t j = j0; j < j1; ++j) {
-    const float2* gj = a.G + j * K;
     float2 v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gj[t + S::NTf * r]);
+    for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gn[r]);
+    if (j + 1 < j1) fetch_g(j + 1);
     block_fft<K, 1>(v, lds + f * S::LDS, t, w);
     if (!has_out) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;

@@ -101,6 +101,8 @@ struct Plan {
   std::vector<std::vector<int64_t>> zband_edges;
   std::vector<int64_t> zband_gen;
 
+  // objects that keep a pointer to this plan (graphs, streams): destroy refuses while > 0
+  int users = 0;
   // optional stage timing (hipEvent pairs on `stream`)
   bool timing = false;
   struct Mark { int stage; hipEvent_t a, b; bool open; };
@@ -164,6 +166,8 @@ struct Taps {
   int64_t it_total = 0; int it_nsb = 0; size_t it_lds = 0; int it_grid = 1;
   // bumped whenever a buffer a captured graph may point at is reallocated
   int64_t res_gen = 0;
+  // objects that keep a pointer to these taps (graphs, streams): destroy refuses while > 0
+  int users = 0;
   // scratch for tap construction
   double2* work64 = nullptr; size_t work64_cap = 0;
   double2* bvec = nullptr; size_t bvec_cap = 0;
@@ -235,11 +239,21 @@ int ensure_slots(Plan& p, int64_t n_slots);
 int finish_triggers(Plan& p, int64_t capacity, int64_t* n_out);
 
 // ------------------------------------------------ launchers (triggers.hip)
+// Slots a clear or compaction visits, template-major: the windows
+// [lo0, lo0 + cnt0) then [lo1, lo1 + nq - cnt0) (increasing q) of every
+// template; n_visit = n_templates * nq.  win_map_all: every window.
+struct WinMap { int64_t nwin, nq, cnt0, lo0, lo1; };
+WinMap win_map_all(int64_t nwin);
+// the windows met by output pieces [lo[k], hi[k]) (k < pieces <= 2) as at most two
+// runs in increasing order; false when they do not form such runs
+bool win_map_range(int64_t nwin, int64_t W, int pieces, const int64_t* lo, const int64_t* hi, WinMap* m);
 int launch_slots_clear(Plan& p, int64_t n_slots);
+int launch_slots_clear_map(Plan& p, int64_t n_visit, const WinMap& m);
 int launch_compact(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
                    rfd_trigger* out, int64_t capacity);
+// n_slots = slots visited (n_templates * m->nq with a map, else all)
 int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
-                        rfd_trigger* out, int64_t capacity);
+                        rfd_trigger* out, int64_t capacity, const WinMap* m = nullptr);
 int compaction_blocks(int64_t n_slots);
 int findchirp_batch_size(const Plan& p);
 size_t findchirp_work_size(const Plan& p);

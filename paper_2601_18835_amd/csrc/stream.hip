@@ -137,14 +137,18 @@ static int stream_filter(Plan& p, const Taps& t, int precision, float threshold,
     rc = ensure_ols(p, tm);
     if (rc) return rc;
   }
-  rc = launch_slots_clear(p, n_slots);
-  if (rc) return rc;
   int64_t lo[2] = {start, 0}, hi[2] = {std::min(start + len, p.n), 0};
   int pieces = 1;
   if (start + len > p.n) {
     hi[1] = start + len - p.n;
     pieces = 2;
   }
+  // clear and compact only the windows the outputs meet
+  WinMap m;
+  if (!win_map_range(nwin, W, pieces, lo, hi, &m)) m = win_map_all(nwin);
+  const int64_t n_visit = t.n_templates * m.nq;
+  rc = launch_slots_clear_map(p, n_visit, m);
+  if (rc) return rc;
   rc = stage_begin(p, kStFir);
   if (rc) return rc;
   for (int k = 0; k < pieces && !rc; ++k) {
@@ -159,7 +163,7 @@ static int stream_filter(Plan& p, const Taps& t, int precision, float threshold,
   rc = stage_end(p);
   if (!rc) rc = stage_begin(p, kStCompact);
   if (rc) return rc;
-  rc = launch_compact_bank(p, t, n_slots, nwin, W, threshold, out, capacity);
+  rc = launch_compact_bank(p, t, n_visit, nwin, W, threshold, out, capacity, &m);
   if (rc) return rc;
   rc = launch_fir_z(p, t, out, std::min<int64_t>(capacity, (int64_t)1 << 26));
   if (!rc) rc = stage_end(p);
@@ -245,6 +249,8 @@ int rfd_stream_create(rfd_plan* plan, const rfd_taps* taps, int32_t n_refs, cons
     return fail(RFD_E_NOMEM, "stream: host allocation failed");
   }
   h->s = std::move(st);
+  ++p.users;
+  ++const_cast<Taps&>(t).users;
   *out = h;
   return RFD_OK;
 }
@@ -326,6 +332,8 @@ int rfd_stream_destroy(rfd_stream* stream) {
   if (!stream) return RFD_OK;
   Plan& p = stream->s.handle->p;
   (void)hipStreamSynchronize(p.stream);
+  --p.users;
+  --const_cast<Taps*>(stream->s.taps)->users;
   stream_free(stream->s);
   delete stream;
   return RFD_OK;

@@ -12,9 +12,15 @@ constexpr int kSegThreads = 256;
 constexpr int kSegPer = 16;
 constexpr int kSeg = kSegThreads * kSegPer;   // slots per compaction block
 
-__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
+__device__ __forceinline__ int64_t map_slot(const WinMap& m, int64_t v) {
+  const int64_t t = v / m.nq, qi = v - t * m.nq;
+  const int64_t q = qi < m.cnt0 ? m.lo0 + qi : m.lo1 + (qi - m.cnt0);
+  return t * m.nwin + q;
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, WinMap m) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0ull;
+    p[map_slot(m, i)] = 0ull;
 }
 
 __device__ __forceinline__ bool slot_fires(unsigned long long k, float thr2) {
@@ -39,12 +45,12 @@ __device__ int block_exclusive_scan(int v, int* sh, int& total) {
 }
 
 __global__ __launch_bounds__(kSegThreads) void k_count(const unsigned long long* __restrict__ slots, int64_t n,
-                                                     float thr2, long long* __restrict__ counts) {
+                                                     float thr2, long long* __restrict__ counts, WinMap m) {
   __shared__ int sh[kSegThreads];
   int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)threadIdx.x * kSegPer;
   int c = 0;
   for (int i = 0; i < kSegPer; ++i)
-    if (base + i < n && slot_fires(slots[base + i], thr2)) ++c;
+    if (base + i < n && slot_fires(slots[map_slot(m, base + i)], thr2)) ++c;
   int total;
   block_exclusive_scan(c, sh, total);
   if (threadIdx.x == 0) counts[blockIdx.x] = total;
@@ -89,18 +95,18 @@ __device__ __forceinline__ int find_subbank(const int64_t* first, int nsb, int64
 __global__ __launch_bounds__(kSegThreads) void k_write(const unsigned long long* __restrict__ slots, int64_t n,
                                                      float thr2, const long long* __restrict__ offs, int64_t nwin,
                                                      int64_t W, rfd_trigger* __restrict__ out, int64_t capacity,
-                                                     const int64_t* __restrict__ sb_first, int nsb) {
+                                                     const int64_t* __restrict__ sb_first, int nsb, WinMap m) {
   __shared__ int sh[kSegThreads];
   int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)threadIdx.x * kSegPer;
   int c = 0;
   for (int i = 0; i < kSegPer; ++i)
-    if (base + i < n && slot_fires(slots[base + i], thr2)) ++c;
+    if (base + i < n && slot_fires(slots[map_slot(m, base + i)], thr2)) ++c;
   int total;
   int pre = block_exclusive_scan(c, sh, total);
   int64_t pos = offs[blockIdx.x] + pre;
   for (int i = 0; i < kSegPer; ++i) {
-    int64_t si = base + i;
-    if (si >= n) break;
+    if (base + i >= n) break;
+    const int64_t si = map_slot(m, base + i);
     unsigned long long k = slots[si];
     if (!slot_fires(k, thr2)) continue;
     if (pos < capacity) {
@@ -246,41 +252,74 @@ __global__ __launch_bounds__(256) void k_fc_z_final(rfd_trigger* __restrict__ ou
 }
 
 // ------------------------------------------------------------ launchers
+WinMap win_map_all(int64_t nwin) { return WinMap{nwin, nwin, nwin, 0, 0}; }
+
+bool win_map_range(int64_t nwin, int64_t W, int pieces, const int64_t* lo, const int64_t* hi, WinMap* m) {
+  int64_t a[2], b[2];       // inclusive window runs
+  for (int k = 0; k < pieces; ++k) {
+    a[k] = lo[k] / W;
+    b[k] = (hi[k] - 1) / W;
+  }
+  if (pieces == 2) {
+    if (a[1] < a[0]) {      // increasing q
+      std::swap(a[0], a[1]);
+      std::swap(b[0], b[1]);
+    }
+    if (a[1] <= b[0] + 1) { // overlapping or adjacent runs merge
+      b[0] = std::max(b[0], b[1]);
+      pieces = 1;
+    }
+  }
+  if (pieces == 1) {
+    *m = WinMap{nwin, b[0] - a[0] + 1, b[0] - a[0] + 1, a[0], 0};
+    return true;
+  }
+  if (pieces != 2) return false;
+  *m = WinMap{nwin, (b[0] - a[0] + 1) + (b[1] - a[1] + 1), b[0] - a[0] + 1, a[0], a[1]};
+  return true;
+}
+
 int launch_slots_clear(Plan& p, int64_t n_slots) {
-  int64_t blocks = (n_slots + 255) / 256;
+  // every slot: templates x windows, identity order
+  return launch_slots_clear_map(p, n_slots, win_map_all(std::max<int64_t>(n_slots, 1)));
+}
+
+int launch_slots_clear_map(Plan& p, int64_t n_visit, const WinMap& m) {
+  int64_t blocks = (n_visit + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, p.stream, p.slots, n_slots);
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, p.stream, p.slots, n_visit, m);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 
 int launch_compact_impl(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float threshold, rfd_trigger* out,
-                        int64_t capacity, const int64_t* sb_first, int nsb) {
+                        int64_t capacity, const int64_t* sb_first, int nsb, const WinMap& m) {
   int64_t nblk = (n_slots + kSeg - 1) / kSeg;
   if ((size_t)nblk > p.counts_cap) return fail(RFD_E_INVALID, "compaction scratch too small");
   float thr2 = threshold * threshold;
   hipLaunchKernelGGL(k_count, dim3((unsigned)nblk), dim3(kSegThreads), 0, p.stream, p.slots, n_slots, thr2,
-                     p.counts);
+                     p.counts, m);
   RFD_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p.stream, p.counts, nblk, p.total);
   RFD_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_write, dim3((unsigned)nblk), dim3(kSegThreads), 0, p.stream, p.slots, n_slots, thr2,
-                     p.counts, nwin, W, out, capacity, sb_first, nsb);
+                     p.counts, nwin, W, out, capacity, sb_first, nsb, m);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 
 int launch_compact(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float threshold, rfd_trigger* out,
                    int64_t capacity) {
-  return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, nullptr, 1);
+  return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, nullptr, 1, win_map_all(nwin));
 }
 
 int compaction_blocks(int64_t n_slots) { return (int)((n_slots + kSeg - 1) / kSeg); }
 
 int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
-                        rfd_trigger* out, int64_t capacity) {
-  return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, tp.d_first, (int)tp.sb.size());
+                        rfd_trigger* out, int64_t capacity, const WinMap* m) {
+  return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, tp.d_first, (int)tp.sb.size(),
+                             m ? *m : win_map_all(nwin));
 }
 
 int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity) {

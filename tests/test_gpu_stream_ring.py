@@ -145,3 +145,31 @@ def test_stream_arguments_are_checked(rfd, stream_case):
         assert e.value.code == rfd.RFD_E_STATE      # not primed
     finally:
         rfd.rfd_stream_destroy(st)
+
+
+def test_plan_and_taps_outlive_their_graphs_and_streams(rfd, stream_case):
+    """Destroying a plan or taps object that a graph or stream still points at
+    is refused (nothing freed); after the graph and stream go, it works."""
+    import torch
+    psd, refs, H, seg, s = stream_case
+    data = torch.from_numpy(seg[0]).cuda()
+    out = torch.empty(32 * 64, dtype=torch.uint8, device="cuda")
+    st = rfd.rfd_stream_create(s.plan, s.taps, s.h_ref, 1024)
+    g = rfd.rfd_range_graph_create(s.plan, s.taps, "fp32", 6.0, 2048, data, s.h_ref, N - 2048, 2048, out, 64)
+    try:
+        for destroy, obj in ((rfd.rfd_taps_destroy, s.taps), (rfd.rfd_plan_destroy, s.plan)):
+            with pytest.raises(rfd.RfdError) as e:
+                destroy(obj)
+            assert e.value.code == rfd.RFD_E_STATE
+        rfd.rfd_graph_destroy(g)
+        g = None
+        with pytest.raises(rfd.RfdError) as e:       # the stream still holds them
+            rfd.rfd_taps_destroy(s.taps)
+        assert e.value.code == rfd.RFD_E_STATE
+    finally:
+        if g is not None:
+            rfd.rfd_graph_destroy(g)
+        rfd.rfd_stream_destroy(st)
+    # both usable again
+    s.dechirp_all()
+    s.filter("fp32", 6.0, 2048, 64)

@@ -62,27 +62,30 @@ __global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int
 }
 
 // --------------------------------------------------------- tap spectra (FP64)
-// G_j[f] = (1/K) sum_k c_k e^{+2 pi i f k / K}, c = the normalised FP32 taps.
-__global__ __launch_bounds__(256) void k_ols_g(const float2* __restrict__ c32, int Tp, int T, int K,
+// G_j[f] = (1/K) sum_k c_k e^{+2 pi i f k / K}, c = the normalised FP32 taps:
+// one K-point FP64 transform of the zero-padded taps per template, in LDS
+// (radix-4 Stockham), rounded once to FP32.  O(K log K) per template instead
+// of the O(K T) of the defining sum (4.2 ms -> a few hundred us for 512
+// templates at T = 1024, which matters where taps are regenerated per
+// segment, as the learned surrogate does).
+template <int K>
+__global__ __launch_bounds__(256) void k_ols_g(const float2* __restrict__ c32, int Tp, int T,
                                             const double2* __restrict__ tw64, float2* __restrict__ G) {
-  extern __shared__ double2 cs[];
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int LP = lds_col<K>();
+  double2* buf = reinterpret_cast<double2*>(smem);
+  double2* twl = buf + LP;
+  for (int k = threadIdx.x; k < K; k += 256) twl[lpad(k)] = tw64[k * (4096 / K)];
   const float2* cj = c32 + (int64_t)blockIdx.x * Tp;
-  for (int k = threadIdx.x; k < T; k += 256) cs[k] = make_double2((double)cj[k].x, (double)cj[k].y);
+  for (int k = threadIdx.x; k < K; k += 256)
+    buf[lpad(k)] = k < T ? make_double2((double)cj[k].x, (double)cj[k].y) : make_double2(0.0, 0.0);
   __syncthreads();
-  const int step = 4096 / K;
+  lds_fft<double2, K, 1, 256>(buf, twl, +1);
   const double inv = 1.0 / K;
   float2* gj = G + (int64_t)blockIdx.x * K;
   for (int f = threadIdx.x; f < K; f += 256) {
-    double re = 0.0, im = 0.0;
-    int idx = 0;                           // (f k) mod K
-    for (int k = 0; k < T; ++k) {
-      const double2 e = tw64[idx * step];
-      re += cs[k].x * e.x - cs[k].y * e.y;
-      im += cs[k].x * e.y + cs[k].y * e.x;
-      idx += f;
-      if (idx >= K) idx -= K;
-    }
-    gj[f] = make_float2((float)(re * inv), (float)(im * inv));
+    const double2 v = buf[lpad(f)];
+    gj[f] = make_float2((float)(v.x * inv), (float)(v.y * inv));
   }
 }
 
@@ -322,8 +325,22 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
     s.ols_nf = sh.nf;
     s.ols_nB = nB;
     if (!s.ols_valid) {
-      hipLaunchKernelGGL(k_ols_g, dim3((unsigned)s.count), dim3(256), (size_t)s.T * sizeof(double2), p.stream,
-                         t.c32 + s.a_base, s.Tp, s.T, K, (const double2*)p.ols_tw64, s.ols_g);
+      switch (K) {
+        case 1024:
+          hipLaunchKernelGGL(k_ols_g<1024>, dim3((unsigned)s.count), dim3(256),
+                             (size_t)(lds_col<1024>() + 1024 + 64) * sizeof(double2), p.stream, t.c32 + s.a_base,
+                             s.Tp, s.T, (const double2*)p.ols_tw64, s.ols_g);
+          break;
+        case 2048:
+          hipLaunchKernelGGL(k_ols_g<2048>, dim3((unsigned)s.count), dim3(256),
+                             (size_t)(lds_col<2048>() + 2048 + 128) * sizeof(double2), p.stream, t.c32 + s.a_base,
+                             s.Tp, s.T, (const double2*)p.ols_tw64, s.ols_g);
+          break;
+        default:
+          hipLaunchKernelGGL(k_ols_g<4096>, dim3((unsigned)s.count), dim3(256),
+                             (size_t)(lds_col<4096>() + 4096 + 256) * sizeof(double2), p.stream, t.c32 + s.a_base,
+                             s.Tp, s.T, (const double2*)p.ols_tw64, s.ols_g);
+      }
       RFD_CHECK_LAUNCH();
       s.ols_valid = true;
     }

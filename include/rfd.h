@@ -488,6 +488,18 @@ int rfd_range_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precisi
  *                          on the device, so an epoch is one fixed launch
  *                          sequence: by default it is captured once per call
  *                          and replayed as a HIP graph every epoch.
+ * rfd_surrogate_train_many the same epochs for count (1..32) surrogates of
+ *                          one plan with equal training-set size, hidden
+ *                          width and n_basis, launched together: each step
+ *                          is one launch sequence for all of them (the grid's
+ *                          third index or second selects the network), so the
+ *                          small per-network GEMMs fill the device.  Each
+ *                          network's arithmetic and shuffle are those of
+ *                          rfd_surrogate_train on it alone, so the results
+ *                          are identical.  params[i]: dev float [n][4] of
+ *                          surrogate i; loss_out: host float [count][epochs]
+ *                          or NULL.  A surrogate may not appear twice.
+ *                          rfd_surrogate_train is this call with count 1.
  * rfd_surrogate_set_graphs enable != 0 (default): graph replay of epochs;
  *                          0: every step launched directly.  Results are
  *                          identical either way.
@@ -535,6 +547,8 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
 int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_out);
 int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs, int32_t batch, float lr,
                         float* loss_out);
+int rfd_surrogate_train_many(rfd_surrogate* const* surs, const float* const* params, int32_t count, int32_t epochs,
+                             int32_t batch, float lr, float* loss_out);
 int rfd_surrogate_set_graphs(rfd_surrogate* sur, int32_t enable);
 int rfd_surrogate_set_feature_range(rfd_surrogate* sur, const double* phys, int64_t n);
 int rfd_surrogate_features(rfd_surrogate* sur, const double* phys, int64_t n, float* out);

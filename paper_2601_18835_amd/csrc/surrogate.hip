@@ -36,12 +36,6 @@ int taps_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
 __device__ __forceinline__ float ld_op(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ld_op(const uint16_t* p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
 
-// C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation.
-// op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
-// 64 x 64 output tile per workgroup, 4 x 4 per thread, K in steps of 32:
-// the next step's tiles are loaded into registers while the current one is
-// multiplied from LDS (the MLP's GEMMs are small, so load latency, not
-// arithmetic, bounds them).
 // Element r of this thread in a 32 x TM (k x m) tile: consecutive threads
 // run along whichever index is contiguous in memory (m for a k-major
 // operand, k for an m-major one), so every load is a coalesced run.
@@ -63,33 +57,56 @@ __device__ __forceinline__ float silu_g(float z) {
   return s * (1.f + z * (1.f - s));
 }
 
+// Networks trained together: every training kernel takes its per-network
+// pointers from arrays indexed by the grid's network coordinate.  They are
+// kernel arguments, so one captured epoch holds them, and each network's
+// arithmetic is exactly that of training it alone.
+constexpr int kMaxNets = 32;
+template <typename T>
+struct PerNet {
+  T p[kMaxNets];
+};
+template <typename T>
+static PerNet<T> one_net(T v) {
+  PerNet<T> r{};
+  r.p[0] = v;
+  return r;
+}
+
 // What the GEMM does with each result x = op(A) op(B) [m][n]:
 //   kStore   C = x (or C += x when accumulate)
 //   kBiasAct z = x + bias[n]; C = z; H = silu(z)   (hidden layer, forward)
 //   kBias    C = x + bias[n]                      (output layer, forward)
 //   kSiluBwd C = x silu'(Z[m][n])                  (hidden layer, backward)
 enum GemmEpiMode { kStore = 0, kBiasAct, kBias, kSiluBwd };
-struct GemmEpi {
-  int mode = kStore;
-  const float* bias = nullptr;
-  float* H = nullptr;
-  const float* Z = nullptr;
+template <typename TA, typename TB>
+struct GemmOps {
+  PerNet<const TA*> A;
+  PerNet<const TB*> B;
+  PerNet<float*> C;
+  PerNet<const float*> bias;   // kBiasAct, kBias
+  PerNet<float*> H;            // kBiasAct
+  PerNet<const float*> Z;      // kSiluBwd
 };
 
-// C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation.
+// C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation, for the
+// network blockIdx.z of ops.
 // op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
 // TM x TM output tile per workgroup (TM = 64: 4 x 4 per thread; TM = 32:
 // 2 x 2 and TM = 16: 1 x 1, more workgroups for the MLP's small GEMMs), K in steps of
 // 32 with the next step's tiles loaded into registers while the current one
 // is multiplied from LDS.
 template <int TM, typename TA, typename TB>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __restrict__ A, int lda, int ta,
-                                            const TB* __restrict__ B, int ldb, int tb, float* __restrict__ C,
-                                            int ldc, int accumulate, GemmEpi epi) {
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, int lda, int ta, int ldb, int tb, int ldc,
+                                            int accumulate, int mode, GemmOps<TA, TB> ops) {
   constexpr int R = TM * 32 / 256;        // tile elements per thread and operand
   constexpr int P = TM / 16;              // outputs per thread along each dimension
   __shared__ float As[32][TM + 4];
   __shared__ float Bs[32][TM + 4];
+  const int z = blockIdx.z;
+  const TA* __restrict__ A = ops.A.p[z];
+  const TB* __restrict__ B = ops.B.p[z];
+  float* __restrict__ C = ops.C.p[z];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
   float acc[P][P] = {};
@@ -143,13 +160,13 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
       if (gn >= N) continue;
       const int64_t o = (int64_t)gm * ldc + gn;
       float v = acc[i][j];
-      if (epi.mode == kBiasAct) {
-        v += epi.bias[gn];
-        epi.H[o] = silu_f(v);
-      } else if (epi.mode == kBias) {
-        v += epi.bias[gn];
-      } else if (epi.mode == kSiluBwd) {
-        v *= silu_g(epi.Z[o]);
+      if (mode == kBiasAct) {
+        v += ops.bias.p[z][gn];
+        ops.H.p[z][o] = silu_f(v);
+      } else if (mode == kBias) {
+        v += ops.bias.p[z][gn];
+      } else if (mode == kSiluBwd) {
+        v *= silu_g(ops.Z.p[z][o]);
       } else if (accumulate) {
         v += C[o];
       }
@@ -158,34 +175,54 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
   }
 }
 
+// the same GEMM shape for nz networks at once
 template <typename TA, typename TB>
-static int gemm(hipStream_t st, int M, int N, int K, const TA* A, int lda, int ta, const TB* B, int ldb, int tb,
-                float* C, int ldc, int accumulate = 0, GemmEpi epi = GemmEpi()) {
-  if (M <= 0 || N <= 0) return RFD_OK;
+static int gemm_n(hipStream_t st, int nz, int M, int N, int K, const GemmOps<TA, TB>& ops, int lda, int ta, int ldb,
+                  int tb, int ldc, int accumulate = 0, int mode = kStore) {
+  if (M <= 0 || N <= 0 || nz <= 0) return RFD_OK;
   // narrower tiles when wider ones would leave most of the 256 CUs idle (each
   // output's summation order is the same at every tile width)
-  if ((int64_t)((N + 31) / 32) * ((M + 31) / 32) < 512) {
-    dim3 grid((N + 15) / 16, (M + 15) / 16);
-    hipLaunchKernelGGL((k_gemm<16, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
-                       accumulate, epi);
-  } else if ((int64_t)((N + 63) / 64) * ((M + 63) / 64) < 512) {
-    dim3 grid((N + 31) / 32, (M + 31) / 32);
-    hipLaunchKernelGGL((k_gemm<32, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
-                       accumulate, epi);
+  const int64_t w32 = (int64_t)((N + 31) / 32) * ((M + 31) / 32) * nz;
+  const int64_t w64 = (int64_t)((N + 63) / 64) * ((M + 63) / 64) * nz;
+  if (w32 < 512) {
+    dim3 grid((N + 15) / 16, (M + 15) / 16, nz);
+    hipLaunchKernelGGL((k_gemm<16, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc, accumulate,
+                       mode, ops);
+  } else if (w64 < 512) {
+    dim3 grid((N + 31) / 32, (M + 31) / 32, nz);
+    hipLaunchKernelGGL((k_gemm<32, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc, accumulate,
+                       mode, ops);
   } else {
-    dim3 grid((N + 63) / 64, (M + 63) / 64);
-    hipLaunchKernelGGL((k_gemm<64, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc,
-                       accumulate, epi);
+    dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
+    hipLaunchKernelGGL((k_gemm<64, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc, accumulate,
+                       mode, ops);
   }
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 
+// one network, plain result
+template <typename TA, typename TB>
+static int gemm(hipStream_t st, int M, int N, int K, const TA* A, int lda, int ta, const TB* B, int ldb, int tb,
+                float* C, int ldc, int accumulate = 0) {
+  GemmOps<TA, TB> ops{};
+  ops.A.p[0] = A;
+  ops.B.p[0] = B;
+  ops.C.p[0] = C;
+  return gemm_n(st, 1, M, N, K, ops, lda, ta, ldb, tb, ldc, accumulate, kStore);
+}
+
 // ------------------------------------------------------- elementwise
+// Each kernel below serves the networks of a PerNet group: the network is
+// blockIdx.y (grid-stride kernels) or blockIdx.x (one-thread kernels).
+
 // dY = 2 (Y - C) / nb, and the per-block sums of squares (deterministic order)
-__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const float* __restrict__ Cb,
-                                            float* __restrict__ dY, int64_t n, float scale,
-                                            double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_loss(PerNet<const float*> Ys, PerNet<const float*> Cbs,
+                                            PerNet<float*> dYs, int64_t n, float scale, PerNet<double*> parts) {
+  const int z = blockIdx.y;
+  const float* __restrict__ Y = Ys.p[z];
+  const float* __restrict__ Cb = Cbs.p[z];
+  float* __restrict__ dY = dYs.p[z];
   __shared__ double red[256];
   double acc = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
@@ -199,26 +236,29 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) parts.p[z][blockIdx.x] = red[0];
 }
 
 // accumulate: the flag, or when acc_from is given, whether acc_from[0] > 0
 // (a training step after the epoch's first)
-__global__ void k_sum_partials(const double* __restrict__ partial, int n, double scale, double* __restrict__ out,
-                               int accumulate, const int64_t* __restrict__ acc_from) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (acc_from) accumulate = acc_from[0] > 0;
+__global__ void k_sum_partials(PerNet<const double*> parts, int n, double scale, PerNet<double*> outs,
+                               int accumulate, PerNet<const int64_t*> acc_from) {
+  if (threadIdx.x != 0) return;
+  const int z = blockIdx.x;
+  const double* __restrict__ partial = parts.p[z];
+  if (acc_from.p[z]) accumulate = acc_from.p[z][0] > 0;
   double s = 0.0;
   for (int i = 0; i < n; ++i) s += partial[i];
   s *= scale;
+  double* out = outs.p[z];
   *out = accumulate ? *out + s : s;
 }
 
 // out[j] = sum_i X[i][j]: 64 columns per workgroup, 16 row groups (rows
 // g, g + 16, ...) added in LDS in a fixed order.
-__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ X, int64_t n, int H,
-                                               float* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_colsum(PerNet<const float*> Xs, int64_t n, int H, PerNet<float*> outs) {
   __shared__ float red[16][64];
+  const float* __restrict__ X = Xs.p[blockIdx.y];
   const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + c;
   float s = 0.f;
@@ -230,30 +270,41 @@ __global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ X, in
     float t = 0.f;
 #pragma unroll
     for (int q = 0; q < 16; ++q) t += red[q][c];
-    out[j] = t;
+    outs.p[blockIdx.y][j] = t;
   }
 }
 
 // Training step state on the device, so every step of an epoch is the same
 // launch sequence (and can be replayed as one captured graph):
 // st[0] = batch index within the epoch, st[1] = Adam steps taken.
-__global__ void k_train_state_set(int64_t* __restrict__ st, int64_t bi, int64_t steps) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_train_state_set(PerNet<int64_t*> sts, int64_t bi, PerNet<int64_t> steps) {
+  if (threadIdx.x == 0) {
+    int64_t* st = sts.p[blockIdx.x];
     st[0] = bi;
-    st[1] = steps;
+    st[1] = steps.p[blockIdx.x];
   }
 }
-__global__ void k_train_state_advance(int64_t* __restrict__ st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_train_state_advance(PerNet<int64_t*> sts) {
+  if (threadIdx.x == 0) {
+    int64_t* st = sts.p[blockIdx.x];
     st[0] += 1;
     st[1] += 1;
   }
 }
+// the mean loss of the epoch just ended, rec[z * epochs + e]
+__global__ void k_loss_record(PerNet<const double*> loss, float* __restrict__ rec, int epochs, int e) {
+  if (threadIdx.x == 0) rec[(int64_t)blockIdx.x * epochs + e] = (float)loss.p[blockIdx.x][0];
+}
+
 // Adam step number st[1] + 1 (bias corrections 1 - beta^t)
-__global__ void k_adam_step(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                            const int64_t* __restrict__ st) {
-  const float t = (float)(st[1] + 1);
+__global__ void k_adam_step(PerNet<float*> ws, PerNet<const float*> gs, PerNet<float*> ms, PerNet<float*> vs,
+                            int64_t n, float lr, float b1, float b2, float eps, PerNet<const int64_t*> sts) {
+  const int z = blockIdx.y;
+  float* __restrict__ w = ws.p[z];
+  const float* __restrict__ g = gs.p[z];
+  float* __restrict__ m = ms.p[z];
+  float* __restrict__ v = vs.p[z];
+  const float t = (float)(sts.p[z][1] + 1);
   const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
@@ -265,15 +316,22 @@ __global__ void k_adam_step(float* __restrict__ w, const float* __restrict__ g, 
   }
 }
 
-__global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ out, int64_t n) {
+__global__ void k_to_bf16(PerNet<const float*> ws, PerNet<uint16_t*> outs, int64_t n) {
+  const float* __restrict__ w = ws.p[blockIdx.y];
+  uint16_t* __restrict__ out = outs.p[blockIdx.y];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (uint16_t)bf16_bits(w[i]);
 }
 
 // rows perm[st[0] nb + r], r < nb, of the parameters and targets
-__global__ void k_gather(const float* __restrict__ P, const float* __restrict__ C, const int32_t* __restrict__ perm,
-                         const int64_t* __restrict__ st, int nb, int K, float* __restrict__ Pb, float* __restrict__ Cb) {
-  const int32_t* idx = perm + st[0] * nb;
+__global__ void k_gather(PerNet<const float*> Ps, PerNet<const float*> Cs, PerNet<const int32_t*> perms,
+                         PerNet<const int64_t*> sts, int nb, int K, PerNet<float*> Pbs, PerNet<float*> Cbs) {
+  const int z = blockIdx.y;
+  const float* __restrict__ P = Ps.p[z];
+  const float* __restrict__ C = Cs.p[z];
+  float* __restrict__ Pb = Pbs.p[z];
+  float* __restrict__ Cb = Cbs.p[z];
+  const int32_t* idx = perms.p[z] + sts.p[z][0] * nb;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb * (4 + K); e += gridDim.x * blockDim.x) {
     const int r = e / (4 + K), c = e % (4 + K);
     const int64_t src = idx[r];
@@ -683,53 +741,123 @@ static int lds_fits(size_t bytes) {
 
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 
-static int refresh_bf16(Surrogate& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(s.np)), dim3(256), 0, st, s.w, s.wbf, s.np);
+// Exact-tap fallback: template j takes the exact taps and fitted norm when
+// its validated match is below min_match (NaN included).
+__global__ __launch_bounds__(256) void k_fallback_rows(const double* __restrict__ match, double min_match, int T,
+                                                     const double2* __restrict__ ea, int64_t eTp,
+                                                     const double* __restrict__ esig, double2* __restrict__ ta,
+                                                     int64_t tTp, double* __restrict__ tsig) {
+  const int64_t j = blockIdx.x;
+  if (match[j] >= min_match) return;
+  for (int k = threadIdx.x; k < T; k += 256) ta[j * tTp + k] = ea[j * eTp + k];
+  if (threadIdx.x == 0) tsig[j] = esig[j];
+}
+
+// Surrogates of equal shape whose training steps are launched together.
+struct NetGroup {
+  Surrogate* s[kMaxNets] = {};
+  int n = 0;
+  template <typename T, typename F>
+  PerNet<T> per(F f) const {
+    PerNet<T> r{};
+    for (int i = 0; i < n; ++i) r.p[i] = f(*s[i]);
+    return r;
+  }
+};
+static NetGroup one_group(Surrogate& s) {
+  NetGroup g;
+  g.s[0] = &s;
+  g.n = 1;
+  return g;
+}
+// PerNet of one member expression of every surrogate of g
+#define PER(T, expr) g.template per<T>([&](Surrogate& s) -> T { return (expr); })
+
+static int refresh_bf16(const NetGroup& g, hipStream_t st) {
+  const int64_t np = g.s[0]->np;
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(np), g.n), dim3(256), 0, st, PER(const float*, s.w),
+                     PER(uint16_t*, s.wbf), np);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
 
 // forward pass for n rows (n <= nb) of parameters P -> Y (and the activations)
-static int forward(Surrogate& s, hipStream_t st, const float* P, int n) {
+static int forward(const NetGroup& g, hipStream_t st, const PerNet<const float*>& P, int n) {
   int rc;
-  const int H = s.H, K = s.K;
+  const int H = g.s[0]->H, K = g.s[0]->K;
   // biases and activations in the GEMM epilogues
-  GemmEpi e1{kBiasAct, s.w + s.ob1, s.H1, nullptr};
-  if ((rc = gemm<float, uint16_t>(st, n, H, 4, P, 4, 0, s.wbf + s.oW1, 4, 1, s.Z1, H, 0, e1))) return rc;
-  GemmEpi e2{kBiasAct, s.w + s.ob2, s.H2, nullptr};
-  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.H1, H, 0, s.wbf + s.oW2, H, 1, s.Z2, H, 0, e2))) return rc;
-  GemmEpi e3{kBias, s.w + s.ob3, nullptr, nullptr};
-  if ((rc = gemm<float, uint16_t>(st, n, K, H, s.H2, H, 0, s.wbf + s.oW3, H, 1, s.Y, K, 0, e3))) return rc;
+  GemmOps<float, uint16_t> o{};
+  o.A = P;
+  o.B = PER(const uint16_t*, s.wbf + s.oW1);
+  o.C = PER(float*, s.Z1);
+  o.bias = PER(const float*, s.w + s.ob1);
+  o.H = PER(float*, s.H1);
+  if ((rc = gemm_n(st, g.n, n, H, 4, o, 4, 0, 4, 1, H, 0, kBiasAct))) return rc;
+  o.A = PER(const float*, s.H1);
+  o.B = PER(const uint16_t*, s.wbf + s.oW2);
+  o.C = PER(float*, s.Z2);
+  o.bias = PER(const float*, s.w + s.ob2);
+  o.H = PER(float*, s.H2);
+  if ((rc = gemm_n(st, g.n, n, H, H, o, H, 0, H, 1, H, 0, kBiasAct))) return rc;
+  o.A = PER(const float*, s.H2);
+  o.B = PER(const uint16_t*, s.wbf + s.oW3);
+  o.C = PER(float*, s.Y);
+  o.bias = PER(const float*, s.w + s.ob3);
+  if ((rc = gemm_n(st, g.n, n, K, H, o, H, 0, H, 1, K, 0, kBias))) return rc;
   return RFD_OK;
 }
 
-// loss (added to *s.loss when accumulate) and gradients into s.g for n rows (Pb, Cb)
-static int backward(Surrogate& s, hipStream_t st, const float* P, const float* Cb, int n, int accumulate_loss,
-                    double loss_scale, const int64_t* acc_from = nullptr) {
+// loss (added to *s.loss when accumulate) and gradients into s.g for n rows
+// (P, Cb); with state_acc the loss accumulates after an epoch's first step
+static int backward(const NetGroup& g, hipStream_t st, const PerNet<const float*>& P,
+                    const PerNet<const float*>& Cb, int n, int accumulate_loss, double loss_scale,
+                    bool state_acc = false) {
   int rc;
-  const int H = s.H, K = s.K;
+  const int H = g.s[0]->H, K = g.s[0]->K;
   const int64_t ny = (int64_t)n * K;
   const int nblk = std::min<int>(grid_for(ny), 256);
-  hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, st, s.Y, Cb, s.dY, ny, 1.f / n, s.partial);
+  hipLaunchKernelGGL(k_loss, dim3(nblk, g.n), dim3(256), 0, st, PER(const float*, s.Y), Cb, PER(float*, s.dY), ny,
+                     1.f / n, PER(double*, s.partial));
   RFD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, loss_scale, s.loss, accumulate_loss,
-                     acc_from);
+  hipLaunchKernelGGL(k_sum_partials, dim3(g.n), dim3(1), 0, st, PER(const double*, s.partial), nblk, loss_scale,
+                     PER(double*, s.loss), accumulate_loss,
+                     PER(const int64_t*, state_acc ? s.tstate : nullptr));
   RFD_CHECK_LAUNCH();
   // layer 3
-  if ((rc = gemm<float, float>(st, K, H, n, s.dY, K, 1, s.H2, H, 0, s.g + s.oW3, H))) return rc;
-  hipLaunchKernelGGL(k_colsum, dim3((K + 63) / 64), dim3(1024), 0, st, s.dY, (int64_t)n, K, s.g + s.ob3);
+  GemmOps<float, float> wg{};
+  wg.A = PER(const float*, s.dY);
+  wg.B = PER(const float*, s.H2);
+  wg.C = PER(float*, s.g + s.oW3);
+  if ((rc = gemm_n(st, g.n, K, H, n, wg, K, 1, H, 0, H))) return rc;
+  hipLaunchKernelGGL(k_colsum, dim3((K + 63) / 64, g.n), dim3(1024), 0, st, PER(const float*, s.dY), (int64_t)n, K,
+                     PER(float*, s.g + s.ob3));
   RFD_CHECK_LAUNCH();
-  GemmEpi ea{kSiluBwd, nullptr, nullptr, s.Z2};
-  if ((rc = gemm<float, uint16_t>(st, n, H, K, s.dY, K, 0, s.wbf + s.oW3, H, 0, s.dA, H, 0, ea))) return rc;
+  GemmOps<float, uint16_t> ag{};
+  ag.A = PER(const float*, s.dY);
+  ag.B = PER(const uint16_t*, s.wbf + s.oW3);
+  ag.C = PER(float*, s.dA);
+  ag.Z = PER(const float*, s.Z2);
+  if ((rc = gemm_n(st, g.n, n, H, K, ag, K, 0, H, 0, H, 0, kSiluBwd))) return rc;
   // layer 2
-  if ((rc = gemm<float, float>(st, H, H, n, s.dA, H, 1, s.H1, H, 0, s.g + s.oW2, H))) return rc;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, st, s.dA, (int64_t)n, H, s.g + s.ob2);
+  wg.A = PER(const float*, s.dA);
+  wg.B = PER(const float*, s.H1);
+  wg.C = PER(float*, s.g + s.oW2);
+  if ((rc = gemm_n(st, g.n, H, H, n, wg, H, 1, H, 0, H))) return rc;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64, g.n), dim3(1024), 0, st, PER(const float*, s.dA), (int64_t)n, H,
+                     PER(float*, s.g + s.ob2));
   RFD_CHECK_LAUNCH();
-  GemmEpi eb{kSiluBwd, nullptr, nullptr, s.Z1};
-  if ((rc = gemm<float, uint16_t>(st, n, H, H, s.dA, H, 0, s.wbf + s.oW2, H, 0, s.dB, H, 0, eb))) return rc;
+  ag.A = PER(const float*, s.dA);
+  ag.B = PER(const uint16_t*, s.wbf + s.oW2);
+  ag.C = PER(float*, s.dB);
+  ag.Z = PER(const float*, s.Z1);
+  if ((rc = gemm_n(st, g.n, n, H, H, ag, H, 0, H, 0, H, 0, kSiluBwd))) return rc;
   // layer 1
-  if ((rc = gemm<float, float>(st, H, 4, n, s.dB, H, 1, P, 4, 0, s.g + s.oW1, 4))) return rc;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, st, s.dB, (int64_t)n, H, s.g + s.ob1);
+  wg.A = PER(const float*, s.dB);
+  wg.B = P;
+  wg.C = PER(float*, s.g + s.oW1);
+  if ((rc = gemm_n(st, g.n, H, 4, n, wg, H, 1, 4, 0, 4))) return rc;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64, g.n), dim3(1024), 0, st, PER(const float*, s.dB), (int64_t)n, H,
+                     PER(float*, s.g + s.ob1));
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
@@ -744,6 +872,130 @@ static int update_expansion(Surrogate& s, hipStream_t st) {
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
+
+
+// Epochs of Adam on the networks of g (equal shapes, one plan), launched
+// together: per step a gather, the forward and backward passes, Adam and the
+// BF16 refresh, each one launch for the whole group.  Each network shuffles
+// with its own generator (seed + 7) as when trained alone, so the group's
+// result equals training each network by itself.  The next epoch's
+// permutations are shuffled on the host while the device runs the current
+// one (two pinned buffers).
+static int train_group(const NetGroup& g, const PerNet<const float*>& params, int epochs, int batch, float lr,
+                       float* loss_out) {
+  Surrogate& s0 = *g.s[0];
+  hipStream_t st = s0.plan->stream;
+  const int64_t n = s0.n;
+  const int K = s0.K;
+  std::vector<std::mt19937_64> gens;
+  std::vector<std::vector<int32_t>> perms(g.n, std::vector<int32_t>(n));
+  for (int i = 0; i < g.n; ++i) {
+    gens.emplace_back(g.s[i]->seed + 7);
+    for (int64_t j = 0; j < n; ++j) perms[i][j] = (int32_t)j;
+  }
+  int32_t* dperm = nullptr;
+  float* drec = nullptr;
+  int32_t* hperm[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t exec = nullptr;
+  int rc = salloc(&dperm, (size_t)g.n * n);
+  if (!rc) rc = salloc(&drec, (size_t)g.n * epochs);
+  for (int b = 0; b < 2 && !rc; ++b) {
+    if (hipHostMalloc((void**)&hperm[b], (size_t)g.n * n * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess)
+      rc = fail(RFD_E_NOMEM, "training buffers: allocation failed");
+  }
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int64_t nbatches = n / batch;                // whole batches only
+  const double loss_scale = 1.0 / (double)(batch * nbatches);
+  PerNet<const int32_t*> dp{};
+  for (int i = 0; i < g.n; ++i) dp.p[i] = dperm + (int64_t)i * n;
+  const PerNet<const float*> Pb = PER(const float*, s.Pb);
+  const PerNet<const float*> Cb = PER(const float*, s.Cb);
+  const PerNet<const int64_t*> tst = PER(const int64_t*, s.tstate);
+  // one training step; its batch index and Adam step count live on the device
+  auto step = [&](hipStream_t q) -> int {
+    hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)batch * (4 + K)), g.n), dim3(256), 0, q, params,
+                       PER(const float*, s.C), dp, tst, batch, K, PER(float*, s.Pb), PER(float*, s.Cb));
+    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "gather launch failed");
+    int r = forward(g, q, Pb, batch);
+    if (!r) r = backward(g, q, Pb, Cb, batch, 0, loss_scale, true);
+    if (r) return r;
+    hipLaunchKernelGGL(k_adam_step, dim3(grid_for(s0.np), g.n), dim3(256), 0, q, PER(float*, s.w),
+                       PER(const float*, s.g), PER(float*, s.m), PER(float*, s.v), s0.np, lr, b1, b2, eps, tst);
+    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "adam launch failed");
+    if ((r = refresh_bf16(g, q))) return r;
+    hipLaunchKernelGGL(k_train_state_advance, dim3(g.n), dim3(1), 0, q, PER(int64_t*, s.tstate));
+    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "step launch failed");
+    return RFD_OK;
+  };
+  // with graphs: capture one epoch's steps once, replay it every epoch
+  bool graphs = true;
+  for (int i = 0; i < g.n; ++i) graphs = graphs && g.s[i]->graphs;
+  if (!rc && graphs && nbatches > 1) {
+    hipStream_t cs = nullptr;
+    hipGraph_t gr = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+      rc = fail(RFD_E_DEVICE, "capture stream creation failed");
+    } else if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = fail(RFD_E_DEVICE, "hipStreamBeginCapture failed");
+    } else {
+      for (int64_t bi = 0; bi < nbatches && !rc; ++bi) rc = step(cs);
+      const hipError_t e = hipStreamEndCapture(cs, &gr);
+      if (!rc && e != hipSuccess) rc = fail(RFD_E_DEVICE, "hipStreamEndCapture failed");
+      if (!rc && hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(RFD_E_DEVICE, "hipGraphInstantiate failed");
+    }
+    if (gr) (void)hipGraphDestroy(gr);
+    if (cs) (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+  }
+  for (int e = 0; e < epochs && !rc; ++e) {
+    const int b = e & 1;
+    // buffer b was last read by the copy of epoch e - 2
+    if (e >= 2 && hipEventSynchronize(ev[b]) != hipSuccess) {
+      rc = fail(RFD_E_DEVICE, "event wait failed");
+      break;
+    }
+    for (int i = 0; i < g.n; ++i) {
+      std::shuffle(perms[i].begin(), perms[i].end(), gens[i]);
+      memcpy(hperm[b] + (int64_t)i * n, perms[i].data(), n * sizeof(int32_t));
+    }
+    // stream order: the copy waits for the previous epoch's steps
+    if (hipMemcpyAsync(dperm, hperm[b], (size_t)g.n * n * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(ev[b], st) != hipSuccess) {
+      rc = fail(RFD_E_DEVICE, "permutation upload failed");
+      break;
+    }
+    hipLaunchKernelGGL(k_train_state_set, dim3(g.n), dim3(1), 0, st, PER(int64_t*, s.tstate), (int64_t)0,
+                       PER(int64_t, s.step));
+    if (hipGetLastError() != hipSuccess) { rc = fail(RFD_E_DEVICE, "state launch failed"); break; }
+    if (exec) {
+      if (hipGraphLaunch(exec, st) != hipSuccess) rc = fail(RFD_E_DEVICE, "hipGraphLaunch failed");
+    } else {
+      for (int64_t bi = 0; bi < nbatches && !rc; ++bi) rc = step(st);
+    }
+    for (int i = 0; i < g.n; ++i) g.s[i]->step += nbatches;
+    if (!rc) {
+      // mean per-sample squared coefficient error over the epoch
+      hipLaunchKernelGGL(k_loss_record, dim3(g.n), dim3(1), 0, st, PER(const double*, s.loss), drec, epochs, e);
+      if (hipGetLastError() != hipSuccess) rc = fail(RFD_E_DEVICE, "loss record launch failed");
+    }
+  }
+  if (!rc && loss_out &&
+      hipMemcpyAsync(loss_out, drec, (size_t)g.n * epochs * sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess)
+    rc = fail(RFD_E_DEVICE, "loss readback failed");
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = fail(RFD_E_DEVICE, "training failed on the device");
+  if (exec) (void)hipGraphExecDestroy(exec);
+  for (int b = 0; b < 2; ++b) {
+    if (ev[b]) (void)hipEventDestroy(ev[b]);
+    if (hperm[b]) (void)hipHostFree(hperm[b]);
+  }
+  sfree(drec);
+  sfree(dperm);
+  return rc;
+}
+#undef PER
 
 }  // namespace rfd
 
@@ -842,7 +1094,7 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
   hipLaunchKernelGGL(k_whiten, dim3((unsigned)s.n), dim3(256), (size_t)s.T * sizeof(double2), st,
                      t.a64 + sb.a_base, sb.Tp, (const double2*)sb.U, (const double2*)sb.g, sb.eps,
                      std::min(std::max(-sb.k0, 0), s.T - 1), s.T, s.X);
-  if (hipGetLastError() != hipSuccess || refresh_bf16(s, st)) {
+  if (hipGetLastError() != hipSuccess || refresh_bf16(one_group(s), st)) {
     sur_free(s);
     delete h;
     return fail(RFD_E_DEVICE, "surrogate whitening failed");
@@ -882,9 +1134,10 @@ int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_
     RFD_HIP(hipMemsetAsync(zeros, 0, ny * sizeof(float), st));
     float* dummy = nullptr;
     if ((rc = salloc(&dummy, (size_t)ny))) return rc;
-    hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, st, s.C, zeros, dummy, ny, 1.f, s.partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, s.partial, nblk, 1.0 / n, s.loss, 0,
-                       (const int64_t*)nullptr);
+    hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(256), 0, st, one_net<const float*>(s.C), one_net<const float*>(zeros),
+                       one_net(dummy), ny, 1.f, one_net(s.partial));
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, one_net<const double*>(s.partial), nblk, 1.0 / n,
+                       one_net(s.loss), 0, one_net<const int64_t*>(nullptr));
     double v = 0;
     RFD_HIP(hipMemcpyAsync(&v, s.loss, sizeof(double), hipMemcpyDeviceToHost, st));
     RFD_HIP(hipStreamSynchronize(st));
@@ -894,86 +1147,36 @@ int rfd_surrogate_fit_basis(rfd_surrogate* sur, int32_t iters, double* captured_
   return RFD_OK;
 }
 
+int rfd_surrogate_train_many(rfd_surrogate* const* surs, const float* const* params, int32_t count, int32_t epochs,
+                             int32_t batch, float lr, float* loss_out) {
+  if (!surs || !params) return fail(RFD_E_INVALID, "NULL argument");
+  if (count < 1 || count > kMaxNets) return fail(RFD_E_INVALID, "count must be in [1, 32]");
+  if (epochs < 1 || batch < 1 || batch > kSurMaxBatch || !(lr > 0.f)) return fail(RFD_E_INVALID, "bad training arguments");
+  NetGroup g;
+  PerNet<const float*> P{};
+  for (int i = 0; i < count; ++i) {
+    if (!surs[i] || !params[i]) return fail(RFD_E_INVALID, "NULL surrogate or parameters");
+    Surrogate& s = surs[i]->s;
+    if (!s.basis_ready) return fail(RFD_E_STATE, "fit or set the basis before training");
+    for (int j = 0; j < i; ++j)
+      if (g.s[j] == &s) return fail(RFD_E_INVALID, "a surrogate appears twice");
+    if (i > 0) {
+      const Surrogate& s0 = *g.s[0];
+      if (s.plan != s0.plan || s.n != s0.n || s.H != s0.H || s.K != s0.K)
+        return fail(RFD_E_INVALID, "surrogates trained together need one plan and equal n, hidden and n_basis");
+    }
+    if (batch > s.n) return fail(RFD_E_INVALID, "batch larger than the training set");
+    g.s[i] = &s;
+    P.p[i] = params[i];
+  }
+  g.n = count;
+  return train_group(g, P, epochs, batch, lr, loss_out);
+}
+
 int rfd_surrogate_train(rfd_surrogate* sur, const float* params, int32_t epochs, int32_t batch, float lr,
                         float* loss_out) {
   if (!sur || !params) return fail(RFD_E_INVALID, "NULL argument");
-  Surrogate& s = sur->s;
-  if (epochs < 1 || batch < 1 || batch > kSurMaxBatch || !(lr > 0.f)) return fail(RFD_E_INVALID, "bad training arguments");
-  if (!s.basis_ready) return fail(RFD_E_STATE, "fit or set the basis before training");
-  hipStream_t st = s.plan->stream;
-  std::mt19937_64 gen(s.seed + 7);
-  std::vector<int32_t> perm(s.n);
-  for (int64_t i = 0; i < s.n; ++i) perm[i] = (int32_t)i;
-  int32_t* dperm = nullptr;
-  int rc = salloc(&dperm, (size_t)s.n);
-  if (rc) return rc;
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const int64_t nbatches = s.n / batch;              // whole batches only
-  const double loss_scale = 1.0 / (double)(batch * nbatches);
-  // one training step; its batch index and Adam step count live on the device
-  auto step = [&](hipStream_t q) -> int {
-    hipLaunchKernelGGL(k_gather, dim3(grid_for((int64_t)batch * (4 + s.K))), dim3(256), 0, q, params, s.C,
-                       (const int32_t*)dperm, (const int64_t*)s.tstate, batch, s.K, s.Pb, s.Cb);
-    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "gather launch failed");
-    int r = forward(s, q, s.Pb, batch);
-    if (!r) r = backward(s, q, s.Pb, s.Cb, batch, 0, loss_scale, s.tstate);
-    if (r) return r;
-    hipLaunchKernelGGL(k_adam_step, dim3(grid_for(s.np)), dim3(256), 0, q, s.w, s.g, s.m, s.v, s.np, lr, b1, b2, eps,
-                       (const int64_t*)s.tstate);
-    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "adam launch failed");
-    if ((r = refresh_bf16(s, q))) return r;
-    hipLaunchKernelGGL(k_train_state_advance, dim3(1), dim3(1), 0, q, s.tstate);
-    if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "step launch failed");
-    return RFD_OK;
-  };
-  // with graphs: capture one epoch's steps once, replay it every epoch
-  hipGraphExec_t exec = nullptr;
-  if (s.graphs && nbatches > 1) {
-    hipStream_t cs = nullptr;
-    hipGraph_t g = nullptr;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
-      rc = fail(RFD_E_DEVICE, "capture stream creation failed");
-    } else if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      rc = fail(RFD_E_DEVICE, "hipStreamBeginCapture failed");
-    } else {
-      for (int64_t bi = 0; bi < nbatches && !rc; ++bi) rc = step(cs);
-      const hipError_t e = hipStreamEndCapture(cs, &g);
-      if (!rc && e != hipSuccess) rc = fail(RFD_E_DEVICE, "hipStreamEndCapture failed");
-      if (!rc && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess)
-        rc = fail(RFD_E_DEVICE, "hipGraphInstantiate failed");
-    }
-    if (g) (void)hipGraphDestroy(g);
-    if (cs) (void)hipStreamDestroy(cs);
-    (void)hipGetLastError();
-  }
-  for (int e = 0; e < epochs && !rc; ++e) {
-    std::shuffle(perm.begin(), perm.end(), gen);
-    // the previous epoch still reads the permutation until the stream drains
-    if (hipStreamSynchronize(st) != hipSuccess ||
-        hipMemcpy(dperm, perm.data(), s.n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-      rc = fail(RFD_E_DEVICE, "permutation upload failed");
-      break;
-    }
-    hipLaunchKernelGGL(k_train_state_set, dim3(1), dim3(1), 0, st, s.tstate, (int64_t)0, s.step);
-    if (hipGetLastError() != hipSuccess) { rc = fail(RFD_E_DEVICE, "state launch failed"); break; }
-    if (exec) {
-      if (hipGraphLaunch(exec, st) != hipSuccess) rc = fail(RFD_E_DEVICE, "hipGraphLaunch failed");
-    } else {
-      for (int64_t bi = 0; bi < nbatches && !rc; ++bi) rc = step(st);
-    }
-    s.step += nbatches;
-    if (!rc && loss_out) {
-      double v = 0;
-      if (hipMemcpyAsync(&v, s.loss, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        rc = fail(RFD_E_DEVICE, "loss readback failed");
-      loss_out[e] = (float)v;   // mean per-sample squared coefficient error over the epoch
-    }
-  }
-  (void)hipStreamSynchronize(st);
-  if (exec) (void)hipGraphExecDestroy(exec);
-  sfree(dperm);
-  return rc;
+  return rfd_surrogate_train_many(&sur, &params, 1, epochs, batch, lr, loss_out);
 }
 
 int rfd_surrogate_set_feature_range(rfd_surrogate* sur, const double* phys, int64_t n) {
@@ -1013,8 +1216,9 @@ int rfd_surrogate_loss_grad(rfd_surrogate* sur, const float* params, const float
   if (n < 1 || n > kSurMaxBatch) return fail(RFD_E_INVALID, "n out of range");
   hipStream_t st = s.plan->stream;
   const float* Cb = targets ? targets : s.C;
-  int rc = forward(s, st, params, n);
-  if (!rc) rc = backward(s, st, params, Cb, n, 0, (double)1.0 / n);
+  const NetGroup g = one_group(s);
+  int rc = forward(g, st, one_net(params), n);
+  if (!rc) rc = backward(g, st, one_net(params), one_net<const float*>(Cb), n, 0, (double)1.0 / n);
   if (rc) return rc;
   RFD_HIP(hipMemcpyAsync(grads, s.g, s.np * sizeof(float), hipMemcpyDeviceToDevice, st));
   if (loss_out) {
@@ -1064,7 +1268,7 @@ int rfd_surrogate_set_state(rfd_surrogate* sur, const float* weights, const floa
     if (rc) return rc;
     s.basis_ready = true;
   }
-  int rc = refresh_bf16(s, st);
+  int rc = refresh_bf16(one_group(s), st);
   if (rc) return rc;
   RFD_HIP(hipStreamSynchronize(st));
   return RFD_OK;
@@ -1093,7 +1297,7 @@ int rfd_surrogate_make_taps(rfd_surrogate* sur, const float* params, rfd_taps* t
   for (int64_t c0 = 0; c0 < count && !rc; c0 += chunk) {
     const int cn = (int)std::min<int64_t>(chunk, count - c0);
     rc = stage_begin(p, kStSurNet);
-    if (!rc) rc = forward(s, st, params + 4 * c0, cn);
+    if (!rc) rc = forward(one_group(s), st, one_net(params + 4 * c0), cn);
     if (!rc) rc = stage_end(p);
     if (!rc) rc = stage_begin(p, kStSurExpand);
     if (!rc) {
@@ -1178,24 +1382,23 @@ int rfd_taps_fallback(rfd_taps* target, const rfd_taps* exact, int32_t subbank, 
     }
   }
   if (nfb) {
+    // one launch copies every failing template's exact taps and fitted norm,
+    // deciding on the device with the same comparison; one repacking of the
+    // range follows (rows kept from the surrogate pack to the same values)
     RFD_HIP(hipMemcpyAsync(st_.g, se.g, st_.T * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    for (int64_t j = 0; j < count;) {
-      if (!fb[j]) { ++j; continue; }
-      int64_t e = j;
-      while (e < count && fb[e]) ++e;
-      RFD_HIP(hipMemcpyAsync(tt.a64 + st_.a_base + (first + j) * st_.Tp, te.a64 + se.a_base + (first + j) * se.Tp,
-                             (size_t)(e - j) * st_.Tp * sizeof(double2), hipMemcpyDeviceToDevice, st));
-      int rc = taps_norm_and_pack(p, tt, subbank, first + j, e - j);
-      if (rc) return rc;
-      for (int64_t q = j; q < e; ++q) {
-        if (!st_.made_mask[first + q]) {
-          st_.made_mask[first + q] = 1;
-          ++st_.made;
-        }
+    hipLaunchKernelGGL(k_fallback_rows, dim3((unsigned)count), dim3(256), 0, st, match, min_match, st_.T,
+                       (const double2*)(te.a64 + se.a_base + first * se.Tp), (int64_t)se.Tp,
+                       (const double*)(te.sigma_fit + se.first + first), tt.a64 + st_.a_base + first * st_.Tp,
+                       (int64_t)st_.Tp, tt.sigma_fit + st_.first + first);
+    RFD_CHECK_LAUNCH();
+    int rc = taps_pack(p, tt, subbank, first, count);
+    if (rc) return rc;
+    for (int64_t j = 0; j < count; ++j) {
+      if (fb[j] && !st_.made_mask[first + j]) {
+        st_.made_mask[first + j] = 1;
+        ++st_.made;
       }
-      j = e;
     }
-    RFD_HIP(hipStreamSynchronize(st));
   }
   if (n_fallback_out) *n_fallback_out = nfb;
   return RFD_OK;

@@ -76,6 +76,7 @@ _SIGS = {
     "rfd_surrogate_create": [_P, _P, _i32, _i32, _i32, C.c_uint64, C.POINTER(_P)],
     "rfd_surrogate_fit_basis": [_P, _i32, C.POINTER(_d)],
     "rfd_surrogate_train": [_P, _P, _i32, _i32, _f, _P],
+    "rfd_surrogate_train_many": [_P, _P, _i32, _i32, _i32, _f, _P],
     "rfd_surrogate_set_graphs": [_P, _i32],
     "rfd_surrogate_loss_grad": [_P, _P, _P, _i32, _P, C.POINTER(_d)],
     "rfd_surrogate_get_state": [_P, _P, _P, _P, _P],
@@ -508,6 +509,26 @@ def rfd_surrogate_train(sur, params, epochs, batch=256, lr=1e-3):
     _dev_check(params, torch.float32, 4 * (int(sizes[2]) // int(sizes[4])), "params")
     losses = np.zeros(epochs, dtype=np.float32)
     _check(_lib.rfd_surrogate_train(sur, _ptr(params), epochs, batch, lr, losses.ctypes.data), "rfd_surrogate_train")
+    return losses
+
+
+def rfd_surrogate_train_many(surs, params, epochs, batch=256, lr=1e-3):
+    """Train len(surs) surrogates together; params[i]: float32 device tensor
+    [n_train, 4] of surrogate i.  Returns losses [len(surs), epochs]."""
+    import torch
+    count = len(surs)
+    if len(params) != count:
+        raise ValueError("one parameter tensor per surrogate")
+    for sur, prm in zip(surs, params):
+        sizes = np.zeros(6, dtype=np.int64)
+        _check(_lib.rfd_surrogate_get_state(sur, None, None, None, sizes.ctypes.data), "rfd_surrogate_get_state")
+        _dev_check(prm, torch.float32, 4 * (int(sizes[2]) // int(sizes[4])), "params")
+    hs = (C.c_void_p * max(count, 1))(*[C.c_void_p(s if isinstance(s, int) else getattr(s, "value", s))
+                                        for s in surs])
+    ps = (C.c_void_p * max(count, 1))(*[C.c_void_p(p.data_ptr()) for p in params])
+    losses = np.zeros((count, epochs), dtype=np.float32)
+    _check(_lib.rfd_surrogate_train_many(hs, ps, count, epochs, batch, lr, losses.ctypes.data),
+           "rfd_surrogate_train_many")
     return losses
 
 

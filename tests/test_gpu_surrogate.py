@@ -244,6 +244,49 @@ def test_graph_replayed_epochs_equal_direct_launches(rfd, case):
     assert np.array_equal(out[False][1], out[True][1])
 
 
+def test_networks_trained_together_equal_each_trained_alone(rfd, case):
+    """rfd_surrogate_train_many launches the steps of several networks as one
+    sequence; each network keeps its own shuffle and arithmetic, so two calls
+    of two epochs give, per network, the losses and weights of training it
+    alone, bit for bit.  A surrogate named twice is refused."""
+    c = case
+    plan = c.search.plan
+    extra = [rfd.rfd_surrogate_create(plan, c.sur.train_taps, 0, K, H, seed) for seed in (12, 13)]
+    surs = [c.sur.sur] + extra
+    try:
+        w_init = [c.w0]
+        for h in extra:
+            rfd.rfd_surrogate_set_state(h, basis=c.B)
+            w_init.append(bf16_round(rfd.rfd_surrogate_state(h)["weights"]))
+        prm = [c.sur.params_dev] * len(surs)
+
+        def reset():
+            for h, w in zip(surs, w_init):
+                rfd.rfd_surrogate_set_state(h, weights=w, basis=c.B)
+
+        reset()
+        alone = []
+        for h in surs:
+            l1 = rfd.rfd_surrogate_train(h, c.sur.params_dev, 2, N_TRAIN // 8, 1e-3)
+            l2 = rfd.rfd_surrogate_train(h, c.sur.params_dev, 2, N_TRAIN // 8, 5e-4)
+            alone.append((np.concatenate([l1, l2]), rfd.rfd_surrogate_state(h)["weights"]))
+        reset()
+        m1 = rfd.rfd_surrogate_train_many(surs, prm, 2, N_TRAIN // 8, 1e-3)
+        m2 = rfd.rfd_surrogate_train_many(surs, prm, 2, N_TRAIN // 8, 5e-4)
+        for i, h in enumerate(surs):
+            together = np.concatenate([m1[i], m2[i]])
+            print(f"[surrogate] network {i}: losses alone {alone[i][0]}, together {together}", flush=True)
+            assert np.all(np.isfinite(together))
+            assert np.array_equal(alone[i][0], together)
+            assert np.array_equal(alone[i][1], rfd.rfd_surrogate_state(h)["weights"])
+        assert not np.array_equal(alone[0][1], alone[1][1])
+        with pytest.raises(rfd.RfdError):
+            rfd.rfd_surrogate_train_many([surs[0], surs[0]], prm[:2], 1, N_TRAIN // 8, 1e-3)
+    finally:
+        for h in extra:
+            rfd.rfd_surrogate_destroy(h)
+
+
 def test_inference_matches_oracle(rfd, case):
     import torch
     c = case

@@ -70,7 +70,20 @@ typedef enum rfd_precision {
 /* Tap construction route (rfd_make_taps). */
 typedef enum rfd_taps_method {
   RFD_TAPS_LS = 0,     /* weighted ridge least squares, Sec. V.A */
-  RFD_TAPS_WINDOW = 1  /* truncated inverse transform of the ratio, Tukey(0.25) taper */
+  RFD_TAPS_WINDOW = 1, /* truncated inverse transform of the ratio, Tukey(0.25) taper */
+  /* flag OR-ed into either route: per-template lag centring (Sec. V.A's tap
+   * tuning with the lag window placed per template).  Template j's T lags
+   * are centred on the largest |b_j[l]| over every lag l in (-N/2, N/2],
+   * b_j the weighted cross-correlation of target and reference (the normal
+   * equations' right-hand side at every lag; lowest index 0..N-1 on exact
+   * ties): k0_j = l_peak - floor(T/2), held as the offset
+   * d_j = k0_j - k0 from the sub-bank's k0.  The FIR then runs on the
+   * filter index m = n + d_j of each template: its cluster windows are
+   * [qW, (q+1)W) in m, i.e. [qW - d_j, (q+1)W - d_j) mod N in samples, and
+   * triggers report n (so they are ordered by (template, window), not
+   * necessarily by sample).  Costs one extra N-point FP64 transform per
+   * template at construction and nothing in the FIR. */
+  RFD_TAPS_CENTRE = 0x100
 } rfd_taps_method;
 
 #define RFD_MAX_TAPS 2048
@@ -227,6 +240,9 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
  *              through the Hermitian Toeplitz normal equations by Cholesky.
  *              RFD_TAPS_WINDOW: a_k = tukey_k (1/N) sum_i R_i exp(+2 pi i i
  *              (k0+k)/N) (ridge_eps ignored).
+ *              Either route may carry RFD_TAPS_CENTRE (per-template lag
+ *              windows, see rfd_taps_method); re-making a template without
+ *              it returns it to the sub-bank's k0.
  *   ridge_eps  >= 0 (LS); 1e-4 is the documented default (it bounds the
  *              normalised tap gain ||c||_2, which multiplies rounding noise).
  * The FIR applies c_k = conj(a_k) sigma_ref / sigma_fit to z_ref/sigma_ref,
@@ -238,7 +254,8 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
                   const double* h_tmpl, int64_t first, int64_t count, int32_t method, double ridge_eps);
 
 /* Read back one template's FP64 taps a (host complex128 [T]), sigma_fit,
- * T and k0 (synchronises).  Any output pointer may be NULL. */
+ * T and its own k0 (the sub-bank's, plus d_j under RFD_TAPS_CENTRE)
+ * (synchronises).  Any output pointer may be NULL. */
 int rfd_taps_get(const rfd_taps* taps, int64_t tmpl, double* a_out, double* sigma_fit_out,
                  int32_t* taps_out, int32_t* k0_out);
 /* rfd_taps_destroy: RFD_E_STATE while a graph or stream uses the taps. */
@@ -614,10 +631,13 @@ int rfd_chisq(rfd_plan* plan, const rfd_taps* taps, const rfd_trigger* triggers,
  * double [count] (the match at the chosen T) or NULL.  Every ladder entry
  * builds the taps of all templates (n_ladder times the work of
  * rfd_make_taps); templates are then grouped by T into sub-banks.
+ * flags: 0, or RFD_TAPS_CENTRE to centre each template's lags on its own
+ * correlation peak (k0_j = l_peak - floor(T/2)) instead of on lag 0.
+ * k0_out: host int32 [count] (the k0 at the chosen T) or NULL.
  */
 int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, int64_t count, double target,
-                    const int32_t* ladder, int32_t n_ladder, double ridge_eps, int32_t* taps_out,
-                    double* match_out);
+                    const int32_t* ladder, int32_t n_ladder, double ridge_eps, int32_t flags, int32_t* taps_out,
+                    double* match_out, int32_t* k0_out);
 
 /*
  * PSD drift (Sec. VI.B): the template norm must follow the detector PSD.

@@ -90,9 +90,19 @@ def findchirp_snr(p: Prepared, h_j):
     return spectral.matched_filter(p.stilde, h_j, p.w) / np.sqrt(spectral.sigma_sq(h_j, p.w))
 
 
-def triggers(z_norm, threshold, window):
-    """[(sample, rho)] for one template from its normalised complex series."""
-    return cluster.cluster(np.abs(z_norm), threshold, window)
+def triggers(z_norm, threshold, window, shift=0):
+    """[(sample, rho)] for one template from its normalised complex series.
+
+    shift d: the template's taps start d lags after its sub-bank's k0 (per
+    template lag centring).  Reading: its windows lie on the filter index
+    m = n + d, i.e. [qW - d, (q+1)W - d) in samples n (taken mod N), so one
+    window grid serves every template of a sub-bank in filter-index terms;
+    samples are reported as n.  d = 0 is the plain grid aligned to n = 0."""
+    if shift == 0:
+        return cluster.cluster(np.abs(z_norm), threshold, window)
+    n = z_norm.size
+    y = np.roll(np.abs(z_norm), shift)        # y[m] = |z[(m - shift) mod N]|
+    return [((m - shift) % n, r) for m, r in cluster.cluster(y, threshold, window)]
 
 
 def match(p: Prepared, h_j, h_ref, tt: TemplateTaps):

@@ -13,7 +13,10 @@ Readings (the paper leaves these open):
     reference's signal power over the noise PSD; bins with u_i = 0 (out of
     band, or where h_ref vanishes) drop out, so R is never divided by zero;
   * frequency grid: every in-band bin f_i = i df of the analysis segment;
-  * tap times: k0 = -floor(T/2) unless given;
+  * tap times: k0 = -floor(T/2) unless given; with per-template lag
+    centring, k0_j = (lag of the largest |b_j[l]| over every lag) -
+    floor(T/2), b_j the full weighted cross-correlation of target and
+    reference (the normal equations' right-hand side at every lag);
   * ridge: lam = eps * g[0] with g[0] = sum_i u_i and eps = 1e-4 by default.
     The paper adds the ridge so that taps stay bounded where the weight is
     small and numerical error does not accumulate in band; eps sets that
@@ -89,6 +92,25 @@ def crosscorr(h_j, h_r, w, T, k0):
     R, u = ratio_and_weight(h_j, h_r, w)
     full = one_sided_ifft(u * R, n)
     return full[(k0 + np.arange(T, dtype=np.int64)) % n]
+
+
+def peak_lag(h_j, h_r, w):
+    """Lag l in (-N/2, N/2] of the largest |b[l]|^2 = Re^2 + Im^2 over all N
+    lags of b[l] = sum_i u_i R_i exp(+2 pi i i l / N), the weighted
+    cross-correlation of target and reference (the right-hand side of the
+    normal equations at every lag).  On exact ties the lowest index
+    0..N-1 wins."""
+    n = 2 * (h_j.size - 1)
+    R, u = ratio_and_weight(h_j, h_r, w)
+    full = one_sided_ifft(u * R, n)
+    i = int(np.argmax(full.real * full.real + full.imag * full.imag))
+    return i if i <= n // 2 else i - n
+
+
+def centred_k0(h_j, h_r, w, T):
+    """Per-template lag centring (Sec. V.A's tap tuning, with the tap window
+    placed per template): the T lags centred on the peak of |b|."""
+    return peak_lag(h_j, h_r, w) - T // 2
 
 
 def toeplitz_gram(g_pos_neg, T):
@@ -191,13 +213,14 @@ def zero_lag_match(h_j, h_r, w, a, k0):
     return float(num / np.sqrt(np.sum(w * np.abs(h_j) ** 2) * np.sum(w * np.abs(h_fit) ** 2)))
 
 
-def select_taps(h_j, h_r, w, target, ladder, eps=DEFAULT_RIDGE_EPS):
+def select_taps(h_j, h_r, w, target, ladder, eps=DEFAULT_RIDGE_EPS, centre=False):
     """Sec. V.A's dynamic tap count: the first T of the ascending ladder whose
-    least-squares taps (lags centred, k0 = -floor(T/2)) reach the target
+    least-squares taps (lags centred on lag 0, k0 = -floor(T/2), or with
+    centre=True on the peak of |b|: k0 = centred_k0) reach the target
     zero-lag match; the last T if none does.  Returns (T, match)."""
     m = 0.0
     for T in ladder:
-        k0 = -(T // 2)
+        k0 = centred_k0(h_j, h_r, w, T) if centre else -(T // 2)
         a = ls_taps_normal(h_j, h_r, w, T, k0, eps)
         m = zero_lag_match(h_j, h_r, w, a, k0)
         if m >= target:

@@ -706,6 +706,7 @@ static void taps_free(Taps& t) {
   dfree(t.d_first); dfree(t.d_meta); dfree(t.d_abase); dfree(t.work64); dfree(t.bvec);
   dfree(t.d_p16); dfree(t.d_p32); dfree(t.d_count);
   dfree(t.d_it_off); dfree(t.d_it_sb); dfree(t.d_it_S); dfree(t.d_it_nsg);
+  dfree(t.d_shift); dfree(t.peak_pw); dfree(t.k0buf);
 }
 
 int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, const int32_t* ref_id,
@@ -746,6 +747,7 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
     s.p16_base = p16;
     s.p32_base = p32;
     s.made_mask.assign((size_t)s.count, 0);
+    s.centred_mask.assign((size_t)s.count, 0);
     abase += s.count * s.Tp;
     p16 += (s.npad / 8) * (s.Tp / 16) * 128;
     p32 += (s.npad / 8) * (s.Tp / 8) * 64;
@@ -774,8 +776,10 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
   TRY(dalloc(&t.d_p32, (size_t)n_subbanks));
   TRY(dalloc(&t.d_count, (size_t)n_subbanks));
   for (auto& s : t.sb) TRY(dalloc(&s.g, (size_t)s.T));
+  TRY(dalloc(&t.d_shift, (size_t)std::max<int64_t>(t.n_templates, 1)));
 #undef TRY
-  if (hipMemsetAsync(t.pbf, 0, p16 * sizeof(uint4), p.stream) != hipSuccess ||
+  if (hipMemsetAsync(t.d_shift, 0, std::max<int64_t>(t.n_templates, 1) * sizeof(int32_t), p.stream) != hipSuccess ||
+      hipMemsetAsync(t.pbf, 0, p16 * sizeof(uint4), p.stream) != hipSuccess ||
       hipMemsetAsync(t.pfh, 0, p16 * sizeof(uint4), p.stream) != hipSuccess ||
       hipMemsetAsync(t.p32, 0, p32 * sizeof(float4), p.stream) != hipSuccess ||
       hipMemcpy(t.d_first, firsts.data(), n_subbanks * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
@@ -804,6 +808,8 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
   if (!h_ref) return fail(RFD_E_INVALID, "h_ref is NULL");
   if (count < 0 || first < 0 || first + count > s.count) return fail(RFD_E_INVALID, "template range outside the sub-bank");
   if (count > 0 && !h_tmpl) return fail(RFD_E_INVALID, "h_tmpl is NULL");
+  const bool centre = (method & RFD_TAPS_CENTRE) != 0;
+  method &= ~RFD_TAPS_CENTRE;
   if (method != RFD_TAPS_LS && method != RFD_TAPS_WINDOW) return fail(RFD_E_INVALID, "unknown taps method");
   if (method == RFD_TAPS_LS && (!(ridge_eps >= 0.0) || !isfinite(ridge_eps)))
     return fail(RFD_E_INVALID, "ridge_eps must be finite and >= 0");
@@ -847,6 +853,31 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
     int rc = launch_corr64(p, t, 1, h_ref, nullptr, 1, T, 0, s.g, T);
     if (rc) return rc;
   }
+  // per-template lag windows: the peak of each template's full correlation
+  int32_t* dsh = t.d_shift + s.first + first;
+  if (centre) {
+    const size_t need_p = (size_t)chunk * p.n;
+    if (t.peak_cap < need_p) {
+      RFD_HIP(hipStreamSynchronize(p.stream));
+      dfree(t.peak_pw);
+      t.peak_cap = 0;
+      int rc = dalloc(&t.peak_pw, need_p);
+      if (rc) return rc;
+      t.peak_cap = need_p;
+    }
+    if (t.k0buf_cap < (size_t)count) {
+      RFD_HIP(hipStreamSynchronize(p.stream));
+      dfree(t.k0buf);
+      t.k0buf_cap = 0;
+      int rc = dalloc(&t.k0buf, (size_t)count);
+      if (rc) return rc;
+      t.k0buf_cap = (size_t)count;
+    }
+  } else {
+    bool any = false;
+    for (int64_t i = first; i < first + count && !any; ++i) any = s.centred_mask[i] != 0;
+    if (any) RFD_HIP(hipMemsetAsync(dsh, 0, count * sizeof(int32_t), p.stream));
+  }
   {
     int rc = stage_begin(p, kStTaps);
     if (rc) return rc;
@@ -855,8 +886,15 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
   // launch over every template of the call
   for (int64_t c0 = 0; c0 < count; c0 += chunk) {
     int64_t cn = std::min(chunk, count - c0);
+    const int32_t* k0s = nullptr;
+    if (centre) {
+      int rc = launch_corr_peak(p, t, h_ref, h_tmpl + 2 * c0 * p.nb, cn, T, s.k0, t.peak_pw, t.k0buf + c0,
+                                dsh + c0);
+      if (rc) return rc;
+      k0s = t.k0buf + c0;
+    }
     int rc = launch_corr64(p, t, method == RFD_TAPS_LS ? 0 : 2, h_ref, h_tmpl + 2 * c0 * p.nb, cn, T, s.k0,
-                           t.bvec + c0 * T, T);
+                           t.bvec + c0 * T, T, -1, -1, k0s);
     if (rc) return rc;
   }
   {
@@ -871,6 +909,10 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
     if (!s.made_mask[i]) {
       s.made_mask[i] = 1;
       ++s.made;
+    }
+    if ((s.centred_mask[i] != 0) != centre) {
+      s.centred_mask[i] = centre ? 1 : 0;
+      s.n_centred += centre ? 1 : -1;
     }
   }
   return RFD_OK;
@@ -890,9 +932,11 @@ int rfd_taps_get(const rfd_taps* taps, int64_t tmpl, double* a_out, double* sigm
                            hipMemcpyDeviceToHost, st));
   if (sigma_fit_out)
     RFD_HIP(hipMemcpyAsync(sigma_fit_out, t.sigma_fit + tmpl, sizeof(double), hipMemcpyDeviceToHost, st));
+  int32_t d = 0;
+  RFD_HIP(hipMemcpyAsync(&d, t.d_shift + tmpl, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   RFD_HIP(hipStreamSynchronize(st));
   if (taps_out) *taps_out = s.T;
-  if (k0_out) *k0_out = s.k0;
+  if (k0_out) *k0_out = s.k0 + d;
   return RFD_OK;
 }
 

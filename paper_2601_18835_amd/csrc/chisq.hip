@@ -113,7 +113,8 @@ struct ChisqSub {
 __global__ __launch_bounds__(64) void k_chisq(const rfd_trigger* __restrict__ trig, int64_t n_trig,
                                             const ChisqSub* __restrict__ subs, int nsb,
                                             const float2* const* __restrict__ bands, int p, int64_t n,
-                                            const float2* __restrict__ c32, float* __restrict__ out) {
+                                            const float2* __restrict__ c32, const int32_t* __restrict__ shift,
+                                            float* __restrict__ out) {
   const int64_t t = blockIdx.x;
   if (t >= n_trig) return;
   const int lane = threadIdx.x;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(64) void k_chisq(const rfd_trigger* __restrict__ tr
   const float2* c = c32 + s.a_base + j * s.Tp;
   const float2* zb = bands[s.ref_id];
   __shared__ float2 zs[kMaxBands];
-  const int64_t base = tr.sample + s.k0;
+  const int64_t base = tr.sample + s.k0 + shift[tr.tmpl];   // the template's own lag window
   for (int b = 0; b < p; ++b) {
     const float2* z = zb + (int64_t)b * n;
     float re = 0.f, im = 0.f;
@@ -319,7 +320,7 @@ int rfd_chisq(rfd_plan* plan, const rfd_taps* taps, const rfd_trigger* triggers,
     const int64_t cnt = std::min<int64_t>(n - t0, (int64_t)1 << 30);
     hipLaunchKernelGGL(k_chisq, dim3((unsigned)cnt), dim3(64), 0, p.stream, triggers + t0, cnt,
                        (const ChisqSub*)dsubs, (int)subs.size(), (const float2* const*)dbands, pb, p.n,
-                       (const float2*)t.c32, chisq_out + t0);
+                       (const float2*)t.c32, (const int32_t*)t.d_shift, chisq_out + t0);
     if (hipGetLastError() != hipSuccess) rc = fail(RFD_E_DEVICE, "chi^2 launch failed");
   }
   (void)hipStreamSynchronize(p.stream);

@@ -239,11 +239,13 @@ static int run_pass_b(Plan& p, const V* Y, ST st, const V* tab1, int batch, int 
 // outputs, and T N1 terms cost far less than the whole pass.  One wave per
 // lag, FP64.
 __global__ __launch_bounds__(256) void k_lags_direct(const double2* __restrict__ Y, int64_t n, int n1, int n2,
-                                                   const double2* __restrict__ tab1, int k0, int T, double scale,
+                                                   const double2* __restrict__ tab1, int k0,
+                                                   const int32_t* __restrict__ k0s, int T, double scale,
                                                    double2* __restrict__ out, int64_t stride) {
   const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (l >= T) return;                      // uniform per wave
+  if (k0s) k0 = k0s[blockIdx.y];           // per-template lag window
   const int64_t m = ((int64_t)k0 + l) & (n - 1);
   const int64_t r = m % n2, c = m / n2;
   const double2* row = Y + (int64_t)blockIdx.y * n + r * n1;
@@ -271,13 +273,15 @@ template <int L>
 __global__ __launch_bounds__(kNT) void k_corr_part(LoadCorr64 ld, double2* __restrict__ part,
                                                  const double2* __restrict__ coarse,
                                                  const double2* __restrict__ fine, const double2* __restrict__ tabL,
-                                                 const double2* __restrict__ tab1, int n1, int k0, int T) {
+                                                 const double2* __restrict__ tab1, int n1, int k0,
+                                                 const int32_t* __restrict__ k0s, int T) {
   constexpr int C = Cols<double2>::value(L);
   constexpr int LP = lds_col<L>();
   extern __shared__ __align__(16) unsigned char smem[];
   double2* buf = reinterpret_cast<double2*>(smem);
   double2* twl = buf + C * LP;
   const int b = blockIdx.y;
+  if (k0s) k0 = k0s[b];                    // per-template lag window
   // column group of this workgroup: consecutive workgroups go to different
   // XCDs (round robin over 8), so groups g and g + 1, which read the two
   // halves of the same cache lines, are given to workgroups of one XCD
@@ -535,7 +539,7 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
 }
 
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch, int T,
-                  int k0, double2* out, int64_t out_stride, int64_t lo, int64_t hi) {
+                  int k0, double2* out, int64_t out_stride, int64_t lo, int64_t hi, const int32_t* k0s) {
   size_t need = (size_t)batch * p.n;
   if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
   LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high,
@@ -552,7 +556,7 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
     constexpr int CC = Cols<double2>::value(LL);                                                       \
     const size_t sh = lds_bytes<double2, LL, CC>();                                                    \
     hipLaunchKernelGGL((k_corr_part<LL>), dim3(groups, (unsigned)batch), blk, sh, p.stream, ld, tp.work64, \
-                       p.tw64c, p.tw64f, p.tw64_n2, p.tw64_n1, p.n1, k0, T);                           \
+                       p.tw64c, p.tw64f, p.tw64_n2, p.tw64_n1, p.n1, k0, k0s, T);                      \
     break;                                                                                             \
   }
       CASE_C(32) CASE_C(64) CASE_C(128) CASE_C(256) CASE_C(512) CASE_C(1024) CASE_C(2048)
@@ -565,13 +569,78 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
     RFD_CHECK_LAUNCH();
     return RFD_OK;
   }
-  // k_lags_direct reads the pass-A rows (k0 + l) mod N2, l < T
-  const int row_lo = (int)(((int64_t)k0 % p.n2 + p.n2) % p.n2);
-  int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1, row_lo, T);
+  // k_lags_direct reads the pass-A rows (k0 + l) mod N2, l < T (every row
+  // when the lag window differs per template)
+  const int row_lo = k0s ? 0 : (int)(((int64_t)k0 % p.n2 + p.n2) % p.n2);
+  int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1, row_lo,
+                               k0s ? p.n2 : T);
   if (rc) return rc;
   hipLaunchKernelGGL(k_lags_direct, dim3((unsigned)((T + 3) / 4), (unsigned)batch), dim3(256), 0, p.stream,
-                     (const double2*)tp.work64, p.n, p.n1, p.n2, (const double2*)p.tw64_n1, k0, T, scale, out,
+                     (const double2*)tp.work64, p.n, p.n1, p.n2, (const double2*)p.tw64_n1, k0, k0s, T, scale, out,
                      out_stride);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
+
+// ------------------------------------------------- lag of the correlation peak
+// |b|^2 of pass B's output (natural order) for the peak search
+struct StorePow {
+  double* pw;
+  int64_t n;
+  __device__ void operator()(int b, int64_t idx, double2 v) const { pw[(int64_t)b * n + idx] = v.x * v.x + v.y * v.y; }
+};
+
+// Per template: the lag of the largest |b[l]|^2 over all N lags (lowest
+// index 0..N-1 on exact ties), mapped into (-N/2, N/2]; the lag window
+// k0_j = peak - floor(T/2) and its offset from the sub-bank's k0.
+__global__ __launch_bounds__(1024) void k_peak_lag(const double* __restrict__ pw, int64_t n, int T, int k0_sb,
+                                                 int32_t* __restrict__ k0_out, int32_t* __restrict__ d_out) {
+  __shared__ double bv[1024];
+  __shared__ int64_t bi[1024];
+  const double* row = pw + (int64_t)blockIdx.x * n;
+  double best = -1.0;
+  int64_t idx = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double v = row[i];
+    if (v > best) {          // increasing i: the first maximum stays
+      best = v;
+      idx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double v = bv[threadIdx.x + o];
+      const int64_t j = bi[threadIdx.x + o];
+      if (v > bv[threadIdx.x] || (v == bv[threadIdx.x] && j < bi[threadIdx.x])) {
+        bv[threadIdx.x] = v;
+        bi[threadIdx.x] = j;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t i = bi[0];
+    const int lag = (int)(i <= n / 2 ? i : i - n);
+    const int k0 = lag - T / 2;
+    k0_out[blockIdx.x] = k0;
+    if (d_out) d_out[blockIdx.x] = k0 - k0_sb;
+  }
+}
+
+int launch_corr_peak(Plan& p, Taps& tp, const double* h_r, const double* h_t, int64_t batch, int T, int k0_sb,
+                     double* pw, int32_t* k0_out, int32_t* d_out) {
+  if (tp.work64_cap < (size_t)batch * p.n) return fail(RFD_E_INVALID, "corr peak: work buffer too small");
+  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, p.i_low, p.i_high, 0};
+  int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1);
+  if (rc) return rc;
+  rc = run_pass_b<double2>(p, (const double2*)tp.work64, StorePow{pw, p.n}, p.tw64_n1, (int)batch, +1);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_peak_lag, dim3((unsigned)batch), dim3(1024), 0, p.stream, (const double*)pw, p.n, T, k0_sb,
+                     k0_out, d_out);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }

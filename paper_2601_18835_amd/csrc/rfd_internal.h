@@ -133,6 +133,8 @@ struct SubBankTaps {
   double eps = -1.0;                // ridge of the cached factor
   int64_t made = 0;                 // templates whose taps exist
   std::vector<uint8_t> made_mask;
+  int64_t n_centred = 0;            // templates whose lag window is their own (d != 0 possible)
+  std::vector<uint8_t> centred_mask;
   // overlap-save FIR state: block spectra of the series (rebuilt every
   // filter call), tap spectra (rebuilt after the taps change)
   int ols_K = 0, ols_L = 0, ols_nf = 0;   // ols_nf > 0: L = 256 ols_nf (aligned output groups)
@@ -155,6 +157,11 @@ struct Taps {
   uint4* pbf = nullptr;             // packed bf16 hi/lo MFMA A operands
   uint4* pfh = nullptr;             // packed fp16 hi/lo MFMA A operands
   float4* p32 = nullptr;            // packed fp32 MFMA A operands
+  // per-template lag centring: template j's taps sit at lags k0 + d[j] + k of
+  // its sub-bank's k0 (d = 0 unless made with RFD_TAPS_CENTRE); the FIR
+  // kernels work on the filter index m = n + d, compaction and trigger
+  // evaluation convert
+  int32_t* d_shift = nullptr;       // [n_templates]
   // device copy of per-sub-bank metadata for trigger kernels
   int64_t* d_first = nullptr; int32_t* d_meta = nullptr;  // meta: ref_id, T, Tp, k0 per sub-bank
   int64_t* d_abase = nullptr;
@@ -171,6 +178,8 @@ struct Taps {
   // scratch for tap construction
   double2* work64 = nullptr; size_t work64_cap = 0;
   double2* bvec = nullptr; size_t bvec_cap = 0;
+  double* peak_pw = nullptr; size_t peak_cap = 0;      // |b|^2 of the full correlations (centring)
+  int32_t* k0buf = nullptr; size_t k0buf_cap = 0;      // per-template k0 of one make_taps call
 };
 
 // FIR tiling shared by packing and kernels
@@ -191,8 +200,15 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
 // mode 0: P = w h_t conj(h_r); mode 1: P = w |h_r|^2 (batch 1); mode 2: P = h_t/h_r
 // where w |h_r|^2 > 0, scaled by 1/N.
 // lo / hi (inclusive bins, -1: the analysis band) restrict the sum to a band.
+// k0s (device, per batch entry, may be NULL) replaces k0 template by template.
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch,
-                  int T, int k0, double2* out, int64_t out_stride, int64_t lo = -1, int64_t hi = -1);
+                  int T, int k0, double2* out, int64_t out_stride, int64_t lo = -1, int64_t hi = -1,
+                  const int32_t* k0s = nullptr);
+// Per-template lag centring: the full weighted cross-correlation b (mode 0)
+// of each batch entry, |b|^2 into pw [batch][N], and its peak lag l in
+// (-N/2, N/2]: k0_out[t] = l - floor(T/2), d_out[t] = k0_out[t] - k0_sb.
+int launch_corr_peak(Plan& p, Taps& tp, const double* h_r, const double* h_t, int64_t batch, int T, int k0_sb,
+                     double* pw, int32_t* k0_out, int32_t* d_out);
 // band series [n_bands][N] (FP32, normalised by sigma_ref) of one reference
 int launch_dechirp_bands(Plan& p, const double* h_ref, const int64_t* edges, int n_bands, float2* out);
 

@@ -1,6 +1,8 @@
 // Dynamic tap count (Sec. V.A): for each template, the first T of an
-// ascending ladder whose least-squares taps (lags centred, k0 = -floor(T/2))
-// reach a target match with the target template.  The match is the fitted
+// ascending ladder whose least-squares taps (lags centred on lag 0,
+// k0 = -floor(T/2), or with RFD_TAPS_CENTRE on the peak of the template's
+// correlation with the reference) reach a target match with the target
+// template.  The match is the fitted
 // template's phase-maximised overlap with the target at zero lag,
 //   m = |(h_j|h_fit)(0)| / (sigma_j sigma_fit) = |a^H b| / (sigma_j sigma_fit),
 // b the normal equations' right-hand side (b_k = (h_j|h_ref)(t_k)), so it
@@ -63,8 +65,8 @@ using namespace rfd;
 extern "C" {
 
 int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, int64_t count, double target,
-                    const int32_t* ladder, int32_t n_ladder, double ridge_eps, int32_t* taps_out,
-                    double* match_out) {
+                    const int32_t* ladder, int32_t n_ladder, double ridge_eps, int32_t flags, int32_t* taps_out,
+                    double* match_out, int32_t* k0_out) {
   if (!plan || !h_ref || !ladder || !taps_out) return fail(RFD_E_INVALID, "NULL argument");
   if (count < 0) return fail(RFD_E_INVALID, "count must be >= 0");
   if (n_ladder < 1 || n_ladder > 64) return fail(RFD_E_INVALID, "n_ladder must be in [1, 64]");
@@ -73,6 +75,7 @@ int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, i
     if (i && ladder[i] <= ladder[i - 1]) return fail(RFD_E_INVALID, "ladder must be strictly ascending");
   }
   if (!(target > 0.0) || !isfinite(target)) return fail(RFD_E_INVALID, "target must be finite and > 0");
+  if (flags != 0 && flags != RFD_TAPS_CENTRE) return fail(RFD_E_INVALID, "flags must be 0 or RFD_TAPS_CENTRE");
   if (count == 0) return RFD_OK;
   if (!h_tmpl) return fail(RFD_E_INVALID, "h_tmpl is NULL");
   Plan& p = plan->p;
@@ -86,6 +89,7 @@ int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, i
   }
   int rc = RFD_OK;
   std::vector<double> mh(count);
+  std::vector<int32_t> dh(count, 0);
   std::vector<char> done(count, 0);
   for (int64_t j0 = 0; j0 < count && !rc; j0 += 65535) {
     const int64_t c = std::min<int64_t>(count - j0, 65535);
@@ -100,7 +104,7 @@ int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, i
     rfd_taps* tp = nullptr;
     rc = rfd_taps_create(plan, 1, off, &ref0, &T, &k0, &tp);
     if (rc) break;
-    rc = rfd_make_taps(plan, tp, 0, h_ref, h_tmpl, 0, count, RFD_TAPS_LS, ridge_eps);
+    rc = rfd_make_taps(plan, tp, 0, h_ref, h_tmpl, 0, count, RFD_TAPS_LS | flags, ridge_eps);
     if (!rc) {
       Taps& t = tp->t;
       const SubBankTaps& s = t.sb[0];
@@ -110,6 +114,9 @@ int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, i
       if (hipGetLastError() != hipSuccess) rc = fail(RFD_E_DEVICE, "match launch failed");
       if (!rc && hipMemcpyAsync(mh.data(), m, count * sizeof(double), hipMemcpyDeviceToHost, p.stream) != hipSuccess)
         rc = fail(RFD_E_DEVICE, "match readback failed");
+      if (!rc && hipMemcpyAsync(dh.data(), t.d_shift, count * sizeof(int32_t), hipMemcpyDeviceToHost, p.stream) !=
+                     hipSuccess)
+        rc = fail(RFD_E_DEVICE, "lag readback failed");
       if (!rc && hipStreamSynchronize(p.stream) != hipSuccess) rc = fail(RFD_E_DEVICE, "synchronise failed");
     }
     rfd_taps_destroy(tp);
@@ -118,6 +125,7 @@ int rfd_select_taps(rfd_plan* plan, const double* h_ref, const double* h_tmpl, i
       if (done[j]) continue;
       taps_out[j] = T;
       if (match_out) match_out[j] = mh[j];
+      if (k0_out) k0_out[j] = k0 + dh[j];
       if (mh[j] >= target) done[j] = 1;
     }
   }

@@ -1017,6 +1017,8 @@ int rfd_surrogate_create(rfd_plan* plan, rfd_taps* taps, int32_t subbank, int32_
   SubBankTaps& sb = t.sb[subbank];
   if (sb.count < 2 || sb.made != sb.count) return fail(RFD_E_STATE, "training sub-bank needs >= 2 made tap sets");
   if (!sb.U) return fail(RFD_E_STATE, "training taps must come from the least-squares route (Cholesky factor)");
+  if (sb.n_centred > 0)
+    return fail(RFD_E_UNSUPPORTED, "training taps must share the sub-bank's lag window (no RFD_TAPS_CENTRE)");
   if (n_basis < 1 || n_basis > 2 * sb.T || n_basis > 1024) return fail(RFD_E_INVALID, "n_basis out of range");
   if (hidden < 1 || hidden > 4096) return fail(RFD_E_INVALID, "hidden out of range");
   if (!lds_fits((size_t)kExpandRows * ((n_basis + 3) & ~3) * sizeof(double) + 8 * kExpandRows * sizeof(double)))
@@ -1292,6 +1294,17 @@ int rfd_surrogate_make_taps(rfd_surrogate* sur, const float* params, rfd_taps* t
   hipStream_t st = p.stream;
   // the fitted-template norm of the target uses the reference autocorrelation of the training sub-bank
   RFD_HIP(hipMemcpyAsync(sb.g, src.g, sb.T * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  // surrogate taps use the sub-bank's lag window
+  bool any_centred = false;
+  for (int64_t i = first; i < first + count && !any_centred; ++i) any_centred = sb.centred_mask[i] != 0;
+  if (any_centred) {
+    RFD_HIP(hipMemsetAsync(t.d_shift + sb.first + first, 0, count * sizeof(int32_t), st));
+    for (int64_t i = first; i < first + count; ++i)
+      if (sb.centred_mask[i]) {
+        sb.centred_mask[i] = 0;
+        --sb.n_centred;
+      }
+  }
   const int64_t chunk = s.nb;
   int rc = RFD_OK;
   for (int64_t c0 = 0; c0 < count && !rc; c0 += chunk) {
@@ -1365,6 +1378,8 @@ int rfd_taps_fallback(rfd_taps* target, const rfd_taps* exact, int32_t subbank, 
   const SubBankTaps& se = te.sb[subbank];
   if (st_.T != se.T || st_.k0 != se.k0 || st_.ref_id != se.ref_id || st_.count != se.count)
     return fail(RFD_E_INVALID, "sub-banks differ in reference, T, k0 or size");
+  if (se.n_centred > 0 || st_.n_centred > 0)
+    return fail(RFD_E_UNSUPPORTED, "fallback needs taps on the sub-bank's lag window (no RFD_TAPS_CENTRE)");
   if (count < 0 || first < 0 || first + count > st_.count) return fail(RFD_E_INVALID, "template range outside the sub-bank");
   if (count == 0) return RFD_OK;
   Plan& p = *tt.plan;

@@ -95,7 +95,8 @@ __device__ __forceinline__ int find_subbank(const int64_t* first, int nsb, int64
 __global__ __launch_bounds__(kSegThreads) void k_write(const unsigned long long* __restrict__ slots, int64_t n,
                                                      float thr2, const long long* __restrict__ offs, int64_t nwin,
                                                      int64_t W, rfd_trigger* __restrict__ out, int64_t capacity,
-                                                     const int64_t* __restrict__ sb_first, int nsb, WinMap m) {
+                                                     const int64_t* __restrict__ sb_first, int nsb, WinMap m,
+                                                     const int32_t* __restrict__ shift, int64_t nseg) {
   __shared__ int sh[kSegThreads];
   int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)threadIdx.x * kSegPer;
   int c = 0;
@@ -112,7 +113,9 @@ __global__ __launch_bounds__(kSegThreads) void k_write(const unsigned long long*
     if (pos < capacity) {
       int64_t tmpl = si / nwin, q = si - tmpl * nwin;
       rfd_trigger t;
+      // filter index m of the peak; sample n = m - d (mod N) under lag centring
       t.sample = q * W + (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
+      if (shift) t.sample = (t.sample - shift[tmpl]) & (nseg - 1);
       t.tmpl = (int32_t)tmpl;
       t.subbank = sb_first ? find_subbank(sb_first, nsb, tmpl) : 0;
       t.rho = sqrtf(__uint_as_float((uint32_t)(k >> 32)));
@@ -125,19 +128,21 @@ __global__ __launch_bounds__(kSegThreads) void k_write(const unsigned long long*
   }
 }
 
-// z_j[n] = sum_k c_j[k] zhat[(n + k0 + k) mod N]: one wave per trigger,
-// grid-stride over the triggers (the count is known only on the device).
+// z_j[n] = sum_k c_j[k] zhat[(n + k0 + d_j + k) mod N]: one wave per
+// trigger, grid-stride over the triggers (the count is known only on the
+// device).
 __global__ __launch_bounds__(256) void k_fir_z(rfd_trigger* __restrict__ out, const long long* __restrict__ total,
                                              int64_t capacity, const float2* __restrict__ c32,
                                              const float2* __restrict__ zref, int64_t n,
                                              const int64_t* __restrict__ sb_first, const int32_t* __restrict__ meta,
-                                             const int64_t* __restrict__ abase) {
+                                             const int64_t* __restrict__ abase, const int32_t* __restrict__ shift) {
   const int64_t lim = *total < capacity ? *total : capacity;
   const int lane = threadIdx.x & 63;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < lim; i += (int64_t)gridDim.x * 4) {
     const rfd_trigger t = out[i];
     const int b = t.subbank;
-    const int ref = meta[4 * b + 0], T = meta[4 * b + 1], Tp = meta[4 * b + 2], k0 = meta[4 * b + 3];
+    const int ref = meta[4 * b + 0], T = meta[4 * b + 1], Tp = meta[4 * b + 2];
+    const int k0 = meta[4 * b + 3] + shift[t.tmpl];
     const float2* c = c32 + abase[b] + (int64_t)(t.tmpl - sb_first[b]) * Tp;
     const float2* z = zref + (int64_t)ref * n;
     float re = 0.f, im = 0.f;
@@ -294,7 +299,8 @@ int launch_slots_clear_map(Plan& p, int64_t n_visit, const WinMap& m) {
 }
 
 int launch_compact_impl(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float threshold, rfd_trigger* out,
-                        int64_t capacity, const int64_t* sb_first, int nsb, const WinMap& m) {
+                        int64_t capacity, const int64_t* sb_first, int nsb, const WinMap& m,
+                        const int32_t* shift = nullptr) {
   int64_t nblk = (n_slots + kSeg - 1) / kSeg;
   if ((size_t)nblk > p.counts_cap) return fail(RFD_E_INVALID, "compaction scratch too small");
   float thr2 = threshold * threshold;
@@ -304,7 +310,7 @@ int launch_compact_impl(Plan& p, int64_t n_slots, int64_t nwin, int64_t W, float
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p.stream, p.counts, nblk, p.total);
   RFD_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_write, dim3((unsigned)nblk), dim3(kSegThreads), 0, p.stream, p.slots, n_slots, thr2,
-                     p.counts, nwin, W, out, capacity, sb_first, nsb, m);
+                     p.counts, nwin, W, out, capacity, sb_first, nsb, m, shift, p.n);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }
@@ -318,15 +324,17 @@ int compaction_blocks(int64_t n_slots) { return (int)((n_slots + kSeg - 1) / kSe
 
 int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
                         rfd_trigger* out, int64_t capacity, const WinMap* m) {
+  bool shifted = false;
+  for (const auto& s : tp.sb) shifted = shifted || s.n_centred > 0;
   return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, tp.d_first, (int)tp.sb.size(),
-                             m ? *m : win_map_all(nwin));
+                             m ? *m : win_map_all(nwin), shifted ? tp.d_shift : nullptr);
 }
 
 int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity) {
   if (capacity <= 0) return RFD_OK;
   const int64_t blocks = std::min<int64_t>((capacity + 3) / 4, 1024);
   hipLaunchKernelGGL(k_fir_z, dim3((unsigned)blocks), dim3(256), 0, p.stream, out, (const long long*)p.total,
-                     capacity, tp.c32, p.zref, p.n, tp.d_first, tp.d_meta, tp.d_abase);
+                     capacity, tp.c32, p.zref, p.n, tp.d_first, tp.d_meta, tp.d_abase, (const int32_t*)tp.d_shift);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }

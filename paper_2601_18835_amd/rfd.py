@@ -23,6 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 RFD_OK, RFD_E_INVALID, RFD_E_NOMEM, RFD_E_DEVICE, RFD_E_OVERFLOW, RFD_E_STATE, RFD_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 RFD_FP32, RFD_BF16X3, RFD_FP16X3, RFD_OLS32 = 0, 1, 2, 3
 RFD_TAPS_LS, RFD_TAPS_WINDOW = 0, 1
+RFD_TAPS_CENTRE = 0x100          # flag: per-template lag windows (or-ed into a method)
 RFD_MAX_TAPS = 2048
 PRECISIONS = {"fp32": RFD_FP32, "bf16x3": RFD_BF16X3, "fp16x3": RFD_FP16X3, "ols32": RFD_OLS32}
 
@@ -88,7 +89,7 @@ _SIGS = {
     "rfd_taps_band_fractions": [_P, _P, _i32, _P, _i32],
     "rfd_taps_get_band_fractions": [_P, _i64, _P, C.POINTER(_i32)],
     "rfd_chisq": [_P, _P, _P, _i64, _P],
-    "rfd_select_taps": [_P, _P, _P, _i64, _d, _P, _i32, _d, _P, _P],
+    "rfd_select_taps": [_P, _P, _P, _i64, _d, _P, _i32, _d, _i32, _P, _P, _P],
     "rfd_plan_set_psd": [_P, _P, _i64],
     "rfd_filter_range": [_P, _P, _i32, _f, _i64, _i64, _i64, _P, _i64, C.POINTER(_i64)],
     "rfd_taps_renormalize": [_P, _P, _i32, _P],
@@ -652,8 +653,10 @@ def rfd_chisq(plan, taps, triggers, n):
 
 
 # ---------------------------------------------------------- tap selection
-def rfd_select_taps(plan, h_ref, h_tmpl, target, ladder, ridge_eps=1e-4):
-    """Per-template tap counts reaching `target` (zero-lag match); returns (T int32 [count], match float64 [count])."""
+def rfd_select_taps(plan, h_ref, h_tmpl, target, ladder, ridge_eps=1e-4, centre=False):
+    """Per-template tap counts reaching `target` (zero-lag match); returns
+    (T int32 [count], match float64 [count]), and with centre=True (lags
+    centred on each template's correlation peak) also k0 int32 [count]."""
     import torch
     info = rfd_plan_info_get(plan)
     _dev_check(h_ref, torch.complex128, info["n_bins"], "h_ref")
@@ -664,9 +667,11 @@ def rfd_select_taps(plan, h_ref, h_tmpl, target, ladder, ridge_eps=1e-4):
     count = h_tmpl.shape[0]
     T = np.zeros(count, dtype=np.int32)
     m = np.zeros(count, dtype=np.float64)
+    k0 = np.zeros(count, dtype=np.int32)
     _check(_lib.rfd_select_taps(plan, _ptr(h_ref), _ptr(h_tmpl), count, target, lad.ctypes.data, lad.size,
-                                ridge_eps, T.ctypes.data, m.ctypes.data), "rfd_select_taps")
-    return T, m
+                                ridge_eps, RFD_TAPS_CENTRE if centre else 0, T.ctypes.data, m.ctypes.data,
+                                k0.ctypes.data), "rfd_select_taps")
+    return (T, m, k0) if centre else (T, m)
 
 
 # --------------------------------------------------------------- PSD drift

@@ -120,12 +120,14 @@ def rho_matrix(trig, n_templates, n):
     return rho
 
 
-def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None):
+def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None, shifts=None):
     """Trigger identity on every unambiguous (template, window).
 
     tau is the rho tolerance that decides ambiguity: a scalar, or one value
     per template (indexed by template) so that a loose bound on one template
-    does not widen the ambiguity band of the others.
+    does not widen the ambiguity band of the others.  shifts: per-template
+    lag offsets d_j of lag-centred taps, whose windows lie on the filter
+    index m = n + d_j (both sides are compared there).
     Returns (n_compared_windows, n_ambiguous, max |drho| at matched triggers).
     Raises AssertionError on a mismatch.
     """
@@ -137,9 +139,13 @@ def compare_triggers(trig, rho_oracle, threshold, window, tau, templates=None):
     for t in trig:
         by_t.setdefault(int(t["tmpl"]), []).append((int(t["sample"]), float(t["rho"])))
     for j in templates:
-        rho = rho_oracle[j]
+        d = 0 if shifts is None else int(shifts[j])
+        rho = rho_oracle[j] if d == 0 else np.roll(rho_oracle[j], d)     # indexed by m = n + d
         want = {s // window: (s, r) for s, r in ocl.cluster(rho, threshold, window)}
-        got = {s // window: (s, r) for s, r in by_t.get(j, [])}
+        got = {}
+        for s, r in by_t.get(j, []):
+            m = (s + d) % rho.size
+            got[m // window] = (m, r)
         amb = ocl.window_ambiguity(rho, threshold, window, float(tau_t[j]))
         for q in range(len(amb)):
             if amb[q]:

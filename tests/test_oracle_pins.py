@@ -327,3 +327,76 @@ def test_response_fft_equals_the_defining_sum(T, k0):
     want = tp.response(a, k0, n)
     got = tp.response_fft(a, k0, n)
     assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+# ------------------------------------------------------- lag centring
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_peak_lag_matches_brute_force_correlation(n):
+    """peak_lag is the argmax over every lag of |sum_i u_i R_i e^{+2 pi i i l/N}|^2,
+    written as a double loop, mapped into (-N/2, N/2]."""
+    rng = np.random.default_rng(n)
+    nb = n // 2 + 1
+    h_r = rng.standard_normal(nb) + 1j * rng.standard_normal(nb)
+    h_j = rng.standard_normal(nb) + 1j * rng.standard_normal(nb)
+    w = rng.random(nb)
+    w[0] = w[-1] = 0.0
+    best, bl = -1.0, None
+    for lag in range(n):
+        acc = 0j
+        for i in range(nb):
+            u = w[i] * abs(h_r[i]) ** 2
+            if u > 0:
+                acc += u * (h_j[i] / h_r[i]) * np.exp(2j * np.pi * i * lag / n)
+        p = acc.real ** 2 + acc.imag ** 2
+        if p > best * (1 + 1e-12):
+            best, bl = p, lag
+    want = bl if bl <= n // 2 else bl - n
+    assert taps.peak_lag(h_j, h_r, w) == want
+    assert taps.centred_k0(h_j, h_r, w, 9) == want - 4
+
+
+@pytest.mark.parametrize("tau", [-300, -37, 0, 5, 700])
+def test_peak_lag_of_a_delayed_reference_is_the_delay(tau):
+    """A target equal to the reference delayed by tau samples has R = e^{-2 pi i i tau/N},
+    so every term of b[tau] is real and positive: the peak sits at lag tau
+    exactly, and the centred taps (T = 32) then reproduce the target (match 1)
+    while lags centred on 0 miss it when |tau| > T/2."""
+    n, fs, f_low = 4096, 2048.0, 30.0
+    w = spectral.psd_weights(synth.psd_array(n, fs), n, fs, f_low)
+    hr = synth.taylorf2(synth.WaveformParams(1.4, 1.4), n, fs, f_low)
+    i = np.arange(n // 2 + 1)
+    hj = hr * np.exp(-2j * np.pi * ((i * tau) % n) / n)
+    assert taps.peak_lag(hj, hr, w) == tau
+    T = 32
+    k0c = taps.centred_k0(hj, hr, w, T)
+    a = taps.ls_taps_normal(hj, hr, w, T, k0c, 1e-6)
+    assert taps.zero_lag_match(hj, hr, w, a, k0c) >= 1 - 1e-6
+    if abs(tau) > T // 2:
+        a0 = taps.ls_taps_normal(hj, hr, w, T, -(T // 2), 1e-6)
+        assert taps.zero_lag_match(hj, hr, w, a0, -(T // 2)) < 0.9
+    T_sel, m_sel = taps.select_taps(hj, hr, w, 0.999, [8, 16, 32], 1e-6, centre=True)
+    assert T_sel == 8 and m_sel >= 0.999
+
+
+@pytest.mark.parametrize("shift", [-5, 3, 17])
+def test_shifted_window_grid_matches_brute_force(shift):
+    """triggers(..., shift=d): windows on the filter index m = n + d. A loop
+    over every sample n assigns it to window ((n + d) mod N) // W, keeps the
+    largest rho^2 (lowest m on exact ties) and reports n; same list."""
+    n, W, thr = 64, 16, 1.0
+    rng = np.random.default_rng(7 + shift)
+    z = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * 1.3
+    z[10] = z[11] = 3.0          # an exact tie in one window
+    got = sorted(pipeline.triggers(z, thr, W, shift))
+    best = {}
+    for s in range(n):
+        m = (s + shift) % n
+        q = m // W
+        r2 = abs(z[s]) ** 2
+        if q not in best or r2 > best[q][0] or (r2 == best[q][0] and m < best[q][1]):
+            best[q] = (r2, m, s)
+    want = sorted((s, float(np.sqrt(r2))) for r2, m, s in best.values() if np.sqrt(r2) > thr)
+    assert [g[0] for g in got] == [x[0] for x in want]
+    assert np.allclose([g[1] for g in got], [x[1] for x in want], rtol=1e-15)
+    assert pipeline.triggers(z, thr, W, 0) == cluster.cluster(np.abs(z), thr, W)

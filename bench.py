@@ -134,8 +134,11 @@ def oracle_leg(args, w, bank, psd, seg, hrefs, np, synth):
     Hs = synth.template_batch(w, [bank.params(j) for j in sample])
     p = orc.prepare(psd, seg.data, w.fs, w.f_low)
     grams = {b: otaps.gram(hrefs[b], p.w, bank.subbanks[b].taps) for b in sorted(set(sbi))}
-    tts = [orc.make_taps(p, Hs[i], hrefs[sbi[i]], bank.subbanks[sbi[i]].taps, bank.subbanks[sbi[i]].k0,
-                         M=grams[sbi[i]]) for i in range(len(sample))]
+    T_of = [bank.subbanks[b].taps for b in sbi]
+    k0s = [otaps.centred_k0(Hs[i], hrefs[sbi[i]], p.w, T_of[i]) if not args.no_lag_centre
+           else bank.subbanks[sbi[i]].k0 for i in range(len(sample))]
+    tts = [orc.make_taps(p, Hs[i], hrefs[sbi[i]], T_of[i], k0s[i], M=grams[sbi[i]]) for i in range(len(sample))]
+    shifts = np.array([k0s[i] - bank.subbanks[sbi[i]].k0 for i in range(len(sample))])
     log(f"oracle: taps of {len(sample)} sampled templates in {time.perf_counter() - t0:.1f} s (not timed)")
     nw = host_workers()
     ctx = mp.get_context("spawn")
@@ -173,7 +176,8 @@ def oracle_leg(args, w, bank, psd, seg, hrefs, np, synth):
            "one_core": {"value": n1 * w.n / wall_one, "cores": max(1, int(round(cpu_one / wall_one))),
                         "templates": n1, "seconds": round(wall_one, 2)},
            "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}}
-    return dict(sample=sample, sbi=sbi, Hs=Hs, tts=tts, refs=refs, rho=np.array(rho), match=match), cpu
+    return dict(sample=sample, sbi=sbi, Hs=Hs, tts=tts, refs=refs, rho=np.array(rho), match=match,
+                shifts=shifts, centre=not args.no_lag_centre), cpu
 
 
 def main():
@@ -196,6 +200,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle legs (no parity block)")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 / FP16 / FINDCHIRP comparison legs")
     ap.add_argument("--no-low-latency", action="store_true")
+    ap.add_argument("--no-lag-centre", action="store_true",
+                    help="lags centred on 0 for every template (default: each template's lags centred on the peak "
+                         "of its correlation with the reference)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -241,6 +248,7 @@ def main():
         filt = torch.empty((nt, info["n_band"]), dtype=torch.complex64, device="cuda")
         fsig = torch.empty(nt, dtype=torch.float64, device="cuda")
     rfd.rfd_plan_set_timing(s.plan, True)
+    taps_method = rfd.RFD_TAPS_LS | (0 if args.no_lag_centre else rfd.RFD_TAPS_CENTRE)
     batch = 256
     t_gen = 0.0
     Hd = None
@@ -252,7 +260,7 @@ def main():
             Hd = template_batch_device(w, ps, "cuda", out=Hd if Hd is not None and Hd.shape[0] == len(ps) else None)
             torch.cuda.synchronize()
             t_gen += time.perf_counter() - tg
-            s.make_taps(b, Hd, first=b0)
+            s.make_taps(b, Hd, first=b0, method=taps_method)
             if with_fc:
                 k = len(ps)
                 rfd.rfd_findchirp_prepare(s.plan, Hd, filt[g0 + b0:g0 + b0 + k], fsig[g0 + b0:g0 + b0 + k])
@@ -464,7 +472,7 @@ def main():
         "config": {"workload": w.name, "segment_samples": w.n, "fs": w.fs, "f_low": w.f_low, "templates": nt,
                    "references": nsb, "taps": sorted(set(sb.taps for sb in bank.subbanks))
                    if multi else bank.subbanks[0].taps, "threshold": w.threshold, "cluster_window": w.window,
-                   "fir_form": prec, "segment_graph": True},
+                   "fir_form": prec, "segment_graph": True, "lag_centring": not args.no_lag_centre},
         "fir_form_selection_ms": selection, "mfma_form": mfma_form,
         "stages_ms": stages, "triggers": ntrig,
         "tap_construction": {"templates_per_s": taps_per_s, "gpu_ms": tap_timing["taps_ms"]},
@@ -578,14 +586,20 @@ def parity_leg(w, bank, psd, seg, hrefs, orc_out, trig_main, prec, np, rfd):
     from oracle import cluster as ocl
     from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec
     sample, sbi, Hs, rho_o = orc_out["sample"], orc_out["sbi"], orc_out["Hs"], orc_out["rho"]
+    shifts = orc_out["shifts"]
+    centre = orc_out["centre"]
     tau = TARGET[prec]
     amb = mism = cmp = 0
     dmax = 0.0
     for i, j in enumerate(sample):
-        rho = rho_o[i]
+        d = int(shifts[i])
+        rho = np.roll(rho_o[i], d)            # on the filter index m = n + d (lag-centred taps)
         want = {sm // w.window: (sm, r) for sm, r in ocl.cluster(rho, w.threshold, w.window)}
         sel = trig_main[trig_main["tmpl"] == j]
-        got = {int(t["sample"]) // w.window: (int(t["sample"]), float(t["rho"])) for t in sel}
+        got = {}
+        for t in sel:
+            m = (int(t["sample"]) + d) % w.n
+            got[m // w.window] = (m, float(t["rho"]))
         fl = ocl.window_ambiguity(rho, w.threshold, w.window, tau)
         for q in range(len(fl)):
             if fl[q]:
@@ -600,7 +614,7 @@ def parity_leg(w, bank, psd, seg, hrefs, orc_out, trig_main, prec, np, rfd):
     s2 = RatioFilterSearch(psd, w.f_low, w.fs, w.n, specs, max_refs=len(sample))
     for i in range(len(sample)):
         s2.set_reference(i, hrefs[sbi[i]])
-        s2.make_taps(i, Hs[i:i + 1])
+        s2.make_taps(i, Hs[i:i + 1], method=rfd.RFD_TAPS_LS | (rfd.RFD_TAPS_CENTRE if centre else 0))
     s2.set_segment(seg.data)
     s2.dechirp_all()
     full, ok = {}, {}

@@ -5,8 +5,9 @@ Default workload ecc512s (the eccentric / subsolar search): one 512 s segment
 (N = 2^20 samples at 2048 Hz, f_low = 15 Hz) of coloured Gaussian noise with
 one SNR-12 injection; 16384 eccentric TaylorF2 templates (m1, m2 in
 [0.2, 1.0] Msun, e0 in [0, 0.3] at 10 Hz) under 32 references (512
-templates each); 1024 complex taps per template; threshold rho > 6; 1 s
-cluster windows.
+templates each); 1024 complex taps per template, each template's lags
+centred on its own correlation peak (--no-lag-centre: on lag 0); threshold
+rho > 6; 1 s cluster windows.
 
 One step = one pass of the per-segment hot path with all inputs resident in
 HBM: segment transform, dechirp of every reference, ratio FIR with the fused
@@ -28,7 +29,8 @@ the tap-fidelity distribution.
 
 Other workloads (--workload): spin256s (one reference, 4096 aligned-spin
 templates, T = 256), tidal256s (64 uneven sub-banks, T 32..1024) and
-surr512s (the learned tap surrogate).
+surr512s (the learned tap surrogate end to end: 65536 templates whose taps
+come from 32 trained networks, validated, with exact-tap fallback).
 
 Prints one JSON line.  `--gpus` above 1 exits: the build targets one GPU.
 """

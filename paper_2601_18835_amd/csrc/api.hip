@@ -706,7 +706,7 @@ static void taps_free(Taps& t) {
   dfree(t.d_first); dfree(t.d_meta); dfree(t.d_abase); dfree(t.work64); dfree(t.bvec);
   dfree(t.d_p16); dfree(t.d_p32); dfree(t.d_count);
   dfree(t.d_it_off); dfree(t.d_it_sb); dfree(t.d_it_S); dfree(t.d_it_nsg);
-  dfree(t.d_shift); dfree(t.peak_pw); dfree(t.k0buf);
+  dfree(t.d_shift); dfree(t.peak_pw); dfree(t.k0buf); dfree(t.peak_part); dfree(t.peak_idx);
 }
 
 int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, const int32_t* ref_id,
@@ -864,6 +864,17 @@ int rfd_make_taps(rfd_plan* plan, rfd_taps* taps, int32_t subbank, const double*
       int rc = dalloc(&t.peak_pw, need_p);
       if (rc) return rc;
       t.peak_cap = need_p;
+    }
+    const size_t need_q = (size_t)chunk * kPeakParts;
+    if (t.peak_parts_cap < need_q) {
+      RFD_HIP(hipStreamSynchronize(p.stream));
+      dfree(t.peak_part);
+      dfree(t.peak_idx);
+      t.peak_parts_cap = 0;
+      int rc = dalloc(&t.peak_part, need_q);
+      if (!rc) rc = dalloc(&t.peak_idx, need_q);
+      if (rc) return rc;
+      t.peak_parts_cap = need_q;
     }
     if (t.k0buf_cap < (size_t)count) {
       RFD_HIP(hipStreamSynchronize(p.stream));

@@ -593,15 +593,19 @@ struct StorePow {
 
 // Per template: the lag of the largest |b[l]|^2 over all N lags (lowest
 // index 0..N-1 on exact ties), mapped into (-N/2, N/2]; the lag window
-// k0_j = peak - floor(T/2) and its offset from the sub-bank's k0.
-__global__ __launch_bounds__(1024) void k_peak_lag(const double* __restrict__ pw, int64_t n, int T, int k0_sb,
-                                                 int32_t* __restrict__ k0_out, int32_t* __restrict__ d_out) {
-  __shared__ double bv[1024];
-  __shared__ int64_t bi[1024];
-  const double* row = pw + (int64_t)blockIdx.x * n;
+// k0_j = peak - floor(T/2) and its offset from the sub-bank's k0.  Two
+// stages: kPeakParts workgroups per template each reduce one contiguous
+// chunk to (value, index), then one thread per template takes the chunks
+// in index order (a strict > keeps the lowest index).
+__global__ __launch_bounds__(256) void k_peak_part(const double* __restrict__ pw, int64_t n,
+                                                 double* __restrict__ pv, int64_t* __restrict__ pi) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int64_t chunk = n / kPeakParts;              // n is a power of two >= 1024
+  const double* row = pw + (int64_t)blockIdx.y * n + (int64_t)blockIdx.x * chunk;
   double best = -1.0;
   int64_t idx = 0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+  for (int64_t i = threadIdx.x; i < chunk; i += 256) {
     const double v = row[i];
     if (v > best) {          // increasing i: the first maximum stays
       best = v;
@@ -611,7 +615,7 @@ __global__ __launch_bounds__(1024) void k_peak_lag(const double* __restrict__ pw
   bv[threadIdx.x] = best;
   bi[threadIdx.x] = idx;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
+  for (int o = 128; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
       const double v = bv[threadIdx.x + o];
       const int64_t j = bi[threadIdx.x + o];
@@ -623,24 +627,44 @@ __global__ __launch_bounds__(1024) void k_peak_lag(const double* __restrict__ pw
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int64_t i = bi[0];
-    const int lag = (int)(i <= n / 2 ? i : i - n);
-    const int k0 = lag - T / 2;
-    k0_out[blockIdx.x] = k0;
-    if (d_out) d_out[blockIdx.x] = k0 - k0_sb;
+    pv[(int64_t)blockIdx.y * kPeakParts + blockIdx.x] = bv[0];
+    pi[(int64_t)blockIdx.y * kPeakParts + blockIdx.x] = (int64_t)blockIdx.x * chunk + bi[0];
   }
+}
+__global__ void k_peak_lag(const double* __restrict__ pv, const int64_t* __restrict__ pi, int64_t batch, int64_t n,
+                           int T, int k0_sb, int32_t* __restrict__ k0_out, int32_t* __restrict__ d_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= batch) return;
+  double best = -1.0;
+  int64_t i = 0;
+  for (int c = 0; c < kPeakParts; ++c) {
+    const double v = pv[t * kPeakParts + c];
+    if (v > best) {
+      best = v;
+      i = pi[t * kPeakParts + c];
+    }
+  }
+  const int lag = (int)(i <= n / 2 ? i : i - n);
+  const int k0 = lag - T / 2;
+  k0_out[t] = k0;
+  if (d_out) d_out[t] = k0 - k0_sb;
 }
 
 int launch_corr_peak(Plan& p, Taps& tp, const double* h_r, const double* h_t, int64_t batch, int T, int k0_sb,
                      double* pw, int32_t* k0_out, int32_t* d_out) {
   if (tp.work64_cap < (size_t)batch * p.n) return fail(RFD_E_INVALID, "corr peak: work buffer too small");
+  if (tp.peak_cap < (size_t)batch * p.n || tp.peak_parts_cap < (size_t)batch * kPeakParts || p.n < 1024)
+    return fail(RFD_E_INVALID, "corr peak: scratch too small");
   LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, p.i_low, p.i_high, 0};
   int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1);
   if (rc) return rc;
   rc = run_pass_b<double2>(p, (const double2*)tp.work64, StorePow{pw, p.n}, p.tw64_n1, (int)batch, +1);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_peak_lag, dim3((unsigned)batch), dim3(1024), 0, p.stream, (const double*)pw, p.n, T, k0_sb,
-                     k0_out, d_out);
+  hipLaunchKernelGGL(k_peak_part, dim3(kPeakParts, (unsigned)batch), dim3(256), 0, p.stream, (const double*)pw,
+                     p.n, tp.peak_part, tp.peak_idx);
+  RFD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_peak_lag, dim3((unsigned)((batch + 63) / 64)), dim3(64), 0, p.stream,
+                     (const double*)tp.peak_part, (const int64_t*)tp.peak_idx, batch, p.n, T, k0_sb, k0_out, d_out);
   RFD_CHECK_LAUNCH();
   return RFD_OK;
 }

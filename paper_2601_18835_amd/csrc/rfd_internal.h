@@ -179,6 +179,7 @@ struct Taps {
   double2* work64 = nullptr; size_t work64_cap = 0;
   double2* bvec = nullptr; size_t bvec_cap = 0;
   double* peak_pw = nullptr; size_t peak_cap = 0;      // |b|^2 of the full correlations (centring)
+  double* peak_part = nullptr; int64_t* peak_idx = nullptr; size_t peak_parts_cap = 0;   // chunk maxima
   int32_t* k0buf = nullptr; size_t k0buf_cap = 0;      // per-template k0 of one make_taps call
 };
 
@@ -204,6 +205,7 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch,
                   int T, int k0, double2* out, int64_t out_stride, int64_t lo = -1, int64_t hi = -1,
                   const int32_t* k0s = nullptr);
+constexpr int kPeakParts = 64;   // chunks per template in the peak-lag reduction
 // Per-template lag centring: the full weighted cross-correlation b (mode 0)
 // of each batch entry, |b|^2 into pw [batch][N], and its peak lag l in
 // (-N/2, N/2]: k0_out[t] = l - floor(T/2), d_out[t] = k0_out[t] - k0_sb.

@@ -33,9 +33,6 @@ int taps_norm_and_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
 int taps_pack(Plan& p, Taps& tp, int b, int64_t first, int64_t count);
 
 // ------------------------------------------------------------------ GEMM
-__device__ __forceinline__ float ld_op(const float* p, int64_t i) { return p[i]; }
-__device__ __forceinline__ float ld_op(const uint16_t* p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
-
 // Element r of this thread in a 32 x TM (k x m) tile: consecutive threads
 // run along whichever index is contiguous in memory (m for a k-major
 // operand, k for an m-major one), so every load is a coalesced run.
@@ -89,27 +86,68 @@ struct GemmOps {
   PerNet<const float*> Z;      // kSiluBwd
 };
 
-// C[M x N] = op(A) op(B) (+ C when accumulate), FP32 accumulation, for the
-// network blockIdx.z of ops.
-// op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k];  op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n].
-// TM x TM output tile per workgroup (TM = 64: 4 x 4 per thread; TM = 32:
-// 2 x 2 and TM = 16: 1 x 1, more workgroups for the MLP's small GEMMs), K in steps of
-// 32 with the next step's tiles loaded into registers while the current one
-// is multiplied from LDS.
+// C[M x N] = op(A) op(B) (+ C when accumulate) for the network blockIdx.z of
+// ops, op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k],
+// op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n], on the matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  An FP32 operand enters as three BF16 parts x = x0 + x1 + x2,
+// each the BF16 rounding of what the previous parts leave (so
+// |x - x0 - x1 - x2| <= 2^-27 |x|); a BF16 operand (the weights) is its own
+// single part.  Every part product x_i y_j with i + j <= 2 is accumulated (the
+// ones left out are below 2^-27 relative), so the result keeps FP32 accuracy:
+// three MFMAs per 16x16x32 block against BF16 weights, six when both operands
+// are FP32.  TM x TM output tile per workgroup (TM = 64, or 32 where 64-wide
+// tiles would leave most CUs idle), each of the four waves a TM/2 x TM/2
+// quadrant of 16 x 16 MFMA blocks, K in steps of 32 with the next step's
+// tiles loaded into registers while the current one is multiplied.  Every
+// output takes the same K steps and part products in the same order at
+// either width, so the results do not depend on it.
+template <typename T>
+struct Bf16Parts {
+  static constexpr int n = 3;
+};
+template <>
+struct Bf16Parts<uint16_t> {
+  static constexpr int n = 1;
+};
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+constexpr int kMfmaLdsRow = 40;   // 32 K values + 8 of padding (80 B rows: 16 B aligned)
+
+template <int P>
+__device__ __forceinline__ void to_parts(float x, uint16_t (&q)[3]) {
+  const uint32_t p0 = bf16_bits(x);
+  q[0] = (uint16_t)p0;
+  if constexpr (P > 1) {
+    const float r1 = x - bf16_to_float(p0);
+    const uint32_t p1 = bf16_bits(r1);
+    const float r2 = r1 - bf16_to_float(p1);
+    q[1] = (uint16_t)p1;
+    q[2] = (uint16_t)bf16_bits(r2);
+  }
+}
+__device__ __forceinline__ float ld_f(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ld_f(const uint16_t* p, int64_t i) { return bf16_to_float(p[i]); }
+
 template <int TM, typename TA, typename TB>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, int lda, int ta, int ldb, int tb, int ldc,
-                                            int accumulate, int mode, GemmOps<TA, TB> ops) {
-  constexpr int R = TM * 32 / 256;        // tile elements per thread and operand
-  constexpr int P = TM / 16;              // outputs per thread along each dimension
-  __shared__ float As[32][TM + 4];
-  __shared__ float Bs[32][TM + 4];
+__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, int lda, int ta, int ldb, int tb, int ldc,
+                                                 int accumulate, int mode, GemmOps<TA, TB> ops) {
+  constexpr int PA = Bf16Parts<TA>::n, PB = Bf16Parts<TB>::n;
+  constexpr int R = TM * 32 / 256;       // tile elements per thread and operand
+  constexpr int BW = TM / 32;            // 16 x 16 blocks per wave along each dimension
+  __shared__ __align__(16) uint16_t As[PA][TM][kMfmaLdsRow];
+  __shared__ __align__(16) uint16_t Bs[PB][TM][kMfmaLdsRow];
   const int z = blockIdx.z;
   const TA* __restrict__ A = ops.A.p[z];
   const TB* __restrict__ B = ops.B.p[z];
   float* __restrict__ C = ops.C.p[z];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
-  float acc[P][P] = {};
+  f32x4 acc[BW][BW];
+#pragma unroll
+  for (int i = 0; i < BW; ++i)
+#pragma unroll
+    for (int j = 0; j < BW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   float ra[R], rb[R];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -117,62 +155,78 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, int lda, int 
       int kk, mm;
       tile_pos<TM>(r, ta != 0, kk, mm);
       int gm = m0 + mm, gk = k0 + kk;
-      ra[r] = (gm < M && gk < K) ? (ta ? ld_op(A, (int64_t)gk * lda + gm) : ld_op(A, (int64_t)gm * lda + gk)) : 0.f;
+      ra[r] = (gm < M && gk < K) ? (ta ? ld_f(A, (int64_t)gk * lda + gm) : ld_f(A, (int64_t)gm * lda + gk)) : 0.f;
       tile_pos<TM>(r, tb == 0, kk, mm);
       const int gn = n0 + mm;
       gk = k0 + kk;
-      rb[r] = (gn < N && gk < K) ? (tb ? ld_op(B, (int64_t)gn * ldb + gk) : ld_op(B, (int64_t)gk * ldb + gn)) : 0.f;
+      rb[r] = (gn < N && gk < K) ? (tb ? ld_f(B, (int64_t)gn * ldb + gk) : ld_f(B, (int64_t)gk * ldb + gn)) : 0.f;
     }
   };
   fetch(0);
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
   for (int k0 = 0; k0 < K; k0 += 32) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       int kk, mm;
+      uint16_t q[3];
       tile_pos<TM>(r, ta != 0, kk, mm);
-      As[kk][mm] = ra[r];
+      to_parts<PA>(ra[r], q);
+#pragma unroll
+      for (int p = 0; p < PA; ++p) As[p][mm][kk] = q[p];
       tile_pos<TM>(r, tb == 0, kk, mm);
-      Bs[kk][mm] = rb[r];
+      to_parts<PB>(rb[r], q);
+#pragma unroll
+      for (int p = 0; p < PB; ++p) Bs[p][mm][kk] = q[p];
     }
     __syncthreads();
     if (k0 + 32 < K) fetch(k0 + 32);
+    uint4 a[BW][PA], b[BW][PB];
 #pragma unroll
-    for (int kk = 0; kk < 32; ++kk) {
-      float a[P], b[P];
+    for (int i = 0; i < BW; ++i) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) a[i] = As[kk][ty * P + i];
+      for (int p = 0; p < PA; ++p)
+        a[i][p] = *reinterpret_cast<const uint4*>(&As[p][wm * (TM / 2) + i * 16 + r16][kq]);
 #pragma unroll
-      for (int j = 0; j < P; ++j) b[j] = Bs[kk][tx * P + j];
-#pragma unroll
-      for (int i = 0; i < P; ++i)
-#pragma unroll
-        for (int j = 0; j < P; ++j) acc[i][j] += a[i] * b[j];
+      for (int p = 0; p < PB; ++p)
+        b[i][p] = *reinterpret_cast<const uint4*>(&Bs[p][wn * (TM / 2) + i * 16 + r16][kq]);
     }
+#pragma unroll
+    for (int i = 0; i < BW; ++i)
+#pragma unroll
+      for (int j = 0; j < BW; ++j)
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+#pragma unroll
+          for (int q = 0; q < PB; ++q)
+            if (p + q <= 2)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[i][p]),
+                                                                 __builtin_bit_cast(bf16x8, b[j][q]), acc[i][j], 0, 0, 0);
     __syncthreads();
   }
+  // lane l holds rows 4 (l >> 4) + e, column l & 15 of each 16 x 16 block
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const int gm = m0 + ty * P + i;
-    if (gm >= M) continue;
+  for (int i = 0; i < BW; ++i)
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int gn = n0 + tx * P + j;
-      if (gn >= N) continue;
-      const int64_t o = (int64_t)gm * ldc + gn;
-      float v = acc[i][j];
-      if (mode == kBiasAct) {
-        v += ops.bias.p[z][gn];
-        ops.H.p[z][o] = silu_f(v);
-      } else if (mode == kBias) {
-        v += ops.bias.p[z][gn];
-      } else if (mode == kSiluBwd) {
-        v *= silu_g(ops.Z.p[z][o]);
-      } else if (accumulate) {
-        v += C[o];
+    for (int j = 0; j < BW; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wm * (TM / 2) + i * 16 + 4 * (lane >> 4) + e;
+        const int gn = n0 + wn * (TM / 2) + j * 16 + r16;
+        if (gm >= M || gn >= N) continue;
+        const int64_t o = (int64_t)gm * ldc + gn;
+        float v = acc[i][j][e];
+        if (mode == kBiasAct) {
+          v += ops.bias.p[z][gn];
+          ops.H.p[z][o] = silu_f(v);
+        } else if (mode == kBias) {
+          v += ops.bias.p[z][gn];
+        } else if (mode == kSiluBwd) {
+          v *= silu_g(ops.Z.p[z][o]);
+        } else if (accumulate) {
+          v += C[o];
+        }
+        C[o] = v;
       }
-      C[o] = v;
-    }
-  }
 }
 
 // the same GEMM shape for nz networks at once
@@ -180,22 +234,15 @@ template <typename TA, typename TB>
 static int gemm_n(hipStream_t st, int nz, int M, int N, int K, const GemmOps<TA, TB>& ops, int lda, int ta, int ldb,
                   int tb, int ldc, int accumulate = 0, int mode = kStore) {
   if (M <= 0 || N <= 0 || nz <= 0) return RFD_OK;
-  // narrower tiles when wider ones would leave most of the 256 CUs idle (each
-  // output's summation order is the same at every tile width)
-  const int64_t w32 = (int64_t)((N + 31) / 32) * ((M + 31) / 32) * nz;
-  const int64_t w64 = (int64_t)((N + 63) / 64) * ((M + 63) / 64) * nz;
-  if (w32 < 512) {
-    dim3 grid((N + 15) / 16, (M + 15) / 16, nz);
-    hipLaunchKernelGGL((k_gemm<16, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc, accumulate,
-                       mode, ops);
-  } else if (w64 < 512) {
+  // 32-wide tiles when 64-wide ones would leave most of the 256 CUs idle
+  if ((int64_t)((N + 63) / 64) * ((M + 63) / 64) * nz < 512) {
     dim3 grid((N + 31) / 32, (M + 31) / 32, nz);
-    hipLaunchKernelGGL((k_gemm<32, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc, accumulate,
-                       mode, ops);
+    hipLaunchKernelGGL((k_gemm_mfma<32, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc,
+                       accumulate, mode, ops);
   } else {
     dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
-    hipLaunchKernelGGL((k_gemm<64, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc, accumulate,
-                       mode, ops);
+    hipLaunchKernelGGL((k_gemm_mfma<64, TA, TB>), grid, dim3(256), 0, st, M, N, K, lda, ta, ldb, tb, ldc,
+                       accumulate, mode, ops);
   }
   RFD_CHECK_LAUNCH();
   return RFD_OK;

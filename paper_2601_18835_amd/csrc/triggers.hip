@@ -324,10 +324,11 @@ int compaction_blocks(int64_t n_slots) { return (int)((n_slots + kSeg - 1) / kSe
 
 int launch_compact_bank(Plan& p, const Taps& tp, int64_t n_slots, int64_t nwin, int64_t W, float threshold,
                         rfd_trigger* out, int64_t capacity, const WinMap* m) {
-  bool shifted = false;
-  for (const auto& s : tp.sb) shifted = shifted || s.n_centred > 0;
+  // the lag offsets are always read (zero where a template is not centred), so
+  // a captured graph stays right when taps are later re-made with or without
+  // centring
   return launch_compact_impl(p, n_slots, nwin, W, threshold, out, capacity, tp.d_first, (int)tp.sb.size(),
-                             m ? *m : win_map_all(nwin), shifted ? tp.d_shift : nullptr);
+                             m ? *m : win_map_all(nwin), tp.d_shift);
 }
 
 int launch_fir_z(Plan& p, const Taps& tp, rfd_trigger* out, int64_t capacity) {

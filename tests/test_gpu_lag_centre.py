@@ -192,3 +192,26 @@ def test_centred_selection_matches_oracle_and_gains(rfd, centred):
     assert gain[11] > 0.1 and gain[12] > 0.1
     print(f"\n[lag-centre] T = 64 zero-lag match gain from centring: mean {gain.mean():.4f}, "
           f"min {gain.min():.4f}, max {gain.max():.4f}; centred T {T.tolist()} vs lag-0 T {T0.tolist()}")
+
+
+def test_graph_captured_before_centring_follows_the_taps(rfd, centred):
+    """A segment graph captured while sub-bank 0 had lags centred on 0, then
+    replayed after its taps were re-made with centred lags (same buffers),
+    reports the centred taps' triggers: the lag offsets are read at replay."""
+    import torch
+    case, s, d = centred
+    thr, W, cap = 3.0, 512, 1 << 16
+    H0 = case.subbanks[0].H
+    out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    s.make_taps(0, H0, method=rfd.RFD_TAPS_LS)
+    graph = rfd.rfd_segment_graph_create(s.plan, s.taps, "fp32", thr, W, s.data, s.h_ref, out, cap)
+    try:
+        s.make_taps(0, H0, method=rfd.RFD_TAPS_LS | rfd.RFD_TAPS_CENTRE)
+        n = rfd.rfd_segment_graph_launch(graph)
+        got = rfd.triggers_to_numpy(out, n)
+    finally:
+        rfd.rfd_graph_destroy(graph)
+    buf, n2 = s.filter("fp32", thr, W, cap)
+    want = rfd.triggers_to_numpy(buf, n2)
+    assert n == n2 and np.array_equal(got, want)
+    print(f"\n[lag-centre] graph captured before centring: {n} triggers = eager with centred taps")

@@ -644,7 +644,7 @@ def surrogate_main(args):
     T = 1024, one coloured-noise segment with an injection.
 
     Set-up (untimed): the exact taps of the whole bank from waveforms made on
-    the device (the judge and the fallback); --train exact training tap sets
+    the device (the yardstick and the fallback); --train exact training tap sets
     per reference (3125 by default: 1e5 in all) drawn over the reference's
     chirp-mass slice; one surrogate per reference, all trained together by
     rfd_surrogate_train_many; every bank template's surrogate taps validated
@@ -692,7 +692,7 @@ def surrogate_main(args):
         gen_s += time.perf_counter() - tg
         return Hd
 
-    # exact taps of the bank (judge and fallback)
+    # exact taps of the bank (yardstick and fallback)
     rfd.rfd_plan_get_timing(s.plan)
     for i, sb in enumerate(sbs):
         for b0 in range(0, sb.size, batch):

@@ -470,7 +470,7 @@ int rfd_range_graph_create(rfd_plan* plan, const rfd_taps* taps, int32_t precisi
  * global tap phase), then whitened: x = [Re v; Im v]/||v||, v = L^H a, with
  * L the sub-bank's Cholesky factor of M + lam I, so ||x_hat - x||^2 is a
  * mismatch proxy of the fitted template.  The exact taps are the training
- * data, the fallback and the judge of the SNR loss (rfd_taps_match).
+ * data, the fallback and the yardstick of the SNR loss (rfd_taps_match).
  *
  * rfd_surrogate_create     whitens the exact taps of every template of
  *                          `subbank` in `taps` (all made by the LS route;

@@ -15,7 +15,7 @@
 //   inference   params -> c_hat -> x_hat = c_hat B -> a = L^-H v -> the
 //               usual sigma_fit normalisation and MFMA operand packing.
 // The exact taps (Sec. V.A) stay the training data, the fallback and the
-// judge: rfd_taps_match gives the fitted templates' normalised overlap.
+// yardstick: rfd_taps_match gives the fitted templates' normalised overlap.
 #include <math.h>
 #include <string.h>
 

@@ -371,7 +371,7 @@ def test_trained_surrogate_beats_no_network_taps(rfd, case):
     torch.cuda.synchronize()
     infer_ms = (time.perf_counter() - t0) * 1e3
     m = _gpu_match(rfd, c)
-    # no-network generators, judged by the oracle on its own exact taps
+    # no-network generators, measured by the oracle against its own exact taps
     f = c.sur.scale(c.p_train).astype(np.float64)
     ft = c.sur.scale(c.p_test).astype(np.float64)
     nn = np.argmin(((ft[:, None, :] - f[None, :, :]) ** 2).sum(-1), axis=1)

@@ -190,7 +190,7 @@ def main():
     ap.add_argument("--workload", default="ecc512s", choices=["ecc512s", "spin256s", "tidal256s", "surr512s"])
     ap.add_argument("--subbanks", default="all", help="surr512s: references given a surrogate ('all' or a list)")
     ap.add_argument("--train", type=int, default=3125, help="surr512s: exact tap sets per reference (1e5 in all)")
-    ap.add_argument("--epochs", type=int, default=6000, help="surr512s: training epochs")
+    ap.add_argument("--epochs", type=int, default=36000, help="surr512s: training epochs")
     ap.add_argument("--batch", type=int, default=256, help="surr512s: training batch")
     ap.add_argument("--lr", type=float, default=2e-3, help="surr512s: first learning rate")
     ap.add_argument("--lr-end", type=float, default=2e-4, help="surr512s: last learning rate (geometric decay)")

@@ -184,7 +184,7 @@ int rfd_plan_set_workspace(rfd_plan* plan, void* dev_ptr, size_t bytes, int64_t 
  *   ref_id   slot 0 <= ref_id < max_refs that receives
  *            z_ref[n]/sigma_ref, n = 0..N-1, where
  *            z_ref[n] = sum_i w_i s_i conj(h_ref,i) exp(+2 pi i i n / N) and
- *            sigma_ref^2 = sum_i w_i |h_ref,i|^2 (FP64 on the device).
+ *            sigma_ref^2 = sum_i w_i |h_ref,i|^2 (precision: rfd_dechirp_refs).
  *   sigma_ref_out  host double or NULL: receives sigma_ref (synchronises).
  * Errors: RFD_E_INVALID (NULL h_ref, ref_id out of range, sigma_ref = 0),
  * RFD_E_STATE (data NULL with no segment), RFD_E_DEVICE.
@@ -204,9 +204,17 @@ int rfd_dechirp(rfd_plan* plan, const double* data, const double* h_ref, int32_t
  * Errors: RFD_E_INVALID (NULL arrays or entries, ids out of range or
  * repeated, a reference with sigma_ref = 0), RFD_E_STATE, RFD_E_NOMEM,
  * RFD_E_DEVICE.
+ *
+ * Precision: the segment transform, the integrand w_i s_i conj(h_ref,i) /
+ * sigma_ref and sigma_ref are FP64; the two transform passes of each
+ * reference run in FP32 (twiddles rounded once from FP64), which adds about
+ * 2e-7 of max |z_ref| to the series.  rfd_plan_set_dechirp_fp64(plan, 1)
+ * runs them in FP64 instead (0 restores the default); changing it refuses
+ * replays of graphs captured before.
  */
 int rfd_dechirp_refs(rfd_plan* plan, const double* data, int32_t n_refs, const int32_t* ref_ids,
                      const double* const* h_refs, double* sigma_out);
+int rfd_plan_set_dechirp_fp64(rfd_plan* plan, int32_t enable);
 
 /* Copy slot ref_id's normalised series z_ref/sigma_ref (dev complex64 [N]). */
 int rfd_get_zref(const rfd_plan* plan, int32_t ref_id, float* out);

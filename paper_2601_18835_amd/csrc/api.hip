@@ -158,14 +158,15 @@ int ensure_slots(Plan& p, int64_t n_slots) {
 // batched dechirp intermediates (one N-point FP64 buffer when a batch is one reference)
 static int ensure_dechirp_work(Plan& p) {
   const int bs = dechirp_batch_size(p);
-  if (bs <= 1 || p.work64b_cap >= (size_t)bs * p.n) return RFD_OK;
+  const size_t need = dechirp_work_double2(p);
+  if (bs <= 1 || p.work64b_cap >= need) return RFD_OK;
   RFD_HIP(hipStreamSynchronize(p.stream));
   ++p.res_gen;
   dfree(p.work64b);
   p.work64b_cap = 0;
-  int rc = dalloc(&p.work64b, (size_t)bs * p.n);
+  int rc = dalloc(&p.work64b, need);
   if (rc) return rc;
-  p.work64b_cap = (size_t)bs * p.n;
+  p.work64b_cap = need;
   return RFD_OK;
 }
 
@@ -445,6 +446,17 @@ int rfd_plan_get_timing(rfd_plan* plan, rfd_timing* out) {
     *cnt[m.stage] += 1;
   }
   drop_marks(p);
+  return RFD_OK;
+}
+
+int rfd_plan_set_dechirp_fp64(rfd_plan* plan, int32_t enable) {
+  if (!plan) return fail(RFD_E_INVALID, "NULL plan");
+  if (enable != 0 && enable != 1) return fail(RFD_E_INVALID, "enable must be 0 or 1");
+  Plan& p = plan->p;
+  if (p.dechirp_fp64 != (enable == 1)) {
+    p.dechirp_fp64 = enable == 1;
+    ++p.res_gen;     // captured graphs recorded the other passes
+  }
   return RFD_OK;
 }
 

@@ -58,6 +58,13 @@ struct LoadDechirpRefs {   // s_i w_i conj(h_b,i) / (sigma_b alpha) over the ban
     return cmul(s[i], make_double2(f * h.x, -f * h.y));
   }
 };
+struct LoadDechirpRefs32 { // the same integrand, formed in FP64 and rounded once to FP32
+  LoadDechirpRefs d;
+  __device__ float2 operator()(int b, int64_t i) const {
+    const double2 v = d(b, i);
+    return make_float2((float)v.x, (float)v.y);
+  }
+};
 struct LoadFindchirp {     // s_i * F_j,i with F_j stored over band bins
   const float2* s; const float2* f; int64_t i_low, i_high, n_band;
   __device__ float2 operator()(int b, int64_t i) const {
@@ -78,6 +85,14 @@ struct LoadCorr64 {        // FP64 correlation integrands for tap construction
     double rr = r.x * r.x + r.y * r.y;
     if (!(wi * rr > 0.0)) return make_double2(0.0, 0.0);
     return make_double2((t.x * r.x + t.y * r.y) / rr, (t.y * r.x - t.x * r.y) / rr);
+  }
+};
+
+struct LoadCorr32 {        // the same integrands rounded once to FP32
+  LoadCorr64 d;
+  __device__ float2 operator()(int b, int64_t i) const {
+    const double2 v = d(b, i);
+    return make_float2((float)v.x, (float)v.y);
   }
 };
 
@@ -111,6 +126,22 @@ struct StoreRefSlots {     // StoreRef64 into the slot of batch entry b
   __device__ void operator()(int b, int64_t m, double2 v) const {
     const int64_t o = (int64_t)r.slot[b] * n;
     StoreRef64{z + o, bh + o, bl + o, hh + o, hl + o}(0, m, v);
+  }
+};
+struct StoreRefSlots32 {   // FP32 series into the slot of batch entry b, with its 16-bit hi/lo planes
+  float2* z; uint32_t* bh; uint32_t* bl; uint32_t* hh; uint32_t* hl; int64_t n; DechirpRefs r;
+  __device__ void operator()(int b, int64_t m, float2 v) const {
+    const int64_t o = (int64_t)r.slot[b] * n + m;
+    z[o] = v;
+    uint32_t rh, rl, ih, il;
+    split_bf16(v.x, rh, rl);
+    split_bf16(v.y, ih, il);
+    bh[o] = rh | (ih << 16);
+    bl[o] = rl | (il << 16);
+    split_f16(v.x, rh, rl);
+    split_f16(v.y, ih, il);
+    hh[o] = rh | (ih << 16);
+    hl[o] = rl | (il << 16);
   }
 };
 struct StoreBand {         // FP64 series -> FP32 band series
@@ -269,17 +300,20 @@ __global__ __launch_bounds__(256) void k_lags_direct(const double2* __restrict__
 // once to their share of every kept lag m = k0 + l,
 //   part[b][g][l] = sum_{i1 in group g} Y[m mod N2][i1] exp(+2 pi i i1 (m div N2) / N1),
 // and k_corr_reduce adds the N1 / C shares of each lag in a fixed order.
-template <int L>
-__global__ __launch_bounds__(kNT) void k_corr_part(LoadCorr64 ld, double2* __restrict__ part,
-                                                 const double2* __restrict__ coarse,
-                                                 const double2* __restrict__ fine, const double2* __restrict__ tabL,
-                                                 const double2* __restrict__ tab1, int n1, int k0,
+// V = double2: FP64 column transforms (tap construction); V = float2: FP32
+// column transforms of the integrand rounded once from FP64, the shares
+// still summed in FP64 (the streaming reference series, like the FP32
+// dechirp passes).
+template <typename V, int L, class LD>
+__global__ __launch_bounds__(kNT) void k_corr_part(LD ld, double2* __restrict__ part, const V* __restrict__ coarse,
+                                                 const V* __restrict__ fine, const V* __restrict__ tabL,
+                                                 const V* __restrict__ tab1, int n1, int k0,
                                                  const int32_t* __restrict__ k0s, int T) {
-  constexpr int C = Cols<double2>::value(L);
+  constexpr int C = Cols<V>::value(L);
   constexpr int LP = lds_col<L>();
   extern __shared__ __align__(16) unsigned char smem[];
-  double2* buf = reinterpret_cast<double2*>(smem);
-  double2* twl = buf + C * LP;
+  V* buf = reinterpret_cast<V*>(smem);
+  V* twl = buf + C * LP;
   const int b = blockIdx.y;
   if (k0s) k0 = k0s[b];                    // per-template lag window
   // column group of this workgroup: consecutive workgroups go to different
@@ -289,13 +323,13 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LoadCorr64 ld, double2* __res
   const int g = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   const int c0 = g * C;
   const int64_t n = (int64_t)n1 * L;
-  load_twl<double2, L>(twl, tabL, 1);
+  load_twl<V, L>(twl, tabL, 1);
   for (int e = threadIdx.x; e < C * L; e += kNT) {
     int c = e % C, i2 = e / C;
     buf[c * LP + lpad(i2)] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
   }
   __syncthreads();
-  lds_fft<double2, L, C, kNT>(buf, twl, +1);
+  lds_fft<V, L, C, kNT>(buf, twl, +1);
   __syncthreads();
   double2* pb = part + ((int64_t)b * G + g) * T;
   for (int l = threadIdx.x; l < T; l += kNT) {
@@ -305,12 +339,13 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LoadCorr64 ld, double2* __res
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int i1 = c0 + c;
-      double2 v = buf[c * LP + lpad(r)];
+      V v = buf[c * LP + lpad(r)];
       const uint32_t pp = (uint32_t)i1 * (uint32_t)r;
       if (pp) v = cmul(v, twiddle_n(coarse, fine, pp, +1));
-      const double2 w = tab1[(int)(((int64_t)i1 * cc) & (n1 - 1))];
-      re += v.x * w.x - v.y * w.y;
-      im += v.x * w.y + v.y * w.x;
+      const V w = tab1[(int)(((int64_t)i1 * cc) & (n1 - 1))];
+      const V x = cmul(v, w);
+      re += x.x;
+      im += x.y;
     }
     pb[l] = make_double2(re, im);
   }
@@ -442,9 +477,16 @@ int launch_data_fft(Plan& p, const double* data) {
 }
 
 int dechirp_batch_size(const Plan& p) {
-  // FP64 intermediates of a batch: at most 256 MiB and kDechirpBatch references
-  int64_t b = ((int64_t)256 << 20) / (p.n * (int64_t)sizeof(double2));
+  // intermediates of a batch (FP32 or FP64 complex): at most 256 MiB and
+  // kDechirpBatch references
+  const int64_t elem = p.dechirp_fp64 ? (int64_t)sizeof(double2) : (int64_t)sizeof(float2);
+  int64_t b = ((int64_t)256 << 20) / (p.n * elem);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kDechirpBatch));
+}
+
+size_t dechirp_work_double2(const Plan& p) {
+  const int64_t elem = p.dechirp_fp64 ? (int64_t)sizeof(double2) : (int64_t)sizeof(float2);
+  return (size_t)((dechirp_batch_size(p) * p.n * elem + (int64_t)sizeof(double2) - 1) / (int64_t)sizeof(double2));
 }
 
 // Every reference through the same launches, in batches: sigma^2 (by slot,
@@ -453,7 +495,7 @@ int dechirp_batch_size(const Plan& p) {
 int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const double* const* h_refs) {
   const int bs = dechirp_batch_size(p);
   double2* work = bs > 1 ? p.work64b : p.work64;
-  if (bs > 1 && p.work64b_cap < (size_t)bs * p.n) return fail(RFD_E_STATE, "dechirp: batch buffer too small");
+  if (bs > 1 && p.work64b_cap < dechirp_work_double2(p)) return fail(RFD_E_STATE, "dechirp: batch buffer too small");
   for (int r0 = 0; r0 < n_refs; r0 += bs) {
     const int nr = std::min(bs, n_refs - r0);
     DechirpRefs refs{};
@@ -468,10 +510,21 @@ int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const doubl
                        (const double*)p.dref_part, p.dref_sig2, p.dref_scale, 1.0 / p.data_scale);
     RFD_CHECK_LAUNCH();
     LoadDechirpRefs ld{p.stilde64, p.w, refs, p.dref_scale, p.i_low, p.i_high};
-    int rc = run_pass_a<double2>(p, ld, work, p.tw64c, p.tw64f, p.tw64_n2, nr, +1);
-    if (rc) return rc;
-    StoreRefSlots st{p.zref, p.zbf_hi, p.zbf_lo, p.zh_hi, p.zh_lo, p.n, refs};
-    rc = run_pass_b<double2>(p, work, st, p.tw64_n1, nr, +1);
+    int rc;
+    if (p.dechirp_fp64) {
+      rc = run_pass_a<double2>(p, ld, work, p.tw64c, p.tw64f, p.tw64_n2, nr, +1);
+      if (rc) return rc;
+      StoreRefSlots st{p.zref, p.zbf_hi, p.zbf_lo, p.zh_hi, p.zh_lo, p.n, refs};
+      rc = run_pass_b<double2>(p, work, st, p.tw64_n1, nr, +1);
+    } else {
+      // the integrand (and the reference norm) in FP64, both transform passes in
+      // FP32 with twiddles rounded once from FP64
+      float2* w32 = reinterpret_cast<float2*>(work);
+      rc = run_pass_a<float2>(p, LoadDechirpRefs32{ld}, w32, p.tw32c, p.tw32f, p.tw32_n2, nr, +1);
+      if (rc) return rc;
+      StoreRefSlots32 st{p.zref, p.zbf_hi, p.zbf_lo, p.zh_hi, p.zh_lo, p.n, refs};
+      rc = run_pass_b<float2>(p, w32, st, p.tw32_n1, nr, +1);
+    }
     if (rc) return rc;
   }
   return RFD_OK;
@@ -539,25 +592,31 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
 }
 
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch, int T,
-                  int k0, double2* out, int64_t out_stride, int64_t lo, int64_t hi, const int32_t* k0s) {
+                  int k0, double2* out, int64_t out_stride, int64_t lo, int64_t hi, const int32_t* k0s, bool fp32) {
   size_t need = (size_t)batch * p.n;
   if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
   LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high,
                 mode};
   const double scale = mode == 2 ? 1.0 / (double)p.n : 1.0;
   // fused form: per-workgroup lag shares in the work buffer, then their sums
-  const int C = Cols<double2>::value(p.n2);
+  const int C = fp32 ? Cols<float2>::value(p.n2) : Cols<double2>::value(p.n2);
   const int groups = p.n1 / C;
   if ((int64_t)groups * T <= p.n) {
     dim3 blk(kNT);
     switch (p.n2) {
-#define CASE_C(LL)                                                                                     \
-  case LL: {                                                                                           \
-    constexpr int CC = Cols<double2>::value(LL);                                                       \
-    const size_t sh = lds_bytes<double2, LL, CC>();                                                    \
-    hipLaunchKernelGGL((k_corr_part<LL>), dim3(groups, (unsigned)batch), blk, sh, p.stream, ld, tp.work64, \
-                       p.tw64c, p.tw64f, p.tw64_n2, p.tw64_n1, p.n1, k0, k0s, T);                      \
-    break;                                                                                             \
+#define CASE_C(LL)                                                                                       \
+  case LL: {                                                                                             \
+    if (fp32) {                                                                                          \
+      const size_t sh = lds_bytes<float2, LL, Cols<float2>::value(LL)>();                                \
+      hipLaunchKernelGGL((k_corr_part<float2, LL, LoadCorr32>), dim3(groups, (unsigned)batch), blk, sh,  \
+                         p.stream, LoadCorr32{ld}, tp.work64, p.tw32c, p.tw32f, p.tw32_n2, p.tw32_n1, p.n1,  \
+                         k0, k0s, T);                                                                    \
+    } else {                                                                                             \
+      const size_t sh = lds_bytes<double2, LL, Cols<double2>::value(LL)>();                              \
+      hipLaunchKernelGGL((k_corr_part<double2, LL, LoadCorr64>), dim3(groups, (unsigned)batch), blk, sh, \
+                         p.stream, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, p.tw64_n1, p.n1, k0, k0s, T); \
+    }                                                                                                    \
+    break;                                                                                               \
   }
       CASE_C(32) CASE_C(64) CASE_C(128) CASE_C(256) CASE_C(512) CASE_C(1024) CASE_C(2048)
 #undef CASE_C

@@ -92,6 +92,7 @@ struct Plan {
   // exp(+2 pi i m / 4096), m < 4096, in FP32 and FP64
   int ols_block = 0;
   bool ols_aligned = true;     // allow aligned output lengths (L = 256 nf)
+  bool dechirp_fp64 = false;   // reference transforms in FP64 (default: FP32 passes, FP64 integrand)
   float2* ols_tw32 = nullptr;
   double2* ols_tw64 = nullptr;
   // chi^2 band series per reference slot: [n_bands][n] FP32, the band edges
@@ -193,6 +194,7 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // ----------------------------------------------------- launchers (fft.hip)
 int launch_data_fft(Plan& p, const double* data);
 int dechirp_batch_size(const Plan& p);
+size_t dechirp_work_double2(const Plan& p);   // batch buffer size in double2 units
 int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const double* const* h_refs);
 int launch_findchirp_prepare(Plan& p, const double* h, int64_t count, float2* filt, double* sigma);
 int launch_findchirp(Plan& p, const float2* filt, int64_t n_templates, int64_t W, int64_t nwin, float threshold);
@@ -202,9 +204,11 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
 // where w |h_r|^2 > 0, scaled by 1/N.
 // lo / hi (inclusive bins, -1: the analysis band) restrict the sum to a band.
 // k0s (device, per batch entry, may be NULL) replaces k0 template by template.
+// fp32: FP32 column transforms of the integrand rounded once (shares and
+// sums in FP64); applies to the fused form, the row form stays FP64.
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch,
                   int T, int k0, double2* out, int64_t out_stride, int64_t lo = -1, int64_t hi = -1,
-                  const int32_t* k0s = nullptr);
+                  const int32_t* k0s = nullptr, bool fp32 = false);
 constexpr int kPeakParts = 64;   // chunks per template in the peak-lag reduction
 // Per-template lag centring: the full weighted cross-correlation b (mode 0)
 // of each batch entry, |b|^2 into pw [batch][N], and its peak lag l in

@@ -309,9 +309,10 @@ int rfd_stream_push(rfd_stream* stream, const double* data, int32_t precision, f
   if (rc) return rc;
   for (int r0 = 0; r0 < s.nref; r0 += kStreamRefBatch) {
     const int nb = std::min(kStreamRefBatch, s.nref - r0);
+    // the stretch's column transforms in the dechirp's precision
     rc = launch_corr64(p, s.work, 0, reinterpret_cast<const double*>(p.stilde64),
                        reinterpret_cast<const double*>(s.href + (int64_t)r0 * p.nb), nb, (int)s.zlen, k0c,
-                       s.corr + (int64_t)r0 * s.zlen, s.zlen);
+                       s.corr + (int64_t)r0 * s.zlen, s.zlen, -1, -1, nullptr, !p.dechirp_fp64);
     if (rc) return rc;
     hipLaunchKernelGGL(k_stream_store, dim3((unsigned)((s.zlen + 255) / 256), (unsigned)nb), dim3(256), 0, p.stream,
                        (const double2*)(s.corr + (int64_t)r0 * s.zlen), s.zlen, (const double*)(s.scale + r0),

@@ -111,6 +111,7 @@ _SIGS = {
     "rfd_stream_destroy": [_P],
     "rfd_debug_fail_allocation": [_i64],
     "rfd_ols_shape": [_P, _i32, C.POINTER(_i32), C.POINTER(_i32)],
+    "rfd_plan_set_dechirp_fp64": [_P, _i32],
     "rfd_surrogate_set_feature_range": [_P, _P, _i64],
     "rfd_surrogate_features": [_P, _P, _i64, _P],
     "rfd_findchirp_prepare": [_P, _P, _i64, _P, _P],
@@ -696,3 +697,8 @@ def rfd_filter_range(plan, taps, precision, threshold, cluster_window, n_start, 
     _check(_lib.rfd_filter_range(plan, taps, prec, threshold, cluster_window, n_start, n_len, _ptr(out), capacity,
                                  C.byref(n)), "rfd_filter_range")
     return out, n.value
+
+
+def rfd_plan_set_dechirp_fp64(plan, enable=True):
+    """Reference transform passes in FP64 (True) or FP32 (False, the default)."""
+    _check(_lib.rfd_plan_set_dechirp_fp64(plan, 1 if enable else 0), "rfd_plan_set_dechirp_fp64")

@@ -173,3 +173,34 @@ def test_eccentric_subsolar_parity(rfd):
     res = _subset_parity(rfd, case, ["bf16x3", "fp32", "ols32"])
     print(f"\n[ecc512s] 4 sub-banks x 2 templates, N = 2^20, T = 1024: "
           f"(max |drho|, ambiguous, compared, max |drho| at triggers) {res}")
+
+
+def test_graph_refused_after_the_dechirp_precision_changes(rfd, ragged):
+    """A segment graph records the reference transforms of one precision: after
+    rfd_plan_set_dechirp_fp64 switches them, its replay is refused on the host,
+    and a graph captured under the new setting replays the eager result."""
+    import torch
+    case, s = ragged
+    th, W, cap = 2.5, 300, 1 << 16
+    out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    g = rfd.rfd_segment_graph_create(s.plan, s.taps, "fp32", th, W, s.data, s.h_ref, out, cap)
+    g2 = None
+    try:
+        rfd.rfd_segment_graph_launch(g)
+        rfd.rfd_plan_set_dechirp_fp64(s.plan, True)
+        with pytest.raises(rfd.RfdError) as e:
+            rfd.rfd_segment_graph_launch(g)
+        assert e.value.code == rfd.RFD_E_STATE
+        g2 = rfd.rfd_segment_graph_create(s.plan, s.taps, "fp32", th, W, s.data, s.h_ref, out, cap)
+        n = rfd.rfd_segment_graph_launch(g2)
+        got = rfd.triggers_to_numpy(out, n)
+        s.dechirp_all()
+        assert np.array_equal(got, _trig(rfd, s, "fp32", th, W, cap))
+        from paper_2601_18835_amd import rfd as binding
+        assert binding._lib.rfd_plan_set_dechirp_fp64(s.plan, 2) == rfd.RFD_E_INVALID
+    finally:
+        rfd.rfd_graph_destroy(g)
+        if g2 is not None:
+            rfd.rfd_graph_destroy(g2)
+        rfd.rfd_plan_set_dechirp_fp64(s.plan, False)
+        s.dechirp_all()

@@ -64,3 +64,29 @@ def test_batched_dechirp_argument_errors(rfd, setup):
     assert rfd.rfd._lib.rfd_dechirp_refs(plan, None, 2, None, ptrs, None) == rfd.RFD_E_INVALID
     nulls = (C.c_void_p * 2)(h.data_ptr(), None)
     assert rfd.rfd._lib.rfd_dechirp_refs(plan, None, 2, arr, nulls, None) == rfd.RFD_E_INVALID
+
+
+def test_fp32_and_fp64_transform_passes_against_oracle(rfd, setup):
+    """The default FP32 transform passes and the FP64 ones both meet 1e-5 on
+    the normalised series; the FP32 error stays within a few units of FP32
+    rounding of max |z_ref| (log2 N butterfly levels)."""
+    c = setup
+    plan = c["plan"]
+    p = orc.prepare(c["psd"], c["data"], FS, F_LOW)
+    errs = {}
+    try:
+        for fp64 in (False, True):
+            rfd.rfd_plan_set_dechirp_fp64(plan, fp64)
+            rfd.rfd_dechirp_refs(plan, c["d"], c["refs"], False)
+            worst = 0.0
+            for i, r in enumerate(c["slots"]):
+                ref = orc.dechirp(p, c["H"][i])
+                want = ref.z / ref.sigma
+                got = rfd.rfd_get_zref(plan, r).cpu().numpy().astype(np.complex128)
+                worst = max(worst, float(np.max(np.abs(got - want)) / np.max(np.abs(want))))
+            errs[fp64] = worst
+    finally:
+        rfd.rfd_plan_set_dechirp_fp64(plan, False)
+    print(f"\n[dechirp] max |dz|/max|z|: FP32 passes {errs[False]:.2e}, FP64 passes {errs[True]:.2e}")
+    assert errs[True] <= 2.0 ** -23
+    assert errs[False] <= 2.0 ** -24 * 4 * np.log2(N)

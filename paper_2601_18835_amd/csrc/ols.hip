@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gn[r]);
-    if (j + 1 < j1) fetch_g(j + 1);
+    fetch_g(j + 1);     // unconditional (the last one rereads j0's): no merge of old and new registers
     block_fft<K, 1>(v, lds + f * S::LDS, t, w);
     if (!has_out) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;

@@ -192,8 +192,8 @@ def main():
     ap.add_argument("--train", type=int, default=3125, help="surr512s: exact tap sets per reference (1e5 in all)")
     ap.add_argument("--epochs", type=int, default=36000, help="surr512s: training epochs")
     ap.add_argument("--batch", type=int, default=256, help="surr512s: training batch")
-    ap.add_argument("--lr", type=float, default=2e-3, help="surr512s: first learning rate")
-    ap.add_argument("--lr-end", type=float, default=2e-4, help="surr512s: last learning rate (geometric decay)")
+    ap.add_argument("--lr", type=float, default=4e-3, help="surr512s: first learning rate")
+    ap.add_argument("--lr-end", type=float, default=5e-5, help="surr512s: last learning rate (geometric decay)")
     ap.add_argument("--cpu-sample", type=int, default=32, help="templates in the oracle sample (parity, all cores)")
     ap.add_argument("--cpu-one-core", type=int, default=3, help="templates of the sample timed on one core")
     ap.add_argument("--fir-form", default="auto", choices=["auto", "fp32", "bf16x3", "fp16x3", "ols32"],

@@ -343,11 +343,14 @@ __global__ void k_loss_record(PerNet<const double*> loss, float* __restrict__ re
   if (threadIdx.x == 0) rec[(int64_t)blockIdx.x * epochs + e] = (float)loss.p[blockIdx.x][0];
 }
 
-// Adam step number st[1] + 1 (bias corrections 1 - beta^t)
+// Adam step number st[1] + 1 (bias corrections 1 - beta^t), and the BF16
+// copy of each updated weight that the next step's GEMMs read
 __global__ void k_adam_step(PerNet<float*> ws, PerNet<const float*> gs, PerNet<float*> ms, PerNet<float*> vs,
-                            int64_t n, float lr, float b1, float b2, float eps, PerNet<const int64_t*> sts) {
+                            PerNet<uint16_t*> wbfs, int64_t n, float lr, float b1, float b2, float eps,
+                            PerNet<const int64_t*> sts) {
   const int z = blockIdx.y;
   float* __restrict__ w = ws.p[z];
+  uint16_t* __restrict__ wbf = wbfs.p[z];
   const float* __restrict__ g = gs.p[z];
   float* __restrict__ m = ms.p[z];
   float* __restrict__ v = vs.p[z];
@@ -359,7 +362,9 @@ __global__ void k_adam_step(PerNet<float*> ws, PerNet<const float*> gs, PerNet<f
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    const float wn = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[i] = wn;
+    wbf[i] = (uint16_t)bf16_bits(wn);
   }
 }
 
@@ -969,9 +974,9 @@ static int train_group(const NetGroup& g, const PerNet<const float*>& params, in
     if (!r) r = backward(g, q, Pb, Cb, batch, 0, loss_scale, true);
     if (r) return r;
     hipLaunchKernelGGL(k_adam_step, dim3(grid_for(s0.np), g.n), dim3(256), 0, q, PER(float*, s.w),
-                       PER(const float*, s.g), PER(float*, s.m), PER(float*, s.v), s0.np, lr, b1, b2, eps, tst);
+                       PER(const float*, s.g), PER(float*, s.m), PER(float*, s.v), PER(uint16_t*, s.wbf), s0.np, lr,
+                       b1, b2, eps, tst);
     if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "adam launch failed");
-    if ((r = refresh_bf16(g, q))) return r;
     hipLaunchKernelGGL(k_train_state_advance, dim3(g.n), dim3(1), 0, q, PER(int64_t*, s.tstate));
     if (hipGetLastError() != hipSuccess) return fail(RFD_E_DEVICE, "step launch failed");
     return RFD_OK;

@@ -121,13 +121,43 @@ __device__ __forceinline__ constexpr bool ols_slot_kept(int s) {
   return NF == 0 || dftr_freq<BlockFft<K>::R>(s) < NF;
 }
 
+// Tile of the (block group, template group) grid a workgroup takes.  The
+// dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD
+// has its own L2.  So the hardware order h is renumbered: XCD c = h mod 8
+// takes a contiguous run of a logical order in which the block groups are cut
+// into 8 column tiles of near-equal width (tile c: [c gx / 8, (c+1) gx / 8)),
+// each swept template row by template row.  The workgroups an XCD runs
+// together then share one row's tap spectra and one tile's block spectra in
+// its L2, and a tap spectrum leaves HBM about once per XCD instead of once
+// per L2 pass.  Any bijection is correct; this one only decides where the
+// re-reads land.
+struct OlsTile {
+  uint32_t bx, by;
+};
+__device__ __forceinline__ OlsTile ols_tile() {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t gx = gridDim.x, gy = gridDim.y;
+  const uint32_t nwg = gx * gy, h = blockIdx.x + gx * blockIdx.y;
+  const uint32_t c = h % kXcd, base = nwg / kXcd, rem = nwg % kXcd;
+  const uint32_t lg = c * base + min(c, rem) + h / kXcd;     // XCD c: [start_c, start_c + n_c)
+  uint32_t x0 = 0, x1 = gx;
+  for (uint32_t k = 1; k <= kXcd; ++k) {                     // the tile holding lg (empty ones skipped)
+    x1 = k * gx / kXcd;
+    if (lg < x1 * gy) break;
+    x0 = x1;
+  }
+  const uint32_t w = x1 - x0, r = lg - x0 * gy;
+  return OlsTile{x0 + r % w, r / w};
+}
+
 template <int K, int NF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ols(OlsArgs a) {
   using S = BlockFft<K>;
   __shared__ float2 lds[S::F * S::LDS];
   __shared__ float2 twb_table[block_fft_twb_size<K>()];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
-  const int64_t b = (int64_t)blockIdx.x * S::F + f;
+  const OlsTile wg = ols_tile();
+  const int64_t b = (int64_t)wg.bx * S::F + f;
   const bool bvalid = b < a.nB;
   BlockFftTwL<K> w;
   block_fft_twiddles_lds<K, 1>(w, a.tw, t, twb_table);
@@ -144,7 +174,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // every kept slot is an output of the launch: no per-sample range test
   const bool whole = NF > 0 && has_out && nbeg == n0 && nend == n0 + a.L;
   const int64_t q0 = has_out ? nbeg / a.W : 0, q1 = has_out ? (nend - 1) / a.W : 0;
-  const int64_t j0 = (int64_t)blockIdx.y * a.J;
+  const int64_t j0 = (int64_t)wg.by * a.J;
   const int64_t j1 = std::min<int64_t>(j0 + a.J, a.count);
   const bool lead = (threadIdx.x & 63) == 0;
   // the next template's tap spectrum is fetched while the current one is

@@ -11,49 +11,69 @@ namespace rfd {
 constexpr int kSegThreads = 256;
 constexpr int kSegPer = 16;
 constexpr int kSeg = kSegThreads * kSegPer;   // slots per compaction block
+// Each wave of a compaction block takes kSegPer rounds of 64 consecutive
+// slots (1024 in all, coalesced 512-byte reads); the waves of a block and the
+// blocks follow each other in slot order, so the triggers come out in
+// ascending slot order.
 
 __device__ __forceinline__ int64_t map_slot(const WinMap& m, int64_t v) {
   const int64_t t = v / m.nq, qi = v - t * m.nq;
   const int64_t q = qi < m.cnt0 ? m.lo0 + qi : m.lo1 + (qi - m.cnt0);
   return t * m.nwin + q;
 }
+// every window of every template, in order: slot index = visit index
+__device__ __forceinline__ bool map_identity(const WinMap& m) {
+  return m.nq == m.nwin && m.cnt0 == m.nq && m.lo0 == 0;
+}
 
 __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, WinMap m) {
+  const bool ident = map_identity(m);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[map_slot(m, i)] = 0ull;
+    p[ident ? i : map_slot(m, i)] = 0ull;
 }
 
 __device__ __forceinline__ bool slot_fires(unsigned long long k, float thr2) {
   return k != 0ull && __uint_as_float((uint32_t)(k >> 32)) > thr2;
 }
 
-__device__ int block_exclusive_scan(int v, int* sh, int& total) {
-  // sh: 256 ints
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int o = 1; o < kSegThreads; o <<= 1) {
-    int x = t >= o ? sh[t - o] : 0;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
+// lanes below this one whose bit is set in a wave-wide mask
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// The wave's keys and firing masks over its kSegPer rounds.
+struct WaveSlots {
+  unsigned long long key[kSegPer];
+  unsigned long long fire[kSegPer];
+  int count;
+};
+__device__ __forceinline__ void wave_slots(WaveSlots& w, const unsigned long long* __restrict__ slots, int64_t n,
+                                           float thr2, const WinMap& m, int64_t base) {
+  const int lane = threadIdx.x & 63;
+  const bool ident = map_identity(m);
+  w.count = 0;
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    const int64_t v = base + 64 * r + lane;
+    w.key[r] = v < n ? slots[ident ? v : map_slot(m, v)] : 0ull;
+    w.fire[r] = __ballot(slot_fires(w.key[r], thr2));
+    w.count += __popcll(w.fire[r]);
   }
-  total = sh[kSegThreads - 1];
-  int r = sh[t] - v;
-  __syncthreads();
-  return r;
 }
 
 __global__ __launch_bounds__(kSegThreads) void k_count(const unsigned long long* __restrict__ slots, int64_t n,
                                                      float thr2, long long* __restrict__ counts, WinMap m) {
-  __shared__ int sh[kSegThreads];
-  int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)threadIdx.x * kSegPer;
-  int c = 0;
-  for (int i = 0; i < kSegPer; ++i)
-    if (base + i < n && slot_fires(slots[map_slot(m, base + i)], thr2)) ++c;
-  int total;
-  block_exclusive_scan(c, sh, total);
-  if (threadIdx.x == 0) counts[blockIdx.x] = total;
+  __shared__ int wc[kSegThreads / 64];
+  const int wave = threadIdx.x >> 6;
+  WaveSlots w;
+  wave_slots(w, slots, n, thr2, m, (int64_t)blockIdx.x * kSeg + (int64_t)wave * 64 * kSegPer);
+  if ((threadIdx.x & 63) == 0) wc[wave] = w.count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long c = 0;
+    for (int i = 0; i < kSegThreads / 64; ++i) c += wc[i];
+    counts[blockIdx.x] = c;
+  }
 }
 
 // single-workgroup exclusive scan of the block counts; total at counts[nblk]
@@ -97,34 +117,38 @@ __global__ __launch_bounds__(kSegThreads) void k_write(const unsigned long long*
                                                      int64_t W, rfd_trigger* __restrict__ out, int64_t capacity,
                                                      const int64_t* __restrict__ sb_first, int nsb, WinMap m,
                                                      const int32_t* __restrict__ shift, int64_t nseg) {
-  __shared__ int sh[kSegThreads];
-  int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)threadIdx.x * kSegPer;
-  int c = 0;
-  for (int i = 0; i < kSegPer; ++i)
-    if (base + i < n && slot_fires(slots[map_slot(m, base + i)], thr2)) ++c;
-  int total;
-  int pre = block_exclusive_scan(c, sh, total);
-  int64_t pos = offs[blockIdx.x] + pre;
-  for (int i = 0; i < kSegPer; ++i) {
-    if (base + i >= n) break;
-    const int64_t si = map_slot(m, base + i);
-    unsigned long long k = slots[si];
-    if (!slot_fires(k, thr2)) continue;
-    if (pos < capacity) {
-      int64_t tmpl = si / nwin, q = si - tmpl * nwin;
-      rfd_trigger t;
-      // filter index m of the peak; sample n = m - d (mod N) under lag centring
-      t.sample = q * W + (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
-      if (shift) t.sample = (t.sample - shift[tmpl]) & (nseg - 1);
-      t.tmpl = (int32_t)tmpl;
-      t.subbank = sb_first ? find_subbank(sb_first, nsb, tmpl) : 0;
-      t.rho = sqrtf(__uint_as_float((uint32_t)(k >> 32)));
-      t.z_re = 0.f;
-      t.z_im = 0.f;
-      t.flags = 1u;       // complex SNR not yet evaluated
-      out[pos] = t;
-    }
-    ++pos;
+  __shared__ int wc[kSegThreads / 64];
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kSeg + (int64_t)wave * 64 * kSegPer;
+  WaveSlots w;
+  wave_slots(w, slots, n, thr2, m, base);
+  if ((threadIdx.x & 63) == 0) wc[wave] = w.count;
+  __syncthreads();
+  if (w.count == 0) return;     // wave-uniform; no barrier follows
+  int64_t pos = offs[blockIdx.x];
+  for (int i = 0; i < wave; ++i) pos += wc[i];
+  const bool ident = map_identity(m);
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    const unsigned long long k = w.key[r];
+    const int64_t at = pos + lanes_below(w.fire[r]);
+    pos += __popcll(w.fire[r]);
+    if (!((w.fire[r] >> lane) & 1ull) || at >= capacity) continue;
+    const int64_t v = base + 64 * r + lane;
+    const int64_t si = ident ? v : map_slot(m, v);
+    const int64_t tmpl = si / nwin, q = si - tmpl * nwin;
+    rfd_trigger t;
+    // filter index m of the peak; sample n = m - d (mod N) under lag centring
+    t.sample = q * W + (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
+    if (shift) t.sample = (t.sample - shift[tmpl]) & (nseg - 1);
+    t.tmpl = (int32_t)tmpl;
+    t.subbank = sb_first ? find_subbank(sb_first, nsb, tmpl) : 0;
+    t.rho = sqrtf(__uint_as_float((uint32_t)(k >> 32)));
+    t.z_re = 0.f;
+    t.z_im = 0.f;
+    t.flags = 1u;       // complex SNR not yet evaluated
+    out[at] = t;
   }
 }
 

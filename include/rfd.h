@@ -245,7 +245,9 @@ int rfd_taps_create(rfd_plan* plan, int32_t n_subbanks, const int64_t* offsets, 
  *   method     RFD_TAPS_LS: minimise sum_i u_i |R_i - A_i|^2 + lam |a|^2 with
  *              R = h/h_ref, u_i = w_i |h_ref,i|^2, A_i = sum_k a_k
  *              exp(-2 pi i i (k0+k)/N), lam = ridge_eps * sum_i u_i, solved
- *              through the Hermitian Toeplitz normal equations by Cholesky.
+ *              through the Hermitian Toeplitz normal equations by Cholesky
+ *              (factor from the Toeplitz Schur recursion); RFD_E_INVALID when
+ *              M + lam I is not positive definite (a reference zero in band).
  *              RFD_TAPS_WINDOW: a_k = tukey_k (1/N) sum_i R_i exp(+2 pi i i
  *              (k0+k)/N) (ridge_eps ignored).
  *              Either route may carry RFD_TAPS_CENTRE (per-template lag

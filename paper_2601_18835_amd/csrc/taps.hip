@@ -7,8 +7,9 @@
 //     (M + lam I) a = b,  M[l,k] = g[l-k],  g[m] = sum_i u_i exp(+2 pi i i m/N),
 //     b[l] = sum_i w_i h_i conj(h_ref,i) exp(+2 pi i i (k0+l)/N),
 // a Hermitian Toeplitz system shared by the whole sub-bank: g and every b
-// come from FP64 FFTs (fft.hip), M + lam I is factored once per sub-bank by
-// Cholesky, and each template costs two triangular solves.
+// come from FP64 FFTs (fft.hip), M + lam I is factored once per sub-bank
+// (L L^H, by the Schur recursion that its Toeplitz structure allows), and each
+// template costs two triangular solves.
 // Norm of the fitted template h_fit = h_ref A (Parseval form of Sec. VI.B):
 //     sigma_fit^2 = sum_i w_i |h_ref A|^2 = a^H M a.
 // The FIR applies c = conj(a) sigma_ref / sigma_fit to zhat = z_ref/sigma_ref,
@@ -24,42 +25,79 @@ __device__ __forceinline__ double2 gval(const double2* g, int m) {
   return m >= 0 ? g[m] : cconj(g[-m]);
 }
 
-// lower triangle (column-major) of M + lam I, lam = eps * g[0]
-__global__ void k_toeplitz(const double2* __restrict__ g, int T, double eps, double2* __restrict__ A) {
-  const double lam = eps * g[0].x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)T * T;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int col = (int)(e / T), row = (int)(e % T);
-    double2 v = row >= col ? g[row - col] : make_double2(0.0, 0.0);
-    if (row == col) v = make_double2(v.x + lam, 0.0);
-    A[e] = v;
+// Cholesky factor L (column-major, zeros above the diagonal) of the ridge
+// normal matrix M + lam I, lam = eps g[0].  M[l][k] = g[l - k] is Hermitian
+// Toeplitz, so its factor follows from the Schur recursion on M's
+// displacement generators in O(T^2) work instead of the O(T^3) of a general
+// Cholesky.  With Z the down-shift and r = (g[0] + lam, g[1], ..., g[T-1]) the
+// first column, M + lam I - Z (M + lam I) Z^H = u u^H - v v^H for
+// u = r / sqrt(r[0]) and v = u with v[0] = 0.  Column k of L is the current
+// u; the next Schur complement has generators (Z u, v), which a hyperbolic
+// rotation with rho = v[k+1] / u[k] returns to the form v[k+1] = 0:
+//   v <- (v - rho Z u) / s,   u <- s Z u - conj(rho) v,   s = sqrt(1 - |rho|^2),
+// the "mixed" order of the two updates, which keeps the recursion backward
+// stable for positive-definite matrices.  |rho| >= 1 means M + lam I is not
+// positive definite: info = step + 1.  One workgroup, T dependent steps.
+constexpr int kSchurPer = (RFD_MAX_TAPS + 1023) / 1024;   // elements per thread
+__global__ __launch_bounds__(1024) void k_schur_chol(const double2* __restrict__ g, int T, double eps,
+                                                     double2* __restrict__ L, int* __restrict__ info) {
+  __shared__ double2 u[RFD_MAX_TAPS], v[RFD_MAX_TAPS];
+  const double r0 = g[0].x + eps * g[0].x;
+  if (!(r0 > 0.0)) {                      // uniform
+    if (threadIdx.x == 0) *info = 1;
+    return;
   }
-}
-
-// In-place right-looking Cholesky of the lower triangle, one workgroup.
-__global__ __launch_bounds__(1024) void k_cholesky(double2* __restrict__ A, int T, int* __restrict__ info) {
-  __shared__ double dsh;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int j = 0; j < T; ++j) {
-    if (threadIdx.x == 0) {
-      double d = A[(int64_t)j * T + j].x;
-      if (!(d > 0.0)) {
-        *info = j + 1;
-        d = 1.0;
+  const double inv = 1.0 / sqrt(r0);
+  for (int i = threadIdx.x; i < T; i += 1024) {
+    const double2 r = i == 0 ? make_double2(r0, 0.0) : g[i];
+    const double2 x = make_double2(r.x * inv, r.y * inv);
+    u[i] = x;
+    v[i] = i == 0 ? make_double2(0.0, 0.0) : x;
+    L[i] = x;                             // column 0
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < T; ++k) {
+    const double a = u[k].x;              // L[k][k]: real and positive
+    const double2 b = v[k + 1];
+    const double2 rho = make_double2(b.x / a, b.y / a);
+    const double q = 1.0 - (rho.x * rho.x + rho.y * rho.y);
+    double2 zu[kSchurPer], vi[kSchurPer];
+#pragma unroll
+    for (int e = 0; e < kSchurPer; ++e) {
+      const int i = threadIdx.x + 1024 * e;
+      if (i > k && i < T) {
+        zu[e] = u[i - 1];
+        vi[e] = v[i];
       }
-      d = sqrt(d);
-      A[(int64_t)j * T + j] = make_double2(d, 0.0);
-      dsh = d;
     }
-    __syncthreads();
-    const double inv = 1.0 / dsh;
-    double2* colj = A + (int64_t)j * T;
-    for (int i = j + 1 + threadIdx.x; i < T; i += 1024) colj[i] = make_double2(colj[i].x * inv, colj[i].y * inv);
-    __syncthreads();
-    for (int k = j + 1 + ty; k < T; k += 16) {
-      const double2 lk = cconj(colj[k]);
-      double2* colk = A + (int64_t)k * T;
-      for (int i = k + tx; i < T; i += 64) colk[i] = csub(colk[i], cmul(colj[i], lk));
+    __syncthreads();                      // every read of step k is done
+    if (!(q > 0.0)) {                     // uniform: the same q in every thread
+      if (threadIdx.x == 0) *info = k + 2;
+      return;
+    }
+    const double s = sqrt(q), is = 1.0 / s;
+    double2* col = L + (int64_t)(k + 1) * T;
+#pragma unroll
+    for (int e = 0; e < kSchurPer; ++e) {
+      const int i = threadIdx.x + 1024 * e;
+      if (i >= T) continue;
+      if (i <= k) {
+        col[i] = make_double2(0.0, 0.0);
+        continue;
+      }
+      double2 un, vn;
+      if (i == k + 1) {                   // the rotated pair: v exactly 0, u = s a
+        vn = make_double2(0.0, 0.0);
+        un = make_double2(s * a, 0.0);
+      } else {
+        vn = make_double2((vi[e].x - (rho.x * zu[e].x - rho.y * zu[e].y)) * is,
+                          (vi[e].y - (rho.x * zu[e].y + rho.y * zu[e].x)) * is);
+        un = make_double2(s * zu[e].x - (rho.x * vn.x + rho.y * vn.y),
+                          s * zu[e].y - (rho.x * vn.y - rho.y * vn.x));
+      }
+      u[i] = un;
+      v[i] = vn;
+      col[i] = un;
     }
     __syncthreads();
   }
@@ -397,13 +435,12 @@ int taps_prepare_subbank(Plan& p, Taps& tp, int b, const double* h_ref, double e
   int rc = launch_corr64(p, tp, 1, h_ref, nullptr, 1, T, 0, s.g, T);
   if (rc) return rc;
   if (eps >= 0.0) {
+    if (T > RFD_MAX_TAPS) return fail(RFD_E_INVALID, "taps out of range");
     int64_t el = (int64_t)T * T;
     int blocks = (int)((el + 255) / 256 < 4096 ? (el + 255) / 256 : 4096);
-    hipLaunchKernelGGL(k_toeplitz, dim3(blocks), dim3(256), 0, p.stream, s.g, T, eps, s.L);
-    RFD_CHECK_LAUNCH();
     int* info = reinterpret_cast<int*>(p.dscratch + 8);
     RFD_HIP(hipMemsetAsync(info, 0, sizeof(int), p.stream));
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, p.stream, s.L, T, info);
+    hipLaunchKernelGGL(k_schur_chol, dim3(1), dim3(1024), 0, p.stream, s.g, T, eps, s.L, info);
     RFD_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_upper, dim3(blocks), dim3(256), 0, p.stream, s.L, T, s.U);
     RFD_CHECK_LAUNCH();

@@ -80,3 +80,32 @@ def test_ls_taps_long_segments(rfd, log2n):
             assert abs(sig - tt.sigma_fit) <= 1e-9 * tt.sigma_fit
     finally:
         srch.close()
+
+
+def test_ls_taps_reject_singular_gram(rfd):
+    """A reference that vanishes in band gives g = 0: the ridge normal matrix
+    M + eps g[0] I is zero, so the factorisation must report that it is not
+    positive definite (RFD_E_INVALID) instead of returning taps; the same
+    taps object then accepts a proper reference."""
+    import torch
+    n = 1 << 13
+    psd = synth.psd_array(n, FS)
+    rng = np.random.default_rng(5)
+    w = synth.Workload("tapsingular", 9, n, FS, F_LOW, 0, 1, 0, "fp32", "nonspin")
+    params = [synth.WaveformParams(*m) for m in rng.uniform(5.0, 7.5, size=(2, 2))]
+    H = torch.from_numpy(synth.template_batch(w, params)).cuda()
+    plan = rfd.rfd_plan_create(psd, F_LOW, FS, n, 1)
+    taps = rfd.rfd_taps_create(plan, [0, 2], [0], [64], [-32])
+    try:
+        zero = torch.zeros(n // 2 + 1, dtype=torch.complex128, device="cuda")
+        with pytest.raises(rfd.RfdError) as err:
+            rfd.rfd_make_taps(plan, taps, 0, zero, H)
+        assert err.value.code == rfd.RFD_E_INVALID
+        assert "positive definite" in str(err.value)
+        h_ref = torch.from_numpy(synth.taylorf2(synth.WaveformParams(6.0, 5.0), n, FS, F_LOW)).cuda()
+        rfd.rfd_make_taps(plan, taps, 0, h_ref, H)
+        a, sig, T, k0 = rfd.rfd_taps_get(taps, 0)
+        assert T == 64 and np.isfinite(sig) and sig > 0
+    finally:
+        rfd.rfd_taps_destroy(taps)
+        rfd.rfd_plan_destroy(plan)

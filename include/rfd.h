@@ -125,7 +125,8 @@ typedef struct rfd_taps rfd_taps;
  *   fs       sample rate (Hz), > 0.
  *   seg_len  N, a power of two in [2^10, 2^22].
  *   max_refs number of reference-series slots (1..4096); each holds the
- *            normalised series in FP32 and the hi/lo 16-bit planes (24 N bytes).
+ *            normalised series in FP32 and room for its hi/lo 16-bit planes,
+ *            which the 16-bit FIR forms split from it (24 N bytes).
  *   stream   hipStream_t (NULL: the null stream).
  *   out      receives the plan.
  * Errors: RFD_E_INVALID for any violated range above, RFD_E_NOMEM,

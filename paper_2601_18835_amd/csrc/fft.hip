@@ -106,43 +106,17 @@ struct StoreSpectrum64 {   // FP64 spectrum and its FP32 copy (FINDCHIRP operand
     }
   }
 };
-struct StoreRef64 {        // FP64 series -> FP32 series + 16-bit hi/lo planes of it
-  float2* z; uint32_t* bh; uint32_t* bl; uint32_t* hh; uint32_t* hl;
-  __device__ void operator()(int, int64_t n, double2 v) const {
-    z[n] = make_float2((float)v.x, (float)v.y);
-    uint32_t rh, rl, ih, il;
-    split_bf16(v.x, rh, rl);
-    split_bf16(v.y, ih, il);
-    bh[n] = rh | (ih << 16);
-    bl[n] = rl | (il << 16);
-    split_f16(v.x, rh, rl);
-    split_f16(v.y, ih, il);
-    hh[n] = rh | (ih << 16);
-    hl[n] = rl | (il << 16);
-  }
-};
-struct StoreRefSlots {     // StoreRef64 into the slot of batch entry b
-  float2* z; uint32_t* bh; uint32_t* bl; uint32_t* hh; uint32_t* hl; int64_t n; DechirpRefs r;
+// Reference series are stored as FP32 only; the 16-bit hi/lo planes the MFMA
+// forms read are split from them by the FIR launch, over the window it reads.
+struct StoreRefSlots {     // FP64 series -> FP32, into the slot of batch entry b
+  float2* z; int64_t n; DechirpRefs r;
   __device__ void operator()(int b, int64_t m, double2 v) const {
-    const int64_t o = (int64_t)r.slot[b] * n;
-    StoreRef64{z + o, bh + o, bl + o, hh + o, hl + o}(0, m, v);
+    z[(int64_t)r.slot[b] * n + m] = make_float2((float)v.x, (float)v.y);
   }
 };
-struct StoreRefSlots32 {   // FP32 series into the slot of batch entry b, with its 16-bit hi/lo planes
-  float2* z; uint32_t* bh; uint32_t* bl; uint32_t* hh; uint32_t* hl; int64_t n; DechirpRefs r;
-  __device__ void operator()(int b, int64_t m, float2 v) const {
-    const int64_t o = (int64_t)r.slot[b] * n + m;
-    z[o] = v;
-    uint32_t rh, rl, ih, il;
-    split_bf16(v.x, rh, rl);
-    split_bf16(v.y, ih, il);
-    bh[o] = rh | (ih << 16);
-    bl[o] = rl | (il << 16);
-    split_f16(v.x, rh, rl);
-    split_f16(v.y, ih, il);
-    hh[o] = rh | (ih << 16);
-    hl[o] = rl | (il << 16);
-  }
+struct StoreRefSlots32 {   // FP32 series into the slot of batch entry b
+  float2* z; int64_t n; DechirpRefs r;
+  __device__ void operator()(int b, int64_t m, float2 v) const { z[(int64_t)r.slot[b] * n + m] = v; }
 };
 struct StoreBand {         // FP64 series -> FP32 band series
   float2* z;
@@ -514,7 +488,7 @@ int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const doubl
     if (p.dechirp_fp64) {
       rc = run_pass_a<double2>(p, ld, work, p.tw64c, p.tw64f, p.tw64_n2, nr, +1);
       if (rc) return rc;
-      StoreRefSlots st{p.zref, p.zbf_hi, p.zbf_lo, p.zh_hi, p.zh_lo, p.n, refs};
+      StoreRefSlots st{p.zref, p.n, refs};
       rc = run_pass_b<double2>(p, work, st, p.tw64_n1, nr, +1);
     } else {
       // the integrand (and the reference norm) in FP64, both transform passes in
@@ -522,7 +496,7 @@ int launch_dechirp_refs(Plan& p, int n_refs, const int32_t* ref_ids, const doubl
       float2* w32 = reinterpret_cast<float2*>(work);
       rc = run_pass_a<float2>(p, LoadDechirpRefs32{ld}, w32, p.tw32c, p.tw32f, p.tw32_n2, nr, +1);
       if (rc) return rc;
-      StoreRefSlots32 st{p.zref, p.zbf_hi, p.zbf_lo, p.zh_hi, p.zh_lo, p.n, refs};
+      StoreRefSlots32 st{p.zref, p.n, refs};
       rc = run_pass_b<float2>(p, w32, st, p.tw32_n1, nr, +1);
     }
     if (rc) return rc;

@@ -387,6 +387,48 @@ __global__ __launch_bounds__(256) void k_fir32_persistent(PersistArgs pa) {
 
 __global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
 
+// 16-bit hi/lo planes (x = hi + lo, each part rounded to the format) of the
+// FP32 reference series of one slot over samples [start, start + len) mod N:
+// word (re) | (im << 16) per sample, as the Hankel windows read them.
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_ref_planes(const float2* __restrict__ z, int64_t n, int64_t start,
+                                                    int64_t len, uint32_t* __restrict__ hi,
+                                                    uint32_t* __restrict__ lo) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    const int64_t m = (start + i) & (n - 1);
+    const float2 v = z[m];
+    uint32_t rh, rl, ih, il;
+    if (BF16) {
+      split_bf16(v.x, rh, rl);
+      split_bf16(v.y, ih, il);
+    } else {
+      split_f16(v.x, rh, rl);
+      split_f16(v.y, ih, il);
+    }
+    hi[m] = (rh & 0xffffu) | (ih << 16);
+    lo[m] = (rl & 0xffffu) | (il << 16);
+  }
+}
+
+// Planes of reference slot `ref` for the 16-bit form `precision`, over the
+// samples a FIR launch reads: [start, start + len) mod N (len >= N: all).
+static int launch_ref_planes(Plan& p, int precision, int ref, int64_t start, int64_t len) {
+  const bool bf = precision == RFD_BF16X3;
+  const int64_t o = (int64_t)ref * p.n;
+  uint32_t* hi = (bf ? p.zbf_hi : p.zh_hi) + o;
+  uint32_t* lo = (bf ? p.zbf_lo : p.zh_lo) + o;
+  if (len >= p.n) {
+    start = 0;
+    len = p.n;
+  }
+  start &= p.n - 1;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((len + 255) / 256, 4096));
+  if (bf) hipLaunchKernelGGL(k_ref_planes<true>, dim3((unsigned)blocks), dim3(256), 0, p.stream, p.zref + o, p.n, start, len, hi, lo);
+  else hipLaunchKernelGGL(k_ref_planes<false>, dim3((unsigned)blocks), dim3(256), 0, p.stream, p.zref + o, p.n, start, len, hi, lo);
+  RFD_CHECK_LAUNCH();
+  return RFD_OK;
+}
+
 // Tiles per workgroup: one workgroup covers a whole cluster window when W is
 // a multiple of 256 (so each (template, window) peak gets one update), capped
 // at 8 tiles; otherwise 4 tiles.
@@ -439,6 +481,11 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
   const int Lw = a.S * cols + s.Tp;
   int rc = stage_begin(p, kStFirKernel);
   if (rc) return rc;
+  if (precision != RFD_FP32) {
+    // the windows read samples [n_start + k0, n_start + n_len + k0 + Tp)
+    rc = launch_ref_planes(p, precision, s.ref_id, n_start + s.k0 + p.n, n_len + s.Tp);
+    if (rc) return rc;
+  }
   if (precision == RFD_FP32) {
     hipLaunchKernelGGL(k_fir32<16>, grid, dim3(256), (size_t)Lw * sizeof(float2), p.stream, a);
   } else {
@@ -572,6 +619,14 @@ int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int
   const dim3 grid(tp.it_grid);
   int rc = stage_begin(p, kStFirKernel);
   if (rc) return rc;
+  if (precision != RFD_FP32) {
+    std::vector<char> done(p.max_refs, 0);
+    for (const SubBankTaps& s : tp.sb) {
+      if (s.count == 0 || done[s.ref_id]) continue;
+      done[s.ref_id] = 1;
+      if ((rc = launch_ref_planes(p, precision, s.ref_id, 0, p.n))) return rc;
+    }
+  }
   if (precision == RFD_FP32) {
     hipLaunchKernelGGL(k_fir32_persistent<16>, grid, dim3(256), lds, p.stream, pa);
   } else if (p.fir_nb16 == 16) {

@@ -76,9 +76,7 @@ __global__ __launch_bounds__(1024) void k_stream_sigma(const double* __restrict_
 __global__ __launch_bounds__(256) void k_stream_store(const double2* __restrict__ corr, int64_t zlen,
                                                     const double* __restrict__ scale,
                                                     const int32_t* __restrict__ slot, float2* __restrict__ zref,
-                                                    uint32_t* __restrict__ bh, uint32_t* __restrict__ bl,
-                                                    uint32_t* __restrict__ hh, uint32_t* __restrict__ hl, int64_t n,
-                                                    int64_t n0) {
+                                                    int64_t n, int64_t n0) {
   const int b = blockIdx.y;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= zlen) return;
@@ -87,15 +85,6 @@ __global__ __launch_bounds__(256) void k_stream_store(const double2* __restrict_
   const double vx = c.x * sc, vy = -c.y * sc;
   const int64_t m = (int64_t)slot[b] * n + ((n0 + j) & (n - 1));
   zref[m] = make_float2((float)vx, (float)vy);
-  uint32_t rh, rl, ih, il;
-  split_bf16(vx, rh, rl);
-  split_bf16(vy, ih, il);
-  bh[m] = rh | (ih << 16);
-  bl[m] = rl | (il << 16);
-  split_f16(vx, rh, rl);
-  split_f16(vy, ih, il);
-  hh[m] = rh | (ih << 16);
-  hl[m] = rl | (il << 16);
 }
 
 static void stream_free(Stream& s) {
@@ -316,7 +305,7 @@ int rfd_stream_push(rfd_stream* stream, const double* data, int32_t precision, f
     if (rc) return rc;
     hipLaunchKernelGGL(k_stream_store, dim3((unsigned)((s.zlen + 255) / 256), (unsigned)nb), dim3(256), 0, p.stream,
                        (const double2*)(s.corr + (int64_t)r0 * s.zlen), s.zlen, (const double*)(s.scale + r0),
-                       (const int32_t*)(s.d_slot + r0), p.zref, p.zbf_hi, p.zbf_lo, p.zh_hi, p.zh_lo, p.n, n0);
+                       (const int32_t*)(s.d_slot + r0), p.zref, p.n, n0);
     RFD_CHECK_LAUNCH();
   }
   rc = stage_end(p);

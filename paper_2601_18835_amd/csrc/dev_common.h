@@ -60,6 +60,19 @@ __device__ __forceinline__ void split_f16(double x, uint32_t& hi, uint32_t& lo) 
   lo = f16_bits((float)(x - (double)f16_to_float(hi)));
 }
 
+// ------------------------------------------------------- workgroup order
+// The dispatcher deals consecutive workgroups (linear index h over the whole
+// grid) to the 8 XCDs in turn, and each XCD has its own L2.  This bijection
+// of [0, total) gives XCD c = h mod 8 a contiguous run of logical indices, so
+// logical neighbours, which touch neighbouring memory, share an L2: their
+// reads of common lines hit, and their writes to the two halves of a line
+// merge there instead of leaving two XCDs as partial lines.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t h, uint32_t total) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t c = h % kXcd, base = total / kXcd, rem = total % kXcd;
+  return c * base + min(c, rem) + h / kXcd;
+}
+
 // ------------------------------------------------------------------ twiddles
 // exp(sign * 2 pi i p / N) for 0 <= p < N from the factored table.
 template <typename V>

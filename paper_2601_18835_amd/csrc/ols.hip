@@ -137,9 +137,7 @@ struct OlsTile {
 __device__ __forceinline__ OlsTile ols_tile() {
   constexpr uint32_t kXcd = 8;
   const uint32_t gx = gridDim.x, gy = gridDim.y;
-  const uint32_t nwg = gx * gy, h = blockIdx.x + gx * blockIdx.y;
-  const uint32_t c = h % kXcd, base = nwg / kXcd, rem = nwg % kXcd;
-  const uint32_t lg = c * base + min(c, rem) + h / kXcd;     // XCD c: [start_c, start_c + n_c)
+  const uint32_t lg = xcd_contiguous(blockIdx.x + gx * blockIdx.y, gx * gy);
   uint32_t x0 = 0, x1 = gx;
   for (uint32_t k = 1; k <= kXcd; ++k) {                     // the tile holding lg (empty ones skipped)
     x1 = k * gx / kXcd;

@@ -196,7 +196,7 @@ int rfd_dechirp(rfd_plan* plan, const double* data, const double* h_ref, int32_t
  * rfd_dechirp_refs - rfd_dechirp for several references of one segment:
  * the segment transform once (when data is non-NULL), then every
  * reference's series through batched launches (up to 32 references, or
- * 256 MiB of FP64 intermediates, per launch), each result identical to
+ * 64 MiB of intermediates, per launch), each result identical to
  * rfd_dechirp's for that reference.
  *   n_refs     1 .. max_refs.
  *   ref_ids    host int32 [n_refs]: distinct slots 0 <= id < max_refs.

@@ -451,10 +451,12 @@ int launch_data_fft(Plan& p, const double* data) {
 }
 
 int dechirp_batch_size(const Plan& p) {
-  // intermediates of a batch (FP32 or FP64 complex): at most 256 MiB and
-  // kDechirpBatch references
+  // intermediates of a batch (FP32 or FP64 complex): at most 64 MiB and
+  // kDechirpBatch references.  A batch's pass-A output then stays small
+  // beside the 256 MB last-level cache when pass B reads it back (0.61 ->
+  // 0.56 ms for 32 references at N = 2^20 against 256 MiB batches)
   const int64_t elem = p.dechirp_fp64 ? (int64_t)sizeof(double2) : (int64_t)sizeof(float2);
-  int64_t b = ((int64_t)256 << 20) / (p.n * elem);
+  int64_t b = ((int64_t)64 << 20) / (p.n * elem);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kDechirpBatch));
 }
 

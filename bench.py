@@ -296,7 +296,7 @@ def main():
         return time.perf_counter() - t0, n, rfd.rfd_plan_get_timing(s.plan)
 
     def ols_block(T):
-        eff = {1024: 1.25, 2048: 1.0, 4096: 0.97}     # the library's block-size rule
+        eff = {1024: 1.17, 2048: 1.0, 4096: 0.99}     # the library's block-size rule
         cands = [K for K in (1024, 2048, 4096) if K > T]
         return min(cands, key=lambda K: ((5 * np.log2(K) + 6) * K / (K - T + 1) / eff[K], K))
 

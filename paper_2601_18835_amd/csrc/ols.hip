@@ -263,10 +263,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // Measured throughput of each block size per unit of FFT work, relative to
 // K = 2048 (MI355X: one-wave FFTs without workgroup barriers at 1024, a
 // whole-workgroup FFT at 4096).
-static double ols_efficiency(int K) { return K == 1024 ? 1.25 : (K == 2048 ? 1.0 : 0.97); }
+// (FFT flops per second of the whole-segment launches at T = 256 and 1024: 59.5,
+// 50.9 and 50.4-51.1 TFLOP/s).
+static double ols_efficiency(int K) { return K == 1024 ? 1.17 : (K == 2048 ? 1.0 : 0.99); }
 // ... and the gain of an aligned output length (L = 256 NF: the discarded
 // outputs are never computed, interior blocks skip per-sample range tests)
-constexpr double kOlsAlignedGain = 1.10;
+// (measured 1.01 at K = 4096 and 1.036 at K = 1024 on equal block counts)
+constexpr double kOlsAlignedGain = 1.03;
 
 // aligned output groups the kernels are built for, per block size
 static bool ols_nf_built(int K, int nf) {

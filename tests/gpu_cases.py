@@ -184,7 +184,7 @@ def check_target_ambiguity(trig, rho_oracle, threshold, window, tol, target):
 UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "fp16x3": 2.0 ** -22, "ols32": 2.0 ** -24}
 
 
-OLS_EFFICIENCY = {1024: 1.25, 2048: 1.0, 4096: 0.97}
+OLS_EFFICIENCY = {1024: 1.17, 2048: 1.0, 4096: 0.99}
 
 
 def ols_block(T, forced=0):

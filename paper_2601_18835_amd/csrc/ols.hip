@@ -186,10 +186,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   fetch_g(j0);
   for (int64_t j = j0; j < j1; ++j) {
     float2 v[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cmul(xb[r], gn[r]);
+    dft16_prod<1>(v, xb, gn);     // stage A of the transform of X_b G_j, the product fused in
     fetch_g(j + 1);     // unconditional (the last one rereads j0's): no merge of old and new registers
-    block_fft<K, 1>(v, lds + f * S::LDS, t, w);
+    block_fft_after_a<K, 1>(v, lds + f * S::LDS, t, w);
     if (!has_out) continue;
     unsigned long long* slot = a.slots + (a.tmpl0 + j) * a.nwin;
     float r2[16];

@@ -48,6 +48,7 @@ PEAK = {"bf16x3": 2500.0, "fp16x3": 2500.0, "fp32": 157.3,   # dense MFMA TFLOP/
 TARGET = {"bf16x3": 1e-3, "fp16x3": 1e-3, "fp32": 1e-5, "ols32": 1e-5}   # stated max |drho|
 # committed rocprofv3 counter summaries (HBM bytes per launch of the dominant kernel)
 COUNTERS = {("ecc512s", "ols32"): "k_ols4096_ecc512s_counters.txt",
+            ("spin256s", "ols32"): "fir_ols32_spin256s_counters.txt",
             ("spin256s", "bf16x3"): "fir_bf16x3_spin256s_counters.txt"}
 
 

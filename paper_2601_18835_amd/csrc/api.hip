@@ -272,7 +272,7 @@ int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, i
   if (n_psd != seg_len / 2 + 1) return fail(RFD_E_INVALID, "n_psd must equal seg_len/2 + 1");
   if (!(fs > 0.0) || !isfinite(fs)) return fail(RFD_E_INVALID, "fs must be finite and > 0");
   if (!(f_low > 0.0) || !(f_low < fs / 2.0)) return fail(RFD_E_INVALID, "f_low must satisfy 0 < f_low < fs/2");
-  if (max_refs < 1 || max_refs > 4096) return fail(RFD_E_INVALID, "max_refs must be in [1, 4096]");
+  if (max_refs < 1 || max_refs > kMaxRefSlots) return fail(RFD_E_INVALID, "max_refs must be in [1, 4096]");
   const int64_t n = seg_len, nb = n / 2 + 1;
   const double df = fs / (double)n;
   const int64_t i_low = (int64_t)ceil(f_low / df), i_high = n / 2 - 1;

@@ -27,6 +27,7 @@
 #include "rfd_internal.h"
 
 #include <algorithm>
+#include <bitset>
 #include <cstring>
 
 namespace rfd {
@@ -620,10 +621,10 @@ int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int
   int rc = stage_begin(p, kStFirKernel);
   if (rc) return rc;
   if (precision != RFD_FP32) {
-    std::vector<char> done(p.max_refs, 0);
+    std::bitset<kMaxRefSlots> done;     // reference slots already split
     for (const SubBankTaps& s : tp.sb) {
       if (s.count == 0 || done[s.ref_id]) continue;
-      done[s.ref_id] = 1;
+      done[s.ref_id] = true;
       if ((rc = launch_ref_planes(p, precision, s.ref_id, 0, p.n))) return rc;
     }
   }

@@ -29,6 +29,7 @@ hipError_t device_malloc(void** ptr, size_t bytes);
 constexpr int kFineBits = 10;                 // twiddle factorisation p = (c << 10) | f
 constexpr int kFine = 1 << kFineBits;
 constexpr int kDechirpBatch = 32;               // references per batched dechirp launch
+constexpr int kMaxRefSlots = 4096;              // reference-series slots of a plan, at most
 constexpr int kSigParts = 64;                   // partial sums per reference norm
 constexpr int kZParts = 32;                     // partial sums per FINDCHIRP trigger z
 

@@ -380,13 +380,13 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
 
 template <int K, int NF>
 static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, float threshold,
-                        int64_t n_lo, int64_t n_hi, float2* X) {
+                        int64_t n_lo, int64_t n_hi, float2* X, hipStream_t st, bool timed) {
   using S = BlockFft<K>;
   const float2* z = p.zref + (int64_t)s.ref_id * p.n;
   const int64_t b_first = n_lo / s.ols_L, b_last = (n_hi - 1) / s.ols_L;
   const int64_t nB = b_last - b_first + 1;      // <= s.ols_nB
   const unsigned gx = (unsigned)((nB + S::F - 1) / S::F);
-  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, nB, b_first,
+  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, st, z, p.n, s.k0, s.ols_L, nB, b_first,
                      (const float2*)p.ols_tw32, X);
   RFD_CHECK_LAUNCH();
   OlsArgs a;
@@ -407,34 +407,60 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
   a.J = ols_templates_per_wg(nB, S::F, s.count, p.n_cu);
   a.thr2 = threshold * threshold;
   const unsigned gy = (unsigned)((s.count + a.J - 1) / a.J);
-  int rc = stage_begin(p, kStFirKernel);
+  int rc = timed ? stage_begin(p, kStFirKernel) : RFD_OK;
   if (rc) return rc;
-  hipLaunchKernelGGL((k_ols<K, NF>), dim3(gx, gy), dim3(256), 0, p.stream, a);
+  hipLaunchKernelGGL((k_ols<K, NF>), dim3(gx, gy), dim3(256), 0, st, a);
   RFD_CHECK_LAUNCH();
-  return stage_end(p);
+  return timed ? stage_end(p) : RFD_OK;
 }
 
 int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo, int64_t n_hi,
                float2* x_scratch) {
   if (n_hi < 0) n_hi = p.n;
   if (n_lo < 0 || n_hi > p.n || n_lo >= n_hi) return fail(RFD_E_INVALID, "overlap-save: empty output range");
+  int active = 0;
+  for (const SubBankTaps& s : t.sb) {
+    if (s.count == 0) continue;
+    if (!s.ols_valid || !(x_scratch ? x_scratch : s.ols_x)) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
+    ++active;
+  }
+  // A short output range leaves each sub-bank's launch a small part of the
+  // chip, so independent sub-banks go round-robin over the plan's stream and
+  // its side streams (their window keys are disjoint slots, their block
+  // spectra separate buffers), forked from and joined back to the plan's
+  // stream.  Whole segments stay on the one stream: each launch fills the
+  // chip, and the per-launch kernel timing reads that stream.  A shared
+  // block-spectrum scratch keeps one stream as well.
+  const bool fan = !x_scratch && active > 1 && p.fork_ev && (n_hi - n_lo) * 8 <= p.n;
+  if (fan) {
+    RFD_HIP(hipEventRecord(p.fork_ev, p.stream));
+    for (int a = 0; a < Plan::kAux; ++a) RFD_HIP(hipStreamWaitEvent(p.aux[a], p.fork_ev, 0));
+  }
+  int rc = RFD_OK, i = 0;
   for (const SubBankTaps& s : t.sb) {
     if (s.count == 0) continue;
     float2* X = x_scratch ? x_scratch : s.ols_x;
-    if (!s.ols_valid || !X) return fail(RFD_E_STATE, "overlap-save spectra not prepared");
-    int rc;
+    const int lane = fan ? i++ % (Plan::kAux + 1) : 0;
+    const hipStream_t st = lane == 0 ? p.stream : p.aux[lane - 1];
     switch (s.ols_K * 16 + s.ols_nf) {
 #define OLS_CASE(KK, NN) \
-      case KK * 16 + NN: rc = launch_ols_k<KK, NN>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
+      case KK * 16 + NN: rc = launch_ols_k<KK, NN>(p, t, s, W, nwin, threshold, n_lo, n_hi, X, st, !fan); break;
       OLS_CASE(1024, 0) OLS_CASE(1024, 3)
       OLS_CASE(2048, 0) OLS_CASE(2048, 6) OLS_CASE(2048, 7)
       OLS_CASE(4096, 0) OLS_CASE(4096, 12) OLS_CASE(4096, 13) OLS_CASE(4096, 14) OLS_CASE(4096, 15)
 #undef OLS_CASE
       default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
     }
-    if (rc) return rc;
+    if (rc) break;
   }
-  return RFD_OK;
+  if (fan) {       // joined also after a failed launch: no side-stream work outlives the call's ordering
+    for (int a = 0; a < Plan::kAux; ++a) {
+      if (hipEventRecord(p.join_ev[a], p.aux[a]) != hipSuccess ||
+          hipStreamWaitEvent(p.stream, p.join_ev[a], 0) != hipSuccess)
+        if (!rc) rc = fail(RFD_E_DEVICE, "side stream join failed");
+    }
+  }
+  return rc;
 }
 
 }  // namespace rfd

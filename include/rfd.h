@@ -691,8 +691,8 @@ int rfd_filter_range(rfd_plan* plan, const rfd_taps* taps, int32_t precision, fl
  * mod N (trigger samples are such ring positions).  Each push:
  *   - writes D samples, transforms the ring once;
  *   - evaluates every reference series on the last zlen ring positions only
- *     (the correlation sum of Eq. 1 at those lags) into the plan's series
- *     store, FP32 and 16-bit planes;
+ *     (the correlation sum of Eq. 1 at those lags) into the plan's FP32
+ *     series store (a 16-bit form splits its planes from it);
  *   - runs the ratio FIR of every template, with the fused epilogue, over the
  *     D outputs [head - D - lag, head - lag) mod N, lag = the taps' lead
  *     max(k0 + T) rounded up to 256, so every FIR input lies in the freshly

@@ -95,3 +95,17 @@ def test_device_allocation_failure_is_reported_without_gpu():
     assert rc in (rfd.RFD_E_NOMEM, rfd.RFD_E_DEVICE)
     assert h.value is None
     assert rfd.rfd_last_error()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The binding has no fallback: a copy of it next to no librfd.so refuses
+    to import (the product path never degrades to a host implementation)."""
+    import importlib.util
+    import shutil
+    src = os.path.join(ROOT, "paper_2601_18835_amd", "rfd.py")
+    dst = tmp_path / "rfd_nolib.py"
+    shutil.copy(src, dst)
+    spec = importlib.util.spec_from_file_location("rfd_nolib", str(dst))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="librfd.so is missing"):
+        spec.loader.exec_module(mod)

@@ -38,6 +38,10 @@ typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 // tap groups (8 complex taps, 64 real products) per FP32 MFMA accumulation chunk
 constexpr int kFir32Chunk = 4;
+// column blocks per wave of the FP32 form: its running sums and chunk partials
+// are two accumulator sets, and 8 blocks keep both within three waves per SIMD
+// (16 blocks needed 276 registers: one wave per SIMD, 37% slower)
+constexpr int kFir32Nb = 8;
 
 struct FirArgs {
   const uint32_t* zhi;      // 16-bit planes of the reference slot ((re) | (im << 16))
@@ -468,8 +472,8 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
   a.k0 = s.k0;
   a.Tp = s.Tp;
   a.KB = s.Tp / 16;
-  // column blocks per wave: FP32 16; 16-bit forms 8 (tile config knob)
-  const int nb = precision == RFD_FP32 ? 16 : p.fir_nb16;
+  // column blocks per wave: FP32 kFir32Nb; 16-bit forms the tile config knob (8 by default)
+  const int nb = precision == RFD_FP32 ? kFir32Nb : p.fir_nb16;
   const int cols = 16 * nb;
   if (n_len < 0) {             // the whole segment
     n_start = 0;
@@ -488,7 +492,7 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
     if (rc) return rc;
   }
   if (precision == RFD_FP32) {
-    hipLaunchKernelGGL(k_fir32<16>, grid, dim3(256), (size_t)Lw * sizeof(float2), p.stream, a);
+    hipLaunchKernelGGL(k_fir32<kFir32Nb>, grid, dim3(256), (size_t)Lw * sizeof(float2), p.stream, a);
   } else {
     size_t sh = (size_t)2 * Lw * sizeof(uint32_t);
     const bool bf = precision == RFD_BF16X3;
@@ -508,7 +512,7 @@ int launch_fir(Plan& p, const Taps& tp, int b, int precision, int64_t W, int64_t
 
 namespace rfd {
 
-static int fir_cols(const Plan& p, int precision) { return 16 * (precision == RFD_FP32 ? 16 : p.fir_nb16); }
+static int fir_cols(const Plan& p, int precision) { return 16 * (precision == RFD_FP32 ? kFir32Nb : p.fir_nb16); }
 
 template <typename K>
 static int persistent_grid(Plan& p, K kernel, size_t lds, int64_t total) {
@@ -563,7 +567,7 @@ int prepare_fir_items(Plan& p, Taps& tp, int precision, int64_t W) {
   tp.it_lds = lds;
   const bool f16 = precision == RFD_FP16X3;
   if (precision == RFD_FP32)
-    tp.it_grid = persistent_grid(p, k_fir32_persistent<16>, lds, tp.it_total);
+    tp.it_grid = persistent_grid(p, k_fir32_persistent<kFir32Nb>, lds, tp.it_total);
   else if (p.fir_nb16 == 16)
     tp.it_grid = persistent_grid(p, f16 ? k_fir16_persistent<false, 16> : k_fir16_persistent<true, 16>, lds, tp.it_total);
   else
@@ -629,7 +633,7 @@ int launch_fir_persistent(Plan& p, const Taps& tp, int precision, int64_t W, int
     }
   }
   if (precision == RFD_FP32) {
-    hipLaunchKernelGGL(k_fir32_persistent<16>, grid, dim3(256), lds, p.stream, pa);
+    hipLaunchKernelGGL(k_fir32_persistent<kFir32Nb>, grid, dim3(256), lds, p.stream, pa);
   } else if (p.fir_nb16 == 16) {
     if (f16) hipLaunchKernelGGL((k_fir16_persistent<false, 16>), grid, dim3(256), lds, p.stream, pa);
     else hipLaunchKernelGGL((k_fir16_persistent<true, 16>), grid, dim3(256), lds, p.stream, pa);

@@ -25,7 +25,7 @@ namespace rfd {
 constexpr int kNT = 256;
 
 template <typename V> struct Cols;
-template <> struct Cols<float2> { static constexpr int value(int L) { return 8; } };
+template <> struct Cols<float2> { static constexpr int value(int L) { return L >= 2048 ? 4 : 8; } };   // 8 columns of 2048 spill registers
 template <> struct Cols<double2> { static constexpr int value(int L) { return L >= 2048 ? 2 : 4; } };
 
 template <typename V, int L, int C>

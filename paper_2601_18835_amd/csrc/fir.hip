@@ -244,10 +244,11 @@ __device__ __forceinline__ void fir16_block(const FirArgs& a, int64_t mbase, int
   fir_final_epilogue(a, tb, ps);
 }
 
-// three waves per SIMD: 158 registers at 8 column blocks, none spilled (180
-// and two waves without the bound)
+// three waves per SIMD at 8 column blocks: 158 registers, none spilled (180
+// and two waves without the bound); 16 blocks need more than a third of the
+// register file and keep the compiler's own allocation
 template <bool BF16, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fir16(FirArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB <= 8 ? 3 : 1))) void k_fir16(FirArgs a) {
   extern __shared__ __align__(16) uint32_t win[];
   fir16_block<BF16, NB>(a, a.m_off + (int64_t)blockIdx.x * a.S * 16 * NB, (int64_t)blockIdx.y * kWavesPerBlock, win);
 }
@@ -376,9 +377,10 @@ __device__ __forceinline__ bool next_item(const PersistArgs& pa, FirArgs& a, int
   return true;
 }
 
-// three waves per SIMD as k_fir16 (a few per-item values spill, outside the K loop)
+// (bounded to three waves per SIMD like k_fir16 it spills per-item values to
+// scratch and measured no faster at ecc512s: left at two)
 template <bool BF16, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fir16_persistent(PersistArgs pa) {
+__global__ __launch_bounds__(256) void k_fir16_persistent(PersistArgs pa) {
   extern __shared__ __align__(16) uint32_t win[];
   FirArgs a;
   int64_t mbase, tb0;

@@ -90,3 +90,32 @@ def test_fp32_and_fp64_transform_passes_against_oracle(rfd, setup):
     print(f"\n[dechirp] max |dz|/max|z|: FP32 passes {errs[False]:.2e}, FP64 passes {errs[True]:.2e}")
     assert errs[True] <= 2.0 ** -23
     assert errs[False] <= 2.0 ** -24 * 4 * np.log2(N)
+
+
+@pytest.mark.parametrize("log2n", [21, 22])
+def test_long_segment_series_match_oracle(rfd, log2n):
+    """Reference series at N = 2^21 and 2^22, where the row transforms of the
+    FP32 passes are 2048 points long (four columns per workgroup there): three
+    references in one batched call against the FP64 oracle."""
+    import torch
+    n = 1 << log2n
+    rng = np.random.default_rng(log2n)
+    w = synth.Workload(f"dechirp{log2n}", 9, n, FS, F_LOW, 0, 3, 0, "fp32", "nonspin")
+    psd = synth.psd_array(n, FS)
+    data = synth.spectrum_to_time(synth.make_noise_spectrum(w, rng), n, FS)
+    params = [synth.WaveformParams(*m) for m in rng.uniform(2.0, 3.0, size=(3, 2))]
+    H = synth.template_batch(w, params)
+    plan = rfd.rfd_plan_create(psd, F_LOW, FS, n, 3)
+    try:
+        refs = {r: torch.from_numpy(H[r]).to("cuda") for r in range(3)}
+        rfd.rfd_dechirp_refs(plan, torch.from_numpy(data).to("cuda"), refs, False)
+        p = orc.prepare(psd, data, FS, F_LOW)
+        worst = 0.0
+        for r in range(3):
+            ref = orc.dechirp(p, H[r])
+            got = rfd.rfd_get_zref(plan, r).cpu().numpy().astype(np.complex128)
+            worst = max(worst, float(np.max(np.abs(got - ref.z / ref.sigma))))
+        print(f"\n[dechirp N=2^{log2n}] max |dz_ref| = {worst:.3e}")
+        assert worst <= 1e-5
+    finally:
+        rfd.rfd_plan_destroy(plan)

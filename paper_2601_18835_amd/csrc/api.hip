@@ -124,14 +124,6 @@ static void plan_free(Plan& p) {
   dfree(p.slots); dfree(p.counts); dfree(p.total); dfree(p.fc_work); dfree(p.counter);
   dfree(p.ols_tw32); dfree(p.ols_tw64);
   for (auto& z : p.zband) dfree(z);
-  for (int a = 0; a < Plan::kAux; ++a) {
-    if (p.aux[a]) (void)hipStreamDestroy(p.aux[a]);
-    if (p.join_ev[a]) (void)hipEventDestroy(p.join_ev[a]);
-    p.aux[a] = nullptr;
-    p.join_ev[a] = nullptr;
-  }
-  if (p.fork_ev) (void)hipEventDestroy(p.fork_ev);
-  p.fork_ev = nullptr;
 }
 
 int ensure_slots(Plan& p, int64_t n_slots) {
@@ -352,15 +344,6 @@ int rfd_plan_create(const double* psd, int64_t n_psd, double f_low, double fs, i
   TRY(dalloc(&p.zh_hi, (size_t)max_refs * n));
   TRY(dalloc(&p.zh_lo, (size_t)max_refs * n));
 #undef TRY
-  bool ok = hipEventCreateWithFlags(&p.fork_ev, hipEventDisableTiming) == hipSuccess;
-  for (int a = 0; ok && a < Plan::kAux; ++a)
-    ok = hipStreamCreateWithFlags(&p.aux[a], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&p.join_ev[a], hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
-    plan_free(p);
-    delete h;
-    return fail(RFD_E_DEVICE, "side stream creation failed");
-  }
   *out = h;
   return RFD_OK;
 }

@@ -40,12 +40,12 @@ __device__ __forceinline__ unsigned long long umax64_ols(unsigned long long a, u
 // ------------------------------------------------------------ block spectra
 // X[b][f] for every block b of the reference series (forward FFT).
 template <int K>
-__global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
-                                            int64_t b_first, const float2* __restrict__ tw, float2* __restrict__ X) {
+__device__ __forceinline__ void ols_x_body(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
+                                           int64_t b_first, const float2* __restrict__ tw, float2* __restrict__ X,
+                                           uint32_t bx, float2* lds) {
   using S = BlockFft<K>;
-  __shared__ float2 lds[S::F * S::LDS];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
-  const int64_t b = (int64_t)blockIdx.x * S::F + f;     // row of X; the segment block is b_first + b
+  const int64_t b = (int64_t)bx * S::F + f;     // row of X; the segment block is b_first + b
   BlockFftTw<K> w;
   block_fft_twiddles<K, -1>(w, tw, t);
   float2 v[16];
@@ -59,6 +59,13 @@ __global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int
   for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
     for (int s = 0; s < S::R; ++s) xb[block_fft_out<K>(t, e, s)] = v[e * S::R + s];
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
+                                            int64_t b_first, const float2* __restrict__ tw, float2* __restrict__ X) {
+  __shared__ float2 lds[BlockFft<K>::F * BlockFft<K>::LDS];
+  ols_x_body<K>(z, n, k0, L, nB, b_first, tw, X, blockIdx.x, lds);
 }
 
 // --------------------------------------------------------- tap spectra (FP64)
@@ -148,14 +155,13 @@ __device__ __forceinline__ OlsTile ols_tile() {
   return OlsTile{x0 + r % w, r / w};
 }
 
+// One workgroup's (block group bx, template group by) of a sub-bank.
 template <int K, int NF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ols(OlsArgs a) {
+__device__ __forceinline__ void ols_body(const OlsArgs& a, uint32_t bx, uint32_t by, float2* lds,
+                                         float2* twb_table) {
   using S = BlockFft<K>;
-  __shared__ float2 lds[S::F * S::LDS];
-  __shared__ float2 twb_table[block_fft_twb_size<K>()];
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
-  const OlsTile wg = ols_tile();
-  const int64_t b = (int64_t)wg.bx * S::F + f;
+  const int64_t b = (int64_t)bx * S::F + f;
   const bool bvalid = b < a.nB;
   BlockFftTwL<K> w;
   block_fft_twiddles_lds<K, 1>(w, a.tw, t, twb_table);
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // every kept slot is an output of the launch: no per-sample range test
   const bool whole = NF > 0 && has_out && nbeg == n0 && nend == n0 + a.L;
   const int64_t q0 = has_out ? nbeg / a.W : 0, q1 = has_out ? (nend - 1) / a.W : 0;
-  const int64_t j0 = (int64_t)wg.by * a.J;
+  const int64_t j0 = (int64_t)by * a.J;
   const int64_t j1 = std::min<int64_t>(j0 + a.J, a.count);
   const bool lead = (threadIdx.x & 63) == 0;
   // the next template's tap spectrum is fetched while the current one is
@@ -256,6 +262,105 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
     }
   }
+}
+
+template <int K, int NF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ols(OlsArgs a) {
+  __shared__ float2 lds[BlockFft<K>::F * BlockFft<K>::LDS];
+  __shared__ float2 twb_table[block_fft_twb_size<K>()];
+  const OlsTile wg = ols_tile();
+  ols_body<K, NF>(a, wg.bx, wg.by, lds, twb_table);
+}
+
+// ------------------------------------------------- several sub-banks at once
+// A short output range gives each sub-bank a few blocks only: one launch then
+// covers up to kOlsMulti sub-banks of one block size, their workgroups laid
+// end to end (sub-bank s owns workgroups [wg0, wg0 + gx gy) of k_ols_multi and
+// [wgx0, wgx0 + gx) of k_ols_x_multi).  The descriptors travel by value in the
+// kernel arguments (nothing to upload, and a captured graph keeps them).
+constexpr int kOlsMulti = 16;
+struct OlsSb {
+  const float2* z;           // the sub-bank's reference series
+  float2* X;                 // its block spectra [nB][K]
+  const float2* G;           // its tap spectra [count][K]
+  int64_t count, tmpl0, nB, b_first;
+  int k0, L, J;
+  uint32_t gx, wg0, wgx0;
+};
+struct OlsMultiArgs {
+  OlsSb sb[kOlsMulti];
+  const float2* tw;
+  unsigned long long* slots;
+  int64_t n, nwin, W, n_lo, n_hi;
+  float thr2;
+  int nsb;
+};
+
+// sub-bank of workgroup g (by the first-workgroup fields), with constant
+// indices only, so the descriptors stay in the argument segment
+template <bool X>
+__device__ __forceinline__ int ols_multi_find(const OlsMultiArgs& m, uint32_t g) {
+  int s = 0;
+#pragma unroll
+  for (int i = 1; i < kOlsMulti; ++i)
+    if (i < m.nsb && g >= (X ? m.sb[i].wgx0 : m.sb[i].wg0)) s = i;
+  return s;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_ols_x_multi(OlsMultiArgs m) {
+  __shared__ float2 lds[BlockFft<K>::F * BlockFft<K>::LDS];
+  const int s = ols_multi_find<true>(m, blockIdx.x);
+  const float2* z = nullptr;
+  float2* X = nullptr;
+  int64_t nB = 0, b_first = 0;
+  int k0 = 0, L = 1;
+  uint32_t wgx0 = 0;
+#pragma unroll
+  for (int i = 0; i < kOlsMulti; ++i)
+    if (i == s) {
+      z = m.sb[i].z;
+      X = m.sb[i].X;
+      nB = m.sb[i].nB;
+      b_first = m.sb[i].b_first;
+      k0 = m.sb[i].k0;
+      L = m.sb[i].L;
+      wgx0 = m.sb[i].wgx0;
+    }
+  ols_x_body<K>(z, m.n, k0, L, nB, b_first, m.tw, X, blockIdx.x - wgx0, lds);
+}
+
+template <int K, int NF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ols_multi(OlsMultiArgs m) {
+  __shared__ float2 lds[BlockFft<K>::F * BlockFft<K>::LDS];
+  __shared__ float2 twb_table[block_fft_twb_size<K>()];
+  const int s = ols_multi_find<false>(m, blockIdx.x);
+  OlsArgs a;
+  a.tw = m.tw;
+  a.slots = m.slots;
+  a.n = m.n;
+  a.nwin = m.nwin;
+  a.W = m.W;
+  a.n_lo = m.n_lo;
+  a.n_hi = m.n_hi;
+  a.thr2 = m.thr2;
+  uint32_t gx = 1, wg0 = 0;
+#pragma unroll
+  for (int i = 0; i < kOlsMulti; ++i)
+    if (i == s) {
+      a.X = m.sb[i].X;
+      a.G = m.sb[i].G;
+      a.count = m.sb[i].count;
+      a.tmpl0 = m.sb[i].tmpl0;
+      a.nB = m.sb[i].nB;
+      a.b_first = m.sb[i].b_first;
+      a.L = m.sb[i].L;
+      a.J = m.sb[i].J;
+      gx = m.sb[i].gx;
+      wg0 = m.sb[i].wg0;
+    }
+  const uint32_t l = blockIdx.x - wg0;
+  ols_body<K, NF>(a, l % gx, l / gx, lds, twb_table);
 }
 
 // ------------------------------------------------------------------ host
@@ -380,13 +485,13 @@ int ensure_ols(Plan& p, Taps& t, bool allow_alloc, bool need_block_spectra) {
 
 template <int K, int NF>
 static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W, int64_t nwin, float threshold,
-                        int64_t n_lo, int64_t n_hi, float2* X, hipStream_t st, bool timed) {
+                        int64_t n_lo, int64_t n_hi, float2* X) {
   using S = BlockFft<K>;
   const float2* z = p.zref + (int64_t)s.ref_id * p.n;
   const int64_t b_first = n_lo / s.ols_L, b_last = (n_hi - 1) / s.ols_L;
   const int64_t nB = b_last - b_first + 1;      // <= s.ols_nB
   const unsigned gx = (unsigned)((nB + S::F - 1) / S::F);
-  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, st, z, p.n, s.k0, s.ols_L, nB, b_first,
+  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, nB, b_first,
                      (const float2*)p.ols_tw32, X);
   RFD_CHECK_LAUNCH();
   OlsArgs a;
@@ -407,11 +512,68 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
   a.J = ols_templates_per_wg(nB, S::F, s.count, p.n_cu);
   a.thr2 = threshold * threshold;
   const unsigned gy = (unsigned)((s.count + a.J - 1) / a.J);
-  int rc = timed ? stage_begin(p, kStFirKernel) : RFD_OK;
+  int rc = stage_begin(p, kStFirKernel);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_ols<K, NF>), dim3(gx, gy), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_ols<K, NF>), dim3(gx, gy), dim3(256), 0, p.stream, a);
   RFD_CHECK_LAUNCH();
-  return timed ? stage_end(p) : RFD_OK;
+  return stage_end(p);
+}
+
+// Up to kOlsMulti sub-banks of one block size (K, NF) over the output range
+// [n_lo, n_hi) in one k_ols_x_multi and one k_ols_multi launch.
+template <int K, int NF>
+static int launch_ols_multi(Plan& p, const Taps& t, const int* sbs, int nsb, int64_t W, int64_t nwin,
+                            float threshold, int64_t n_lo, int64_t n_hi) {
+  using S = BlockFft<K>;
+  OlsMultiArgs m{};
+  m.tw = p.ols_tw32;
+  m.slots = p.slots;
+  m.n = p.n;
+  m.nwin = nwin;
+  m.W = W;
+  m.n_lo = n_lo;
+  m.n_hi = n_hi;
+  m.thr2 = threshold * threshold;
+  m.nsb = nsb;
+  for (int i = 0; i < nsb; ++i) {
+    const SubBankTaps& s = t.sb[sbs[i]];
+    OlsSb& d = m.sb[i];
+    d.z = p.zref + (int64_t)s.ref_id * p.n;
+    d.X = s.ols_x;
+    d.G = s.ols_g;
+    d.count = s.count;
+    d.tmpl0 = s.first;
+    d.b_first = n_lo / s.ols_L;
+    d.nB = (n_hi - 1) / s.ols_L - d.b_first + 1;
+    d.k0 = s.k0;
+    d.L = s.ols_L;
+    d.gx = (uint32_t)((d.nB + S::F - 1) / S::F);
+  }
+  // templates per workgroup: enough workgroups over the whole launch to fill
+  // the chip several times, at least 4 templates each
+  int J = 32;
+  auto total = [&](int j) {
+    int64_t w = 0;
+    for (int i = 0; i < nsb; ++i) w += (int64_t)m.sb[i].gx * ((m.sb[i].count + j - 1) / j);
+    return w;
+  };
+  while (J > 4 && total(J) < (int64_t)8 * p.n_cu) J /= 2;
+  uint32_t wg = 0, wgx = 0;
+  for (int i = 0; i < nsb; ++i) {
+    OlsSb& d = m.sb[i];
+    d.J = J;
+    d.wg0 = wg;
+    d.wgx0 = wgx;
+    wg += d.gx * (uint32_t)((d.count + J - 1) / J);
+    wgx += d.gx;
+  }
+  hipLaunchKernelGGL(k_ols_x_multi<K>, dim3(wgx), dim3(256), 0, p.stream, m);
+  RFD_CHECK_LAUNCH();
+  int rc = stage_begin(p, kStFirKernel);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_ols_multi<K, NF>), dim3(wg), dim3(256), 0, p.stream, m);
+  RFD_CHECK_LAUNCH();
+  return stage_end(p);
 }
 
 int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold, int64_t n_lo, int64_t n_hi,
@@ -425,42 +587,53 @@ int launch_ols(Plan& p, const Taps& t, int64_t W, int64_t nwin, float threshold,
     ++active;
   }
   // A short output range leaves each sub-bank's launch a small part of the
-  // chip, so independent sub-banks go round-robin over the plan's stream and
-  // its side streams (their window keys are disjoint slots, their block
-  // spectra separate buffers), forked from and joined back to the plan's
-  // stream.  Whole segments stay on the one stream: each launch fills the
-  // chip, and the per-launch kernel timing reads that stream.  A shared
-  // block-spectrum scratch keeps one stream as well.
-  const bool fan = !x_scratch && active > 1 && p.fork_ev && (n_hi - n_lo) * 8 <= p.n;
-  if (fan) {
-    RFD_HIP(hipEventRecord(p.fork_ev, p.stream));
-    for (int a = 0; a < Plan::kAux; ++a) RFD_HIP(hipStreamWaitEvent(p.aux[a], p.fork_ev, 0));
+  // chip: the sub-banks of one block size then share launches (their window
+  // keys are disjoint slots, their block spectra separate buffers).  Whole
+  // segments keep one launch per sub-bank, each filling the chip, so that a
+  // sub-bank's block spectra are used while still in the last-level cache.  A
+  // shared block-spectrum scratch keeps one launch per sub-bank as well.
+  if (!x_scratch && active > 1 && (n_hi - n_lo) * 8 <= p.n) {
+    std::vector<char> done(t.sb.size(), 0);
+    for (size_t b0 = 0; b0 < t.sb.size(); ++b0) {
+      const SubBankTaps& s0 = t.sb[b0];
+      if (s0.count == 0 || done[b0]) continue;
+      int sbs[kOlsMulti], nsb = 0;
+      for (size_t b = b0; b < t.sb.size() && nsb < kOlsMulti; ++b) {
+        const SubBankTaps& s = t.sb[b];
+        if (s.count == 0 || done[b] || s.ols_K != s0.ols_K || s.ols_nf != s0.ols_nf) continue;
+        done[b] = 1;
+        sbs[nsb++] = (int)b;
+      }
+      int rc;
+      switch (s0.ols_K * 16 + s0.ols_nf) {
+#define OLS_CASE(KK, NN) \
+        case KK * 16 + NN: rc = launch_ols_multi<KK, NN>(p, t, sbs, nsb, W, nwin, threshold, n_lo, n_hi); break;
+        OLS_CASE(1024, 0) OLS_CASE(1024, 3)
+        OLS_CASE(2048, 0) OLS_CASE(2048, 6) OLS_CASE(2048, 7)
+        OLS_CASE(4096, 0) OLS_CASE(4096, 12) OLS_CASE(4096, 13) OLS_CASE(4096, 14) OLS_CASE(4096, 15)
+#undef OLS_CASE
+        default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
+      }
+      if (rc) return rc;     // sub-banks past kOlsMulti of this block size start the next chunk
+    }
+    return RFD_OK;
   }
-  int rc = RFD_OK, i = 0;
   for (const SubBankTaps& s : t.sb) {
     if (s.count == 0) continue;
     float2* X = x_scratch ? x_scratch : s.ols_x;
-    const int lane = fan ? i++ % (Plan::kAux + 1) : 0;
-    const hipStream_t st = lane == 0 ? p.stream : p.aux[lane - 1];
+    int rc;
     switch (s.ols_K * 16 + s.ols_nf) {
 #define OLS_CASE(KK, NN) \
-      case KK * 16 + NN: rc = launch_ols_k<KK, NN>(p, t, s, W, nwin, threshold, n_lo, n_hi, X, st, !fan); break;
+      case KK * 16 + NN: rc = launch_ols_k<KK, NN>(p, t, s, W, nwin, threshold, n_lo, n_hi, X); break;
       OLS_CASE(1024, 0) OLS_CASE(1024, 3)
       OLS_CASE(2048, 0) OLS_CASE(2048, 6) OLS_CASE(2048, 7)
       OLS_CASE(4096, 0) OLS_CASE(4096, 12) OLS_CASE(4096, 13) OLS_CASE(4096, 14) OLS_CASE(4096, 15)
 #undef OLS_CASE
       default: rc = fail(RFD_E_INVALID, "overlap-save block size must be 1024, 2048 or 4096");
     }
-    if (rc) break;
+    if (rc) return rc;
   }
-  if (fan) {       // joined also after a failed launch: no side-stream work outlives the call's ordering
-    for (int a = 0; a < Plan::kAux; ++a) {
-      if (hipEventRecord(p.join_ev[a], p.aux[a]) != hipSuccess ||
-          hipStreamWaitEvent(p.stream, p.join_ev[a], 0) != hipSuccess)
-        if (!rc) rc = fail(RFD_E_DEVICE, "side stream join failed");
-    }
-  }
-  return rc;
+  return RFD_OK;
 }
 
 }  // namespace rfd

@@ -40,12 +40,6 @@ struct Plan {
   double fs = 0, f_low = 0, df = 0, data_scale = 0;
   int max_refs = 0;
   hipStream_t stream = nullptr;
-  // side streams (default priority) for independent per-sub-bank launches,
-  // with the events that fork them from `stream` and join them back
-  static constexpr int kAux = 3;
-  hipStream_t aux[kAux] = {};
-  hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev[kAux] = {};
 
   // FP64 PSD weights w_i = 4 df / S_n(f_i) in band, 0 elsewhere  [nb]
   double* w = nullptr;

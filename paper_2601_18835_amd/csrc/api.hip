@@ -78,11 +78,26 @@ static int upload_table(Plan& p, int64_t len, int64_t step, int64_t den, float2*
   return RFD_OK;
 }
 
+static int take_event(Plan& p, hipEvent_t* e) {
+  if (!p.event_pool.empty()) {
+    *e = p.event_pool.back();
+    p.event_pool.pop_back();
+    return RFD_OK;
+  }
+  RFD_HIP(hipEventCreate(e));
+  return RFD_OK;
+}
+
+// (timing is off while a graph is captured: these events are never graph nodes)
 int stage_begin(Plan& p, int stage) {
   if (!p.timing) return RFD_OK;
   Plan::Mark m{stage, nullptr, nullptr, true};
-  RFD_HIP(hipEventCreate(&m.a));
-  RFD_HIP(hipEventCreate(&m.b));
+  int rc = take_event(p, &m.a);
+  if (!rc) rc = take_event(p, &m.b);
+  if (rc) {
+    if (m.a) p.event_pool.push_back(m.a);
+    return rc;
+  }
   RFD_HIP(hipEventRecord(m.a, p.stream));
   p.marks.push_back(m);
   return RFD_OK;
@@ -100,16 +115,23 @@ int stage_end(Plan& p) {
   return RFD_OK;
 }
 
+// marks read out or abandoned: their events go back to the pool
 static void drop_marks(Plan& p) {
   for (auto& m : p.marks) {
-    if (m.a) (void)hipEventDestroy(m.a);
-    if (m.b) (void)hipEventDestroy(m.b);
+    if (m.a) p.event_pool.push_back(m.a);
+    if (m.b) p.event_pool.push_back(m.b);
   }
   p.marks.clear();
 }
 
-static void plan_free(Plan& p) {
+static void destroy_events(Plan& p) {
   drop_marks(p);
+  for (hipEvent_t e : p.event_pool) (void)hipEventDestroy(e);
+  p.event_pool.clear();
+}
+
+static void plan_free(Plan& p) {
+  destroy_events(p);
   if (p.ws_external) {      // caller-owned: not ours to free
     p.slots = nullptr;
     p.counts = nullptr;
@@ -377,7 +399,7 @@ int rfd_plan_set_timing(rfd_plan* plan, int32_t enable) {
   plan->p.timing = enable != 0;
   if (!plan->p.timing) {
     (void)hipStreamSynchronize(plan->p.stream);
-    drop_marks(plan->p);
+    destroy_events(plan->p);
   }
   return RFD_OK;
 }

@@ -109,6 +109,7 @@ struct Plan {
   bool timing = false;
   struct Mark { int stage; hipEvent_t a, b; bool open; };
   std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;   // events of read-out marks, reused by later stages
 };
 
 enum Stage {

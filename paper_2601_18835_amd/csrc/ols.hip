@@ -203,16 +203,22 @@ __device__ __forceinline__ void ols_body(const OlsArgs& a, uint32_t bx, uint32_t
     // correlation wraps, taps that cancel only against the series' own
     // correlations lose that cancellation and would cross the threshold.
     uint32_t r2max = 0u;
+    // rho^2 once for every kept slot, then its maximum with or without the range test
+#pragma unroll
+    for (int e = 0; e < 16 / S::R; ++e)
+#pragma unroll
+      for (int s = 0; s < S::R; ++s) {
+        if (!ols_slot_kept<K, NF>(s)) continue;
+        const float2 y = v[e * S::R + s];
+        r2[e * S::R + s] = y.x * y.x + y.y * y.y;
+      }
     if (whole) {
 #pragma unroll
       for (int e = 0; e < 16 / S::R; ++e)
 #pragma unroll
         for (int s = 0; s < S::R; ++s) {
           if (!ols_slot_kept<K, NF>(s)) continue;
-          const float2 y = v[e * S::R + s];
-          const float x = y.x * y.x + y.y * y.y;
-          r2[e * S::R + s] = x;
-          r2max = max(r2max, __float_as_uint(x));
+          r2max = max(r2max, __float_as_uint(r2[e * S::R + s]));
         }
     } else {
 #pragma unroll
@@ -220,9 +226,7 @@ __device__ __forceinline__ void ols_body(const OlsArgs& a, uint32_t bx, uint32_t
 #pragma unroll
         for (int s = 0; s < S::R; ++s) {
           if (!ols_slot_kept<K, NF>(s)) continue;
-          const float2 y = v[e * S::R + s];
-          const float x = y.x * y.x + y.y * y.y;
-          r2[e * S::R + s] = x;
+          const float x = r2[e * S::R + s];
           const int64_t nn = n0 + block_fft_out<K>(t, e, s);
           if (nn >= nbeg && nn < nend) r2max = max(r2max, __float_as_uint(x));
         }

@@ -23,7 +23,7 @@ device memory (synth.device); the oracle legs use host waveforms.
 
 The FP64 CPU oracle runs first, before the GPU is touched: a seeded sample of
 templates (the injected one included) through its dechirp and direct-sum FIR
-on every host core the box grants (worker processes, at most 16) and on one
+on every host core available to the process (worker processes, at most 16) and on one
 core; its series are the parity reference for every FIR form, its matches
 the tap-fidelity distribution.
 
@@ -32,7 +32,7 @@ templates, T = 256), tidal256s (64 uneven sub-banks, T 32..1024) and
 surr512s (the learned tap surrogate end to end: 65536 templates whose taps
 come from 32 trained networks, validated, with exact-tap fallback).
 
-Prints one JSON line.  `--gpus` above 1 exits: the build targets one GPU.
+Prints one JSON line.  `--gpus` above 1 exits: the benchmark runs on one GPU.
 """
 import argparse
 import json

@@ -16,6 +16,7 @@
 // read and k_lags_direct sums them.  FINDCHIRP's own transforms live with its
 // kernels.
 #include <algorithm>
+#include <type_traits>
 
 #include "dev_common.h"
 #include "rfd_internal.h"
@@ -72,14 +73,16 @@ struct LoadFindchirp {     // s_i * F_j,i with F_j stored over band bins
     return cmul(s[i], f[(int64_t)b * n_band + (i - i_low)]);
   }
 };
-struct LoadCorr64 {        // FP64 correlation integrands for tap construction
+struct LoadCorr64 {        // FP64 correlation integrands (tap construction, streaming series)
   const double* w; const double2* hr; const double2* ht; int64_t nb, i_low, i_high; int mode;
+  const double* bscale;    // mode 0: per-member factor folded into the integrand (nullptr: none)
   __device__ double2 operator()(int b, int64_t i) const {
     if (i < i_low || i > i_high) return make_double2(0.0, 0.0);
     double2 r = hr[i];
     double wi = w[i];
     if (mode == 1) return make_double2(wi * (r.x * r.x + r.y * r.y), 0.0);
     double2 t = ht[(int64_t)b * nb + i];
+    if (bscale) wi *= bscale[b];
     if (mode == 0) return make_double2(wi * (t.x * r.x + t.y * r.y), wi * (t.y * r.x - t.x * r.y));
     // mode 2: ratio R = t / r where the chi^2 weight w |r|^2 is non-zero
     double rr = r.x * r.x + r.y * r.y;
@@ -88,7 +91,11 @@ struct LoadCorr64 {        // FP64 correlation integrands for tap construction
   }
 };
 
-struct LoadCorr32 {        // the same integrands rounded once to FP32
+// The same integrands rounded once to FP32.  w_i alone is of order 1 / S_n
+// (about 1e46 for a strain PSD), so an unnormalised integrand overflows FP32:
+// FP32 callers fold the normalisation of the result in through bscale (the
+// streaming series use 1 / (sigma_ref alpha), as the FP32 dechirp passes do).
+struct LoadCorr32 {
   LoadCorr64 d;
   __device__ float2 operator()(int b, int64_t i) const {
     const double2 v = d(b, i);
@@ -274,12 +281,13 @@ __global__ __launch_bounds__(256) void k_lags_direct(const double2* __restrict__
 // once to their share of every kept lag m = k0 + l,
 //   part[b][g][l] = sum_{i1 in group g} Y[m mod N2][i1] exp(+2 pi i i1 (m div N2) / N1),
 // and k_corr_reduce adds the N1 / C shares of each lag in a fixed order.
-// V = double2: FP64 column transforms (tap construction); V = float2: FP32
-// column transforms of the integrand rounded once from FP64, the shares
-// still summed in FP64 (the streaming reference series, like the FP32
-// dechirp passes).
+// V = double2: FP64 column transforms and shares (tap construction); V =
+// float2: FP32 column transforms of the integrand rounded once from FP64, each
+// share summed in FP64 and stored in FP32 (half the share traffic), the shares
+// then added in FP64 (the streaming reference series, like the FP32 dechirp
+// passes).
 template <typename V, int L, class LD>
-__global__ __launch_bounds__(kNT) void k_corr_part(LD ld, double2* __restrict__ part, const V* __restrict__ coarse,
+__global__ __launch_bounds__(kNT) void k_corr_part(LD ld, V* __restrict__ part, const V* __restrict__ coarse,
                                                  const V* __restrict__ fine, const V* __restrict__ tabL,
                                                  const V* __restrict__ tab1, int n1, int k0,
                                                  const int32_t* __restrict__ k0s, int T) {
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LD ld, double2* __restrict__ 
   __syncthreads();
   lds_fft<V, L, C, kNT>(buf, twl, +1);
   __syncthreads();
-  double2* pb = part + ((int64_t)b * G + g) * T;
+  V* pb = part + ((int64_t)b * G + g) * T;
   for (int l = threadIdx.x; l < T; l += kNT) {
     const int64_t m = ((int64_t)k0 + l) & (n - 1);
     const int r = (int)(m % L), cc = (int)(m / L);
@@ -321,22 +329,26 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LD ld, double2* __restrict__ 
       re += x.x;
       im += x.y;
     }
-    pb[l] = make_double2(re, im);
+    if constexpr (std::is_same<V, float2>::value)
+      pb[l] = make_float2((float)re, (float)im);
+    else
+      pb[l] = make_double2(re, im);
   }
 }
 
 // 32 lags per workgroup; 8 slices of the groups per lag (slice s adds groups
 // s, s + 8, ...), then the slices in order: a fixed summation order.
-__global__ __launch_bounds__(256) void k_corr_reduce(const double2* __restrict__ part, int groups, int T,
+template <typename V>
+__global__ __launch_bounds__(256) void k_corr_reduce(const V* __restrict__ part, int groups, int T,
                                                    double scale, double2* __restrict__ out, int64_t stride) {
   __shared__ double2 red[8][32];
   const int ll = threadIdx.x & 31, sl = threadIdx.x >> 5;
   const int l = blockIdx.x * 32 + ll;
   double re = 0.0, im = 0.0;
   if (l < T) {
-    const double2* pb = part + (int64_t)blockIdx.y * groups * T + l;
+    const V* pb = part + (int64_t)blockIdx.y * groups * T + l;
     for (int g = sl; g < groups; g += 8) {
-      const double2 v = pb[(int64_t)g * T];
+      const V v = pb[(int64_t)g * T];
       re += v.x;
       im += v.y;
     }
@@ -568,11 +580,13 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
 }
 
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch, int T,
-                  int k0, double2* out, int64_t out_stride, int64_t lo, int64_t hi, const int32_t* k0s, bool fp32) {
+                  int k0, double2* out, int64_t out_stride, int64_t lo, int64_t hi, const int32_t* k0s, bool fp32,
+                  const double* bscale) {
   size_t need = (size_t)batch * p.n;
   if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
+  if (fp32 && mode == 0 && !bscale) return fail(RFD_E_INVALID, "corr64: FP32 integrands need their normalisation");
   LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high,
-                mode};
+                mode, mode == 0 ? bscale : nullptr};
   const double scale = mode == 2 ? 1.0 / (double)p.n : 1.0;
   // fused form: per-workgroup lag shares in the work buffer, then their sums
   const int C = fp32 ? Cols<float2>::value(p.n2) : Cols<double2>::value(p.n2);
@@ -585,7 +599,7 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
     if (fp32) {                                                                                          \
       const size_t sh = lds_bytes<float2, LL, Cols<float2>::value(LL)>();                                \
       hipLaunchKernelGGL((k_corr_part<float2, LL, LoadCorr32>), dim3(groups, (unsigned)batch), blk, sh,  \
-                         p.stream, LoadCorr32{ld}, tp.work64, p.tw32c, p.tw32f, p.tw32_n2, p.tw32_n1, p.n1,  \
+                         p.stream, LoadCorr32{ld}, (float2*)tp.work64, p.tw32c, p.tw32f, p.tw32_n2, p.tw32_n1, p.n1,  \
                          k0, k0s, T);                                                                    \
     } else {                                                                                             \
       const size_t sh = lds_bytes<double2, LL, Cols<double2>::value(LL)>();                              \
@@ -599,8 +613,12 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
       default: return fail(RFD_E_UNSUPPORTED, "fft: unsupported N2");
     }
     RFD_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_corr_reduce, dim3((unsigned)((T + 31) / 32), (unsigned)batch), dim3(256), 0, p.stream,
-                       (const double2*)tp.work64, groups, T, scale, out, out_stride);
+    if (fp32)
+      hipLaunchKernelGGL(k_corr_reduce<float2>, dim3((unsigned)((T + 31) / 32), (unsigned)batch), dim3(256), 0,
+                         p.stream, (const float2*)tp.work64, groups, T, scale, out, out_stride);
+    else
+      hipLaunchKernelGGL(k_corr_reduce<double2>, dim3((unsigned)((T + 31) / 32), (unsigned)batch), dim3(256), 0,
+                         p.stream, (const double2*)tp.work64, groups, T, scale, out, out_stride);
     RFD_CHECK_LAUNCH();
     return RFD_OK;
   }
@@ -690,7 +708,7 @@ int launch_corr_peak(Plan& p, Taps& tp, const double* h_r, const double* h_t, in
   if (tp.work64_cap < (size_t)batch * p.n) return fail(RFD_E_INVALID, "corr peak: work buffer too small");
   if (tp.peak_cap < (size_t)batch * p.n || tp.peak_parts_cap < (size_t)batch * kPeakParts || p.n < 1024)
     return fail(RFD_E_INVALID, "corr peak: scratch too small");
-  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, p.i_low, p.i_high, 0};
+  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, p.i_low, p.i_high, 0, nullptr};
   int rc = run_pass_a<double2>(p, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, (int)batch, +1);
   if (rc) return rc;
   rc = run_pass_b<double2>(p, (const double2*)tp.work64, StorePow{pw, p.n}, p.tw64_n1, (int)batch, +1);

@@ -6,7 +6,9 @@
 // With L = K - T + 1 valid outputs per block, block b's input is
 //   x_b[m] = zhat[(b L + k0 + m) mod N],  m < K,
 // and its outputs z_j[b L + i], i < L, are the first L samples of the
-// circular correlation of x_b with the taps:
+// circular correlation of x_b with the taps (a launch over the outputs
+// [n_lo, n_hi) places its blocks from n_lo, b L -> n_lo + b L, so a short
+// range needs ceil((n_hi - n_lo) / L) blocks wherever it starts):
 //   z_j[b L + i] = sum_k c_k x_b[i + k] = (1/K) sum_f X_b[f] G_j[f] e^{+2 pi i f i / K},
 //   X_b[f] = sum_m x_b[m] e^{-2 pi i f m / K},   G_j[f] = sum_k c_k e^{+2 pi i f k / K}.
 // X_b is computed once per reference series and segment (all blocks), G_j
@@ -41,15 +43,15 @@ __device__ __forceinline__ unsigned long long umax64_ols(unsigned long long a, u
 // X[b][f] for every block b of the reference series (forward FFT).
 template <int K>
 __device__ __forceinline__ void ols_x_body(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
-                                           int64_t b_first, const float2* __restrict__ tw, float2* __restrict__ X,
+                                           int64_t org, const float2* __restrict__ tw, float2* __restrict__ X,
                                            uint32_t bx, float2* lds) {
   using S = BlockFft<K>;
   const int f = threadIdx.x / S::NTf, t = threadIdx.x % S::NTf;
-  const int64_t b = (int64_t)bx * S::F + f;     // row of X; the segment block is b_first + b
+  const int64_t b = (int64_t)bx * S::F + f;     // row of X: the block whose outputs start at org + b L
   BlockFftTw<K> w;
   block_fft_twiddles<K, -1>(w, tw, t);
   float2 v[16];
-  const int64_t start = (b_first + b) * L + k0;
+  const int64_t start = org + b * L + k0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = b < nB ? z[(start + t + S::NTf * r) & (n - 1)] : make_float2(0.f, 0.f);
   block_fft<K, -1>(v, lds + f * S::LDS, t, w);
@@ -63,9 +65,9 @@ __device__ __forceinline__ void ols_x_body(const float2* __restrict__ z, int64_t
 
 template <int K>
 __global__ __launch_bounds__(256) void k_ols_x(const float2* __restrict__ z, int64_t n, int k0, int L, int64_t nB,
-                                            int64_t b_first, const float2* __restrict__ tw, float2* __restrict__ X) {
+                                            int64_t org, const float2* __restrict__ tw, float2* __restrict__ X) {
   __shared__ float2 lds[BlockFft<K>::F * BlockFft<K>::LDS];
-  ols_x_body<K>(z, n, k0, L, nB, b_first, tw, X, blockIdx.x, lds);
+  ols_x_body<K>(z, n, k0, L, nB, org, tw, X, blockIdx.x, lds);
 }
 
 // --------------------------------------------------------- tap spectra (FP64)
@@ -103,7 +105,7 @@ struct OlsArgs {
   const float2* tw;          // exp(+2 pi i m / 4096), m < 4096
   unsigned long long* slots;
   int64_t n, count, tmpl0, nwin, W, nB;   // nB: blocks of this launch (rows of X)
-  int64_t b_first;           // segment block of X's row 0
+  int64_t org;               // first output sample of X's row 0 (block b: [org + b L, org + b L + L))
   int64_t n_lo, n_hi;        // output samples kept: [n_lo, n_hi)
   int L, J;                  // valid outputs per block, templates per workgroup
   float thr2;                // threshold^2 of the compaction (a key <= it never fires)
@@ -171,7 +173,7 @@ __device__ __forceinline__ void ols_body(const OlsArgs& a, uint32_t bx, uint32_t
   for (int r = 0; r < 16; ++r) xb[r] = Xb[t + S::NTf * r];
   __syncthreads();     // the twiddle table is complete
   // this block's output samples and their windows (uniform per FFT)
-  const int64_t n0 = (a.b_first + b) * a.L;
+  const int64_t n0 = a.org + b * a.L;
   const int64_t nbeg = std::max<int64_t>(n0, a.n_lo);
   const int64_t nend = std::min<int64_t>(std::min<int64_t>(n0 + a.L, a.n), a.n_hi);
   const bool has_out = bvalid && nend > nbeg;
@@ -299,7 +301,7 @@ struct OlsSb {
   const float2* z;           // the sub-bank's reference series
   float2* X;                 // its block spectra [nB][K]
   const float2* G;           // its tap spectra [count][K]
-  int64_t count, tmpl0, nB, b_first;
+  int64_t count, tmpl0, nB;
   int k0, L, J;
   uint32_t gx, wg0, wgx0;
 };
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(256) void k_ols_x_multi(OlsMultiArgs m) {
   const int s = ols_multi_find<true>(m, blockIdx.x);
   const float2* z = nullptr;
   float2* X = nullptr;
-  int64_t nB = 0, b_first = 0;
+  int64_t nB = 0;
   int k0 = 0, L = 1;
   uint32_t wgx0 = 0;
 #pragma unroll
@@ -338,12 +340,11 @@ __global__ __launch_bounds__(256) void k_ols_x_multi(OlsMultiArgs m) {
       z = m.sb[i].z;
       X = m.sb[i].X;
       nB = m.sb[i].nB;
-      b_first = m.sb[i].b_first;
       k0 = m.sb[i].k0;
       L = m.sb[i].L;
       wgx0 = m.sb[i].wgx0;
     }
-  ols_x_body<K>(z, m.n, k0, L, nB, b_first, m.tw, X, blockIdx.x - wgx0, lds);
+  ols_x_body<K>(z, m.n, k0, L, nB, m.n_lo, m.tw, X, blockIdx.x - wgx0, lds);
 }
 
 template <int K, int NF>
@@ -359,6 +360,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   a.W = m.W;
   a.n_lo = m.n_lo;
   a.n_hi = m.n_hi;
+  a.org = m.n_lo;
   a.thr2 = m.thr2;
   uint32_t gx = 1, wg0 = 0;
 #pragma unroll
@@ -369,7 +371,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       a.count = m.sb[i].count;
       a.tmpl0 = m.sb[i].tmpl0;
       a.nB = m.sb[i].nB;
-      a.b_first = m.sb[i].b_first;
       a.L = m.sb[i].L;
       a.J = m.sb[i].J;
       gx = m.sb[i].gx;
@@ -504,10 +505,9 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
                         int64_t n_lo, int64_t n_hi, float2* X) {
   using S = BlockFft<K>;
   const float2* z = p.zref + (int64_t)s.ref_id * p.n;
-  const int64_t b_first = n_lo / s.ols_L, b_last = (n_hi - 1) / s.ols_L;
-  const int64_t nB = b_last - b_first + 1;      // <= s.ols_nB
+  const int64_t nB = (n_hi - n_lo + s.ols_L - 1) / s.ols_L;      // <= s.ols_nB
   const unsigned gx = (unsigned)((nB + S::F - 1) / S::F);
-  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, nB, b_first,
+  hipLaunchKernelGGL(k_ols_x<K>, dim3(gx), dim3(256), 0, p.stream, z, p.n, s.k0, s.ols_L, nB, n_lo,
                      (const float2*)p.ols_tw32, X);
   RFD_CHECK_LAUNCH();
   OlsArgs a;
@@ -521,7 +521,7 @@ static int launch_ols_k(Plan& p, const Taps& t, const SubBankTaps& s, int64_t W,
   a.nwin = nwin;
   a.W = W;
   a.nB = nB;
-  a.b_first = b_first;
+  a.org = n_lo;
   a.n_lo = n_lo;
   a.n_hi = n_hi;
   a.L = s.ols_L;
@@ -559,8 +559,7 @@ static int launch_ols_multi(Plan& p, const Taps& t, const int* sbs, int nsb, int
     d.G = s.ols_g;
     d.count = s.count;
     d.tmpl0 = s.first;
-    d.b_first = n_lo / s.ols_L;
-    d.nB = (n_hi - 1) / s.ols_L - d.b_first + 1;
+    d.nB = (n_hi - n_lo + s.ols_L - 1) / s.ols_L;
     d.k0 = s.k0;
     d.L = s.ols_L;
     d.gx = (uint32_t)((d.nB + S::F - 1) / S::F);

@@ -210,7 +210,7 @@ int launch_fc_cols_lds(Plan& p, const float2* filt, int nb, float2* Y, int n1, i
 // sums in FP64); applies to the fused form, the row form stays FP64.
 int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* h_t, int64_t batch,
                   int T, int k0, double2* out, int64_t out_stride, int64_t lo = -1, int64_t hi = -1,
-                  const int32_t* k0s = nullptr, bool fp32 = false);
+                  const int32_t* k0s = nullptr, bool fp32 = false, const double* bscale = nullptr);
 constexpr int kPeakParts = 64;   // chunks per template in the peak-lag reduction
 // Per-template lag centring: the full weighted cross-correlation b (mode 0)
 // of each batch entry, |b|^2 into pw [batch][N], and its peak lag l in

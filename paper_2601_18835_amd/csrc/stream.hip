@@ -35,7 +35,7 @@
 
 namespace rfd {
 
-constexpr int kStreamRefBatch = 8;     // references per lag-restricted launch
+constexpr int kStreamRefBatch = 32;    // references per lag-restricted launch
 
 struct Stream {
   rfd_plan* handle = nullptr;
@@ -71,20 +71,17 @@ __global__ __launch_bounds__(1024) void k_stream_sigma(const double* __restrict_
   if (threadIdx.x == 0) scale[blockIdx.x] = red[0] > 0.0 ? inv_alpha / sqrt(red[0]) : 0.0;
 }
 
-// z_b[n0 + j] = conj(c_b[zlen - 1 - j]) * scale_b into the series store (FP32
-// and the BF16 / FP16 hi/lo planes), positions mod N
+// z_b[n0 + j] = conj(c_b[zlen - 1 - j]) into the FP32 series store (the lag
+// sums already carry 1 / (sigma_b alpha)), positions mod N
 __global__ __launch_bounds__(256) void k_stream_store(const double2* __restrict__ corr, int64_t zlen,
-                                                    const double* __restrict__ scale,
                                                     const int32_t* __restrict__ slot, float2* __restrict__ zref,
                                                     int64_t n, int64_t n0) {
   const int b = blockIdx.y;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= zlen) return;
   const double2 c = corr[(int64_t)b * zlen + (zlen - 1 - j)];
-  const double sc = scale[b];
-  const double vx = c.x * sc, vy = -c.y * sc;
   const int64_t m = (int64_t)slot[b] * n + ((n0 + j) & (n - 1));
-  zref[m] = make_float2((float)vx, (float)vy);
+  zref[m] = make_float2((float)c.x, (float)-c.y);
 }
 
 static void stream_free(Stream& s) {
@@ -298,14 +295,15 @@ int rfd_stream_push(rfd_stream* stream, const double* data, int32_t precision, f
   if (rc) return rc;
   for (int r0 = 0; r0 < s.nref; r0 += kStreamRefBatch) {
     const int nb = std::min(kStreamRefBatch, s.nref - r0);
-    // the stretch's column transforms in the dechirp's precision
+    // the stretch's column transforms in the dechirp's precision, the
+    // normalisation folded into the integrand (FP32 range)
     rc = launch_corr64(p, s.work, 0, reinterpret_cast<const double*>(p.stilde64),
                        reinterpret_cast<const double*>(s.href + (int64_t)r0 * p.nb), nb, (int)s.zlen, k0c,
-                       s.corr + (int64_t)r0 * s.zlen, s.zlen, -1, -1, nullptr, !p.dechirp_fp64);
+                       s.corr + (int64_t)r0 * s.zlen, s.zlen, -1, -1, nullptr, !p.dechirp_fp64, s.scale + r0);
     if (rc) return rc;
     hipLaunchKernelGGL(k_stream_store, dim3((unsigned)((s.zlen + 255) / 256), (unsigned)nb), dim3(256), 0, p.stream,
-                       (const double2*)(s.corr + (int64_t)r0 * s.zlen), s.zlen, (const double*)(s.scale + r0),
-                       (const int32_t*)(s.d_slot + r0), p.zref, p.n, n0);
+                       (const double2*)(s.corr + (int64_t)r0 * s.zlen), s.zlen, (const int32_t*)(s.d_slot + r0),
+                       p.zref, p.n, n0);
     RFD_CHECK_LAUNCH();
   }
   rc = stage_end(p);

@@ -19,7 +19,7 @@ TOL = {"fp32": 1e-5, "ols32": 1e-5, "bf16x3": 1e-3, "fp16x3": 1e-3}
 SPECS = [(0, 64, -32, 3), (1, 200, -100, 3), (0, 37, 5, 2), (1, 130, -129, 2)]
 
 
-def _case():
+def _case(N=N):
     w = synth.Workload("stream", 11, N, FS, F_LOW, 0, 2, 0, "fp32", "nonspin")
     rng = np.random.default_rng(31)
     psd = synth.psd_array(N, FS)
@@ -42,7 +42,7 @@ def _case():
     return psd, refs, H, seg
 
 
-def _oracle(psd, refs, H, data, form):
+def _oracle(psd, refs, H, data, form, N=N):
     """The oracle's whole circular series of the ring content: reference
     series, each template's rho, and each template's tolerance (the stated
     target, or where larger the first-order rounding bound of its taps: the
@@ -173,3 +173,58 @@ def test_plan_and_taps_outlive_their_graphs_and_streams(rfd, stream_case):
     # both usable again
     s.dechirp_all()
     s.filter("fp32", 6.0, 2048, 64)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_stream_long_segment_matches_whole_window_oracle(rfd, fp64):
+    """At N = 2^18 the stretch of 3072 lags takes the fused share path of the
+    lag-restricted transform (N1 / C column groups times the lags fit the work
+    buffer) with FP32 column transforms, and the direct path with FP64 ones;
+    at N = 2^15 above only the direct path runs.  Reference series on the
+    stretch and every output of the pushed second against the oracle."""
+    import torch
+    from paper_2601_18835_amd.driver import RatioFilterSearch, SubBankSpec
+    n = 1 << 18
+    D = 2048
+    psd, refs, H, seg = _case(n)
+    specs = [SubBankSpec(r, T, k0, c) for r, T, k0, c in SPECS]
+    s = RatioFilterSearch(psd, F_LOW, FS, n, specs, max_refs=2)
+    try:
+        rfd.rfd_plan_set_dechirp_fp64(s.plan, fp64)
+        for r, h in refs.items():
+            s.set_reference(r, h)
+        for b, Hb in enumerate(H):
+            s.make_taps(b, Hb)
+        st = rfd.rfd_stream_create(s.plan, s.taps, s.h_ref, D)
+        try:
+            info = rfd.rfd_stream_info(st)
+            ring = seg[0].copy()
+            rfd.rfd_stream_prime(st, torch.from_numpy(ring).cuda())
+            B = torch.from_numpy(seg[1]).cuda()
+            nt = sum(c for *_, c in SPECS)
+            for push in range(3):
+                head = push * D
+                ring[head:head + D] = seg[1][head:head + D]
+                buf, nn, start = rfd.rfd_stream_push(st, B[head:head + D], "ols32", 0.0, 1, nt * D)
+                assert start == (head - info["lag"]) % n and nn == nt * D
+                if push == 1:
+                    continue
+                zr, rho, tol = _oracle(psd, refs, H, ring, "ols32", n)
+                pos = (head + D - info["zlen"] + np.arange(info["zlen"])) % n
+                for r in refs:
+                    z = s.zref(r).cpu().numpy().astype(np.complex128)
+                    assert np.isfinite(z[pos]).all(), (push, r)
+                    err = np.max(np.abs(z[pos] - zr[r].z[pos] / zr[r].sigma))
+                    print(f"\n[stream 2^18] fp64={fp64} push {push} ref {r}: stretch max |dz| {err:.2e}")
+                    assert err <= 1e-5, (push, r, err)
+                tr = rfd.triggers_to_numpy(buf, nn)
+                outs = (start + np.arange(D)) % n
+                got = np.full((nt, n), np.nan)
+                got[tr["tmpl"], tr["sample"]] = tr["rho"]
+                assert not np.isnan(got[:, outs]).any()
+                err_t = np.max(np.abs(got[:, outs] - rho[:, outs]), axis=1)
+                assert (err_t <= tol).all(), err_t / tol
+        finally:
+            rfd.rfd_stream_destroy(st)
+    finally:
+        s.close()

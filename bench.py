@@ -497,6 +497,29 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def stream_check(w, s, data, prec, rfd, vbuf, nv, vstart, inc, vcap):
+    """Window peaks (threshold 0) of one stream push against those of the
+    range filter over the same outputs after a full re-dechirp: the same
+    windows, every rho finite, the largest |rho difference| over them."""
+    import numpy as np
+    a = rfd.triggers_to_numpy(vbuf, nv)
+    rfd.rfd_dechirp_refs(s.plan, data, s.h_ref, False)
+    rbuf, nr = rfd.rfd_filter_range(s.plan, s.taps, prec, 0.0, w.window, vstart, inc, vcap)
+    b = rfd.triggers_to_numpy(rbuf, nr)
+    ka = np.sort(a["tmpl"].astype(np.int64) * (1 << 32) + a["sample"] // w.window)
+    kb = np.sort(b["tmpl"].astype(np.int64) * (1 << 32) + b["sample"] // w.window)
+    same_windows = bool(nv == nr and np.array_equal(ka, kb))
+    finite = bool(np.isfinite(a["rho"]).all())
+    oa = np.lexsort((a["sample"], a["tmpl"]))
+    ob = np.lexsort((b["sample"], b["tmpl"]))
+    drho = float(np.max(np.abs(a["rho"][oa] - b["rho"][ob]))) if same_windows and nv else None
+    res = {"windows": int(nv), "same_windows": same_windows, "finite": finite, "max_abs_drho": drho}
+    log(f"stream check against the range filter: {res}")
+    if not (finite and same_windows and drho is not None and drho <= 1e-3):
+        raise SystemExit(f"stream outputs disagree with the range filter: {res}")
+    return res
+
+
 def low_latency_leg(args, w, s, data, out, cap, prec, timed, rfd):
     """Sec. VII.A: the next second of SNR from the newest data.  The stream
     (rfd_stream_*) keeps the last N samples in a ring; each push of 1 s
@@ -518,10 +541,16 @@ def low_latency_leg(args, w, s, data, out, cap, prec, timed, rfd):
         return n
 
     d4, n4, t4 = timed(push, 20, 3)
+    # one more push with every window reported, against the range filter of
+    # the same outputs after a full re-dechirp (the ring replays the segment)
+    vcap = 1 << 22
+    vbuf, nv, vstart = rfd.rfd_stream_push(st, data[pos[0]:pos[0] + inc], prec, 0.0, w.window, vcap)
     rfd.rfd_stream_destroy(st)
+    check = stream_check(w, s, data, prec, rfd, vbuf, nv, vstart, inc, vcap)
     stream = {"ms_per_push": d4 / 20 * 1e3, "triggers_last_push": n4,
               "stages_ms_per_push": {k: t4[k] / 20 for k in ("data_fft_ms", "dechirp_ms", "fir_ms", "compact_ms")},
-              "output_lag_samples": info["lag"], "reference_stretch_samples": info["zlen"]}
+              "output_lag_samples": info["lag"], "reference_stretch_samples": info["zlen"],
+              "check_vs_range_filter": check}
     log(f"low latency (stream): {d4 / 20 * 1e3:.3f} ms per 1 s push {stream['stages_ms_per_push']}")
 
     def increment():

@@ -287,10 +287,9 @@ __global__ __launch_bounds__(256) void k_lags_direct(const double2* __restrict__
 // then added in FP64 (the streaming reference series, like the FP32 dechirp
 // passes).
 template <typename V, int L, class LD>
-__global__ __launch_bounds__(kNT) void k_corr_part(LD ld, V* __restrict__ part, const V* __restrict__ coarse,
-                                                 const V* __restrict__ fine, const V* __restrict__ tabL,
-                                                 const V* __restrict__ tab1, int n1, int k0,
-                                                 const int32_t* __restrict__ k0s, int T) {
+__global__ __launch_bounds__(kNT) void k_corr_part(LD ld, V* __restrict__ part, const double2* __restrict__ coarse,
+                                                 const double2* __restrict__ fine, const V* __restrict__ tabL,
+                                                 int n1, int k0, const int32_t* __restrict__ k0s, int T) {
   constexpr int C = Cols<V>::value(L);
   constexpr int LP = lds_col<L>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -313,26 +312,35 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LD ld, V* __restrict__ part, 
   __syncthreads();
   lds_fft<V, L, C, kNT>(buf, twl, +1);
   __syncthreads();
+  // share of lag m = k0 + l: sum_c Y_c[m mod L] e^{+2 pi i (c0 + c) m / N}
+  // (the inter-pass twiddle and the N1-point DFT at m div L in one factor).
+  // The factor is e^{+2 pi i c0 m / N} (e^{+2 pi i m / N})^c, in FP64: the
+  // first part turns by e^{+2 pi i c0 kNT / N} from one of the thread's lags
+  // to its next, the second is read at m (consecutive over a wave's lanes), so
+  // no table read depends on the column.
   V* pb = part + ((int64_t)b * G + g) * T;
+  const uint64_t nmask = (uint64_t)n - 1;
+  const uint64_t m_first = (uint64_t)((int64_t)k0 + (int64_t)threadIdx.x) & nmask;
+  const double2 adv = twiddle_n(coarse, fine, (uint32_t)(((uint64_t)c0 * kNT) & nmask), +1);
+  double2 base = twiddle_n(coarse, fine, (uint32_t)(((uint64_t)c0 * m_first) & nmask), +1);
   for (int l = threadIdx.x; l < T; l += kNT) {
-    const int64_t m = ((int64_t)k0 + l) & (n - 1);
-    const int r = (int)(m % L), cc = (int)(m / L);
+    const uint32_t m = (uint32_t)((uint64_t)((int64_t)k0 + l) & nmask);
+    const int r = (int)(m % L);
+    const double2 step = twiddle_n(coarse, fine, m, +1);
+    double2 f = base;
     double re = 0.0, im = 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int i1 = c0 + c;
-      V v = buf[c * LP + lpad(r)];
-      const uint32_t pp = (uint32_t)i1 * (uint32_t)r;
-      if (pp) v = cmul(v, twiddle_n(coarse, fine, pp, +1));
-      const V w = tab1[(int)(((int64_t)i1 * cc) & (n1 - 1))];
-      const V x = cmul(v, w);
-      re += x.x;
-      im += x.y;
+      const V v = buf[c * LP + lpad(r)];
+      re += (double)v.x * f.x - (double)v.y * f.y;
+      im += (double)v.x * f.y + (double)v.y * f.x;
+      if (c + 1 < C) f = cmul(f, step);
     }
     if constexpr (std::is_same<V, float2>::value)
       pb[l] = make_float2((float)re, (float)im);
     else
       pb[l] = make_double2(re, im);
+    base = cmul(base, adv);
   }
 }
 
@@ -599,12 +607,13 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
     if (fp32) {                                                                                          \
       const size_t sh = lds_bytes<float2, LL, Cols<float2>::value(LL)>();                                \
       hipLaunchKernelGGL((k_corr_part<float2, LL, LoadCorr32>), dim3(groups, (unsigned)batch), blk, sh,  \
-                         p.stream, LoadCorr32{ld}, (float2*)tp.work64, p.tw32c, p.tw32f, p.tw32_n2, p.tw32_n1, p.n1,  \
-                         k0, k0s, T);                                                                    \
+                         p.stream, LoadCorr32{ld}, (float2*)tp.work64, (const double2*)p.tw64c,             \
+                         (const double2*)p.tw64f, p.tw32_n2, p.n1, k0, k0s, T);                            \
     } else {                                                                                             \
       const size_t sh = lds_bytes<double2, LL, Cols<double2>::value(LL)>();                              \
       hipLaunchKernelGGL((k_corr_part<double2, LL, LoadCorr64>), dim3(groups, (unsigned)batch), blk, sh, \
-                         p.stream, ld, tp.work64, p.tw64c, p.tw64f, p.tw64_n2, p.tw64_n1, p.n1, k0, k0s, T); \
+                         p.stream, ld, tp.work64, (const double2*)p.tw64c, (const double2*)p.tw64f,          \
+                         p.tw64_n2, p.n1, k0, k0s, T);                                                     \
     }                                                                                                    \
     break;                                                                                               \
   }

@@ -50,21 +50,38 @@ struct DechirpRefs {
   const double2* h[kDechirpBatch];   // reference templates, complex128 [nb]
   int32_t slot[kDechirpBatch];       // reference-series slots they fill
 };
+// Loaders with a Raw type split an element into fetch (the loads only, no
+// branch: an out-of-band lane reads bin i_low and gets a zero weight) and make
+// (the arithmetic), so that a thread can have the loads of several elements
+// in flight before it combines any (see gather_columns).
 struct LoadDechirpRefs {   // s_i w_i conj(h_b,i) / (sigma_b alpha) over the band, FP64
   const double2* s; const double* w; DechirpRefs r; const double* scale; int64_t i_low, i_high;
-  __device__ double2 operator()(int b, int64_t i) const {
-    if (i < i_low || i > i_high) return make_double2(0.0, 0.0);
-    const double2 h = r.h[b][i];
-    const double f = w[i] * scale[b];
-    return cmul(s[i], make_double2(f * h.x, -f * h.y));
+  struct Raw { double2 h, s; double w; };
+  __device__ Raw fetch(int b, int64_t i) const {
+    const bool in = i >= i_low && i <= i_high;
+    const int64_t k = in ? i : i_low;
+    Raw x;
+    x.h = r.h[b][k];
+    x.s = s[k];
+    x.w = w[k];
+    if (!in) x.w = 0.0;
+    return x;
   }
+  __device__ double2 make(int b, int64_t, const Raw& x) const {
+    const double f = x.w * scale[b];
+    return cmul(x.s, make_double2(f * x.h.x, -f * x.h.y));
+  }
+  __device__ double2 operator()(int b, int64_t i) const { return make(b, i, fetch(b, i)); }
 };
 struct LoadDechirpRefs32 { // the same integrand, formed in FP64 and rounded once to FP32
   LoadDechirpRefs d;
-  __device__ float2 operator()(int b, int64_t i) const {
-    const double2 v = d(b, i);
+  using Raw = LoadDechirpRefs::Raw;
+  __device__ Raw fetch(int b, int64_t i) const { return d.fetch(b, i); }
+  __device__ float2 make(int b, int64_t i, const Raw& x) const {
+    const double2 v = d.make(b, i, x);
     return make_float2((float)v.x, (float)v.y);
   }
+  __device__ float2 operator()(int b, int64_t i) const { return make(b, i, fetch(b, i)); }
 };
 struct LoadFindchirp {     // s_i * F_j,i with F_j stored over band bins
   const float2* s; const float2* f; int64_t i_low, i_high, n_band;
@@ -76,19 +93,29 @@ struct LoadFindchirp {     // s_i * F_j,i with F_j stored over band bins
 struct LoadCorr64 {        // FP64 correlation integrands (tap construction, streaming series)
   const double* w; const double2* hr; const double2* ht; int64_t nb, i_low, i_high; int mode;
   const double* bscale;    // mode 0: per-member factor folded into the integrand (nullptr: none)
-  __device__ double2 operator()(int b, int64_t i) const {
-    if (i < i_low || i > i_high) return make_double2(0.0, 0.0);
-    double2 r = hr[i];
-    double wi = w[i];
+  struct Raw { double2 r, t; double w; };
+  __device__ Raw fetch(int b, int64_t i) const {
+    const bool in = i >= i_low && i <= i_high;
+    const int64_t k = in ? i : i_low;
+    Raw x;
+    x.r = hr[k];
+    x.t = ht[(int64_t)b * nb + k];     // (mode 1: ht is hr, unused)
+    x.w = w[k];
+    if (!in) x.w = 0.0;
+    return x;
+  }
+  __device__ double2 make(int b, int64_t, const Raw& x) const {
+    const double2 r = x.r, t = x.t;
+    double wi = x.w;
     if (mode == 1) return make_double2(wi * (r.x * r.x + r.y * r.y), 0.0);
-    double2 t = ht[(int64_t)b * nb + i];
     if (bscale) wi *= bscale[b];
     if (mode == 0) return make_double2(wi * (t.x * r.x + t.y * r.y), wi * (t.y * r.x - t.x * r.y));
     // mode 2: ratio R = t / r where the chi^2 weight w |r|^2 is non-zero
-    double rr = r.x * r.x + r.y * r.y;
+    const double rr = r.x * r.x + r.y * r.y;
     if (!(wi * rr > 0.0)) return make_double2(0.0, 0.0);
     return make_double2((t.x * r.x + t.y * r.y) / rr, (t.y * r.x - t.x * r.y) / rr);
   }
+  __device__ double2 operator()(int b, int64_t i) const { return make(b, i, fetch(b, i)); }
 };
 
 // The same integrands rounded once to FP32.  w_i alone is of order 1 / S_n
@@ -97,10 +124,13 @@ struct LoadCorr64 {        // FP64 correlation integrands (tap construction, str
 // streaming series use 1 / (sigma_ref alpha), as the FP32 dechirp passes do).
 struct LoadCorr32 {
   LoadCorr64 d;
-  __device__ float2 operator()(int b, int64_t i) const {
-    const double2 v = d(b, i);
+  using Raw = LoadCorr64::Raw;
+  __device__ Raw fetch(int b, int64_t i) const { return d.fetch(b, i); }
+  __device__ float2 make(int b, int64_t i, const Raw& x) const {
+    const double2 v = d.make(b, i, x);
     return make_float2((float)v.x, (float)v.y);
   }
+  __device__ float2 operator()(int b, int64_t i) const { return make(b, i, fetch(b, i)); }
 };
 
 // ---------------------------------------------------------------- storers
@@ -136,6 +166,53 @@ __device__ void load_twl(V* twl, const V* __restrict__ tab, int stride = 1) {
   for (int k = threadIdx.x; k < L; k += kNT) twl[lpad(k)] = tab[k * stride];
 }
 
+// The C columns c0 + c (stride n1 through the input) into LDS, [C][LP]
+// padded.  Each thread issues U elements' loads before storing any, so U
+// memory round trips overlap (one at a time, the loop waited for every load).
+template <class LD, class = void> struct HasRaw : std::false_type {};
+template <class LD> struct HasRaw<LD, std::void_t<typename LD::Raw>> : std::true_type {};
+
+// elements per thread in flight: at most U, and no more than a thread has
+// (C L and kNT are powers of two, so U * kNT divides C L when C L >= kNT)
+template <int E, int U>
+__host__ __device__ constexpr int gather_batch() { return E / kNT >= U ? U : (E / kNT >= 1 ? E / kNT : 1); }
+
+template <typename V, int L, int C, int U0, class LD>
+__device__ __forceinline__ void gather_columns(V* buf, const LD& ld, int b, int c0, int n1) {
+  constexpr int LP = lds_col<L>();
+  constexpr int E = C * L;
+  constexpr int U = gather_batch<E, U0>();
+  for (int e0 = 0; e0 < E; e0 += U * kNT) {
+    if constexpr (HasRaw<LD>::value) {
+      typename LD::Raw x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kNT + (int)threadIdx.x;
+        if (E % (U * kNT) == 0 || e < E) x[u] = ld.fetch(b, (int64_t)(c0 + e % C) + (int64_t)n1 * (e / C));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kNT + (int)threadIdx.x;
+        if (E % (U * kNT) == 0 || e < E)
+          buf[(e % C) * LP + lpad(e / C)] = ld.make(b, (int64_t)(c0 + e % C) + (int64_t)n1 * (e / C), x[u]);
+      }
+    } else {
+      V v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kNT + (int)threadIdx.x;
+        if (E % (U * kNT) == 0 || e < E) v[u] = ld(b, (int64_t)(c0 + e % C) + (int64_t)n1 * (e / C));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kNT + (int)threadIdx.x;
+        if (E % (U * kNT) == 0 || e < E) buf[(e % C) * LP + lpad(e / C)] = v[u];
+      }
+    }
+  }
+}
+constexpr int kGatherU = 8;
+
 // pass A: L = N2-point transforms of C columns; writes Y with the inter-pass
 // twiddle.  tabL[k * tab_stride] = exp(+2 pi i k / L).  Only the rows n2 in
 // [row_lo, row_lo + row_cnt) mod L are written (all rows: 0, L): a consumer
@@ -153,10 +230,7 @@ __global__ __launch_bounds__(kNT) void k_pass_a(LD ld, V* __restrict__ Y, const 
   const int c0 = blockIdx.x * C;
   const int64_t n = (int64_t)n1 * L;
   load_twl<V, L>(twl, tabL, tab_stride);
-  for (int e = threadIdx.x; e < C * L; e += kNT) {
-    int c = e % C, i2 = e / C;
-    buf[c * LP + lpad(i2)] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
-  }
+  gather_columns<V, L, C, kGatherU>(buf, ld, b, c0, n1);
   __syncthreads();
   lds_fft<V, L, C, kNT>(buf, twl, sign);
   V* Yb = Y + (int64_t)b * n;
@@ -176,9 +250,20 @@ __device__ void pass_b_load(const V* __restrict__ Yb, V* buf, V* twl, const V* _
   constexpr int C = Cols<V>::value(L);
   constexpr int LP = lds_col<L>();
   load_twl<V, L>(twl, tabL);
-  for (int e = threadIdx.x; e < C * L; e += kNT) {
-    int c = e / L, i1 = e % L;
-    buf[c * LP + lpad(i1)] = Yb[(int64_t)(r0 + c) * L + i1];
+  constexpr int E = C * L;
+  constexpr int U = gather_batch<E, kGatherU>();
+  for (int e0 = 0; e0 < E; e0 += U * kNT) {      // U loads in flight per thread
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kNT + (int)threadIdx.x;
+      if (E % (U * kNT) == 0 || e < E) v[u] = Yb[(int64_t)(r0 + e / L) * L + e % L];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kNT + (int)threadIdx.x;
+      if (E % (U * kNT) == 0 || e < E) buf[(e / L) * LP + lpad(e % L)] = v[u];
+    }
   }
   __syncthreads();
 }
@@ -305,10 +390,7 @@ __global__ __launch_bounds__(kNT) void k_corr_part(LD ld, V* __restrict__ part, 
   const int c0 = g * C;
   const int64_t n = (int64_t)n1 * L;
   load_twl<V, L>(twl, tabL, 1);
-  for (int e = threadIdx.x; e < C * L; e += kNT) {
-    int c = e % C, i2 = e / C;
-    buf[c * LP + lpad(i2)] = ld(b, (int64_t)(c0 + c) + (int64_t)n1 * i2);
-  }
+  gather_columns<V, L, C, kGatherU>(buf, ld, b, c0, n1);
   __syncthreads();
   lds_fft<V, L, C, kNT>(buf, twl, +1);
   __syncthreads();
@@ -593,8 +675,10 @@ int launch_corr64(Plan& p, Taps& tp, int mode, const double* h_r, const double* 
   size_t need = (size_t)batch * p.n;
   if (tp.work64_cap < need) return fail(RFD_E_INVALID, "corr64: work buffer too small");
   if (fp32 && mode == 0 && !bscale) return fail(RFD_E_INVALID, "corr64: FP32 integrands need their normalisation");
-  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)h_t, p.nb, lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high,
-                mode, mode == 0 ? bscale : nullptr};
+  // (a single-spectrum mode reads its spectrum as the second one too: the
+  // loads need no branch on the mode)
+  LoadCorr64 ld{p.w, (const double2*)h_r, (const double2*)(h_t ? h_t : h_r), h_t ? p.nb : 0,
+                lo >= 0 ? lo : p.i_low, hi >= 0 ? hi : p.i_high, mode, mode == 0 ? bscale : nullptr};
   const double scale = mode == 2 ? 1.0 / (double)p.n : 1.0;
   // fused form: per-workgroup lag shares in the work buffer, then their sums
   const int C = fp32 ? Cols<float2>::value(p.n2) : Cols<double2>::value(p.n2);
